@@ -1,0 +1,165 @@
+"""CPU oracle for the warehouse routing hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never calls it
+and shares no code with it.
+
+The C part (``oracle.c`` -> ``liboracle.so``) holds Dijkstra, Jacobi
+Bellman-Ford, canonical predecessors, order gathers, CSR validation and the
+optimality certificate; ``brute.py`` enumerates simple paths on tiny graphs
+and ``closed_forms.py`` holds the grid distance formulas used as pins.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+INF = 0xFFFFFFFF
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (OpenMP over sources)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, os.path.join(_HERE, "oracle.c")])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32, i32 = ctypes.c_uint32, ctypes.c_int
+        L.orc_validate_csr.argtypes = [u32, u32, _u32p, _u32p, _u32p]
+        L.orc_validate_csr.restype = i32
+        L.orc_dijkstra.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p]
+        L.orc_dijkstra.restype = i32
+        L.orc_dijkstra_multi.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p, _u32p, i32]
+        L.orc_dijkstra_multi.restype = i32
+        L.orc_bellman_ford.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p, u32,
+                                       ctypes.POINTER(u32)]
+        L.orc_bellman_ford.restype = i32
+        L.orc_canonical_pred.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p, _i32p]
+        L.orc_canonical_pred.restype = None
+        L.orc_gather_orders.argtypes = [u32, u32, _u32p, _u32p, _u32p, _u32p, _u32p]
+        L.orc_gather_orders.restype = None
+        L.orc_certificate.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p, ctypes.c_void_p]
+        L.orc_certificate.restype = i32
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def _csr(row_ptr, col, w):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.uint32)
+    c = np.ascontiguousarray(col, dtype=np.uint32)
+    ww = np.ascontiguousarray(w, dtype=np.uint32)
+    if c.size == 0:   # ndpointer needs a real buffer
+        c = np.zeros(1, np.uint32)
+        ww = np.zeros(1, np.uint32)
+    return rp, c, ww
+
+
+def validate_csr(row_ptr, col, w) -> int:
+    """0 ok, 1 malformed, 2 overflow risk (see oracle.c).  E is the length
+    of ``col``; ``w`` must have the same length."""
+    E = len(col)
+    if len(w) != E:
+        return 1
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    if V <= 0:
+        return 1
+    return lib().orc_validate_csr(V, E, rp, c, ww)
+
+
+def dijkstra(row_ptr, col, w, src: int) -> np.ndarray:
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    out = np.empty(V, dtype=np.uint32)
+    rc = lib().orc_dijkstra(V, rp, c, ww, int(src), out)
+    assert rc == 0, rc
+    return out
+
+
+def dijkstra_multi(row_ptr, col, w, sources, nthreads: int = 0) -> np.ndarray:
+    """Source-major [S, V] distances, parallel over sources."""
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    src = np.ascontiguousarray(sources, dtype=np.uint32)
+    out = np.empty((len(src), V), dtype=np.uint32)
+    if len(src):
+        rc = lib().orc_dijkstra_multi(V, rp, c, ww, len(src), src, out.reshape(-1), nthreads)
+        assert rc == 0, rc
+    return out
+
+
+def bellman_ford(row_ptr, col, w, src: int, max_rounds: int = 0):
+    """Jacobi Bellman-Ford; returns (dist, changing_rounds, status)."""
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    out = np.empty(V, dtype=np.uint32)
+    r = ctypes.c_uint32(0)
+    rc = lib().orc_bellman_ford(V, rp, c, ww, int(src), out, int(max_rounds), ctypes.byref(r))
+    return out, int(r.value), rc
+
+
+def canonical_pred(row_ptr, col, w, src: int, dist) -> np.ndarray:
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    d = np.ascontiguousarray(dist, dtype=np.uint32)
+    out = np.empty(V, dtype=np.int32)
+    lib().orc_canonical_pred(V, rp, c, ww, int(src), d, out)
+    return out
+
+
+def certificate(row_ptr, col, w, src: int, dist, pred=None) -> int:
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    d = np.ascontiguousarray(dist, dtype=np.uint32)
+    p = None
+    if pred is not None:
+        p = np.ascontiguousarray(pred, dtype=np.int32)
+    return lib().orc_certificate(V, rp, c, ww, int(src), d,
+                                 None if p is None else p.ctypes.data_as(ctypes.c_void_p))
+
+
+def order_matrices(row_ptr, col, w, pick_offsets, picks, nthreads: int = 0) -> np.ndarray:
+    """Concatenated per-order P x P blocks D_o[i][j] = d(p_i, p_j).
+
+    The distance row of each distinct pick vertex is computed once (it is a
+    function of that vertex alone) and read for every (i, j) entry.
+    """
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    off = np.ascontiguousarray(pick_offsets, dtype=np.uint32)
+    pk = np.ascontiguousarray(picks, dtype=np.uint32)
+    n_orders = len(off) - 1
+    sizes = np.diff(off.astype(np.int64))
+    total = int((sizes ** 2).sum())
+    out = np.empty(max(total, 1), dtype=np.uint32)
+    if total == 0:
+        return out[:0]
+    uniq, row_of = np.unique(pk, return_inverse=True)
+    rows = dijkstra_multi(rp, c, ww, uniq, nthreads)
+    lib().orc_gather_orders(V, n_orders, off, pk, row_of.astype(np.uint32),
+                            rows.reshape(-1), out)
+    return out[:total]
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

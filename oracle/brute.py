@@ -1,0 +1,34 @@
+"""Brute-force shortest distances by enumerating every simple path.
+
+Test infrastructure only.  For a tiny directed graph (V <= 9) the minimum over
+all simple s->v paths of the summed arc weights is the definition of d(s, v)
+for non-negative weights (a shortest walk can always drop its cycles).  Pure
+Python, exponential, independent of the C oracle.
+"""
+from __future__ import annotations
+
+INF = 0xFFFFFFFF
+
+
+def all_pairs_by_enumeration(V: int, arcs) -> list[list[int]]:
+    """arcs: iterable of (u, v, w).  Returns D[s][v] (INF if unreachable)."""
+    out_arcs = [[] for _ in range(V)]
+    for u, v, w in arcs:
+        out_arcs[u].append((v, w))
+    D = [[INF] * V for _ in range(V)]
+    for s in range(V):
+        best = D[s]
+        best[s] = 0
+        on_path = [False] * V
+
+        def walk(u, length):
+            on_path[u] = True
+            if length < best[u]:
+                best[u] = length
+            for v, w in out_arcs[u]:
+                if not on_path[v]:
+                    walk(v, length + w)
+            on_path[u] = False
+
+        walk(s, 0)
+    return D

@@ -1,0 +1,355 @@
+/*
+ * Reference oracle for the warehouse routing hot path -- TEST INFRASTRUCTURE.
+ *
+ * Plain, slow, obviously-correct CPU code.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may call it; the product path
+ * never links or loads it, and it shares no source, header or helper with the
+ * HIP library.
+ *
+ * What it computes is the plain definition of the result the paper's routing
+ * step reaches: for a directed graph with non-negative integer arc weights,
+ * d(s, v) = minimum over s->v paths of the sum of arc weights, INF if no path
+ * exists (GPU implementation subsection: Bellman-Ford over integer edge
+ * arrays, validated against Dijkstra on the CPU, which the closing remark of
+ * that subsection says gave identical shortest paths).  Two independent
+ * algorithms reach that definition here:
+ *
+ *   - Dijkstra with a binary heap and lazy deletion (64-bit accumulation);
+ *   - Jacobi Bellman-Ford: d_0 = INF except d_0(s) = 0, then
+ *     d_{k+1}(v) = min(d_k(v), min_{(u,v)} d_k(u) + w(u,v)), stopping when a
+ *     round changes nothing or after V-1 rounds (the round count the paper
+ *     runs).
+ *
+ * plus the canonical predecessor (smallest tight in-neighbour id), the
+ * per-order pick-to-pick matrices D_o[i][j] = d(p_i, p_j) (routes are built
+ * over stop-to-stop distances, Route Optimization section), CSR validation
+ * with the overflow bound, and a certificate checker that proves a
+ * (dist, pred) pair optimal without re-solving.
+ *
+ * Conventions: INF = 0xFFFFFFFF, "no predecessor" = -1, vertex ids < 2^31.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_INF 0xFFFFFFFFu
+
+/* ------------------------------------------------------------------ */
+/* validation                                                          */
+/* ------------------------------------------------------------------ */
+
+/* 0 = ok, 1 = malformed CSR, 2 = a shortest path could reach INF.
+ * Rules: row_ptr[0] = 0, row_ptr non-decreasing, row_ptr[V] = E, every
+ * col < V.  Overflow bound: max_w * (number of vertices incident to an arc
+ * minus 1) must stay below INF, since a simple path visits each such vertex
+ * at most once. */
+int orc_validate_csr(uint32_t V, uint32_t E, const uint32_t *row_ptr,
+                     const uint32_t *col, const uint32_t *w)
+{
+    if (V == 0 || V >= 0x80000000u || !row_ptr) return 1;
+    if (E > 0 && (!col || !w)) return 1;
+    if (row_ptr[0] != 0 || row_ptr[V] != E) return 1;
+    for (uint32_t v = 0; v < V; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return 1;
+    for (uint32_t e = 0; e < E; ++e)
+        if (col[e] >= V) return 1;
+    unsigned char *inc = (unsigned char *)calloc(V, 1);
+    if (!inc) return 1;
+    uint64_t maxw = 0, n_inc = 0;
+    for (uint32_t u = 0; u < V; ++u)
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            inc[u] = 1;
+            inc[col[e]] = 1;
+            if (w[e] > maxw) maxw = w[e];
+        }
+    for (uint32_t v = 0; v < V; ++v) n_inc += inc[v];
+    free(inc);
+    if (n_inc > 1 && maxw * (n_inc - 1) >= (uint64_t)ORC_INF) return 2;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dijkstra                                                            */
+/* ------------------------------------------------------------------ */
+
+typedef struct { uint64_t key; uint32_t v; } heap_item;
+
+static void heap_push(heap_item *h, size_t *n, heap_item it)
+{
+    size_t i = (*n)++;
+    while (i > 0) {
+        size_t p = (i - 1) / 2;
+        if (h[p].key <= it.key) break;
+        h[i] = h[p];
+        i = p;
+    }
+    h[i] = it;
+}
+
+static heap_item heap_pop(heap_item *h, size_t *n)
+{
+    heap_item top = h[0];
+    heap_item last = h[--(*n)];
+    size_t i = 0;
+    for (;;) {
+        size_t l = 2 * i + 1, r = l + 1, m = i;
+        uint64_t mk = last.key;
+        if (l < *n && h[l].key < mk) { m = l; mk = h[l].key; }
+        if (r < *n && h[r].key < mk) { m = r; }
+        if (m == i) break;
+        h[i] = h[m];
+        i = m;
+    }
+    if (*n > 0) h[i] = last;
+    return top;
+}
+
+/* Single-source Dijkstra; dist must hold V entries.  0 = ok, 3 = no memory. */
+int orc_dijkstra(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                 const uint32_t *w, uint32_t src, uint32_t *dist)
+{
+    uint32_t E = row_ptr[V];
+    uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * V);
+    unsigned char *done = (unsigned char *)calloc(V, 1);
+    heap_item *h = (heap_item *)malloc(sizeof(heap_item) * ((size_t)E + 1));
+    if (!d || !done || !h) { free(d); free(done); free(h); return 3; }
+    for (uint32_t v = 0; v < V; ++v) d[v] = UINT64_MAX;
+    size_t n = 0;
+    d[src] = 0;
+    heap_item s0 = {0, src};
+    heap_push(h, &n, s0);
+    while (n > 0) {
+        heap_item it = heap_pop(h, &n);
+        uint32_t u = it.v;
+        if (done[u] || it.key != d[u]) continue;   /* stale entry */
+        done[u] = 1;
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            uint32_t x = col[e];
+            uint64_t nd = d[u] + (uint64_t)w[e];
+            if (nd < d[x]) {
+                d[x] = nd;
+                heap_item ni = {nd, x};
+                heap_push(h, &n, ni);
+            }
+        }
+    }
+    for (uint32_t v = 0; v < V; ++v)
+        dist[v] = (d[v] >= (uint64_t)ORC_INF) ? ORC_INF : (uint32_t)d[v];
+    free(d); free(done); free(h);
+    return 0;
+}
+
+/* Dijkstra from each of S sources into dist[S*V] (source-major), in
+ * parallel over sources on `nthreads` threads (0 = all).  Returns 0 or the
+ * first error. */
+int orc_dijkstra_multi(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                       const uint32_t *w, uint32_t S, const uint32_t *sources,
+                       uint32_t *dist, int nthreads)
+{
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(| : err)
+#endif
+    for (long i = 0; i < (long)S; ++i)
+        err |= orc_dijkstra(V, row_ptr, col, w, sources[i], dist + (size_t)i * V);
+    (void)nthreads;
+    return err;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Jacobi Bellman-Ford                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Rounds of d_{k+1}(v) = min(d_k(v), min over arcs (u,v) of d_k(u)+w) until
+ * a round changes nothing or `max_rounds` rounds ran (0 means V-1).
+ * *rounds_out receives the number of rounds that changed something.
+ * Returns 0, or 4 if the cap was hit while values were still changing. */
+int orc_bellman_ford(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                     const uint32_t *w, uint32_t src, uint32_t *dist,
+                     uint32_t max_rounds, uint32_t *rounds_out)
+{
+    if (max_rounds == 0) max_rounds = V > 1 ? V - 1 : 1;
+    uint64_t *cur = (uint64_t *)malloc(sizeof(uint64_t) * V);
+    uint64_t *nxt = (uint64_t *)malloc(sizeof(uint64_t) * V);
+    if (!cur || !nxt) { free(cur); free(nxt); return 3; }
+    for (uint32_t v = 0; v < V; ++v) cur[v] = UINT64_MAX;
+    cur[src] = 0;
+    uint32_t rounds = 0;
+    int changed = 1;
+    while (changed && rounds < max_rounds) {
+        changed = 0;
+        memcpy(nxt, cur, sizeof(uint64_t) * V);
+        for (uint32_t u = 0; u < V; ++u) {
+            if (cur[u] == UINT64_MAX) continue;
+            for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                uint64_t cand = cur[u] + (uint64_t)w[e];
+                if (cand < nxt[col[e]]) nxt[col[e]] = cand;
+            }
+        }
+        for (uint32_t v = 0; v < V; ++v)
+            if (nxt[v] != cur[v]) { changed = 1; break; }
+        uint64_t *t = cur; cur = nxt; nxt = t;
+        if (changed) ++rounds;
+    }
+    /* one more check round tells whether the cap stopped a changing run */
+    int capped = 0;
+    if (changed) {
+        for (uint32_t u = 0; u < V && !capped; ++u) {
+            if (cur[u] == UINT64_MAX) continue;
+            for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+                if (cur[u] + (uint64_t)w[e] < cur[col[e]]) { capped = 1; break; }
+        }
+    }
+    for (uint32_t v = 0; v < V; ++v)
+        dist[v] = (cur[v] >= (uint64_t)ORC_INF) ? ORC_INF : (uint32_t)cur[v];
+    if (rounds_out) *rounds_out = rounds;
+    free(cur); free(nxt);
+    return capped ? 4 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* canonical predecessor                                               */
+/* ------------------------------------------------------------------ */
+
+/* pred[v] = smallest u with an arc (u, v), d(u) != INF and
+ * d(u) + w(u, v) = d(v); pred[src] = -1; unreachable vertices get -1. */
+void orc_canonical_pred(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                        const uint32_t *w, uint32_t src, const uint32_t *dist,
+                        int32_t *pred)
+{
+    for (uint32_t v = 0; v < V; ++v) pred[v] = -1;
+    for (uint32_t u = 0; u < V; ++u) {
+        if (dist[u] == ORC_INF) continue;
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            uint32_t x = col[e];
+            if (x == src || dist[x] == ORC_INF) continue;
+            if ((uint64_t)dist[u] + w[e] == (uint64_t)dist[x])
+                if (pred[x] < 0 || (uint32_t)pred[x] > u) pred[x] = (int32_t)u;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* order matrices                                                      */
+/* ------------------------------------------------------------------ */
+
+/* out receives, for every order o with picks p_0..p_{P-1}, the P x P block
+ * D_o[i][j] = d(p_i, p_j) (row = source pick), blocks concatenated in order.
+ * `dist_rows` maps each pick position k (0..total picks-1) to a row of
+ * source-major distances already computed for vertex picks[k]. */
+void orc_gather_orders(uint32_t V, uint32_t num_orders, const uint32_t *pick_off,
+                       const uint32_t *picks, const uint32_t *row_of_pick,
+                       const uint32_t *dist_rows, uint32_t *out)
+{
+    size_t o_base = 0;
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        for (uint32_t i = 0; i < P; ++i) {
+            const uint32_t *row = dist_rows + (size_t)row_of_pick[a + i] * V;
+            for (uint32_t j = 0; j < P; ++j)
+                out[o_base + (size_t)i * P + j] = row[picks[a + j]];
+        }
+        o_base += (size_t)P * P;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* certificate                                                         */
+/* ------------------------------------------------------------------ */
+
+/* Proves that dist (and pred, if not NULL) is a shortest-path solution from
+ * src without re-solving.  Returns 0 if valid, else a code naming the first
+ * failed condition:
+ *   10 d(src) != 0
+ *   11 an arc (u,v) with d(u) finite and d(v) > d(u) + w (infeasible)
+ *   12 a finite d(v) not reachable from src through tight arcs
+ *      (d(u) + w = d(v)), so d(v) is not the length of any path
+ *   13 an INF vertex reachable from src
+ *   20 pred[src] != -1, 21 pred set on an INF vertex or missing on a finite
+ *      one, 22 pred[v] -> v is not a tight arc, 23 pred chain does not reach
+ *      src (cycle)
+ * Feasibility gives d(v) <= length of every s->v path; tight reachability
+ * gives a path of length exactly d(v); together they prove optimality. */
+int orc_certificate(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                    const uint32_t *w, uint32_t src, const uint32_t *dist,
+                    const int32_t *pred)
+{
+    if (dist[src] != 0) return 10;
+    for (uint32_t u = 0; u < V; ++u) {
+        if (dist[u] == ORC_INF) continue;
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if ((uint64_t)dist[col[e]] > (uint64_t)dist[u] + w[e]) return 11;
+    }
+    uint32_t *stack = (uint32_t *)malloc(sizeof(uint32_t) * V);
+    unsigned char *seen = (unsigned char *)calloc(V, 1);
+    unsigned char *reach = (unsigned char *)calloc(V, 1);
+    if (!stack || !seen || !reach) { free(stack); free(seen); free(reach); return 3; }
+    int rc = 0;
+    /* tight-arc reachability */
+    size_t n = 0;
+    stack[n++] = src; seen[src] = 1;
+    while (n) {
+        uint32_t u = stack[--n];
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            uint32_t x = col[e];
+            if (!seen[x] && (uint64_t)dist[u] + w[e] == (uint64_t)dist[x]) {
+                seen[x] = 1; stack[n++] = x;
+            }
+        }
+    }
+    for (uint32_t v = 0; v < V && !rc; ++v)
+        if (dist[v] != ORC_INF && !seen[v]) rc = 12;
+    /* plain reachability */
+    if (!rc) {
+        n = 0; stack[n++] = src; reach[src] = 1;
+        while (n) {
+            uint32_t u = stack[--n];
+            for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+                if (!reach[col[e]]) { reach[col[e]] = 1; stack[n++] = col[e]; }
+        }
+        for (uint32_t v = 0; v < V && !rc; ++v)
+            if (dist[v] == ORC_INF && reach[v]) rc = 13;
+    }
+    if (!rc && pred) {
+        if (pred[src] != -1) rc = 20;
+        for (uint32_t v = 0; v < V && !rc; ++v) {
+            if (v == src) continue;
+            if ((dist[v] == ORC_INF) != (pred[v] < 0)) { rc = 21; break; }
+            if (pred[v] < 0) continue;
+            uint32_t u = (uint32_t)pred[v];
+            int tight = 0;
+            if (u < V && dist[u] != ORC_INF)
+                for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+                    if (col[e] == v && (uint64_t)dist[u] + w[e] == (uint64_t)dist[v]) { tight = 1; break; }
+            if (!tight) rc = 22;
+        }
+        /* every chain must reach src: resolve depths iteratively */
+        if (!rc) {
+            memset(seen, 0, V);          /* 0 unknown, 1 on current chain, 2 ok */
+            seen[src] = 2;
+            for (uint32_t v = 0; v < V && !rc; ++v) {
+                if (dist[v] == ORC_INF || seen[v] == 2) continue;
+                n = 0;
+                uint32_t x = v;
+                while (seen[x] == 0) { seen[x] = 1; stack[n++] = x; x = (uint32_t)pred[x]; }
+                if (seen[x] == 1) { rc = 23; break; }
+                while (n) seen[stack[--n]] = 2;
+            }
+        }
+    }
+    free(stack); free(seen); free(reach);
+    return rc;
+}

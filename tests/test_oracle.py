@@ -1,0 +1,318 @@
+"""Pins for the CPU oracle: every check here compares it with something other
+than itself (brute-force enumeration, closed forms, scipy's Dijkstra, planted
+mistakes that the certificate must catch)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+
+import oracle
+from oracle.brute import all_pairs_by_enumeration
+from oracle.closed_forms import manhattan, rack_distance
+from tests.helpers import random_csr, csr_arcs
+from wgen import build_grid_graph, make_config, rack_layout
+
+INF = oracle.INF
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _scipy_rows(row_ptr, col, w, sources):
+    """scipy csgraph Dijkstra; parallel arcs are reduced to their minimum."""
+    V = len(row_ptr) - 1
+    rows = np.repeat(np.arange(V), np.diff(row_ptr.astype(np.int64)))
+    keep = rows != col
+    # csgraph treats explicit zeros as absent arcs; shift weights by +1 and
+    # rebuild exact distances through a tiny epsilon-free trick is not
+    # possible, so only use positive-weight graphs here
+    assert (w[keep] > 0).all()
+    m = {}
+    for a, b, c in zip(rows[keep], col[keep], w[keep]):
+        k = (int(a), int(b))
+        m[k] = min(m.get(k, 1 << 62), int(c))
+    if m:
+        r, c = zip(*m.keys())
+        data = list(m.values())
+    else:
+        r, c, data = [], [], []
+    G = sp.csr_matrix((np.asarray(data, float), (r, c)), shape=(V, V))
+    D = sp_dijkstra(G, indices=np.asarray(sources))
+    out = np.where(np.isfinite(D), D, INF).astype(np.uint64)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_dijkstra_and_bf_match_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    V = int(rng.integers(1, 10))
+    E = int(rng.integers(0, 3 * V + 1))
+    rp, col, w = random_csr(rng, V, E, wmax=7, zero_frac=0.25 if seed % 2 else 0.0)
+    D = all_pairs_by_enumeration(V, csr_arcs(rp, col, w))
+    for s in range(V):
+        d = oracle.dijkstra(rp, col, w, s)
+        b, _, st = oracle.bellman_ford(rp, col, w, s)
+        assert st == 0
+        assert d.tolist() == D[s], (s, d, D[s])
+        assert b.tolist() == D[s]
+        assert oracle.certificate(rp, col, w, s, d) == 0
+
+
+def test_obstacle_free_grid_is_manhattan():
+    for c in (1, 4):
+        W, H = 13, 9
+        g = build_grid_graph(W, H, range(H), c, c, np.random.default_rng(0))
+        assert not g.blocked.any()
+        for s in [0, 5, W * 4 + 6, W * H - 1]:
+            d = oracle.dijkstra(g.row_ptr, g.col, g.w, s)
+            sx, sy = s % W, s // W
+            exp = [manhattan(sx, sy, v % W, v // W, c) for v in range(W * H)]
+            assert d.tolist() == exp
+
+
+@pytest.mark.parametrize("c", [1, 3])
+def test_tiny_rack_layout_closed_form(c):
+    rows = [0, 19, 39]
+    g = build_grid_graph(20, 40, rows, c, c, np.random.default_rng(0))
+    aisle = [(x, y) for y in range(40) for x in range(20)
+             if not g.blocked[y, x] and x % 3 != 2]
+    src = np.asarray([y * 20 + x for x, y in aisle], dtype=np.uint32)
+    D = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)
+    bad = 0
+    for i, (x1, y1) in enumerate(aisle):
+        for (x2, y2) in aisle:
+            if D[i, y2 * 20 + x2] != rack_distance(x1, y1, x2, y2, rows, c):
+                bad += 1
+    assert bad == 0
+
+
+def test_larger_rack_layout_closed_form_sampled():
+    rows = [0, 32, 64, 95]
+    W, H = 64, 96
+    g = build_grid_graph(W, H, rows, 2, 2, np.random.default_rng(0))
+    rng = np.random.default_rng(5)
+    aisle = np.asarray([y * W + x for y in range(H) for x in range(W)
+                        if not g.blocked[y, x] and x % 3 != 2])
+    src = aisle[rng.choice(len(aisle), 40, replace=False)].astype(np.uint32)
+    D = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)
+    for i, s in enumerate(src):
+        x1, y1 = int(s) % W, int(s) // W
+        for t in aisle:
+            x2, y2 = int(t) % W, int(t) // W
+            assert D[i, t] == rack_distance(x1, y1, x2, y2, rows, 2)
+
+
+def test_blocked_cells_unreachable_and_isolated():
+    wl = make_config("tiny")
+    g = wl.graph
+    d = oracle.dijkstra(g.row_ptr, g.col, g.w, int(wl.picks[0]))
+    blocked = np.flatnonzero(g.blocked.ravel())
+    assert (d[blocked] == INF).all()
+    free = np.flatnonzero(~g.blocked.ravel())
+    assert (d[free] != INF).all()
+    # a source on a blocked cell reaches only itself
+    d2 = oracle.dijkstra(g.row_ptr, g.col, g.w, int(blocked[0]))
+    assert d2[blocked[0]] == 0 and (np.delete(d2, blocked[0]) == INF).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_matches_scipy_on_random_graphs(seed):
+    rng = np.random.default_rng(77 + seed)
+    V = 300
+    rp, col, w = random_csr(rng, V, 1200, wmax=50)
+    src = rng.choice(V, 12, replace=False).astype(np.uint32)
+    D = oracle.dijkstra_multi(rp, col, w, src)
+    ref = _scipy_rows(rp, col, w, src)
+    assert (D.astype(np.uint64) == ref).all()
+    for i, s in enumerate(src):
+        b, _, st = oracle.bellman_ford(rp, col, w, int(s))
+        assert st == 0 and (b == D[i]).all()
+
+
+def test_matches_scipy_on_medium_sample():
+    wl = make_config("medium")
+    g = wl.graph
+    src = wl.picks[:6]
+    D = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)
+    ref = _scipy_rows(g.row_ptr, g.col, g.w, src)
+    assert (D.astype(np.uint64) == ref).all()
+
+
+def test_bellman_ford_round_cap_is_hop_depth():
+    # a directed path 0->1->...->V-1 needs exactly V-1 changing rounds
+    V = 25
+    rp = np.arange(V + 1, dtype=np.uint32)
+    rp[-1] = V - 1
+    col = np.arange(1, V, dtype=np.uint32)
+    w = np.full(V - 1, 3, dtype=np.uint32)
+    d, rounds, st = oracle.bellman_ford(rp, col, w, 0)
+    assert st == 0 and rounds == V - 1
+    assert d.tolist() == [3 * i for i in range(V)]
+    # with a cap below the hop depth the run reports that it was cut short
+    d, rounds, st = oracle.bellman_ford(rp, col, w, 0, max_rounds=5)
+    assert st == 4 and rounds == 5
+
+
+def _brute_pred(V, arcs, src, d):
+    pred = [-1] * V
+    for v in range(V):
+        if v == src or d[v] == INF:
+            continue
+        cands = [u for (u, x, ww) in arcs if x == v and d[u] != INF and d[u] + ww == d[v]]
+        pred[v] = min(cands)
+    return pred
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_canonical_pred_definition(seed):
+    rng = np.random.default_rng(4000 + seed)
+    V = int(rng.integers(2, 30))
+    rp, col, w = random_csr(rng, V, 4 * V, wmax=4)
+    arcs = list(csr_arcs(rp, col, w))
+    for s in range(min(V, 5)):
+        d = oracle.dijkstra(rp, col, w, s)
+        p = oracle.canonical_pred(rp, col, w, s, d)
+        assert p.tolist() == _brute_pred(V, arcs, s, d.tolist())
+        assert oracle.certificate(rp, col, w, s, d, p) == 0
+
+
+def test_certificate_catches_planted_mistakes():
+    wl = make_config("tiny")
+    g = wl.graph
+    s = int(wl.picks[3])
+    d = oracle.dijkstra(g.row_ptr, g.col, g.w, s)
+    p = oracle.canonical_pred(g.row_ptr, g.col, g.w, s, d)
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, d, p) == 0
+    free = np.flatnonzero(d != INF)
+    far = int(free[np.argmax(d[free])])
+    mid = int(free[len(free) // 2])
+    bad = d.copy(); bad[s] = 1
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, bad) != 0
+    bad = d.copy(); bad[mid] += 1           # too long: some in-arc is infeasible
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, bad) == 11
+    bad = d.copy(); bad[far] -= 1           # too short: not the length of a path
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, bad) == 12
+    bad = d.copy(); bad[mid] = INF          # dropped vertex
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, bad) != 0
+    bp = p.copy(); bp[mid] = s if p[mid] != s else -1   # non-tight predecessor
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, d, bp) in (21, 22)
+    bp = p.copy(); bp[s] = 0
+    assert oracle.certificate(g.row_ptr, g.col, g.w, s, d, bp) == 20
+
+
+def test_certificate_catches_pred_cycle():
+    # two vertices joined by zero-weight arcs, both at distance 1 from 0
+    rp = np.asarray([0, 2, 4, 6], dtype=np.uint32)
+    col = np.asarray([1, 2, 0, 2, 0, 1], dtype=np.uint32)
+    w = np.asarray([1, 1, 1, 0, 1, 0], dtype=np.uint32)
+    d = oracle.dijkstra(rp, col, w, 0)
+    assert d.tolist() == [0, 1, 1]
+    assert oracle.certificate(rp, col, w, 0, d, np.asarray([-1, 2, 1], np.int32)) == 23
+    assert oracle.certificate(rp, col, w, 0, d, np.asarray([-1, 0, 0], np.int32)) == 0
+
+
+def test_order_matrix_properties():
+    wl = make_config("medium", num_orders=6)
+    g = wl.graph
+    M = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    off = wl.pick_offsets
+    base = 0
+    for o in range(len(off) - 1):
+        pk = wl.picks[off[o]:off[o + 1]]
+        P = len(pk)
+        D = M[base:base + P * P].reshape(P, P).astype(np.int64)
+        base += P * P
+        assert (np.diag(D) == 0).all()
+        assert (D == D.T).all()                      # symmetric weights
+        # metric closure: D[i][j] <= D[i][k] + D[k][j]
+        assert (D[:, None, :] <= D[:, :, None] + D[None, :, :]).all()
+        rows = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, pk[:2])
+        assert (D[:2] == rows[:, pk]).all()
+
+
+def test_order_matrix_duplicates_and_empty():
+    wl = make_config("tiny")
+    g = wl.graph
+    a, b = int(wl.picks[0]), int(wl.picks[1])
+    off = np.asarray([0, 3, 3, 4], dtype=np.uint32)   # 3 picks, empty, 1 pick
+    picks = np.asarray([a, b, a, b], dtype=np.uint32)
+    M = oracle.order_matrices(g.row_ptr, g.col, g.w, off, picks)
+    assert len(M) == 9 + 0 + 1
+    D = M[:9].reshape(3, 3)
+    assert D[0, 2] == 0 and D[2, 0] == 0
+    assert (D[0] == D[2]).all() and (D[:, 0] == D[:, 2]).all()
+    assert M[9] == 0
+
+
+def test_validate_csr_rules():
+    rp = np.asarray([0, 1, 2], np.uint32)
+    col = np.asarray([1, 0], np.uint32)
+    w = np.asarray([5, 5], np.uint32)
+    assert oracle.validate_csr(rp, col, w) == 0
+    assert oracle.validate_csr(np.asarray([0, 1, 3], np.uint32), col, w) == 1   # row_ptr[V] != E
+    assert oracle.validate_csr(np.asarray([0, 2, 1], np.uint32), col, w) == 1   # decreasing
+    assert oracle.validate_csr(rp, np.asarray([1, 2], np.uint32), w) == 1       # col >= V
+    big = np.asarray([0xFFFFFFFF, 1], np.uint32)
+    assert oracle.validate_csr(rp, col, big) == 2                              # overflow
+    # bound uses incident vertices: 3 incident vertices, max_w * 2 >= INF
+    rp3 = np.asarray([0, 1, 2, 2, 2], np.uint32)
+    col3 = np.asarray([1, 2], np.uint32)
+    assert oracle.validate_csr(rp3, col3, np.asarray([0x80000000, 1], np.uint32)) == 2
+    assert oracle.validate_csr(rp3, col3, np.asarray([0x7FFFFFFF, 1], np.uint32)) == 0
+
+
+def test_generator_counts_match_layout_reading():
+    wl = make_config("tiny")
+    g = wl.graph
+    assert (g.V, g.E) == (800, 1724)
+    assert len(g.free_vertices()) == 578
+    assert len(g.aisle_adjacent_vertices()) == 462
+    wl2 = make_config("medium", num_orders=1)
+    assert (wl2.graph.V, wl2.graph.E) == (262144, 536188)
+    assert len(wl2.graph.free_vertices()) == 177994
+    assert len(wl2.graph.aisle_adjacent_vertices()) == 171190
+
+
+def _golden(name):
+    import os
+    return os.path.join(os.path.dirname(__file__), "golden", name)
+
+
+def test_tiny_golden_matrix_is_stable():
+    """The stored matrix was written from the oracle; a change in the
+    generator recipe or the oracle's arithmetic shows up here."""
+    lines = [l for l in open(_golden("tiny_order_matrix.txt")) if not l.startswith("#")]
+    picks = [int(x) for x in lines[0].split()[1:]]
+    D = np.asarray([[int(x) for x in l.split()] for l in lines[1:]])
+    wl = make_config("tiny")
+    assert picks == wl.picks.tolist()
+    g = wl.graph
+    M = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    assert (M.reshape(8, 8) == D).all()
+
+
+def test_paper_printed_launch_arithmetic():
+    vals = {}
+    for l in open(_golden("paper_numbers.txt")):
+        l = l.split("#")[0].split()
+        if l:
+            vals[l[0]] = float(l[1])
+    E = int(vals["bf_edges"])
+    assert -(-E // int(vals["threads_per_block"])) == vals["blocks_per_round"]
+    # the printed MTEPS counts (V-1) full rounds of E edges over the run
+    V = int(vals["bf_vertices"])
+    mteps = (V - 1) * E / (vals["bf_time_ms"] * 1e-3) / 1e6
+    assert abs(mteps - vals["bf_mteps"]) / vals["bf_mteps"] < 0.01
+    import math
+    assert math.factorial(9) * 8 == vals["perm_limit"]
+
+
+def test_generators_are_deterministic():
+    a = make_config("medium", num_orders=4)
+    b = make_config("medium", num_orders=4)
+    assert (a.graph.w == b.graph.w).all() and (a.picks == b.picks).all()
+    c = make_config("medium", num_orders=4, rep=1)
+    assert not (a.graph.w == c.graph.w).all()
+    # picks are distinct within an order and aisle-adjacent
+    adj = set(a.graph.aisle_adjacent_vertices().tolist())
+    for o in range(4):
+        pk = a.picks[a.pick_offsets[o]:a.pick_offsets[o + 1]].tolist()
+        assert len(set(pk)) == len(pk) and set(pk) <= adj
