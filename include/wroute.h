@@ -1,0 +1,274 @@
+/*
+ * wroute.h -- C ABI of the MI355X warehouse routing library.
+ *
+ * The library computes the routing step of arXiv 2504.20655: shortest-path
+ * distances over a warehouse graph with non-negative integer arc weights,
+ * for one or many sources at once (Bellman-Ford relaxation, GPU
+ * Implementation subsection, where `dist`/`pred` hold V x N entries for N
+ * sources), optionally split into memory-bounded segments stitched through
+ * their boundary vertices (the segmentation strategy named in the abstract
+ * and in the Discussion), and the per-order pick-to-pick distance matrices
+ * that route optimisation consumes (Route Optimization section; the picks of
+ * an order are its stopping nodes, routes-and-clusters subsection).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns a wr_status.  Nothing aborts, nothing throws
+ *    across the ABI.  wr_last_error() returns a thread-local message for the
+ *    last failing call on the calling thread.
+ *  - Validation happens before any device work; a validation error leaves
+ *    every output buffer untouched.  After WR_E_DEVICE / WR_E_NOMEM /
+ *    WR_E_INTERNAL the contents of output buffers are unspecified.
+ *  - Ownership: inputs are copied before a call returns, so the caller may
+ *    free them.  Outputs go to caller-provided buffers.  Handles are opaque
+ *    and freed by their *_destroy function (NULL is accepted and ignored).
+ *  - Host vs device buffers: index inputs (sources, pick_offsets, picks,
+ *    segment maps, weight updates) are always host pointers, because the
+ *    batch plan is made on the host.  Output buffers (dist, pred, dist_out,
+ *    pred_out) are host pointers unless WR_DEVICE_PTRS is set, in which case
+ *    they are device pointers (for example torch's data_ptr()) and the
+ *    results are written by work enqueued on `stream` (a hipStream_t, NULL =
+ *    the default stream).  In both cases the call returns after the
+ *    relaxation has converged; with WR_DEVICE_PTRS the final writes are
+ *    ordered on `stream`.
+ *  - Sentinels and types: WR_INF = 0xFFFFFFFF marks "no path";
+ *    WR_NO_PRED = -1 marks "no predecessor".  V < 2^31, E < 2^32, weights
+ *    are uint32 >= 0.
+ *  - Threading: a context and its graphs are not thread-safe; the
+ *    wr_server_* calls are internally synchronised.
+ */
+#ifndef WROUTE_H
+#define WROUTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum wr_status {
+    WR_OK = 0,
+    WR_E_INVALID = 1,      /* malformed argument (bad CSR, id out of range, NULL) */
+    WR_E_RANGE = 2,        /* a distance could reach WR_INF (overflow bound)      */
+    WR_E_NOMEM = 3,        /* device memory or the context's budget exhausted     */
+    WR_E_DEVICE = 4,       /* a HIP call failed                                   */
+    WR_E_UNSUPPORTED = 5,  /* valid request the library does not serve            */
+    WR_E_BUSY = 6,         /* queue full / result not ready                       */
+    WR_E_INTERNAL = 7      /* invariant broken (e.g. round cap hit)               */
+} wr_status;
+
+#define WR_INF 0xFFFFFFFFu
+#define WR_NO_PRED (-1)
+
+/* ---- flags for wr_sssp / wr_order_matrices -------------------------- */
+#define WR_DEVICE_PTRS      0x0001u  /* output buffers are device pointers */
+/* relaxation schedule (all give bit-identical distances; 0 = automatic) */
+#define WR_ALGO_AUTO        0x0000u
+#define WR_ALGO_SWEEP       0x0010u  /* unsegmented pull sweeps (Jacobi/in-place) */
+#define WR_ALGO_FRONTIER    0x0020u  /* unsegmented push frontier with ballot masks */
+#define WR_ALGO_SEGMENTED   0x0030u  /* LDS-resident segments + boundary exchange   */
+#define WR_ALGO_EDGE_B1     0x0040u  /* paper-structured: thread per arc, early exit */
+#define WR_ALGO_EDGE_B0     0x0050u  /* paper-structured: exactly V-1 rounds         */
+#define WR_ALGO_MASK        0x00F0u
+#define WR_NO_GRAPH_CAPTURE 0x0100u  /* launch passes eagerly instead of replaying a hipGraph */
+
+/* ---- opaque handles -------------------------------------------------- */
+typedef struct wr_context wr_context;
+typedef struct wr_graph wr_graph;
+typedef struct wr_server wr_server;
+
+/* Name of a status code (static string). */
+const char *wr_status_str(wr_status s);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *wr_last_error(void);
+
+/* Library version string (static). */
+const char *wr_version(void);
+
+/* ---- context --------------------------------------------------------- */
+
+/* Creates a context on HIP device `device`.  mem_budget_bytes bounds the
+ * device memory the context allocates (graph, segment tables, per-batch
+ * work buffers); 0 = 90% of the device's free memory at creation.
+ * Errors: WR_E_INVALID (out == NULL, bad device), WR_E_DEVICE. */
+wr_status wr_context_create(int device, uint64_t mem_budget_bytes, wr_context **out);
+wr_status wr_context_destroy(wr_context *ctx);
+
+/* Bytes the context currently holds and its budget. */
+wr_status wr_context_memory(const wr_context *ctx, uint64_t *used, uint64_t *budget);
+
+/* ---- graph ----------------------------------------------------------- */
+
+/* Checks a CSR graph without a context.  The graph is directed; arc e goes
+ * from the row u with row_ptr[u] <= e < row_ptr[u+1] to col[e] with weight
+ * w[e] (the paper stores arcs as integer arrays u, v, w; CSR groups them by
+ * u).  Parallel arcs and self-loops are allowed.
+ * WR_E_INVALID: NULL arrays, V == 0, V >= 2^31, row_ptr[0] != 0,
+ *   row_ptr decreasing, row_ptr[V] != E, col[e] >= V.
+ * WR_E_RANGE: max_w * (number of vertices incident to an arc - 1) >= WR_INF,
+ *   i.e. a shortest path could overflow the uint32 distance. */
+wr_status wr_validate_csr(uint32_t V, uint32_t E, const uint32_t *row_ptr,
+                          const uint32_t *col, const uint32_t *w);
+
+/* Validates (as above) and uploads a graph; it stays device-resident until
+ * wr_graph_destroy.  row_ptr: uint32[V+1]; col, w: uint32[E]; host pointers,
+ * copied.  `flags` is reserved (pass 0).  The graph starts at weight epoch 0.
+ * Errors: those of wr_validate_csr, WR_E_NOMEM, WR_E_DEVICE. */
+wr_status wr_graph_create_csr(wr_context *ctx, uint32_t V, uint32_t E,
+                              const uint32_t *row_ptr, const uint32_t *col,
+                              const uint32_t *w, uint32_t flags, wr_graph **out);
+wr_status wr_graph_destroy(wr_graph *g);
+
+/* Partitions the vertices into segments: segment_of_vertex[v] < num_segments
+ * (uint32[V], host).  A segment is a vertex set; its boundary vertices are
+ * those with an arc to or from another segment.  Segments are relaxed
+ * independently in on-chip memory and stitched by relaxing the cross-segment
+ * arcs until nothing changes (the Discussion's sub-routes processed
+ * independently within the GPU's memory).  A segment larger than one LDS
+ * tile is split internally into tiles of consecutive vertex ids; vertices
+ * without arcs belong to no tile.  Replaces any earlier segmentation.
+ * Errors: WR_E_INVALID (NULL, num_segments == 0, id >= num_segments),
+ * WR_E_NOMEM, WR_E_DEVICE. */
+wr_status wr_graph_set_segments(wr_graph *g, const uint32_t *segment_of_vertex,
+                                uint32_t num_segments);
+
+/* Segments a grid whose vertex ids are level*W*H + y*W + x into
+ * tile_w x tile_h rectangles per level.  Requires V == W*H*levels.
+ * Errors: WR_E_INVALID (sizes zero or not matching V), as above. */
+wr_status wr_graph_segment_grid(wr_graph *g, uint32_t W, uint32_t H, uint32_t levels,
+                                uint32_t tile_w, uint32_t tile_h);
+
+/* Number of segments and LDS tiles of the current segmentation (0 if none). */
+wr_status wr_graph_segment_info(const wr_graph *g, uint32_t *num_segments,
+                                uint32_t *num_tiles, uint32_t *num_boundary);
+
+/* Sets w[arc_index[i]] = new_w[i] for i < n (arc_index = CSR position, host
+ * arrays; a later entry for the same arc wins) and starts a new weight epoch,
+ * returned in *out_epoch (may be NULL).  Work started after the call returns
+ * uses the new weights.  Errors: WR_E_INVALID (index >= E, NULL with n > 0),
+ * WR_E_RANGE (the overflow bound of wr_validate_csr would break; nothing is
+ * changed), WR_E_DEVICE. */
+wr_status wr_graph_update_weights(wr_graph *g, uint32_t n, const uint32_t *arc_index,
+                                  const uint32_t *new_w, uint64_t *out_epoch);
+
+/* Current weight epoch. */
+wr_status wr_graph_epoch(const wr_graph *g, uint64_t *epoch);
+
+/* ---- shortest paths -------------------------------------------------- */
+
+/* Single- and multi-source shortest distances.
+ * sources: uint32[S] (host), duplicates allowed.
+ * dist:    uint32[S*V], source-major: dist[i*V + v] = d(sources[i], v),
+ *          WR_INF where v is unreachable.
+ * pred:    int32[S*V] or NULL: pred[i*V + v] = the smallest vertex id u with
+ *          an arc (u, v) such that d(u) + w(u, v) = d(v); WR_NO_PRED for the
+ *          source itself and for unreachable v.  With every weight >= 1 this
+ *          is a shortest-path tree.
+ * flags:   WR_DEVICE_PTRS, one WR_ALGO_* value, WR_NO_GRAPH_CAPTURE.
+ * Errors: WR_E_INVALID (NULL, a source >= V), WR_E_UNSUPPORTED (pred
+ * requested while some weight is 0: ties could then form cycles; or the
+ * requested schedule cannot serve this graph), WR_E_NOMEM (not even one
+ * source fits the budget), WR_E_DEVICE, WR_E_INTERNAL. */
+wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *dist,
+                  int32_t *pred, uint32_t flags, void *stream);
+
+/* Per-order pick-to-pick distance matrices.
+ * pick_offsets: uint32[num_orders+1] (host), non-decreasing, first 0;
+ *               order o owns picks[pick_offsets[o] .. pick_offsets[o+1]).
+ * picks:        uint32[pick_offsets[num_orders]] vertex ids (host).
+ * dist_out:     uint32[sum_o P_o^2]: for order o with P_o picks, the block
+ *               D_o[i][j] = d(p_i, p_j) (row = source pick, row-major),
+ *               blocks concatenated in order.  Duplicate picks give equal
+ *               rows and columns with 0 between them; an empty order
+ *               contributes nothing.
+ * pred_out:     int32[sum_o P_o * V] or NULL: the canonical predecessor row
+ *               (as in wr_sssp) of every pick, in pick order.
+ * Distinct pick vertices are solved once per call, whatever order they
+ * belong to.  Errors as for wr_sssp, plus WR_E_INVALID for bad offsets. */
+wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pick_offsets,
+                            const uint32_t *picks, uint32_t *dist_out, int32_t *pred_out,
+                            uint32_t flags, void *stream);
+
+/* Statistics of the last wr_sssp / wr_order_matrices call on this graph. */
+typedef struct wr_run_info {
+    uint32_t algo;             /* WR_ALGO_* value that ran                      */
+    uint32_t unique_sources;   /* distinct sources solved                       */
+    uint32_t chunks;           /* memory-bounded chunks                         */
+    uint32_t passes;           /* relaxation passes (rounds) over all chunks    */
+    uint64_t work_items;       /* visits: (tile, source) or (vertex, block)     */
+    double relax_ms;           /* device time of the relaxation passes          */
+    double total_ms;           /* wall time of the call                         */
+} wr_run_info;
+wr_status wr_graph_last_run(const wr_graph *g, wr_run_info *info);
+
+/* Chooses schedule parameters (tile size, waves per tile, passes per
+ * graph replay) by timing candidates on this graph with `sources_hint`
+ * synthetic sources; every candidate gives identical distances, so results
+ * never depend on the outcome.  cache_path (may be NULL) is a JSON file
+ * read before and written after tuning.  Errors: WR_E_INVALID, WR_E_DEVICE. */
+wr_status wr_autotune(wr_graph *g, uint32_t sources_hint, const char *cache_path);
+
+/* Sets schedule parameters explicitly (0 keeps the current value). */
+wr_status wr_graph_set_schedule(wr_graph *g, uint32_t tile_vertices,
+                                uint32_t waves_per_group, uint32_t passes_per_replay);
+
+/* ---- continuous-batching server -------------------------------------- */
+
+typedef struct wr_server_opts {
+    uint32_t max_source_slots;   /* sources relaxed concurrently (0 = auto)   */
+    uint64_t mem_budget_bytes;   /* device bytes for in-flight work (0 = auto) */
+    uint32_t max_queue;          /* queued requests before WR_E_BUSY (0 = 65536) */
+    uint32_t passes_per_step;    /* relaxation passes per scheduler step (0 = auto) */
+} wr_server_opts;
+
+typedef struct wr_req_info {
+    uint64_t epoch;      /* weight epoch the request was solved on  */
+    double t_arrive;     /* seconds, server clock                   */
+    double t_admit;
+    double t_done;
+    uint32_t P;          /* picks                                   */
+    wr_status status;
+} wr_req_info;
+
+typedef struct wr_stats {
+    uint64_t submitted, completed, failed;
+    double p50_ms, p99_ms, mean_ms;   /* arrival -> result ready on the host */
+    double throughput_per_s;          /* completed / (last done - first arrival) */
+    uint32_t max_inflight_requests;
+    uint64_t steps;
+} wr_stats;
+
+/* Creates a server over graph g (the server keeps g and its segmentation
+ * resident; g must outlive the server and must not be used directly while
+ * the server runs).  opts may be NULL for defaults. */
+wr_status wr_server_create(wr_graph *g, const wr_server_opts *opts, wr_server **out);
+
+/* Queues one order of P picks (host array, copied; P == 0 is allowed and
+ * completes at once).  Non-blocking.  WR_E_BUSY if the queue is full;
+ * WR_E_INVALID for a pick >= V or picks == NULL with P > 0. */
+wr_status wr_server_submit(wr_server *srv, uint32_t P, const uint32_t *picks, uint64_t *ticket);
+
+/* WR_OK and the P x P matrix in dist_out (host, row-major) once done;
+ * WR_E_BUSY while pending; WR_E_INVALID for an unknown or already-collected
+ * ticket.  info may be NULL.  A request that failed returns its status. */
+wr_status wr_server_poll(wr_server *srv, uint64_t ticket, uint32_t *dist_out, wr_req_info *info);
+
+/* Queues a weight update; it is applied between scheduler steps, and every
+ * request admitted after that point is solved on the new epoch. */
+wr_status wr_server_update_weights(wr_server *srv, uint32_t n, const uint32_t *arc_index,
+                                   const uint32_t *new_w);
+
+/* Latency and throughput statistics so far. */
+wr_status wr_server_stats(wr_server *srv, wr_stats *out);
+
+/* Blocks until every submitted request is done (or failed). */
+wr_status wr_server_drain(wr_server *srv);
+
+wr_status wr_server_destroy(wr_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WROUTE_H */

@@ -1,0 +1,208 @@
+"""MI355X warehouse routing: multi-source Bellman-Ford shortest paths, the
+segmented (LDS-tile) schedule with boundary exchange, and per-order
+pick-to-pick distance matrices, as a C ABI (include/wroute.h) over gfx950
+HIP kernels.  This module only marshals arguments for that ABI.
+
+Host arrays are numpy uint32; device outputs may be torch CUDA tensors
+(int32 storage holding uint32 bit patterns), in which case the call runs
+with WR_DEVICE_PTRS on the tensor's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+INF = 0xFFFFFFFF
+NO_PRED = -1
+
+DEVICE_PTRS = 0x0001
+ALGO = {"auto": 0x00, "sweep": 0x10, "frontier": 0x20, "segmented": 0x30,
+        "edge_b1": 0x40, "edge_b0": 0x50}
+ALGO_NAME = {v: k for k, v in ALGO.items()}
+NO_GRAPH_CAPTURE = 0x0100
+
+STATUS = {0: "WR_OK", 1: "WR_E_INVALID", 2: "WR_E_RANGE", 3: "WR_E_NOMEM", 4: "WR_E_DEVICE",
+          5: "WR_E_UNSUPPORTED", 6: "WR_E_BUSY", 7: "WR_E_INTERNAL"}
+
+
+class WrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def lib():
+    return _lib.load()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise WrError(rc, (lib().wr_last_error() or b"").decode())
+
+
+def _u32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _ptr(a) -> ctypes.c_void_p | None:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(a.ctypes.data or 1)
+    return ctypes.c_void_p(a.data_ptr())   # torch tensor
+
+
+def version() -> str:
+    return lib().wr_version().decode()
+
+
+def validate_csr(row_ptr, col, w) -> int:
+    """Returns the wr_status of wr_validate_csr (0 = valid)."""
+    rp, c, ww = _u32(row_ptr), _u32(col), _u32(w)
+    V = max(len(rp) - 1, 0)
+    return lib().wr_validate_csr(V, len(c), _ptr(rp), _ptr(c), _ptr(ww))
+
+
+class Context:
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().wr_context_create(device, mem_budget_bytes, ctypes.byref(h)))
+        self.h = h
+
+    def memory(self):
+        used, budget = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().wr_context_memory(self.h, ctypes.byref(used), ctypes.byref(budget)))
+        return used.value, budget.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wr_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_of(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+class Graph:
+    """A device-resident CSR graph (wr_graph_create_csr)."""
+
+    def __init__(self, ctx: Context, row_ptr, col, w):
+        self.ctx = ctx
+        self.row_ptr, self.col, self.w = _u32(row_ptr), _u32(col), _u32(w)
+        self.V = len(self.row_ptr) - 1
+        self.E = len(self.col)
+        h = ctypes.c_void_p()
+        _check(lib().wr_graph_create_csr(ctx.h, self.V, self.E, _ptr(self.row_ptr), _ptr(self.col),
+                                         _ptr(self.w), 0, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wr_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # segmentation
+    def set_segments(self, segment_of_vertex, num_segments: int):
+        s = _u32(segment_of_vertex)
+        _check(lib().wr_graph_set_segments(self.h, _ptr(s), int(num_segments)))
+
+    def segment_grid(self, W, H, levels, tile_w, tile_h):
+        _check(lib().wr_graph_segment_grid(self.h, W, H, levels, tile_w, tile_h))
+
+    def segment_info(self):
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().wr_graph_segment_info(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"segments": a.value, "tiles": b.value, "boundary": c.value}
+
+    def set_schedule(self, tile_vertices=0, waves_per_group=0, passes_per_replay=0):
+        _check(lib().wr_graph_set_schedule(self.h, tile_vertices, waves_per_group, passes_per_replay))
+
+    def autotune(self, sources_hint: int = 256, cache_path: str | None = None):
+        _check(lib().wr_autotune(self.h, sources_hint, cache_path.encode() if cache_path else None))
+
+    def update_weights(self, arc_index, new_w) -> int:
+        a, v = _u32(arc_index), _u32(new_w)
+        ep = ctypes.c_uint64()
+        _check(lib().wr_graph_update_weights(self.h, len(a), _ptr(a), _ptr(v), ctypes.byref(ep)))
+        return ep.value
+
+    def epoch(self) -> int:
+        ep = ctypes.c_uint64()
+        _check(lib().wr_graph_epoch(self.h, ctypes.byref(ep)))
+        return ep.value
+
+    def last_run(self) -> dict:
+        r = _lib.RunInfo()
+        _check(lib().wr_graph_last_run(self.h, ctypes.byref(r)))
+        d = {k: getattr(r, k) for k, _ in r._fields_}
+        d["algo"] = ALGO_NAME.get(d["algo"], d["algo"])
+        return d
+
+    # solves
+    def sssp(self, sources, pred: bool = False, algo: str = "auto", out=None, pred_out=None,
+             graph_capture: bool = True):
+        """Distances [S, V] (uint32, source-major); with pred=True also the
+        canonical predecessors.  `out`/`pred_out` may be torch CUDA tensors
+        of S*V 32-bit elements, in which case results stay on the device."""
+        src = _u32(sources)
+        S = len(src)
+        flags = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
+        if out is not None:
+            flags |= DEVICE_PTRS
+            stream = _stream_of(out)
+            _check(lib().wr_sssp(self.h, S, _ptr(src), _ptr(out), _ptr(pred_out), flags, stream))
+            return out, pred_out
+        d = np.empty((S, self.V), dtype=np.uint32)
+        p = np.empty((S, self.V), dtype=np.int32) if pred else None
+        _check(lib().wr_sssp(self.h, S, _ptr(src), _ptr(d), _ptr(p), flags, None))
+        return (d, p) if pred else d
+
+    def order_matrices(self, pick_offsets, picks, pred: bool = False, algo: str = "auto",
+                       out=None, pred_out=None, graph_capture: bool = True):
+        """Concatenated per-order P x P matrices (uint32); with pred=True also
+        the predecessor row of every pick ([total picks, V])."""
+        off, pk = _u32(pick_offsets), _u32(picks)
+        n = len(off) - 1
+        sizes = np.diff(off.astype(np.int64))
+        total = int((sizes ** 2).sum())
+        flags = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
+        if out is not None:
+            flags |= DEVICE_PTRS
+            stream = _stream_of(out)
+            _check(lib().wr_order_matrices(self.h, n, _ptr(off), _ptr(pk), _ptr(out),
+                                           _ptr(pred_out), flags, stream))
+            return out, pred_out
+        d = np.empty(max(total, 1), dtype=np.uint32)
+        p = np.empty((len(pk), self.V), dtype=np.int32) if pred else None
+        _check(lib().wr_order_matrices(self.h, n, _ptr(off), _ptr(pk), _ptr(d), _ptr(p), flags, None))
+        d = d[:total]
+        return (d, p) if pred else d
+
+
+def split_matrices(flat, pick_offsets):
+    """Splits the concatenated output into a list of P x P arrays."""
+    off = np.asarray(pick_offsets, dtype=np.int64)
+    res, base = [], 0
+    for o in range(len(off) - 1):
+        P = int(off[o + 1] - off[o])
+        res.append(np.asarray(flat[base:base + P * P]).reshape(P, P))
+        base += P * P
+    return res

@@ -1,0 +1,825 @@
+// gfx950 kernels of the routing hot path.
+//
+// Every kernel computes a piece of the min-plus relaxation
+//     d(v) <- min(d(v), d(u) + w(u, v))   for arcs (u, v)
+// that Bellman-Ford iterates to its unique fixpoint on graphs with
+// non-negative weights (GPU Implementation subsection of the paper), or
+// reads the fixpoint out (order matrices, predecessors).  Distances are
+// uint32 with WR_INF = 0xFFFFFFFF; candidate sums use a saturating add, so
+// INF + w stays INF and no candidate wraps.
+//
+// Wave64 is assumed throughout (CDNA).  Values a whole wave agrees on are
+// passed through readfirstlane so that the compiler keeps them in SGPRs and
+// loads CSR rows through the scalar cache.
+#include "wr_internal.hpp"
+
+namespace wr {
+
+namespace {
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+    return __builtin_elementwise_add_sat(a, b);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
+    uint32_t lo = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u);
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32), lo);
+}
+
+inline uint32_t blocks_for(size_t n, uint32_t threads, uint32_t cap = 65535u * 4u) {
+    size_t b = (n + threads - 1) / threads;
+    if (b == 0) b = 1;
+    if (b > cap) b = cap;
+    return static_cast<uint32_t>(b);
+}
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
+    size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+    size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    const size_t n4 = n / 4;
+    uint4 *p4 = reinterpret_cast<uint4 *>(p);
+    const uint4 v4 = make_uint4(v, v, v, v);
+    for (size_t k = i; k < n4; k += stride) p4[k] = v4;
+    for (size_t k = n4 * 4 + i; k < n; k += stride) p[k] = v;
+}
+
+__global__ void k_fill_u32_unaligned(uint32_t *__restrict__ p, size_t n, uint32_t v) {
+    size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+    size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t k = i; k < n; k += stride) p[k] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *__restrict__ p, size_t n, uint8_t v) {
+    size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+    size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t k = i; k < n; k += stride) p[k] = v;
+}
+
+// --------------------------------------------------- blocked layout kernels
+// dist[b][v][l]: source 64*b + l of the chunk, vertex v; one wave covers the
+// 64 sources of a block at one vertex, so every access is a 256-byte line.
+__global__ void k_blk_seed(uint32_t *__restrict__ dist, uint32_t V, uint32_t S,
+                           const uint32_t *__restrict__ src) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    size_t b = i / LANES, l = i % LANES;
+    dist[(b * V + src[i]) * LANES + l] = 0;
+}
+
+// Pull sweep, in place: d(v) <- min(d(v), min over in-arcs (u,v) of d(u)+w).
+// One wave per (block, vertex) unit, lanes = sources.  Any order of these
+// updates converges to the same fixpoint; `changed` is set if a value moved.
+__global__ __launch_bounds__(256) void k_sweep_pull(uint32_t *__restrict__ dist, uint32_t V,
+                                                    uint32_t nb,
+                                                    const uint32_t *__restrict__ in_ptr,
+                                                    const uint32_t *__restrict__ in_src,
+                                                    const uint32_t *__restrict__ in_w,
+                                                    uint32_t *__restrict__ changed) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = uniform(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
+    const uint64_t units = static_cast<uint64_t>(nb) * V;
+    bool moved = false;
+    for (uint64_t u = wave; u < units; u += nwaves) {
+        const uint32_t b = static_cast<uint32_t>(u / V);
+        const uint32_t v = static_cast<uint32_t>(u - static_cast<uint64_t>(b) * V);
+        const uint32_t beg = uniform(in_ptr[v]), end = uniform(in_ptr[v + 1]);
+        if (beg == end) continue;
+        uint32_t *db = dist + static_cast<size_t>(b) * V * LANES;
+        const uint32_t old = db[static_cast<size_t>(v) * LANES + lane];
+        uint32_t m = old;
+        for (uint32_t e = beg; e < end; ++e) {
+            const uint32_t x = uniform(in_src[e]);
+            const uint32_t ww = uniform(in_w[e]);
+            m = min(m, sat_add(db[static_cast<size_t>(x) * LANES + lane], ww));
+        }
+        if (m < old) {
+            db[static_cast<size_t>(v) * LANES + lane] = m;
+            moved = true;
+        }
+    }
+    if (moved) *changed = 1u;
+}
+
+__global__ void k_frontier_seed(uint64_t *__restrict__ list, uint32_t *__restrict__ count,
+                                uint32_t S, const uint32_t *__restrict__ src) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S) list[i] = (static_cast<uint64_t>(i / LANES) << 32) | src[i];
+    if (i == 0) *count = S;
+}
+
+// Push relaxation of the frontier items (block, v): each lane (source)
+// relaxes every out-arc of v; an arc target whose value dropped for any lane
+// is queued once for the next pass (a 32-bit pass stamp per (block, vertex)
+// dedups; the wave's ballot decides whether to queue).
+__global__ __launch_bounds__(256) void k_frontier_push(
+    uint32_t *__restrict__ dist, uint32_t V, const uint32_t *__restrict__ row_ptr,
+    const uint32_t *__restrict__ col, const uint32_t *__restrict__ w,
+    const uint64_t *__restrict__ list_in, const uint32_t *__restrict__ count_in,
+    uint64_t *__restrict__ list_out, uint32_t *__restrict__ count_out,
+    uint32_t *__restrict__ stamps, const uint32_t *__restrict__ pass_ctr) {
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    const uint32_t nwaves = gridDim.x * (blockDim.x / 64);
+    const uint32_t n = uniform(*count_in);
+    const uint32_t stamp = uniform(*pass_ctr) + 1u;
+    for (uint32_t i = wave; i < n; i += nwaves) {
+        const uint64_t item = list_in[i];
+        const uint32_t b = uniform(static_cast<uint32_t>(item >> 32));
+        const uint32_t v = uniform(static_cast<uint32_t>(item));
+        uint32_t *db = dist + static_cast<size_t>(b) * V * LANES;
+        const uint32_t dv = db[static_cast<size_t>(v) * LANES + lane];
+        const uint32_t beg = uniform(row_ptr[v]), end = uniform(row_ptr[v + 1]);
+        for (uint32_t e = beg; e < end; ++e) {
+            const uint32_t x = uniform(col[e]);
+            const uint32_t nd = sat_add(dv, uniform(w[e]));
+            uint32_t *px = db + static_cast<size_t>(x) * LANES + lane;
+            bool imp = false;
+            if (nd < *px) imp = nd < atomicMin(px, nd);
+            if (__builtin_amdgcn_ballot_w64(imp) != 0 && lane == 0) {
+                const uint32_t o = atomicMax(&stamps[static_cast<size_t>(b) * V + x], stamp);
+                if (o < stamp) {
+                    const uint32_t pos = atomicAdd(count_out, 1u);
+                    list_out[pos] = (static_cast<uint64_t>(b) << 32) | x;
+                }
+            }
+        }
+    }
+}
+
+// out[r][v] = dist of chunk source row_src_idx[r] at v (source-major rows).
+__global__ void k_blk_emit(const uint32_t *__restrict__ dist, uint32_t V, uint32_t rows,
+                           const uint32_t *__restrict__ row_src_idx,
+                           const uint32_t *__restrict__ out_row, uint32_t *__restrict__ out) {
+    for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const uint32_t idx = row_src_idx[r];
+        const size_t b = idx / LANES, l = idx % LANES;
+        const uint32_t *db = dist + b * V * LANES;
+        uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
+        for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
+            o[v] = db[static_cast<size_t>(v) * LANES + l];
+    }
+}
+
+__global__ void k_pass_prologue(uint32_t *__restrict__ count_next,
+                                const uint32_t *__restrict__ count_cur,
+                                unsigned long long *__restrict__ stats,
+                                uint32_t *__restrict__ pass_ctr) {
+    const uint32_t c = *count_cur;
+    stats[0] += c;
+    stats[1] += c ? 1ull : 0ull;
+    *count_next = 0;
+    *pass_ctr += 1u;
+}
+
+// ------------------------------------------------------ segmented schedule
+// Work state of one chunk of S sources over T tiles (see TileSet):
+//   gdist[s][Vt]   full distance state, written at a tile's first visit
+//   inbox[s][NP]   values pushed into boundary-in vertices by other tiles
+//   visited[s][T]  whether gdist of (s, t) has been written
+//   stamps[s][T]   pass stamp of the last activation (dedup)
+//   bucket[par][t][k], cnt[par][t]   sources active in tile t for a pass
+//   tiles[par][j], ntiles[par]       tiles with a non-empty bucket
+//   units[u] = (tile, slice)         slices of G sources, built per pass
+struct SegPassArgs {
+    // tables
+    const uint32_t *tile_base, *l_off, *l_arc, *x_off, *x_port, *x_w, *x_tile, *port_base,
+        *port_local, *bo_base, *bo_local;
+    uint32_t T, Vt, NP;
+    // state
+    uint32_t S;
+    uint32_t *gdist, *inbox;
+    uint8_t *visited;
+    uint32_t *stamps;
+    const uint32_t *src_pos, *src_tile;
+    // activation buffers (current / next parity)
+    const uint32_t *cnt_cur, *bucket_cur;
+    uint32_t *cnt_next, *bucket_next, *tiles_next, *ntiles_next;
+    const uint2 *units;
+    const uint32_t *nunits;
+    uint32_t *cursor;
+    const uint32_t *pass_ctr;
+    uint32_t G;
+};
+
+__device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
+                                             uint32_t stamp) {
+    const uint32_t o = atomicMax(&A.stamps[static_cast<size_t>(s) * A.T + t], stamp);
+    if (o < stamp) {
+        const uint32_t k = atomicAdd(&A.cnt_next[t], 1u);
+        A.bucket_next[static_cast<size_t>(t) * A.S + k] = s;
+        if (k == 0) {
+            const uint32_t j = atomicAdd(A.ntiles_next, 1u);
+            A.tiles_next[j] = t;
+        }
+    }
+}
+
+// One pass over the active (tile, source) items.  A workgroup takes one
+// unit (a tile and up to G of its active sources), stages the tile's
+// in-tile arcs in LDS once, and its NW waves each relax one source of the
+// unit at a time: the tile's distances for that source live in the wave's
+// own LDS array, and a FIFO of changed vertices (deduplicated by a bitmap)
+// drives push relaxation until the tile reaches its local fixpoint.  Changed
+// values are written back, and every changed boundary-out vertex pushes its
+// cross-tile arcs into the target tile's inbox with atomicMin, activating
+// (source, target tile) for the next pass when the inbox value dropped.
+template <int CAP, int NW>
+__global__ __launch_bounds__(NW * 64) void k_seg_pass(SegPassArgs A) {
+    constexpr uint32_t ARC_CAP = 4u * CAP;
+    constexpr uint32_t WORDS = CAP / 32;
+    __shared__ uint16_t s_off[CAP + 2];
+    __shared__ uint32_t s_arc[ARC_CAP];
+    __shared__ uint32_t s_dist[NW][CAP];
+    __shared__ uint16_t s_q[NW][CAP];
+    __shared__ uint32_t s_inq[NW][WORDS];
+    __shared__ uint32_t s_dirty[NW][WORDS];
+    __shared__ uint32_t s_unit;
+
+    const uint32_t lane = lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    const uint32_t nunits = uniform(*A.nunits);
+    const uint32_t stamp = uniform(*A.pass_ctr) + 1u;
+    uint32_t *dist = s_dist[wv];
+    uint16_t *q = s_q[wv];
+    uint32_t *inq = s_inq[wv];
+    uint32_t *dirty = s_dirty[wv];
+    uint32_t staged = NONE;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(A.cursor, 1u);
+        __syncthreads();
+        const uint32_t u = uniform(s_unit);
+        __syncthreads();
+        if (u >= nunits) break;
+        const uint2 unit = A.units[u];
+        const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
+        const uint32_t base = uniform(A.tile_base[t]);
+        const uint32_t n = uniform(A.tile_base[t + 1]) - base;
+        if (t != staged) {
+            const uint32_t a0 = A.l_off[base];
+            for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x)
+                s_off[i] = static_cast<uint16_t>(A.l_off[base + i] - a0);
+            const uint32_t na = A.l_off[base + n] - a0;
+            for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) s_arc[i] = A.l_arc[a0 + i];
+            staged = t;
+            __syncthreads();
+        }
+        const uint32_t total = uniform(A.cnt_cur[t]);
+        const uint32_t first_k = slice * A.G;
+        const uint32_t cnt = min(A.G, total - first_k);
+        for (uint32_t k = wv; k < cnt; k += NW) {
+            const uint32_t s = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + k]);
+            const size_t st = static_cast<size_t>(s) * A.T + t;
+            const bool first = A.visited[st] == 0;
+            uint32_t *gd = A.gdist + static_cast<size_t>(s) * A.Vt + base;
+            for (uint32_t i = lane; i < n; i += 64) dist[i] = first ? INF : gd[i];
+            for (uint32_t i = lane; i < WORDS; i += 64) {
+                inq[i] = 0;
+                dirty[i] = 0;
+            }
+            __builtin_amdgcn_wave_barrier();
+            uint32_t head = 0, tail = 0;
+            // seed: the source itself
+            if (uniform(A.src_tile[s]) == t) {
+                const uint32_t loc = uniform(A.src_pos[s]) - base;
+                // decide once for the wave before lane 0 writes the value
+                const bool need = uniform(dist[loc]) != 0;
+                __builtin_amdgcn_wave_barrier();
+                if (need) {
+                    if (lane == 0) {
+                        dist[loc] = 0;
+                        inq[loc >> 5] |= 1u << (loc & 31);
+                        dirty[loc >> 5] |= 1u << (loc & 31);
+                        q[0] = static_cast<uint16_t>(loc);
+                    }
+                    tail = 1;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // seed: boundary-in vertices whose inbox value beats the stored one
+            const uint32_t p0 = uniform(A.port_base[t]), p1 = uniform(A.port_base[t + 1]);
+            const uint32_t *ib = A.inbox + static_cast<size_t>(s) * A.NP;
+            for (uint32_t kk = p0; kk < p1; kk += 64) {
+                const uint32_t k2 = kk + lane;
+                bool push = false;
+                uint32_t loc = 0;
+                if (k2 < p1) {
+                    loc = A.port_local[k2];
+                    const uint32_t v = ib[k2];
+                    if (v < dist[loc]) {
+                        dist[loc] = v;
+                        atomicOr(&dirty[loc >> 5], 1u << (loc & 31));
+                        const uint32_t ob = atomicOr(&inq[loc >> 5], 1u << (loc & 31));
+                        push = (ob & (1u << (loc & 31))) == 0;
+                    }
+                }
+                const uint64_t m = __builtin_amdgcn_ballot_w64(push);
+                if (push) q[(tail + mbcnt64(m)) & (CAP - 1)] = static_cast<uint16_t>(loc);
+                tail += __builtin_popcountll(m);
+                __builtin_amdgcn_wave_barrier();
+            }
+            // relax to the local fixpoint
+            while (head != tail) {
+                const uint32_t avail = tail - head;
+                const uint32_t take = avail < 64 ? avail : 64;
+                const bool act = lane < take;
+                uint32_t x0 = 0, du = INF, e = 0, e_end = 0;
+                if (act) {
+                    x0 = q[(head + lane) & (CAP - 1)];
+                    atomicAnd(&inq[x0 >> 5], ~(1u << (x0 & 31)));
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (act) {
+                    du = __hip_atomic_load(&dist[x0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    e = s_off[x0];
+                    e_end = s_off[x0 + 1];
+                }
+                head += take;
+                while (__builtin_amdgcn_ballot_w64(e < e_end) != 0) {
+                    bool newq = false;
+                    uint32_t x = 0;
+                    if (e < e_end) {
+                        const uint32_t a = s_arc[e];
+                        ++e;
+                        x = a >> 16;
+                        const uint32_t nd = sat_add(du, a & 0xFFFFu);
+                        const uint32_t old = atomicMin(&dist[x], nd);
+                        if (nd < old) {
+                            const uint32_t bit = 1u << (x & 31);
+                            atomicOr(&dirty[x >> 5], bit);
+                            newq = (atomicOr(&inq[x >> 5], bit) & bit) == 0;
+                        }
+                    }
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(newq);
+                    if (newq) q[(tail + mbcnt64(m)) & (CAP - 1)] = static_cast<uint16_t>(x);
+                    tail += __builtin_popcountll(m);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // write back: everything on the first visit, changed values after
+            for (uint32_t i = lane; i < n; i += 64) {
+                const bool d = first || ((dirty[i >> 5] >> (i & 31)) & 1u);
+                if (d) gd[i] = dist[i];
+            }
+            if (lane == 0 && first) A.visited[st] = 1;
+            // boundary exchange: push changed boundary-out vertices across tiles
+            const uint32_t b0 = uniform(A.bo_base[t]), b1 = uniform(A.bo_base[t + 1]);
+            uint32_t *ibox = A.inbox + static_cast<size_t>(s) * A.NP;
+            for (uint32_t kk = b0 + lane; kk < b1; kk += 64) {
+                const uint32_t loc = A.bo_local[kk];
+                if (!((dirty[loc >> 5] >> (loc & 31)) & 1u)) continue;
+                const uint32_t dv = dist[loc];
+                const uint32_t pos = base + loc;
+                const uint32_t xe1 = A.x_off[pos + 1];
+                for (uint32_t xe = A.x_off[pos]; xe < xe1; ++xe) {
+                    const uint32_t nd = sat_add(dv, A.x_w[xe]);
+                    uint32_t *pi = ibox + A.x_port[xe];
+                    if (nd < *pi && nd < atomicMin(pi, nd)) seg_activate(A, s, A.x_tile[xe], stamp);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
+}
+
+// Seeds pass 0: (s, tile of source s) for every source with a tile.
+__global__ void k_seg_seed(SegPassArgs A, uint32_t n) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t t = A.src_tile[s];
+    if (t != NONE) seg_activate(A, s, t, 1u);
+}
+
+// Splits every active tile's bucket into units of G sources, zeroes the
+// unit cursor and the next-pass counters, and counts work.
+__global__ void k_seg_plan(const uint32_t *__restrict__ tiles_cur,
+                           const uint32_t *__restrict__ ntiles_cur,
+                           const uint32_t *__restrict__ cnt_cur, uint32_t G,
+                           uint2 *__restrict__ units, uint32_t *__restrict__ nunits,
+                           unsigned long long *__restrict__ stats) {
+    const uint32_t nt = *ntiles_cur;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nt; j += gridDim.x * blockDim.x) {
+        const uint32_t t = tiles_cur[j];
+        const uint32_t c = cnt_cur[t];
+        const uint32_t sl = (c + G - 1) / G;
+        const uint32_t b = atomicAdd(nunits, sl);
+        for (uint32_t k = 0; k < sl; ++k) units[b + k] = make_uint2(t, k);
+        atomicAdd(&stats[0], static_cast<unsigned long long>(c));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nt) atomicAdd(&stats[1], 1ull);
+}
+
+// Zeroes the next pass's activation counters; bumps the pass counter.
+__global__ void k_seg_prologue(uint32_t *__restrict__ cnt_next, uint32_t T,
+                               uint32_t *__restrict__ ntiles_next, uint32_t *__restrict__ nunits,
+                               uint32_t *__restrict__ cursor, uint32_t *__restrict__ pass_ctr) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x)
+        cnt_next[t] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ntiles_next = 0;
+        *nunits = 0;
+        *cursor = 0;
+        *pass_ctr += 1u;
+    }
+}
+
+__device__ __forceinline__ uint32_t seg_value(const uint32_t *tile_of, const uint32_t *pos_of,
+                                              const uint8_t *visited, const uint32_t *gdist,
+                                              uint32_t T, uint32_t Vt, uint32_t s, uint32_t src_v,
+                                              uint32_t v) {
+    const uint32_t t = tile_of[v];
+    if (t == NONE) return v == src_v ? 0u : INF;
+    if (!visited[static_cast<size_t>(s) * T + t]) return INF;
+    return gdist[static_cast<size_t>(s) * Vt + pos_of[v]];
+}
+
+__global__ void k_seg_emit(const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
+                           const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
+                           uint32_t T, uint32_t Vt, uint32_t V, uint32_t rows,
+                           const uint32_t *__restrict__ row_src_idx,
+                           const uint32_t *__restrict__ row_src_vertex,
+                           const uint32_t *__restrict__ out_row, uint32_t *__restrict__ out) {
+    for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const uint32_t s = row_src_idx[r], sv = row_src_vertex[r];
+        uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
+        for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
+            o[v] = seg_value(tile_of, pos_of, visited, gdist, T, Vt, s, sv, v);
+    }
+}
+
+// ---------------------------------------------------------- order gathers
+// One workgroup per order; entry (i, j) of order o is written at
+// out_base[o] + i*P + j.
+__global__ void k_gather_rows(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
+                              const uint32_t *__restrict__ picks,
+                              const uint64_t *__restrict__ out_base,
+                              const uint32_t *__restrict__ row_of_pick,
+                              const uint32_t *__restrict__ rows, uint32_t V,
+                              uint32_t *__restrict__ out) {
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        const uint64_t ob = out_base[o];
+        for (uint32_t k = threadIdx.x; k < P * P; k += blockDim.x) {
+            const uint32_t i = k / P, j = k - i * P;
+            out[ob + k] = rows[static_cast<size_t>(row_of_pick[a + i]) * V + picks[a + j]];
+        }
+    }
+}
+
+__global__ void k_gather_blk(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
+                             const uint32_t *__restrict__ picks,
+                             const uint64_t *__restrict__ out_base,
+                             const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n,
+                             const uint32_t *__restrict__ dist, uint32_t V,
+                             uint32_t *__restrict__ out) {
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        const uint64_t ob = out_base[o];
+        for (uint32_t k = threadIdx.x; k < P * P; k += blockDim.x) {
+            const uint32_t i = k / P, j = k - i * P;
+            const uint32_t si = src_idx_of_pick[a + i];
+            if (si < lo || si >= lo + n) continue;
+            const uint32_t c = si - lo;
+            const size_t b = c / LANES, l = c % LANES;
+            out[ob + k] = dist[(b * V + picks[a + j]) * LANES + l];
+        }
+    }
+}
+
+__global__ void k_gather_seg(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
+                             const uint32_t *__restrict__ picks,
+                             const uint64_t *__restrict__ out_base,
+                             const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n,
+                             const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
+                             const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
+                             uint32_t T, uint32_t Vt, uint32_t *__restrict__ out) {
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        const uint64_t ob = out_base[o];
+        for (uint32_t k = threadIdx.x; k < P * P; k += blockDim.x) {
+            const uint32_t i = k / P, j = k - i * P;
+            const uint32_t si = src_idx_of_pick[a + i];
+            if (si < lo || si >= lo + n) continue;
+            out[ob + k] = seg_value(tile_of, pos_of, visited, gdist, T, Vt, si - lo, picks[a + i],
+                                    picks[a + j]);
+        }
+    }
+}
+
+// ------------------------------------------------- canonical predecessors
+// pred[r][v] = smallest u over in-arcs (u, v) with d(u) != INF and
+// d(u) + w = d(v); -1 for the row's source and for INF vertices.
+__global__ void k_pred_rows(const uint32_t *__restrict__ rows, uint32_t nrows, uint32_t V,
+                            const uint32_t *__restrict__ row_src_vertex,
+                            const uint32_t *__restrict__ in_ptr, const uint32_t *__restrict__ in_src,
+                            const uint32_t *__restrict__ in_w, const uint32_t *__restrict__ in_row,
+                            const uint32_t *__restrict__ out_row, int32_t *__restrict__ pred) {
+    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+    const uint32_t *d = rows + static_cast<size_t>(in_row[r]) * V;
+    int32_t *p = pred + static_cast<size_t>(out_row[r]) * V;
+    const uint32_t sv = row_src_vertex[r];
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
+        const uint32_t dv = d[v];
+        int32_t best = -1;
+        if (v != sv && dv != INF) {
+            uint32_t bu = NONE;
+            for (uint32_t e = in_ptr[v]; e < in_ptr[v + 1]; ++e) {
+                const uint32_t u = in_src[e];
+                const uint32_t du = d[u];
+                if (du != INF && static_cast<uint64_t>(du) + in_w[e] == dv && u < bu) bu = u;
+            }
+            best = bu == NONE ? -1 : static_cast<int32_t>(bu);
+        }
+        p[v] = best;
+    }
+    }
+}
+
+// ------------------------------------------- paper-structured edge baseline
+// One thread per arc (u, v, w), 256 threads per block; each thread loops
+// over the N sources and lowers d_n(v) in place (the paper's one-thread-per-
+// edge kernel over integer arrays u, v, w with dist of size V x N).
+__global__ __launch_bounds__(256) void k_edge_round(const uint32_t *__restrict__ arc_src,
+                                                    const uint32_t *__restrict__ col,
+                                                    const uint32_t *__restrict__ w, uint32_t E,
+                                                    uint32_t *__restrict__ dist, uint32_t V,
+                                                    uint32_t N, uint32_t *__restrict__ changed) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const uint32_t u = arc_src[e], v = col[e], ww = w[e];
+    bool moved = false;
+    for (uint32_t n = 0; n < N; ++n) {
+        uint32_t *dn = dist + static_cast<size_t>(n) * V;
+        const uint32_t nd = sat_add(dn[u], ww);
+        if (nd < dn[v]) moved |= nd < atomicMin(&dn[v], nd);
+    }
+    if (moved) *changed = 1u;
+}
+
+__global__ void k_rows_seed(uint32_t *__restrict__ dist, uint32_t V, uint32_t N,
+                            const uint32_t *__restrict__ src) {
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) dist[static_cast<size_t>(n) * V + src[n]] = 0;
+}
+
+__global__ void k_arc_src(const uint32_t *__restrict__ row_ptr, uint32_t V,
+                          uint32_t *__restrict__ arc_src) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < V; u += gridDim.x * blockDim.x)
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) arc_src[e] = u;
+}
+
+// ----------------------------------------------------------- weight epochs
+__global__ void k_weight_scatter(uint32_t n, const uint32_t *__restrict__ arc,
+                                 const uint32_t *__restrict__ neww, uint32_t *__restrict__ w,
+                                 uint32_t *__restrict__ in_w, const uint32_t *__restrict__ in_pos,
+                                 uint32_t *__restrict__ l_arc, uint32_t *__restrict__ x_w,
+                                 const uint32_t *__restrict__ arc_slot) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t a = arc[i], nw = neww[i];
+    w[a] = nw;
+    in_w[in_pos[a]] = nw;
+    if (arc_slot) {
+        const uint32_t sl = arc_slot[a];
+        if (sl == NONE) return;
+        if (sl & 0x80000000u)
+            x_w[sl & 0x7FFFFFFFu] = nw;
+        else
+            l_arc[sl] = (l_arc[sl] & 0xFFFF0000u) | (nw & 0xFFFFu);
+    }
+}
+
+}  // namespace
+
+// ========================================================== host launchers
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st) {
+    if (!n) return;
+    if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (fill)");
+    if ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)
+        hipLaunchKernelGGL(k_fill_u32, blocks_for(n / 4 + 1, 256, 8192), 256, 0, st, p, n, v);
+    else
+        hipLaunchKernelGGL(k_fill_u32_unaligned, blocks_for(n, 256, 8192), 256, 0, st, p, n, v);
+    check_launch("fill_u32");
+}
+
+void launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u8, blocks_for(n, 256, 8192), 256, 0, st, p, n, v);
+    check_launch("fill_u8");
+}
+
+void launch_blk_seed(uint32_t *dist, uint32_t V, uint32_t S, const uint32_t *src, hipStream_t st) {
+    if (!S) return;
+    hipLaunchKernelGGL(k_blk_seed, blocks_for(S, 256), 256, 0, st, dist, V, S, src);
+    check_launch("blk_seed");
+}
+
+void launch_sweep_pull(uint32_t *dist, uint32_t V, uint32_t nb, const uint32_t *in_ptr,
+                       const uint32_t *in_src, const uint32_t *in_w, uint32_t *changed,
+                       uint32_t grid, hipStream_t st) {
+    if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (sweep)");
+    hipLaunchKernelGGL(k_sweep_pull, grid, 256, 0, st, dist, V, nb, in_ptr, in_src, in_w, changed);
+    check_launch("sweep_pull");
+}
+
+void launch_frontier_seed(uint64_t *list, uint32_t *count, uint32_t S, const uint32_t *src,
+                          uint32_t V, hipStream_t st) {
+    (void)V;
+    hipLaunchKernelGGL(k_frontier_seed, blocks_for(S ? S : 1, 256), 256, 0, st, list, count, S, src);
+    check_launch("frontier_seed");
+}
+
+void launch_frontier_push(uint32_t *dist, uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                          const uint32_t *w, const uint64_t *list_in, const uint32_t *count_in,
+                          uint64_t *list_out, uint32_t *count_out, uint32_t *stamps,
+                          const uint32_t *pass_ctr, uint32_t grid, hipStream_t st) {
+    if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (frontier)");
+    hipLaunchKernelGGL(k_frontier_push, grid, 256, 0, st, dist, V, row_ptr, col, w, list_in, count_in, list_out,
+                                          count_out, stamps, pass_ctr);
+    check_launch("frontier_push");
+}
+
+void launch_pass_prologue(uint32_t *count_next, const uint32_t *count_cur,
+                          unsigned long long *stats, uint32_t *pass_ctr, hipStream_t st) {
+    hipLaunchKernelGGL(k_pass_prologue, 1, 1, 0, st, count_next, count_cur, stats, pass_ctr);
+    check_launch("pass_prologue");
+}
+
+void launch_blk_emit(const uint32_t *dist, uint32_t V, uint32_t rows, const uint32_t *row_src_idx,
+                     const uint32_t *out_row, uint32_t *out, hipStream_t st) {
+    if (!rows) return;
+    dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
+    hipLaunchKernelGGL(k_blk_emit, grid, 256, 0, st, dist, V, rows, row_src_idx, out_row, out);
+    check_launch("blk_emit");
+}
+
+static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t G) {
+    SegPassArgs A{};
+    A.tile_base = ts.d_tile_base.p;
+    A.l_off = ts.d_l_off.p;
+    A.l_arc = ts.d_l_arc.p;
+    A.x_off = ts.d_x_off.p;
+    A.x_port = ts.d_x_port.p;
+    A.x_w = ts.d_x_w.p;
+    A.x_tile = ts.d_x_tile.p;
+    A.port_base = ts.d_port_base.p;
+    A.port_local = ts.d_port_local.p;
+    A.bo_base = ts.d_bo_base.p;
+    A.bo_local = ts.d_bo_local.p;
+    A.T = ts.T;
+    A.Vt = ts.Vt;
+    A.NP = ts.NP;
+    A.S = ss.S;
+    A.gdist = ss.gdist;
+    A.inbox = ss.inbox;
+    A.visited = ss.visited;
+    A.stamps = ss.stamps;
+    A.src_pos = ss.src_pos;
+    A.src_tile = ss.src_tile;
+    const uint32_t nx = par ^ 1u;
+    A.cnt_cur = ss.cnt + static_cast<size_t>(par) * ts.T;
+    A.bucket_cur = ss.bucket + static_cast<size_t>(par) * ts.T * ss.S;
+    A.cnt_next = ss.cnt + static_cast<size_t>(nx) * ts.T;
+    A.bucket_next = ss.bucket + static_cast<size_t>(nx) * ts.T * ss.S;
+    A.tiles_next = ss.tiles + static_cast<size_t>(nx) * ts.T;
+    A.ntiles_next = ss.ntiles + nx;
+    A.units = ss.units;
+    A.nunits = ss.nunits;
+    A.cursor = ss.cursor;
+    A.pass_ctr = ss.pass_ctr;
+    A.G = G;
+    return A;
+}
+
+void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st) {
+    // seeds land in parity 0; their stamp is 1 (pass 0's list)
+    SegPassArgs A = seg_args(ts, ss, 1u, 1u);
+    hipLaunchKernelGGL(k_seg_seed, blocks_for(n ? n : 1, 256), 256, 0, st, A, n);
+    check_launch("seg_seed");
+}
+
+void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t tile_cap,
+                     uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st) {
+    if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (segment pass)");
+    const uint32_t nx = par ^ 1u;
+    hipLaunchKernelGGL(k_seg_prologue, blocks_for(ts.T, 256, 64), 256, 0, st, 
+        ss.cnt + static_cast<size_t>(nx) * ts.T, ts.T, ss.ntiles + nx, ss.nunits, ss.cursor,
+        ss.pass_ctr);
+    check_launch("seg_prologue");
+    hipLaunchKernelGGL(k_seg_plan, blocks_for(ts.T, 256, 64), 256, 0, st, 
+        ss.tiles + static_cast<size_t>(par) * ts.T, ss.ntiles + par,
+        ss.cnt + static_cast<size_t>(par) * ts.T, G, ss.units, ss.nunits, ss.stats);
+    check_launch("seg_plan");
+    SegPassArgs A = seg_args(ts, ss, par, G);
+#define WR_SEG_CASE(CAPV, NWV)                                      \
+    if (tile_cap == CAPV && waves == NWV) {                         \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_seg_pass<CAPV, NWV>), grid, NWV * 64, 0, st, A);        \
+        check_launch("seg_pass");                                   \
+        return;                                                     \
+    }
+    WR_SEG_CASE(1024, 4)
+    WR_SEG_CASE(1024, 8)
+    WR_SEG_CASE(2048, 4)
+    WR_SEG_CASE(2048, 8)
+    WR_SEG_CASE(4096, 2)
+#undef WR_SEG_CASE
+    fail(WR_E_UNSUPPORTED, "no segment kernel for tile size " + std::to_string(tile_cap) +
+                               " with " + std::to_string(waves) + " waves");
+}
+
+uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves) {
+    const uint32_t words = tile_cap / 32;
+    return (tile_cap + 2) * 2 + 4 * tile_cap * 4 +
+           waves * (tile_cap * 4 + tile_cap * 2 + 2 * words * 4) + 4;
+}
+
+void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t rows,
+                     const uint32_t *row_src_idx, const uint32_t *row_src_vertex,
+                     const uint32_t *out_row, uint32_t *out, hipStream_t st) {
+    if (!rows) return;
+    dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
+    hipLaunchKernelGGL(k_seg_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited, ss.gdist, ts.T,
+                                      ts.Vt, V, rows, row_src_idx, row_src_vertex, out_row, out);
+    check_launch("seg_emit");
+}
+
+void launch_gather_rows(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                        const uint64_t *out_base, const uint32_t *row_of_pick, const uint32_t *rows,
+                        uint32_t V, uint32_t *out, hipStream_t st) {
+    if (!num_orders) return;
+    hipLaunchKernelGGL(k_gather_rows, blocks_for(num_orders, 1, 65535), 256, 0, st, 
+        num_orders, pick_off, picks, out_base, row_of_pick, rows, V, out);
+    check_launch("gather_rows");
+}
+
+void launch_gather_blk(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                       const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
+                       uint32_t chunk_n, const uint32_t *dist, uint32_t V, uint32_t *out,
+                       hipStream_t st) {
+    if (!num_orders) return;
+    hipLaunchKernelGGL(k_gather_blk, blocks_for(num_orders, 1, 65535), 256, 0, st, 
+        num_orders, pick_off, picks, out_base, src_idx_of_pick, chunk_lo, chunk_n, dist, V, out);
+    check_launch("gather_blk");
+}
+
+void launch_gather_seg(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                       const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
+                       uint32_t chunk_n, const TileSet &ts, const SegState &ss, uint32_t *out,
+                       hipStream_t st) {
+    if (!num_orders) return;
+    hipLaunchKernelGGL(k_gather_seg, blocks_for(num_orders, 1, 65535), 256, 0, st, 
+        num_orders, pick_off, picks, out_base, src_idx_of_pick, chunk_lo, chunk_n, ts.d_tile_of.p,
+        ts.d_pos_of.p, ss.visited, ss.gdist, ts.T, ts.Vt, out);
+    check_launch("gather_seg");
+}
+
+void launch_pred_rows(const uint32_t *rows, uint32_t nrows, uint32_t V, const uint32_t *row_src_vertex,
+                      const uint32_t *in_ptr, const uint32_t *in_src, const uint32_t *in_w,
+                      const uint32_t *in_row, const uint32_t *out_row, int32_t *pred, hipStream_t st) {
+    if (!nrows) return;
+    dim3 grid(blocks_for(V, 256, 1024), nrows < 65535u ? nrows : 65535u);
+    hipLaunchKernelGGL(k_pred_rows, grid, 256, 0, st, rows, nrows, V, row_src_vertex, in_ptr, in_src, in_w, in_row,
+                                       out_row, pred);
+    check_launch("pred_rows");
+}
+
+void launch_edge_round(const uint32_t *arc_src, const uint32_t *col, const uint32_t *w, uint32_t E,
+                       uint32_t *dist, uint32_t V, uint32_t N, uint32_t *changed, hipStream_t st) {
+    if (!E) return;
+    if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (edge round)");
+    hipLaunchKernelGGL(k_edge_round, (E + 255) / 256, 256, 0, st, arc_src, col, w, E, dist, V, N, changed);
+    check_launch("edge_round");
+}
+
+void launch_rows_seed(uint32_t *dist, uint32_t V, uint32_t N, const uint32_t *src, hipStream_t st) {
+    if (!N) return;
+    hipLaunchKernelGGL(k_rows_seed, blocks_for(N, 256), 256, 0, st, dist, V, N, src);
+    check_launch("rows_seed");
+}
+
+void launch_arc_src(const uint32_t *row_ptr, uint32_t V, uint32_t *arc_src, hipStream_t st) {
+    hipLaunchKernelGGL(k_arc_src, blocks_for(V, 256, 4096), 256, 0, st, row_ptr, V, arc_src);
+    check_launch("arc_src");
+}
+
+void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww, uint32_t *w,
+                           uint32_t *in_w, const uint32_t *in_pos, uint32_t *l_arc, uint32_t *x_w,
+                           const uint32_t *arc_slot, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_weight_scatter, blocks_for(n, 256), 256, 0, st, n, arc, neww, w, in_w, in_pos, l_arc, x_w,
+                                                          arc_slot);
+    check_launch("weight_scatter");
+}
+
+}  // namespace wr

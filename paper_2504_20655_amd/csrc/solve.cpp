@@ -1,0 +1,804 @@
+// Batch planner and relaxation drivers behind wr_sssp / wr_order_matrices.
+//
+// Planning (host): distinct sources are solved once per call (many picks
+// share vertices); they are ordered by tile and vertex id so that sources
+// relaxed together sit close to each other, then cut into chunks whose work
+// buffers fit the context's memory budget.  Each chunk is relaxed to the
+// fixpoint by one of the schedules, then read out (rows, order matrices,
+// predecessors) before the next chunk reuses the buffers.
+//
+// Pass loops run on device with device-side termination counters; a fixed
+// number of passes is captured once in a hipGraph and replayed until a
+// replay ends with nothing left to do (one host read per replay).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+#include <memory>
+#include <numeric>
+#include <sstream>
+
+#include "wr_internal.hpp"
+
+namespace wr {
+
+// --------------------------------------------------------------- workspace
+struct SegWork {
+    uint64_t gen = 0;
+    uint32_t S_cap = 0, tile_cap = 0, waves = 0, G = 0, K = 0, grid = 0;
+    DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile;
+    DBuf<uint8_t> visited;
+    DBuf<uint2> units;
+    DBuf<unsigned long long> stats;
+    hipGraphExec_t exec = nullptr;
+    SegState ss;
+    ~SegWork() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+struct BlkWork {
+    uint32_t nb_cap = 0, K = 0, grid = 0;
+    bool frontier = false;
+    DBuf<uint32_t> dist, stamps, ctr, src;
+    DBuf<uint64_t> list;
+    DBuf<unsigned long long> stats;
+    hipGraphExec_t exec = nullptr;
+    ~BlkWork() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+struct Workspace {
+    std::unique_ptr<SegWork> seg;
+    std::unique_ptr<BlkWork> blk;
+    uint32_t *h_flag = nullptr;   // pinned host word for termination checks
+    ~Workspace() {
+        if (h_flag) (void)hipHostFree(h_flag);
+    }
+};
+
+void destroy_workspace(Workspace *ws) { delete ws; }
+
+namespace {
+
+Workspace &workspace(wr_graph *g) {
+    if (!g->ws) {
+        g->ws = new Workspace();
+        WR_HIP(hipHostMalloc(reinterpret_cast<void **>(&g->ws->h_flag), 64, hipHostMallocDefault));
+    }
+    return *g->ws;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint32_t resolve_algo(wr_graph *g, uint32_t flags) {
+    uint32_t a = flags & WR_ALGO_MASK;
+    if (a == WR_ALGO_AUTO) a = g->max_w < 65536u ? WR_ALGO_SEGMENTED : WR_ALGO_FRONTIER;
+    switch (a) {
+    case WR_ALGO_SWEEP:
+    case WR_ALGO_FRONTIER:
+    case WR_ALGO_SEGMENTED:
+    case WR_ALGO_EDGE_B1:
+    case WR_ALGO_EDGE_B0:
+        break;
+    default:
+        fail(WR_E_INVALID, "unknown WR_ALGO value");
+    }
+    if (a == WR_ALGO_SEGMENTED && g->max_w >= 65536u)
+        fail(WR_E_UNSUPPORTED, "segmented schedule packs weights in 16 bits; max weight is too large");
+    return a;
+}
+
+// Distinct sources in processing order plus, for each requested vertex, its
+// index among them.
+struct Plan {
+    std::vector<uint32_t> usrc;
+    std::vector<uint32_t> uidx;
+};
+
+Plan make_plan(wr_graph *g, const uint32_t *verts, size_t n, bool by_tile) {
+    Plan p;
+    std::vector<uint32_t> v(verts, verts + n);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    if (by_tile && g->tiles) {
+        const auto &tof = g->tiles->tile_of;
+        std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) {
+            const uint64_t ka = (static_cast<uint64_t>(tof[a]) << 32) | a;
+            const uint64_t kb = (static_cast<uint64_t>(tof[b]) << 32) | b;
+            return ka < kb;
+        });
+    }
+    p.usrc = v;
+    std::vector<std::pair<uint32_t, uint32_t>> key(v.size());
+    for (uint32_t i = 0; i < v.size(); ++i) key[i] = {v[i], i};
+    std::sort(key.begin(), key.end());
+    p.uidx.resize(n);
+    for (size_t k = 0; k < n; ++k) {
+        auto it = std::lower_bound(key.begin(), key.end(), std::make_pair(verts[k], 0u));
+        p.uidx[k] = it->second;
+    }
+    return p;
+}
+
+// -------------------------------------------------------- segmented driver
+uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
+    return ts.T * ((S + G - 1) / G) + ts.T;
+}
+
+uint64_t seg_bytes_per_source(const TileSet &ts, uint32_t G) {
+    return 4ull * ts.Vt + 4ull * ts.NP + 1ull * ts.T + 4ull * ts.T + 8ull * ts.T +
+           8ull * ts.T / G + 8;
+}
+
+SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode) {
+    Workspace &ws = workspace(g);
+    TileSet &ts = *g->tiles;
+    const uint32_t waves = g->waves_per_group;
+    const uint32_t G = g->sources_per_unit ? g->sources_per_unit : 4 * waves;
+    const uint32_t K = std::max(2u, g->passes_per_replay & ~1u);
+    SegWork *w = ws.seg.get();
+    const bool fits = w && w->gen == g->tiles_gen && w->S_cap >= S_need && w->tile_cap == ts.tile_cap &&
+                      w->waves == waves && w->G == G && w->K == K;
+    if (fits) return *w;
+    // size the chunk: the request, bounded by the budget (keep what we hold)
+    ws.seg.reset();
+    const uint64_t per = seg_bytes_per_source(ts, G);
+    const uint64_t avail = g->ctx->available();
+    uint64_t S_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
+    uint32_t S_cap = static_cast<uint32_t>(std::min<uint64_t>(S_need, S_fit));
+    if (S_cap == 0) fail(WR_E_NOMEM, "not even one source fits the memory budget (segmented)");
+    auto nw = std::make_unique<SegWork>();
+    nw->gen = g->tiles_gen;
+    nw->S_cap = S_cap;
+    nw->tile_cap = ts.tile_cap;
+    nw->waves = waves;
+    nw->G = G;
+    nw->K = K;
+    wr_context *ctx = g->ctx;
+    nw->gdist.alloc(ctx, static_cast<size_t>(S_cap) * ts.Vt);
+    nw->inbox.alloc(ctx, static_cast<size_t>(S_cap) * std::max(ts.NP, 1u));
+    nw->stamps.alloc(ctx, static_cast<size_t>(S_cap) * ts.T);
+    nw->visited.alloc(ctx, static_cast<size_t>(S_cap) * ts.T);
+    nw->cnt.alloc(ctx, 2ull * ts.T);
+    nw->bucket.alloc(ctx, 2ull * ts.T * S_cap);
+    nw->tiles.alloc(ctx, 2ull * ts.T);
+    nw->ctr.alloc(ctx, 8);
+    nw->units.alloc(ctx, seg_units_cap(ts, S_cap, G));
+    nw->stats.alloc(ctx, 2);
+    nw->src_pos.alloc(ctx, S_cap);
+    nw->src_tile.alloc(ctx, S_cap);
+    SegState &ss = nw->ss;
+    ss.S = S_cap;
+    ss.gdist = nw->gdist.p;
+    ss.inbox = nw->inbox.p;
+    ss.visited = nw->visited.p;
+    ss.stamps = nw->stamps.p;
+    ss.cnt = nw->cnt.p;
+    ss.bucket = nw->bucket.p;
+    ss.tiles = nw->tiles.p;
+    ss.units = nw->units.p;
+    ss.ntiles = nw->ctr.p + 0;   // [2]
+    ss.nunits = nw->ctr.p + 2;
+    ss.cursor = nw->ctr.p + 3;
+    ss.pass_ctr = nw->ctr.p + 4;
+    ss.stats = nw->stats.p;
+    ss.src_pos = nw->src_pos.p;
+    ss.src_tile = nw->src_tile.p;
+    // persistent grid: as many workgroups as fit on the chip at once
+    const uint32_t lds = seg_pass_lds_bytes(ts.tile_cap, waves);
+    uint32_t per_cu = std::max(1u, (160u * 1024u) / lds);
+    per_cu = std::min(per_cu, 32u / waves);
+    nw->grid = static_cast<uint32_t>(ctx->num_cus) * per_cu;
+    if (graph_mode) {
+        hipStream_t st = ctx->stream;
+        hipGraph_t graph;
+        WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            for (uint32_t i = 0; i < K; ++i)
+                launch_seg_step(ts, ss, i & 1u, ts.tile_cap, waves, G, nw->grid, st);
+        } catch (...) {
+            hipGraph_t dummy;
+            (void)hipStreamEndCapture(st, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+        }
+        WR_HIP(hipStreamEndCapture(st, &graph));
+        hipError_t e = hipGraphInstantiate(&nw->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) fail(WR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    ws.seg = std::move(nw);
+    return *ws.seg;
+}
+
+// Relaxes sources usrc[lo .. lo+n) to the fixpoint in the segmented state.
+void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc, uint32_t lo,
+                     uint32_t n, bool graph_mode, wr_run_info &info) {
+    const TileSet &ts = *g->tiles;
+    wr_context *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    SegState ss = w.ss;
+    // per-source tables
+    std::vector<uint32_t> sp(n), stl(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t v = usrc[lo + i];
+        sp[i] = ts.pos_of[v];
+        stl[i] = ts.tile_of[v];
+    }
+    WR_HIP(hipMemcpyAsync(w.src_pos.p, sp.data(), n * 4ull, hipMemcpyHostToDevice, st));
+    WR_HIP(hipMemcpyAsync(w.src_tile.p, stl.data(), n * 4ull, hipMemcpyHostToDevice, st));
+    // reset the chunk state (S stays the buffer capacity for indexing)
+    launch_fill_u32(w.inbox.p, static_cast<size_t>(n) * std::max(ts.NP, 1u), INF, st);
+    launch_fill_u32(w.stamps.p, static_cast<size_t>(n) * ts.T, 0u, st);
+    launch_fill_u8(w.visited.p, static_cast<size_t>(n) * ts.T, 0u, st);
+    launch_fill_u32(w.cnt.p, 2ull * ts.T, 0u, st);
+    launch_fill_u32(w.ctr.p, 8, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.stats.p), 4, 0u, st);
+    launch_seg_seed_n(ts, ss, n, st);
+    hipEvent_t e0, e1;
+    WR_HIP(hipEventCreate(&e0));
+    WR_HIP(hipEventCreate(&e1));
+    WR_HIP(hipEventRecord(e0, st));
+    const uint32_t K = w.K;
+    uint64_t passes = 0;
+    const uint64_t cap = static_cast<uint64_t>(g->V) + 2ull * K + 8;
+    for (;;) {
+        if (graph_mode) {
+            WR_HIP(hipGraphLaunch(w.exec, st));
+        } else {
+            for (uint32_t i = 0; i < K; ++i)
+                launch_seg_step(ts, ss, i & 1u, ts.tile_cap, w.waves, w.G, w.grid, st);
+        }
+        passes += K;
+        WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + 0, 4, hipMemcpyDeviceToHost, st));
+        WR_HIP(hipStreamSynchronize(st));
+        if (*workspace(g).h_flag == 0) break;
+        if (passes > cap) fail(WR_E_INTERNAL, "segmented relaxation exceeded its pass cap");
+    }
+    WR_HIP(hipEventRecord(e1, st));
+    unsigned long long stats[2];
+    WR_HIP(hipMemcpyAsync(stats, w.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
+    WR_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    WR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    info.relax_ms += ms;
+    info.passes += static_cast<uint32_t>(stats[1]);
+    info.work_items += stats[0];
+}
+
+// ------------------------------------------------------ blocked-layout driver
+uint64_t blk_bytes_per_block(uint32_t V, bool frontier) {
+    return static_cast<uint64_t>(V) * (LANES * 4ull + (frontier ? 4ull + 16ull : 0ull));
+}
+
+BlkWork &blk_workspace(wr_graph *g, uint32_t nb_need, bool frontier, bool graph_mode) {
+    Workspace &ws = workspace(g);
+    const uint32_t K = std::max(2u, g->passes_per_replay & ~1u);
+    BlkWork *w = ws.blk.get();
+    if (w && w->nb_cap >= nb_need && w->frontier == frontier && w->K == K && (!graph_mode || w->exec))
+        return *w;
+    ws.blk.reset();
+    const uint64_t per = blk_bytes_per_block(g->V, frontier);
+    const uint64_t avail = g->ctx->available();
+    uint64_t nb_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
+    const uint32_t nb_cap = static_cast<uint32_t>(std::min<uint64_t>(nb_need, nb_fit));
+    if (nb_cap == 0) fail(WR_E_NOMEM, "not even one source block fits the memory budget");
+    auto nw = std::make_unique<BlkWork>();
+    nw->nb_cap = nb_cap;
+    nw->frontier = frontier;
+    nw->K = K;
+    wr_context *ctx = g->ctx;
+    const size_t units = static_cast<size_t>(nb_cap) * g->V;
+    nw->dist.alloc(ctx, units * LANES);
+    nw->ctr.alloc(ctx, 8);
+    nw->src.alloc(ctx, static_cast<size_t>(nb_cap) * LANES);
+    nw->stats.alloc(ctx, 2);
+    if (frontier) {
+        nw->stamps.alloc(ctx, units);
+        nw->list.alloc(ctx, 2 * units);
+    }
+    nw->grid = static_cast<uint32_t>(ctx->num_cus) * 8;
+    if (graph_mode) {
+        hipStream_t st = ctx->stream;
+        hipGraph_t graph;
+        WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            if (frontier) {
+                for (uint32_t i = 0; i < K; ++i) {
+                    const uint32_t par = i & 1u, nx = par ^ 1u;
+                    launch_pass_prologue(nw->ctr.p + nx, nw->ctr.p + par, nw->stats.p, nw->ctr.p + 4, st);
+                    launch_frontier_push(nw->dist.p, g->V, g->d_row_ptr.p, g->d_col.p, g->d_w.p,
+                                         nw->list.p + par * units, nw->ctr.p + par,
+                                         nw->list.p + nx * units, nw->ctr.p + nx, nw->stamps.p,
+                                         nw->ctr.p + 4, nw->grid, st);
+                }
+            } else {
+                launch_fill_u32(nw->ctr.p + 2, 1, 0u, st);
+                for (uint32_t i = 0; i < K; ++i)
+                    launch_sweep_pull(nw->dist.p, g->V, nb_cap, g->d_in_ptr.p, g->d_in_src.p,
+                                      g->d_in_w.p, nw->ctr.p + 2, nw->grid, st);
+            }
+        } catch (...) {
+            hipGraph_t dummy;
+            (void)hipStreamEndCapture(st, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+        }
+        WR_HIP(hipStreamEndCapture(st, &graph));
+        hipError_t e = hipGraphInstantiate(&nw->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) fail(WR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    ws.blk = std::move(nw);
+    return *ws.blk;
+}
+
+// Relaxes usrc[lo .. lo+n) in the blocked layout (n <= nb_cap * 64).  The
+// sweep graph spans all nb_cap blocks; unused lanes stay INF and cost only
+// bandwidth.
+void blk_solve_chunk(wr_graph *g, BlkWork &w, const std::vector<uint32_t> &usrc, uint32_t lo,
+                     uint32_t n, bool graph_mode, wr_run_info &info) {
+    wr_context *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    const uint32_t V = g->V;
+    const size_t units = static_cast<size_t>(w.nb_cap) * V;
+    WR_HIP(hipMemcpyAsync(w.src.p, usrc.data() + lo, n * 4ull, hipMemcpyHostToDevice, st));
+    launch_fill_u32(w.dist.p, units * LANES, INF, st);
+    launch_fill_u32(w.ctr.p, 8, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.stats.p), 4, 0u, st);
+    launch_blk_seed(w.dist.p, V, n, w.src.p, st);
+    if (w.frontier) {
+        launch_fill_u32(w.stamps.p, units, 0u, st);
+        launch_frontier_seed(w.list.p, w.ctr.p + 0, n, w.src.p, V, st);
+    }
+    hipEvent_t e0, e1;
+    WR_HIP(hipEventCreate(&e0));
+    WR_HIP(hipEventCreate(&e1));
+    WR_HIP(hipEventRecord(e0, st));
+    const uint32_t K = w.K;
+    uint64_t passes = 0, sweeps_changed = 0;
+    const uint64_t cap = static_cast<uint64_t>(V) + 2ull * K + 8;
+    uint32_t *hf = workspace(g).h_flag;
+    for (;;) {
+        if (graph_mode) {
+            WR_HIP(hipGraphLaunch(w.exec, st));
+        } else if (w.frontier) {
+            for (uint32_t i = 0; i < K; ++i) {
+                const uint32_t par = i & 1u, nx = par ^ 1u;
+                launch_pass_prologue(w.ctr.p + nx, w.ctr.p + par, w.stats.p, w.ctr.p + 4, st);
+                launch_frontier_push(w.dist.p, V, g->d_row_ptr.p, g->d_col.p, g->d_w.p,
+                                     w.list.p + par * units, w.ctr.p + par, w.list.p + nx * units,
+                                     w.ctr.p + nx, w.stamps.p, w.ctr.p + 4, w.grid, st);
+            }
+        } else {
+            launch_fill_u32(w.ctr.p + 2, 1, 0u, st);
+            for (uint32_t i = 0; i < K; ++i)
+                launch_sweep_pull(w.dist.p, V, w.nb_cap, g->d_in_ptr.p, g->d_in_src.p, g->d_in_w.p,
+                                  w.ctr.p + 2, w.grid, st);
+        }
+        passes += K;
+        WR_HIP(hipMemcpyAsync(hf, w.frontier ? w.ctr.p + 0 : w.ctr.p + 2, 4, hipMemcpyDeviceToHost, st));
+        WR_HIP(hipStreamSynchronize(st));
+        if (!w.frontier && *hf) sweeps_changed += K;
+        if (*hf == 0) break;
+        if (passes > cap) fail(WR_E_INTERNAL, "relaxation exceeded its pass cap");
+    }
+    WR_HIP(hipEventRecord(e1, st));
+    unsigned long long stats[2] = {0, 0};
+    WR_HIP(hipMemcpyAsync(stats, w.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
+    WR_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    WR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    info.relax_ms += ms;
+    if (w.frontier) {
+        info.passes += static_cast<uint32_t>(stats[1]);
+        info.work_items += stats[0];
+    } else {
+        info.passes += static_cast<uint32_t>(passes);
+        info.work_items += passes * units;
+    }
+    (void)sweeps_changed;
+}
+
+// --------------------------------------------------- edge-list baseline
+// Runs the N sources of `src` together (dist [N][V]), one launch per round
+// and a host read of the changed flag after each round (the paper's
+// structure: a global synchronisation every iteration).  full_rounds runs
+// exactly V-1 rounds.
+void edge_solve(wr_graph *g, const uint32_t *d_src, uint32_t N, uint32_t *d_rows, bool full_rounds,
+                wr_run_info &info) {
+    wr_context *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    const uint32_t V = g->V;
+    if (!g->d_arc_src.p && g->E) {
+        g->d_arc_src.alloc(ctx, g->E);
+        launch_arc_src(g->d_row_ptr.p, V, g->d_arc_src.p, st);
+    }
+    Workspace &ws = workspace(g);
+    launch_fill_u32(d_rows, static_cast<size_t>(N) * V, INF, st);
+    launch_rows_seed(d_rows, V, N, d_src, st);
+    DBuf<uint32_t> flag;
+    flag.alloc(ctx, 1);
+    hipEvent_t e0, e1;
+    WR_HIP(hipEventCreate(&e0));
+    WR_HIP(hipEventCreate(&e1));
+    WR_HIP(hipEventRecord(e0, st));
+    const uint32_t rounds_cap = V > 1 ? V - 1 : 1;
+    uint32_t rounds = 0;
+    for (; rounds < rounds_cap;) {
+        launch_fill_u32(flag.p, 1, 0u, st);
+        launch_edge_round(g->d_arc_src.p, g->d_col.p, g->d_w.p, g->E, d_rows, V, N, flag.p, st);
+        ++rounds;
+        WR_HIP(hipMemcpyAsync(ws.h_flag, flag.p, 4, hipMemcpyDeviceToHost, st));
+        WR_HIP(hipStreamSynchronize(st));
+        if (!full_rounds && *ws.h_flag == 0) break;
+    }
+    WR_HIP(hipEventRecord(e1, st));
+    WR_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    WR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    info.relax_ms += ms;
+    info.passes += rounds;
+    info.work_items += static_cast<uint64_t>(rounds) * g->E;
+}
+
+// Orders `lo..lo+n)` of usrc that fit one chunk of the chosen schedule.
+uint32_t chunk_sources(wr_graph *g, uint32_t algo, uint32_t total, bool graph_mode) {
+    if (algo == WR_ALGO_SEGMENTED) return seg_workspace(g, total, graph_mode).S_cap;
+    const uint32_t nb_need = (total + LANES - 1) / LANES;
+    return blk_workspace(g, nb_need, algo == WR_ALGO_FRONTIER, graph_mode).nb_cap * LANES;
+}
+
+void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, uint32_t lo,
+                 uint32_t n, bool graph_mode, wr_run_info &info) {
+    if (algo == WR_ALGO_SEGMENTED)
+        seg_solve_chunk(g, *workspace(g).seg, usrc, lo, n, graph_mode, info);
+    else
+        blk_solve_chunk(g, *workspace(g).blk, usrc, lo, n, graph_mode, info);
+}
+
+// Source-major rows of the current chunk's state: out + out_row[r]*V gets the
+// row of chunk source row_idx[r].
+void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
+               const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out);
+
+struct StreamJoin {
+    // The library works on its own stream; with caller (device) buffers it
+    // first waits for the caller's stream so earlier work on them is done.
+    StreamJoin(wr_context *ctx, bool dev, void *user_stream) {
+        if (!dev) return;
+        hipEvent_t ev;
+        WR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        WR_HIP(hipEventRecord(ev, static_cast<hipStream_t>(user_stream)));
+        WR_HIP(hipStreamWaitEvent(ctx->stream, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
+};
+
+void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
+               const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out) {
+    hipStream_t st = g->ctx->stream;
+    if (algo == WR_ALGO_SEGMENTED) {
+        SegWork &w = *workspace(g).seg;
+        launch_seg_emit(*g->tiles, w.ss, g->V, rows, d_row_idx, d_row_vertex, d_out_row, out, st);
+    } else {
+        BlkWork &w = *workspace(g).blk;
+        launch_blk_emit(w.dist.p, g->V, rows, d_row_idx, d_out_row, out, st);
+    }
+}
+
+}  // namespace
+}  // namespace wr
+
+using namespace wr;
+
+extern "C" {
+
+wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *dist, int32_t *pred,
+                  uint32_t flags, void *stream) {
+    WR_API_BEGIN
+    const double t0 = now_ms();
+    if (!g) fail(WR_E_INVALID, "graph is NULL");
+    if (S == 0) return WR_OK;
+    if (!sources || !dist) fail(WR_E_INVALID, "sources or dist is NULL");
+    for (uint32_t i = 0; i < S; ++i)
+        if (sources[i] >= g->V) fail(WR_E_INVALID, "source out of range");
+    if (pred && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
+    const uint32_t algo = resolve_algo(g, flags);
+    const bool dev = (flags & WR_DEVICE_PTRS) != 0;
+    const bool graph_mode = (flags & WR_NO_GRAPH_CAPTURE) == 0;
+    wr_context *ctx = g->ctx;
+    WR_HIP(hipSetDevice(ctx->device));
+    StreamJoin join(ctx, dev, stream);
+    hipStream_t st = ctx->stream;
+    const uint32_t V = g->V;
+    wr_run_info info{};
+    info.algo = algo;
+
+    if (algo == WR_ALGO_EDGE_B1 || algo == WR_ALGO_EDGE_B0) {
+        DBuf<uint32_t> rows, dsrc;
+        uint32_t *d_rows = dist;
+        if (!dev) {
+            rows.alloc(ctx, static_cast<size_t>(S) * V);
+            d_rows = rows.p;
+        }
+        dsrc.alloc(ctx, S);
+        WR_HIP(hipMemcpyAsync(dsrc.p, sources, S * 4ull, hipMemcpyHostToDevice, st));
+        edge_solve(g, dsrc.p, S, d_rows, algo == WR_ALGO_EDGE_B0, info);
+        info.unique_sources = S;
+        info.chunks = 1;
+        if (pred) {
+            DBuf<int32_t> dpred;
+            int32_t *pp = pred;
+            if (!dev) {
+                dpred.alloc(ctx, static_cast<size_t>(S) * V);
+                pp = dpred.p;
+            }
+            DBuf<uint32_t> orow;
+            std::vector<uint32_t> iota(S);
+            std::iota(iota.begin(), iota.end(), 0u);
+            upload(orow, ctx, iota, st);
+            launch_pred_rows(d_rows, S, V, dsrc.p, g->d_in_ptr.p, g->d_in_src.p, g->d_in_w.p,
+                             orow.p, orow.p, pp, st);
+            if (!dev)
+                WR_HIP(hipMemcpyAsync(pred, pp, static_cast<size_t>(S) * V * 4, hipMemcpyDeviceToHost, st));
+        }
+        if (!dev) WR_HIP(hipMemcpyAsync(dist, d_rows, static_cast<size_t>(S) * V * 4, hipMemcpyDeviceToHost, st));
+        WR_HIP(hipStreamSynchronize(st));
+        info.total_ms = now_ms() - t0;
+        g->last = info;
+        return WR_OK;
+    }
+
+    if (algo == WR_ALGO_SEGMENTED) rebuild_tiles_if_needed(g);
+    Plan plan = make_plan(g, sources, S, true);
+    const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
+    info.unique_sources = U;
+    const uint32_t chunk = chunk_sources(g, algo, U, graph_mode);
+    // rows of each chunk (output rows whose unique source falls in it)
+    std::vector<std::vector<uint32_t>> rows_of(( U + chunk - 1) / chunk);
+    for (uint32_t i = 0; i < S; ++i) rows_of[plan.uidx[i] / chunk].push_back(i);
+    for (uint32_t lo = 0, c = 0; lo < U; lo += chunk, ++c) {
+        const uint32_t n = std::min(chunk, U - lo);
+        solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info);
+        info.chunks += 1;
+        const auto &rows = rows_of[c];
+        const uint32_t R = static_cast<uint32_t>(rows.size());
+        std::vector<uint32_t> ridx(R), rvert(R), orow(R);
+        for (uint32_t r = 0; r < R; ++r) {
+            ridx[r] = plan.uidx[rows[r]] - lo;
+            rvert[r] = sources[rows[r]];
+            orow[r] = dev ? rows[r] : r;
+        }
+        DBuf<uint32_t> d_ridx, d_rvert, d_orow, tmp;
+        upload(d_ridx, ctx, ridx, st);
+        upload(d_rvert, ctx, rvert, st);
+        upload(d_orow, ctx, orow, st);
+        uint32_t *out = dist;
+        if (!dev) {
+            tmp.alloc(ctx, static_cast<size_t>(R) * V);
+            out = tmp.p;
+        }
+        emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, out);
+        if (pred) {
+            DBuf<int32_t> ptmp;
+            int32_t *pp = pred;
+            if (!dev) {
+                ptmp.alloc(ctx, static_cast<size_t>(R) * V);
+                pp = ptmp.p;
+            }
+            launch_pred_rows(out, R, V, d_rvert.p, g->d_in_ptr.p, g->d_in_src.p, g->d_in_w.p,
+                             d_orow.p, d_orow.p, pp, st);
+            if (!dev) {
+                std::vector<int32_t> h(static_cast<size_t>(R) * V);
+                WR_HIP(hipMemcpyAsync(h.data(), pp, h.size() * 4, hipMemcpyDeviceToHost, st));
+                WR_HIP(hipStreamSynchronize(st));
+                for (uint32_t r = 0; r < R; ++r)
+                    std::memcpy(pred + static_cast<size_t>(rows[r]) * V, h.data() + static_cast<size_t>(r) * V, V * 4ull);
+            }
+        }
+        if (!dev) {
+            std::vector<uint32_t> h(static_cast<size_t>(R) * V);
+            WR_HIP(hipMemcpyAsync(h.data(), out, h.size() * 4, hipMemcpyDeviceToHost, st));
+            WR_HIP(hipStreamSynchronize(st));
+            for (uint32_t r = 0; r < R; ++r)
+                std::memcpy(dist + static_cast<size_t>(rows[r]) * V, h.data() + static_cast<size_t>(r) * V, V * 4ull);
+        }
+    }
+    WR_HIP(hipStreamSynchronize(st));
+    info.total_ms = now_ms() - t0;
+    g->last = info;
+    WR_API_END
+}
+
+wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pick_offsets,
+                            const uint32_t *picks, uint32_t *dist_out, int32_t *pred_out,
+                            uint32_t flags, void *stream) {
+    WR_API_BEGIN
+    const double t0 = now_ms();
+    if (!g) fail(WR_E_INVALID, "graph is NULL");
+    if (num_orders == 0) return WR_OK;
+    if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
+    if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
+    uint64_t total = 0;
+    std::vector<uint64_t> out_base(num_orders);
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        if (pick_offsets[o + 1] < pick_offsets[o]) fail(WR_E_INVALID, "pick_offsets must be non-decreasing");
+        const uint64_t P = pick_offsets[o + 1] - pick_offsets[o];
+        out_base[o] = total;
+        total += P * P;
+    }
+    const uint32_t NPK = pick_offsets[num_orders];
+    if (NPK == 0) return WR_OK;
+    if (!picks || !dist_out) fail(WR_E_INVALID, "picks or dist_out is NULL");
+    for (uint32_t k = 0; k < NPK; ++k)
+        if (picks[k] >= g->V) fail(WR_E_INVALID, "pick out of range");
+    if (pred_out && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
+    const uint32_t algo = resolve_algo(g, flags);
+    const bool dev = (flags & WR_DEVICE_PTRS) != 0;
+    const bool graph_mode = (flags & WR_NO_GRAPH_CAPTURE) == 0;
+    wr_context *ctx = g->ctx;
+    WR_HIP(hipSetDevice(ctx->device));
+    StreamJoin join(ctx, dev, stream);
+    hipStream_t st = ctx->stream;
+    const uint32_t V = g->V;
+    wr_run_info info{};
+    info.algo = algo;
+
+    std::vector<uint32_t> hoff(pick_offsets, pick_offsets + num_orders + 1);
+    std::vector<uint32_t> hpicks(picks, picks + NPK);
+    DBuf<uint32_t> d_off, d_picks, d_sidx;
+    DBuf<uint64_t> d_base;
+    upload(d_off, ctx, hoff, st);
+    upload(d_picks, ctx, hpicks, st);
+    upload(d_base, ctx, out_base, st);
+    DBuf<uint32_t> dout_tmp;
+    uint32_t *dout = dist_out;
+    if (!dev) {
+        dout_tmp.alloc(ctx, static_cast<size_t>(total));
+        dout = dout_tmp.p;
+    }
+
+    if (algo == WR_ALGO_EDGE_B1 || algo == WR_ALGO_EDGE_B0) {
+        // one order at a time, its picks as the N sources
+        uint32_t maxP = 0;
+        for (uint32_t o = 0; o < num_orders; ++o) maxP = std::max(maxP, hoff[o + 1] - hoff[o]);
+        DBuf<uint32_t> rows, d_local;
+        rows.alloc(ctx, static_cast<size_t>(maxP) * V);
+        std::vector<uint32_t> local(NPK);
+        for (uint32_t o = 0; o < num_orders; ++o)
+            for (uint32_t k = hoff[o]; k < hoff[o + 1]; ++k) local[k] = k - hoff[o];
+        upload(d_local, ctx, local, st);
+        for (uint32_t o = 0; o < num_orders; ++o) {
+            const uint32_t a = hoff[o], P = hoff[o + 1] - a;
+            if (!P) continue;
+            edge_solve(g, d_picks.p + a, P, rows.p, algo == WR_ALGO_EDGE_B0, info);
+            launch_gather_rows(1, d_off.p + o, d_picks.p, d_base.p + o, d_local.p, rows.p, V, dout, st);
+            if (pred_out) {
+                DBuf<int32_t> ptmp;
+                int32_t *pp = pred_out + static_cast<size_t>(a) * V;
+                if (!dev) {
+                    ptmp.alloc(ctx, static_cast<size_t>(P) * V);
+                    pp = ptmp.p;
+                }
+                DBuf<uint32_t> orow;
+                std::vector<uint32_t> iota(P);
+                std::iota(iota.begin(), iota.end(), 0u);
+                upload(orow, ctx, iota, st);
+                launch_pred_rows(rows.p, P, V, d_picks.p + a, g->d_in_ptr.p, g->d_in_src.p,
+                                 g->d_in_w.p, orow.p, orow.p, pp, st);
+                if (!dev)
+                    WR_HIP(hipMemcpyAsync(pred_out + static_cast<size_t>(a) * V, pp,
+                                          static_cast<size_t>(P) * V * 4, hipMemcpyDeviceToHost, st));
+            }
+        }
+        info.unique_sources = NPK;
+        info.chunks = num_orders;
+    } else {
+        if (algo == WR_ALGO_SEGMENTED) rebuild_tiles_if_needed(g);
+        Plan plan = make_plan(g, picks, NPK, true);
+        const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
+        info.unique_sources = U;
+        upload(d_sidx, ctx, plan.uidx, st);
+        const uint32_t chunk = chunk_sources(g, algo, U, graph_mode);
+        for (uint32_t lo = 0; lo < U; lo += chunk) {
+            const uint32_t n = std::min(chunk, U - lo);
+            solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info);
+            info.chunks += 1;
+            if (algo == WR_ALGO_SEGMENTED)
+                launch_gather_seg(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
+                                  workspace(g).seg->ss, dout, st);
+            else
+                launch_gather_blk(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n,
+                                  workspace(g).blk->dist.p, V, dout, st);
+            if (pred_out) {
+                // predecessor rows of the picks whose source is in this chunk,
+                // a bounded group of rows at a time
+                std::vector<uint32_t> ks;
+                for (uint32_t k = 0; k < NPK; ++k)
+                    if (plan.uidx[k] >= lo && plan.uidx[k] < lo + n) ks.push_back(k);
+                const uint32_t RG = 64;
+                DBuf<uint32_t> rtmp;
+                rtmp.alloc(ctx, static_cast<size_t>(std::min<size_t>(RG, ks.size())) * V);
+                DBuf<int32_t> ptmp;
+                if (!dev) ptmp.alloc(ctx, static_cast<size_t>(std::min<size_t>(RG, ks.size())) * V);
+                for (size_t g0 = 0; g0 < ks.size(); g0 += RG) {
+                    const uint32_t R = static_cast<uint32_t>(std::min<size_t>(RG, ks.size() - g0));
+                    std::vector<uint32_t> ridx(R), rvert(R), orow(R), prow(R);
+                    for (uint32_t r = 0; r < R; ++r) {
+                        const uint32_t k = ks[g0 + r];
+                        ridx[r] = plan.uidx[k] - lo;
+                        rvert[r] = picks[k];
+                        orow[r] = r;
+                        prow[r] = dev ? k : r;
+                    }
+                    DBuf<uint32_t> d_ridx, d_rvert, d_orow, d_prow;
+                    upload(d_ridx, ctx, ridx, st);
+                    upload(d_rvert, ctx, rvert, st);
+                    upload(d_orow, ctx, orow, st);
+                    upload(d_prow, ctx, prow, st);
+                    emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, rtmp.p);
+                    int32_t *pp = dev ? pred_out : ptmp.p;
+                    launch_pred_rows(rtmp.p, R, V, d_rvert.p, g->d_in_ptr.p, g->d_in_src.p,
+                                     g->d_in_w.p, d_orow.p, d_prow.p, pp, st);
+                    if (!dev) {
+                        std::vector<int32_t> h(static_cast<size_t>(R) * V);
+                        WR_HIP(hipMemcpyAsync(h.data(), ptmp.p, h.size() * 4, hipMemcpyDeviceToHost, st));
+                        WR_HIP(hipStreamSynchronize(st));
+                        for (uint32_t r = 0; r < R; ++r)
+                            std::memcpy(pred_out + static_cast<size_t>(ks[g0 + r]) * V,
+                                        h.data() + static_cast<size_t>(r) * V, V * 4ull);
+                    }
+                }
+                WR_HIP(hipStreamSynchronize(st));
+            }
+        }
+    }
+    if (!dev) WR_HIP(hipMemcpyAsync(dist_out, dout, static_cast<size_t>(total) * 4, hipMemcpyDeviceToHost, st));
+    WR_HIP(hipStreamSynchronize(st));
+    info.total_ms = now_ms() - t0;
+    g->last = info;
+    WR_API_END
+}
+
+wr_status wr_graph_last_run(const wr_graph *g, wr_run_info *info) {
+    WR_API_BEGIN
+    if (!g || !info) fail(WR_E_INVALID, "NULL argument");
+    *info = g->last;
+    WR_API_END
+}
+
+wr_status wr_graph_set_schedule(wr_graph *g, uint32_t tile_vertices, uint32_t waves_per_group,
+                                uint32_t passes_per_replay) {
+    WR_API_BEGIN
+    if (!g) fail(WR_E_INVALID, "graph is NULL");
+    if (tile_vertices) {
+        if (tile_vertices != 1024 && tile_vertices != 2048 && tile_vertices != 4096)
+            fail(WR_E_INVALID, "tile_vertices must be 1024, 2048 or 4096");
+        g->tile_vertices = tile_vertices;
+    }
+    if (waves_per_group) g->waves_per_group = waves_per_group;
+    const uint32_t t = g->tile_vertices, wv = g->waves_per_group;
+    const bool ok = (t == 1024 && (wv == 4 || wv == 8)) || (t == 2048 && (wv == 4 || wv == 8)) ||
+                    (t == 4096 && wv == 2);
+    if (!ok) fail(WR_E_INVALID, "unsupported (tile_vertices, waves_per_group) pair");
+    if (passes_per_replay) g->passes_per_replay = std::max(2u, passes_per_replay & ~1u);
+    destroy_workspace(g->ws);
+    g->ws = nullptr;
+    WR_API_END
+}
+
+}  // extern "C"

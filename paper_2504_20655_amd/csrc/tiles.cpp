@@ -1,0 +1,309 @@
+// Segment builder: turns a vertex -> segment map (or a grid tile spec, or an
+// automatic breadth-first partition) into LDS tiles with boundary tables.
+//
+// A segment is a vertex set chosen by the caller; its boundary vertices are
+// those with an arc to or from another segment.  The paper divides routing
+// work into sub-problems processed independently within the GPU's memory
+// (Discussion) and joins route pieces through boundary nodes (Route
+// Optimization section, Theorem).  Here a segment is further cut into tiles
+// small enough for one wave's LDS distance array; tiles are what the kernels
+// relax.  Boundary-in vertices ("ports") receive values pushed from other
+// tiles; boundary-out vertices push their cross-tile arcs.
+#include <algorithm>
+#include <memory>
+#include <numeric>
+
+#include "wr_internal.hpp"
+
+namespace wr {
+
+namespace {
+
+// Sorted unique tile list helper: split the id-ordered vertex list of one
+// segment into tiles of at most `cap` vertices whose summed out-degree stays
+// within 4*cap (the LDS arc budget of a tile).
+void cut_segment(const std::vector<uint32_t> &verts, const std::vector<uint32_t> &row_ptr,
+                 uint32_t cap, std::vector<uint32_t> &tile_of, uint32_t &T) {
+    uint32_t n = 0;
+    uint64_t arcs = 0;
+    bool open = false;
+    for (uint32_t v : verts) {
+        const uint32_t deg = row_ptr[v + 1] - row_ptr[v];
+        if (!open || n + 1 > cap || arcs + deg > 4ull * cap) {
+            ++T;
+            n = 0;
+            arcs = 0;
+            open = true;
+        }
+        tile_of[v] = T - 1;
+        ++n;
+        arcs += deg;
+    }
+}
+
+}  // namespace
+
+void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, bool bfs_grow) {
+    const uint32_t V = g->V;
+    const auto &row_ptr = g->row_ptr;
+    const auto &col = g->col;
+    const auto &w = g->w;
+
+    // incident vertices
+    std::vector<uint8_t> inc(V, 0);
+    for (uint32_t u = 0; u < V; ++u)
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            inc[u] = 1;
+            inc[col[e]] = 1;
+        }
+    for (uint32_t u = 0; u < V; ++u)
+        if (row_ptr[u + 1] - row_ptr[u] > 4ull * cap)
+            fail(WR_E_UNSUPPORTED, "a vertex has more out-arcs than one LDS tile holds");
+
+    auto ts = std::make_unique<TileSet>();
+    ts->tile_cap = cap;
+    ts->tile_of.assign(V, NONE);
+    uint32_t T = 0;
+    if (bfs_grow) {
+        // undirected adjacency through out- and in-arcs
+        std::vector<uint32_t> in_ptr(V + 1, 0), in_src(g->E);
+        for (uint32_t e = 0; e < g->E; ++e) in_ptr[col[e] + 1]++;
+        for (uint32_t v = 0; v < V; ++v) in_ptr[v + 1] += in_ptr[v];
+        {
+            std::vector<uint32_t> fill(in_ptr.begin(), in_ptr.end() - 1);
+            for (uint32_t u = 0; u < V; ++u)
+                for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) in_src[fill[col[e]]++] = u;
+        }
+        std::vector<uint32_t> queue;
+        queue.reserve(cap);
+        for (uint32_t s = 0; s < V; ++s) {
+            if (!inc[s] || ts->tile_of[s] != NONE) continue;
+            const uint32_t t = T++;
+            uint32_t n = 0;
+            uint64_t arcs = 0;
+            queue.clear();
+            queue.push_back(s);
+            ts->tile_of[s] = t;
+            n = 1;
+            arcs = row_ptr[s + 1] - row_ptr[s];
+            for (size_t h = 0; h < queue.size(); ++h) {
+                const uint32_t u = queue[h];
+                auto try_add = [&](uint32_t x) {
+                    if (n >= cap || ts->tile_of[x] != NONE || !inc[x]) return;
+                    const uint32_t deg = row_ptr[x + 1] - row_ptr[x];
+                    if (arcs + deg > 4ull * cap) return;
+                    ts->tile_of[x] = t;
+                    ++n;
+                    arcs += deg;
+                    queue.push_back(x);
+                };
+                for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) try_add(col[e]);
+                for (uint32_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) try_add(in_src[e]);
+            }
+        }
+        ts->num_segments = T;
+    } else {
+        // bucket incident vertices by segment, id order inside a segment
+        std::vector<uint32_t> cnt(nseg + 1, 0);
+        for (uint32_t v = 0; v < V; ++v)
+            if (inc[v]) cnt[seg[v] + 1]++;
+        for (uint32_t s = 0; s < nseg; ++s) cnt[s + 1] += cnt[s];
+        std::vector<uint32_t> order(cnt[nseg]);
+        {
+            std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
+            for (uint32_t v = 0; v < V; ++v)
+                if (inc[v]) order[fill[seg[v]]++] = v;
+        }
+        std::vector<uint32_t> verts;
+        for (uint32_t s = 0; s < nseg; ++s) {
+            verts.assign(order.begin() + cnt[s], order.begin() + cnt[s + 1]);
+            cut_segment(verts, row_ptr, cap, ts->tile_of, T);
+        }
+        ts->num_segments = nseg;
+    }
+    ts->T = T;
+
+    // positions: tile by tile, ascending vertex id inside a tile
+    std::vector<uint32_t> tsize(T + 1, 0);
+    for (uint32_t v = 0; v < V; ++v)
+        if (ts->tile_of[v] != NONE) tsize[ts->tile_of[v] + 1]++;
+    for (uint32_t t = 0; t < T; ++t) tsize[t + 1] += tsize[t];
+    ts->tile_base = tsize;
+    const uint32_t Vt = tsize[T];
+    ts->Vt = Vt;
+    ts->pos_of.assign(V, NONE);
+    ts->vert_of.resize(Vt);
+    {
+        std::vector<uint32_t> fill(tsize.begin(), tsize.end() - 1);
+        for (uint32_t v = 0; v < V; ++v) {
+            const uint32_t t = ts->tile_of[v];
+            if (t == NONE) continue;
+            const uint32_t p = fill[t]++;
+            ts->pos_of[v] = p;
+            ts->vert_of[p] = v;
+        }
+    }
+
+    // ports (boundary-in) and boundary-out vertices
+    std::vector<uint8_t> is_port(Vt, 0), is_bout(Vt, 0);
+    uint64_t cross = 0;
+    for (uint32_t u = 0; u < V; ++u) {
+        const uint32_t tu = ts->tile_of[u];
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const uint32_t x = col[e];
+            if (ts->tile_of[x] != tu) {
+                is_port[ts->pos_of[x]] = 1;
+                is_bout[ts->pos_of[u]] = 1;
+                ++cross;
+            }
+        }
+    }
+    ts->cross_arcs = cross;
+    std::vector<uint32_t> port_id(Vt, NONE);
+    ts->port_base.assign(T + 1, 0);
+    ts->bo_base.assign(T + 1, 0);
+    for (uint32_t t = 0; t < T; ++t) {
+        ts->port_base[t + 1] = ts->port_base[t];
+        ts->bo_base[t + 1] = ts->bo_base[t];
+        for (uint32_t p = tsize[t]; p < tsize[t + 1]; ++p) {
+            if (is_port[p]) {
+                port_id[p] = ts->port_base[t + 1]++;
+                ts->port_local.push_back(p - tsize[t]);
+            }
+            if (is_bout[p]) {
+                ts->bo_base[t + 1]++;
+                ts->bo_local.push_back(p - tsize[t]);
+            }
+        }
+    }
+    ts->NP = ts->port_base[T];
+    ts->NB = ts->bo_base[T];
+
+    // per-position arc lists
+    ts->l_off.assign(Vt + 1, 0);
+    ts->x_off.assign(Vt + 1, 0);
+    ts->arc_slot.assign(g->E, NONE);
+    for (uint32_t p = 0; p < Vt; ++p) {
+        const uint32_t u = ts->vert_of[p];
+        const uint32_t tu = ts->tile_of[u];
+        uint32_t nl = 0, nx = 0;
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) (ts->tile_of[col[e]] == tu ? nl : nx)++;
+        ts->l_off[p + 1] = ts->l_off[p] + nl;
+        ts->x_off[p + 1] = ts->x_off[p] + nx;
+    }
+    ts->l_arc.resize(ts->l_off[Vt]);
+    ts->x_port.resize(ts->x_off[Vt]);
+    ts->x_w.resize(ts->x_off[Vt]);
+    ts->x_tile.resize(ts->x_off[Vt]);
+    for (uint32_t p = 0; p < Vt; ++p) {
+        const uint32_t u = ts->vert_of[p];
+        const uint32_t tu = ts->tile_of[u];
+        uint32_t li = ts->l_off[p], xi = ts->x_off[p];
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const uint32_t x = col[e];
+            const uint32_t tx = ts->tile_of[x];
+            if (tx == tu) {
+                const uint32_t loc = ts->pos_of[x] - tsize[tu];
+                ts->l_arc[li] = (loc << 16) | (w[e] & 0xFFFFu);
+                ts->arc_slot[e] = li++;
+            } else {
+                ts->x_port[xi] = port_id[ts->pos_of[x]];
+                ts->x_w[xi] = w[e];
+                ts->x_tile[xi] = tx;
+                ts->arc_slot[e] = 0x80000000u | xi++;
+            }
+        }
+    }
+    for (uint32_t t = 0; t < T; ++t)
+        if (ts->l_off[tsize[t + 1]] - ts->l_off[tsize[t]] > 4ull * cap)
+            fail(WR_E_INTERNAL, "tile arc budget exceeded");
+
+    // upload
+    wr_context *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    upload(ts->d_tile_of, ctx, ts->tile_of, st);
+    upload(ts->d_pos_of, ctx, ts->pos_of, st);
+    upload(ts->d_tile_base, ctx, ts->tile_base, st);
+    upload(ts->d_l_off, ctx, ts->l_off, st);
+    upload(ts->d_l_arc, ctx, ts->l_arc, st);
+    upload(ts->d_x_off, ctx, ts->x_off, st);
+    upload(ts->d_x_port, ctx, ts->x_port, st);
+    upload(ts->d_x_w, ctx, ts->x_w, st);
+    upload(ts->d_x_tile, ctx, ts->x_tile, st);
+    upload(ts->d_port_base, ctx, ts->port_base, st);
+    upload(ts->d_port_local, ctx, ts->port_local, st);
+    upload(ts->d_bo_base, ctx, ts->bo_base, st);
+    upload(ts->d_bo_local, ctx, ts->bo_local, st);
+    upload(ts->d_arc_slot, ctx, ts->arc_slot, st);
+    WR_HIP(hipStreamSynchronize(st));
+    destroy_workspace(g->ws);
+    g->ws = nullptr;
+    delete g->tiles;
+    g->tiles = ts.release();
+    g->tiles_gen += 1;
+}
+
+void rebuild_tiles_if_needed(wr_graph *g) {
+    if (g->tiles && g->tiles->tile_cap == g->tile_vertices) return;
+    if (g->tiles_user)
+        build_tiles(g, g->user_seg.data(), g->user_num_segments, g->tile_vertices, false);
+    else
+        build_tiles(g, nullptr, 0, g->tile_vertices, true);
+}
+
+}  // namespace wr
+
+using namespace wr;
+
+extern "C" {
+
+wr_status wr_graph_set_segments(wr_graph *g, const uint32_t *segment_of_vertex,
+                                uint32_t num_segments) {
+    WR_API_BEGIN
+    if (!g || !segment_of_vertex) fail(WR_E_INVALID, "NULL argument");
+    if (num_segments == 0) fail(WR_E_INVALID, "num_segments must be positive");
+    for (uint32_t v = 0; v < g->V; ++v)
+        if (segment_of_vertex[v] >= num_segments) fail(WR_E_INVALID, "segment id out of range");
+    WR_HIP(hipSetDevice(g->ctx->device));
+    std::vector<uint32_t> seg(segment_of_vertex, segment_of_vertex + g->V);
+    build_tiles(g, seg.data(), num_segments, g->tile_vertices, false);
+    g->user_seg.swap(seg);
+    g->user_num_segments = num_segments;
+    g->tiles_user = true;
+    WR_API_END
+}
+
+wr_status wr_graph_segment_grid(wr_graph *g, uint32_t W, uint32_t H, uint32_t levels,
+                                uint32_t tile_w, uint32_t tile_h) {
+    WR_API_BEGIN
+    if (!g) fail(WR_E_INVALID, "graph is NULL");
+    if (!W || !H || !levels || !tile_w || !tile_h) fail(WR_E_INVALID, "sizes must be positive");
+    if (static_cast<uint64_t>(W) * H * levels != g->V) fail(WR_E_INVALID, "W*H*levels != V");
+    const uint32_t tx = (W + tile_w - 1) / tile_w, ty = (H + tile_h - 1) / tile_h;
+    const uint64_t nseg = static_cast<uint64_t>(tx) * ty * levels;
+    if (nseg >= 0xFFFFFFFFull) fail(WR_E_INVALID, "too many segments");
+    std::vector<uint32_t> seg(g->V);
+    for (uint32_t l = 0; l < levels; ++l)
+        for (uint32_t y = 0; y < H; ++y)
+            for (uint32_t x = 0; x < W; ++x)
+                seg[(static_cast<size_t>(l) * H + y) * W + x] = (l * ty + y / tile_h) * tx + x / tile_w;
+    WR_HIP(hipSetDevice(g->ctx->device));
+    build_tiles(g, seg.data(), static_cast<uint32_t>(nseg), g->tile_vertices, false);
+    g->user_seg.swap(seg);
+    g->user_num_segments = static_cast<uint32_t>(nseg);
+    g->tiles_user = true;
+    WR_API_END
+}
+
+wr_status wr_graph_segment_info(const wr_graph *g, uint32_t *num_segments, uint32_t *num_tiles,
+                                uint32_t *num_boundary) {
+    WR_API_BEGIN
+    if (!g) fail(WR_E_INVALID, "graph is NULL");
+    const TileSet *ts = g->tiles;
+    if (num_segments) *num_segments = ts ? ts->num_segments : 0;
+    if (num_tiles) *num_tiles = ts ? ts->T : 0;
+    if (num_boundary) *num_boundary = ts ? ts->NP : 0;
+    WR_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// Internal declarations of the routing library: device buffers, graph and
+// tile tables, work plans and the kernel launchers implemented in
+// kernels.hip.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <new>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wroute.h"
+
+namespace wr {
+
+constexpr uint32_t INF = 0xFFFFFFFFu;
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr uint32_t LANES = 64;            // CDNA wavefront width; also S_b of the blocked layout
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    wr_status st;
+    std::string msg;
+};
+[[noreturn]] void fail(wr_status st, const std::string &msg);
+void set_last_error(const std::string &msg);
+void clear_last_error();
+
+#define WR_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            ::wr::fail(WR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Fault injection for host-forced failure tests: WR_FAULT="alloc:N" fails the
+// N-th device allocation, "launch:N" the N-th kernel launch (1-based, counted
+// per process).
+bool fault_alloc_now();
+bool fault_launch_now();
+void check_launch(const char *what);
+
+}  // namespace wr
+
+// Every ABI entry point runs its body between these: errors thrown as
+// wr::Error become the returned status plus the thread-local message.
+#define WR_API_BEGIN try { ::wr::clear_last_error();
+#define WR_API_END                                         \
+    return WR_OK;                                          \
+    }                                                      \
+    catch (const ::wr::Error &e) {                         \
+        ::wr::set_last_error(e.msg);                       \
+        return e.st;                                       \
+    }                                                      \
+    catch (const std::bad_alloc &) {                       \
+        ::wr::set_last_error("host allocation failed");    \
+        return WR_E_NOMEM;                                 \
+    }                                                      \
+    catch (...) {                                          \
+        ::wr::set_last_error("unexpected exception");      \
+        return WR_E_INTERNAL;                              \
+    }
+
+// ----------------------------------------------------------------- context
+struct wr_context {
+    int device = 0;
+    int num_cus = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    hipStream_t stream = nullptr;   // internal stream for host-pointer calls
+
+    void *alloc(size_t bytes);      // throws WR_E_NOMEM / WR_E_DEVICE
+    void release(void *p, size_t bytes);
+    uint64_t available() const { return used.load() >= budget ? 0 : budget - used.load(); }
+};
+
+namespace wr {
+
+// Device buffer owned by a context; freed on destruction.
+template <class T>
+struct DBuf {
+    wr_context *ctx = nullptr;
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept { *this = std::move(o); }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) {
+            reset();
+            ctx = o.ctx; p = o.p; n = o.n;
+            o.ctx = nullptr; o.p = nullptr; o.n = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void alloc(wr_context *c, size_t count) {
+        reset();
+        ctx = c;
+        n = count;
+        p = count ? static_cast<T *>(c->alloc(count * sizeof(T))) : nullptr;
+    }
+    void reset() {
+        if (p && ctx) ctx->release(p, n * sizeof(T));
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+template <class T>
+void upload(DBuf<T> &d, wr_context *ctx, const std::vector<T> &h, hipStream_t st) {
+    d.alloc(ctx, h.size());
+    if (!h.empty()) WR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+// ---------------------------------------------------------- LDS tile tables
+// A segmentation turned into LDS tiles.  Tiled vertices (those incident to at
+// least one arc) are renumbered tile by tile into "positions" 0..Vt-1;
+// position = tile_base[t] + local index, local index < tile size.
+struct TileSet {
+    uint32_t num_segments = 0;
+    uint32_t T = 0;               // tiles
+    uint32_t Vt = 0;              // tiled vertices
+    uint32_t NP = 0;              // ports: boundary-in vertices (an arc from another tile ends there)
+    uint32_t NB = 0;              // boundary-out vertices (an arc to another tile starts there)
+    uint32_t tile_cap = 0;        // maximum tile size the tables were built for
+    uint64_t cross_arcs = 0;
+
+    // host copies
+    std::vector<uint32_t> tile_of;      // [V]  tile or NONE
+    std::vector<uint32_t> pos_of;       // [V]  position or NONE
+    std::vector<uint32_t> vert_of;      // [Vt] vertex of a position
+    std::vector<uint32_t> tile_base;    // [T+1]
+    std::vector<uint32_t> l_off;        // [Vt+1] in-tile out-arc offsets
+    std::vector<uint32_t> l_arc;        // packed (local dst << 16) | w   (w < 65536)
+    std::vector<uint32_t> x_off;        // [Vt+1] cross-tile out-arc offsets
+    std::vector<uint32_t> x_port;       // target port
+    std::vector<uint32_t> x_w;          // weight
+    std::vector<uint32_t> x_tile;       // target tile
+    std::vector<uint32_t> port_base;    // [T+1]
+    std::vector<uint32_t> port_local;   // local index of each port in its tile
+    std::vector<uint32_t> bo_base;      // [T+1]
+    std::vector<uint32_t> bo_local;     // local index of each boundary-out vertex
+    std::vector<uint32_t> arc_slot;     // [E] where CSR arc e lives: l_arc index, or 0x80000000|x index
+
+    // device copies
+    DBuf<uint32_t> d_tile_of, d_pos_of, d_tile_base, d_l_off, d_l_arc, d_x_off, d_x_port, d_x_w,
+        d_x_tile, d_port_base, d_port_local, d_bo_base, d_bo_local, d_arc_slot;
+};
+
+}  // namespace wr
+
+namespace wr {
+struct Workspace;
+void destroy_workspace(Workspace *ws);
+}  // namespace wr
+
+// ------------------------------------------------------------------- graph
+struct wr_graph {
+    wr_context *ctx = nullptr;
+    uint32_t V = 0, E = 0;
+    uint32_t n_incident = 0;   // vertices incident to an arc (overflow bound)
+    std::vector<uint32_t> row_ptr, col, w;   // host mirror at the current epoch
+    std::vector<uint32_t> in_pos_of_arc;     // [E] position of arc e in the in-CSR
+    uint64_t epoch = 0;
+    uint32_t max_w = 0;
+    uint64_t zero_w = 0;       // number of arcs with weight 0
+
+    wr::DBuf<uint32_t> d_row_ptr, d_col, d_w;          // out-CSR
+    wr::DBuf<uint32_t> d_in_ptr, d_in_src, d_in_w;     // in-CSR (pull)
+    wr::DBuf<uint32_t> d_in_pos_of_arc;
+    wr::DBuf<uint32_t> d_arc_src;                      // [E] tail of each arc (edge-list baseline), lazy
+
+    wr::TileSet *tiles = nullptr;
+    uint64_t tiles_gen = 0;            // bumped whenever `tiles` is rebuilt
+    wr::Workspace *ws = nullptr;       // cached per-call work buffers and captured graphs
+    bool tiles_user = false;           // segmentation given by the caller
+    std::vector<uint32_t> user_seg;    // caller's segment map (rebuilt on tile-size change)
+    uint32_t user_num_segments = 0;
+
+    // schedule
+    uint32_t tile_vertices = 2048;
+    uint32_t waves_per_group = 4;
+    uint32_t sources_per_unit = 0;     // 0 = 4 * waves_per_group
+    uint32_t passes_per_replay = 8;
+
+    wr_run_info last{};
+    ~wr_graph();
+};
+
+namespace wr {
+
+// -------------------------------------------------------- kernel launchers
+// (kernels.hip)  All enqueue on `st`.
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+void launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);
+
+// blocked layout dist[b][v][64]: source 64*b + l of a chunk at vertex v
+void launch_blk_seed(uint32_t *dist, uint32_t V, uint32_t S, const uint32_t *src, hipStream_t st);
+void launch_sweep_pull(uint32_t *dist, uint32_t V, uint32_t nb, const uint32_t *in_ptr,
+                       const uint32_t *in_src, const uint32_t *in_w, uint32_t *changed,
+                       uint32_t grid, hipStream_t st);
+// frontier items are (block << 32 | vertex); stamps[b*V+v] = pass stamp when queued
+void launch_frontier_seed(uint64_t *list, uint32_t *count, uint32_t S, const uint32_t *src,
+                          uint32_t V, hipStream_t st);
+void launch_frontier_push(uint32_t *dist, uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                          const uint32_t *w, const uint64_t *list_in, const uint32_t *count_in,
+                          uint64_t *list_out, uint32_t *count_out, uint32_t *stamps,
+                          const uint32_t *pass_ctr, uint32_t grid, hipStream_t st);
+// zero count_next, add count_cur into stats[0], (count_cur > 0) into stats[1], ++pass_ctr
+void launch_pass_prologue(uint32_t *count_next, const uint32_t *count_cur,
+                          unsigned long long *stats, uint32_t *pass_ctr, hipStream_t st);
+// row r of the chunk state (source row_src_idx[r]) goes to out + out_row[r]*V
+void launch_blk_emit(const uint32_t *dist, uint32_t V, uint32_t rows, const uint32_t *row_src_idx,
+                     const uint32_t *out_row, uint32_t *out, hipStream_t st);
+
+// segmented schedule: device state of one chunk of S sources
+struct SegState {
+    uint32_t S = 0;
+    uint32_t *gdist = nullptr;      // [S][Vt]
+    uint32_t *inbox = nullptr;      // [S][NP]
+    uint8_t *visited = nullptr;     // [S][T]
+    uint32_t *stamps = nullptr;     // [S][T]
+    uint32_t *cnt = nullptr;        // [2][T]
+    uint32_t *bucket = nullptr;     // [2][T][S]
+    uint32_t *tiles = nullptr;      // [2][T]
+    uint32_t *ntiles = nullptr;     // [2]
+    uint2 *units = nullptr;         // [max units]
+    uint32_t *nunits = nullptr;     // [1]
+    uint32_t *cursor = nullptr;     // [1]
+    uint32_t *pass_ctr = nullptr;   // [1]
+    unsigned long long *stats = nullptr;   // [2]: items, passes with work
+    const uint32_t *src_pos = nullptr;     // [S] position or NONE
+    const uint32_t *src_tile = nullptr;    // [S] tile or NONE
+};
+// activates (s, tile of source s) for the chunk's sources s < n
+void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
+// one pass: prologue (zero next counters) + plan (units) + relaxation
+void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t tile_cap,
+                     uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st);
+uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves);
+void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t rows,
+                     const uint32_t *row_src_idx, const uint32_t *row_src_vertex,
+                     const uint32_t *out_row, uint32_t *out, hipStream_t st);
+
+// order gathers: out[out_base[o] + i*P + j] = d(p_i, p_j)
+void launch_gather_rows(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                        const uint64_t *out_base, const uint32_t *row_of_pick, const uint32_t *rows,
+                        uint32_t V, uint32_t *out, hipStream_t st);
+void launch_gather_blk(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                       const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
+                       uint32_t chunk_n, const uint32_t *dist, uint32_t V, uint32_t *out,
+                       hipStream_t st);
+void launch_gather_seg(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                       const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
+                       uint32_t chunk_n, const TileSet &ts, const SegState &ss, uint32_t *out,
+                       hipStream_t st);
+
+// canonical predecessor: row r is read at rows + in_row[r]*V and written at
+// pred + out_row[r]*V
+void launch_pred_rows(const uint32_t *rows, uint32_t nrows, uint32_t V, const uint32_t *row_src_vertex,
+                      const uint32_t *in_ptr, const uint32_t *in_src, const uint32_t *in_w,
+                      const uint32_t *in_row, const uint32_t *out_row, int32_t *pred, hipStream_t st);
+
+// paper-structured edge-list baseline: dist[N][V] in place, one thread per arc
+void launch_edge_round(const uint32_t *arc_src, const uint32_t *col, const uint32_t *w, uint32_t E,
+                       uint32_t *dist, uint32_t V, uint32_t N, uint32_t *changed, hipStream_t st);
+void launch_rows_seed(uint32_t *dist, uint32_t V, uint32_t N, const uint32_t *src, hipStream_t st);
+void launch_arc_src(const uint32_t *row_ptr, uint32_t V, uint32_t *arc_src, hipStream_t st);
+
+// weight epochs: apply (arc, w) pairs to every weight array of the graph
+void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww, uint32_t *w,
+                           uint32_t *in_w, const uint32_t *in_pos, uint32_t *l_arc, uint32_t *x_w,
+                           const uint32_t *arc_slot, hipStream_t st);
+
+// --------------------------------------------------------------- host side
+void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t tile_cap,
+                 bool bfs_grow);
+void rebuild_tiles_if_needed(wr_graph *g);
+
+}  // namespace wr

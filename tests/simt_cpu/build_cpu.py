@@ -1,0 +1,41 @@
+"""Builds the CPU-executor driver (library sources + simt runtime) with
+AddressSanitizer -- TEST INFRASTRUCTURE ONLY.  Output:
+tests/simt_cpu/_build/wr_cpu_driver."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2504_20655_amd", "csrc")
+OUT = os.path.join(HERE, "_build", "wr_cpu_driver")
+LIB_SOURCES = ["kernels.hip", "runtime.cpp", "tiles.cpp", "solve.cpp", "server.cpp"]
+
+
+def build(sanitize: bool = True) -> str:
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    san = ["-fsanitize=address", "-fno-omit-frame-pointer"] if sanitize else []
+    flags = ["-std=c++20", "-O1", "-g", "-pthread", "-w", *san,
+             "-I", HERE, "-I", os.path.join(ROOT, "include")]
+    objs = []
+    procs = []
+    for src in LIB_SOURCES + ["../../tests/simt_cpu/simt_runtime.cpp", "../../tests/simt_cpu/driver.cpp"]:
+        path = os.path.normpath(os.path.join(CSRC, src))
+        if not os.path.exists(path):
+            continue
+        obj = os.path.join(os.path.dirname(OUT), os.path.basename(src) + ".o")
+        cmd = ["g++", "-x", "c++", *flags, "-c", path, "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"{src}:\n{out}")
+    r = subprocess.run(["g++", *san, "-pthread", "-o", OUT, *objs], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(r.stdout + r.stderr)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(sanitize="--no-asan" not in sys.argv))

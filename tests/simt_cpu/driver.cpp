@@ -1,0 +1,79 @@
+// Runs one wr_sssp / wr_order_matrices request read from a file through the
+// C ABI under the CPU executor -- TEST INFRASTRUCTURE ONLY.
+//   wr_cpu_driver <request.bin> <result.bin>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "wroute.h"
+
+static std::vector<uint32_t> g_in;
+static size_t g_pos = 0;
+static uint32_t rd() { return g_in.at(g_pos++); }
+static std::vector<uint32_t> rdv(size_t n) {
+    std::vector<uint32_t> v(g_in.begin() + g_pos, g_in.begin() + g_pos + n);
+    g_pos += n;
+    return v;
+}
+
+int main(int argc, char **argv) {
+    if (argc != 3) return 2;
+    FILE *f = std::fopen(argv[1], "rb");
+    if (!f) return 2;
+    uint32_t x;
+    while (std::fread(&x, 4, 1, f) == 1) g_in.push_back(x);
+    std::fclose(f);
+    if (rd() != 0x57524F55u) return 2;
+    const uint32_t mode = rd(), flags = rd(), want_pred = rd();
+    const uint32_t V = rd(), E = rd();
+    auto row_ptr = rdv(V + 1), col = rdv(E), w = rdv(E);
+    wr_context *ctx = nullptr;
+    wr_graph *g = nullptr;
+    std::vector<uint32_t> out;
+    std::vector<int32_t> pred;
+    wr_status st = wr_context_create(0, 0, &ctx);
+    if (st == WR_OK) st = wr_graph_create_csr(ctx, V, E, row_ptr.data(), col.data(), w.data(), 0, &g);
+    const uint32_t seg_mode = rd();
+    if (seg_mode == 1) {
+        const uint32_t W = rd(), H = rd(), L = rd(), tw = rd(), th = rd();
+        if (st == WR_OK) st = wr_graph_segment_grid(g, W, H, L, tw, th);
+    } else if (seg_mode == 2) {
+        const uint32_t ns = rd();
+        auto m = rdv(V);
+        if (st == WR_OK) st = wr_graph_set_segments(g, m.data(), ns);
+    }
+    const uint32_t tv = rd(), wv = rd(), kp = rd();
+    if (st == WR_OK && (tv || wv || kp)) st = wr_graph_set_schedule(g, tv, wv, kp);
+    const uint32_t nup = rd();
+    auto ua = rdv(nup), uv = rdv(nup);
+    if (st == WR_OK && nup) st = wr_graph_update_weights(g, nup, ua.data(), uv.data(), nullptr);
+    if (mode == 0) {
+        const uint32_t S = rd();
+        auto src = rdv(S);
+        out.assign(static_cast<size_t>(S) * V, 0);
+        if (want_pred) pred.assign(static_cast<size_t>(S) * V, 0);
+        if (st == WR_OK)
+            st = wr_sssp(g, S, src.data(), out.data(), want_pred ? pred.data() : nullptr, flags, nullptr);
+    } else {
+        const uint32_t no = rd();
+        auto off = rdv(no + 1);
+        auto picks = rdv(off[no]);
+        size_t total = 0;
+        for (uint32_t o = 0; o < no; ++o) total += static_cast<size_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
+        out.assign(total, 0);
+        if (want_pred) pred.assign(static_cast<size_t>(off[no]) * V, 0);
+        if (st == WR_OK)
+            st = wr_order_matrices(g, no, off.data(), picks.data(), out.data(),
+                                   want_pred ? pred.data() : nullptr, flags, nullptr);
+    }
+    if (st != WR_OK) std::fprintf(stderr, "status %s: %s\n", wr_status_str(st), wr_last_error());
+    FILE *o = std::fopen(argv[2], "wb");
+    const uint32_t s32 = st;
+    std::fwrite(&s32, 4, 1, o);
+    std::fwrite(out.data(), 4, out.size(), o);
+    if (!pred.empty()) std::fwrite(pred.data(), 4, pred.size(), o);
+    std::fclose(o);
+    wr_graph_destroy(g);
+    wr_context_destroy(ctx);
+    return 0;
+}

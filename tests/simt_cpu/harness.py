@@ -1,0 +1,69 @@
+"""Runs ABI requests through the CPU-executor driver -- TEST INFRASTRUCTURE.
+
+The request format is a flat little-endian uint32 stream read by driver.cpp.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+from tests.simt_cpu.build_cpu import OUT, build
+
+ALGO = {"auto": 0x00, "sweep": 0x10, "frontier": 0x20, "segmented": 0x30,
+        "edge_b1": 0x40, "edge_b0": 0x50}
+NO_GRAPH_CAPTURE = 0x100
+
+
+def driver(rebuild=False) -> str:
+    if rebuild or not os.path.exists(OUT):
+        build()
+    return OUT
+
+
+def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="auto",
+        pred=False, graph_capture=True, seg=None, schedule=(0, 0, 0), updates=None, timeout=600):
+    """seg: None | ("grid", W, H, L, tw, th) | ("map", nseg, map).  Returns
+    (status, out, pred_or_None, stderr)."""
+    V = len(row_ptr) - 1
+    E = len(col)
+    parts = [np.asarray([0x57524F55, 0 if sources is not None else 1,
+                         ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE),
+                         1 if pred else 0, V, E], np.uint32),
+             np.asarray(row_ptr, np.uint32), np.asarray(col, np.uint32), np.asarray(w, np.uint32)]
+    if seg is None:
+        parts.append(np.asarray([0], np.uint32))
+    elif seg[0] == "grid":
+        parts.append(np.asarray([1, *seg[1:]], np.uint32))
+    else:
+        parts.append(np.asarray([2, seg[1]], np.uint32))
+        parts.append(np.asarray(seg[2], np.uint32))
+    parts.append(np.asarray(schedule, np.uint32))
+    ua, uv = updates if updates is not None else (np.zeros(0), np.zeros(0))
+    parts.append(np.asarray([len(ua)], np.uint32))
+    parts.append(np.asarray(ua, np.uint32))
+    parts.append(np.asarray(uv, np.uint32))
+    if sources is not None:
+        src = np.asarray(sources, np.uint32)
+        parts += [np.asarray([len(src)], np.uint32), src]
+        n_out = len(src) * V
+        n_pred = len(src) * V if pred else 0
+    else:
+        off = np.asarray(pick_offsets, np.uint32)
+        pk = np.asarray(picks, np.uint32)
+        parts += [np.asarray([len(off) - 1], np.uint32), off, pk]
+        sizes = np.diff(off.astype(np.int64))
+        n_out = int((sizes ** 2).sum())
+        n_pred = len(pk) * V if pred else 0
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
+        np.concatenate(parts).astype(np.uint32).tofile(fin)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+        r = subprocess.run([driver(), fin, fout], capture_output=True, text=True, timeout=timeout, env=env)
+        if r.returncode != 0 or not os.path.exists(fout):
+            raise RuntimeError(f"driver failed rc={r.returncode}\n{r.stderr[-6000:]}")
+        res = np.fromfile(fout, dtype=np.uint32)
+    status = int(res[0])
+    out = res[1:1 + n_out]
+    p = res[1 + n_out:1 + n_out + n_pred].view(np.int32) if pred and status == 0 else None
+    return status, out, p, r.stderr

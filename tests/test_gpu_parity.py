@@ -1,0 +1,174 @@
+"""GPU parity: every schedule of the HIP path against the CPU oracle,
+element by element (integer distances: bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import random_csr
+from wgen import make_config
+
+pytestmark = pytest.mark.gpu
+ALGOS = ["segmented", "frontier", "sweep", "edge_b1"]
+INF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def ctx(rt):
+    return rt.Context(0)
+
+
+def _graph(rt, ctx, row_ptr, col, w):
+    return rt.Graph(ctx, row_ptr, col, w)
+
+
+@pytest.mark.parametrize("algo", ALGOS + ["edge_b0"])
+def test_tiny_order_matrix(rt, ctx, algo):
+    wl = make_config("tiny")
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    got = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    assert got.dtype == np.uint32 and (got == exp).all()
+    assert G.last_run()["algo"] == algo
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("seed", range(4))
+def test_random_graph_sssp(rt, ctx, algo, seed):
+    rng = np.random.default_rng(500 + seed)
+    V = 300 + 37 * seed
+    rp, col, w = random_csr(rng, V, 4 * V, wmax=60, zero_frac=0.1 if seed % 2 else 0.0)
+    G = _graph(rt, ctx, rp, col, w)
+    src = rng.choice(V, 70, replace=False).astype(np.uint32)
+    src = np.concatenate([src, src[:5]])            # duplicates
+    got = G.sssp(src, algo=algo)
+    exp = oracle.dijkstra_multi(rp, col, w, src)
+    assert (got == exp).all()
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_pred_matches_canonical(rt, ctx, algo):
+    rng = np.random.default_rng(9)
+    V = 400
+    rp, col, w = random_csr(rng, V, 5 * V, wmax=4)          # many ties
+    G = _graph(rt, ctx, rp, col, w)
+    src = rng.choice(V, 20, replace=False).astype(np.uint32)
+    d, p = G.sssp(src, pred=True, algo=algo)
+    for i, s in enumerate(src):
+        ed = oracle.dijkstra(rp, col, w, int(s))
+        assert (d[i] == ed).all()
+        assert (p[i] == oracle.canonical_pred(rp, col, w, int(s), ed)).all()
+        assert oracle.certificate(rp, col, w, int(s), d[i], p[i]) == 0
+
+
+def test_pred_refused_with_zero_weights(rt, ctx):
+    rp = np.asarray([0, 1, 2], np.uint32)
+    G = _graph(rt, ctx, rp, np.asarray([1, 0], np.uint32), np.asarray([0, 3], np.uint32))
+    with pytest.raises(rt.WrError) as ei:
+        G.sssp([0], pred=True)
+    assert ei.value.name == "WR_E_UNSUPPORTED"
+    assert (G.sssp([0]) == np.asarray([[0, 0]], np.uint32)).all()
+
+
+@pytest.mark.parametrize("seg", ["grid32", "grid_rect", "bfs", "user_map"])
+def test_medium_slice_segmented(rt, ctx, seg):
+    wl = make_config("medium", side=128, num_orders=12)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    if seg == "grid32":
+        G.segment_grid(g.W, g.H, 1, 32, 32)
+    elif seg == "grid_rect":
+        G.segment_grid(g.W, g.H, 1, 64, 40)          # ragged last row of tiles
+    elif seg == "user_map":
+        rng = np.random.default_rng(3)
+        G.set_segments(rng.integers(0, 7, g.V).astype(np.uint32), 7)   # scattered segments
+    got = G.order_matrices(wl.pick_offsets, wl.picks, algo="segmented")
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    assert (got == exp).all()
+    info = G.segment_info()
+    assert info["tiles"] >= 1
+
+
+def test_medium_slice_frontier_and_sweep_agree(rt, ctx):
+    wl = make_config("medium", side=96, num_orders=6)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    for algo in ("frontier", "sweep", "segmented"):
+        assert (G.order_matrices(wl.pick_offsets, wl.picks, algo=algo) == exp).all(), algo
+
+
+def test_edge_cases(rt, ctx):
+    wl = make_config("tiny")
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    blocked = int(np.flatnonzero(g.blocked.ravel())[0])
+    a, b = int(wl.picks[0]), int(wl.picks[1])
+    # empty order, duplicates, an order on a blocked (isolated) cell
+    off = np.asarray([0, 0, 3, 5, 6], np.uint32)
+    picks = np.asarray([a, b, a, blocked, a, blocked], np.uint32)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, off, picks)
+    for algo in ALGOS:
+        got = G.order_matrices(off, picks, algo=algo)
+        assert (got == exp).all(), algo
+    # isolated source row: 0 at itself, INF elsewhere
+    for algo in ALGOS:
+        d = G.sssp([blocked], algo=algo)[0]
+        assert d[blocked] == 0 and (np.delete(d, blocked) == INF).all()
+
+
+def test_single_vertex_and_no_arcs(rt, ctx):
+    G = _graph(rt, ctx, np.asarray([0, 0], np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    for algo in ALGOS:
+        assert (G.sssp([0, 0], algo=algo) == 0).all()
+
+
+def test_graph_capture_matches_eager(rt, ctx):
+    wl = make_config("medium", side=64, num_orders=4)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    for algo in ("segmented", "frontier"):
+        a = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo)
+        b = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo, graph_capture=False)
+        c = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo)   # replay again
+        assert (a == b).all() and (a == c).all()
+
+
+def test_device_pointers(rt, ctx):
+    import torch
+    wl = make_config("medium", side=64, num_orders=5)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    sizes = np.diff(wl.pick_offsets.astype(np.int64))
+    total = int((sizes ** 2).sum())
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    G.order_matrices(wl.pick_offsets, wl.picks, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    assert (got == exp).all()
+    src = wl.picks[:7]
+    d = torch.empty((7, g.V), dtype=torch.int32, device="cuda")
+    G.sssp(src, out=d)
+    torch.cuda.synchronize()
+    assert (d.cpu().numpy().view(np.uint32) == oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)).all()
+
+
+def test_weight_update_epochs(rt, ctx):
+    wl = make_config("medium", side=64, num_orders=4)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    G.segment_grid(g.W, g.H, 1, 32, 32)
+    rng = np.random.default_rng(11)
+    k = len(g.edge_arc_a) // 20
+    pick = rng.choice(len(g.edge_arc_a), k, replace=False)
+    neww = (g.edge_base_w[pick] + rng.integers(0, 21, k)).astype(np.uint32)
+    arcs = np.concatenate([g.edge_arc_a[pick], g.edge_arc_b[pick]]).astype(np.uint32)
+    vals = np.concatenate([neww, neww])
+    ep = G.update_weights(arcs, vals)
+    assert ep == 1
+    w2 = g.w.copy()
+    w2[arcs] = vals
+    exp = oracle.order_matrices(g.row_ptr, g.col, w2, wl.pick_offsets, wl.picks)
+    for algo in ("segmented", "frontier", "sweep", "edge_b1"):
+        assert (G.order_matrices(wl.pick_offsets, wl.picks, algo=algo) == exp).all(), algo
