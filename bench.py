@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of the warehouse routing hot path on one MI355X.
+
+One step = one wr_order_matrices call over the whole batch of the medium
+workload (512x512 rack grid, 256 orders x 32 picks, multi-source relaxation
+in one call): planning, relaxation of every distinct pick, and the gather of
+all 256 pick-to-pick matrices into device memory.  The graph is uploaded
+(and segmented) before the timed region; picks are host index arrays, as the
+C ABI defines them.
+
+Prints ONE JSON line:
+  value        routed orders/s (whole job; one GPU)
+  roofline     dominant kernel (the segment relaxation pass) against HBM:
+               algorithmic bytes per launch / its average launch duration,
+               timed live with HIP events recorded around each launch
+  cpu_baseline the CPU oracle (Dijkstra per distinct pick, all host cores)
+               on a bounded sample of the same orders
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "seg_pass_medium_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--algo", default="segmented")
+    ap.add_argument("--tile", type=int, default=0, help="tile vertices (0 = library default)")
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--passes", type=int, default=0)
+    ap.add_argument("--segment", default="auto", help="auto | grid:TWxTH")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU work of the oracle sample (core-seconds)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--b1-orders", type=int, default=2,
+                    help="orders of the paper-structured B1 baseline to time (0 = skip)")
+    return ap.parse_args()
+
+
+def reach_tables(g):
+    """Per-vertex reachable vertex and arc counts.  The workloads have
+    symmetric arcs, so the vertices reachable from s form s's connected
+    component."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    V = g.V
+    rows = np.repeat(np.arange(V), np.diff(g.row_ptr.astype(np.int64)))
+    A = sp.csr_matrix((np.ones(g.E, np.int8), (rows, g.col.astype(np.int64))), shape=(V, V))
+    ncomp, lab = connected_components(A, directed=True, connection="weak")
+    vcount = np.bincount(lab, minlength=ncomp)
+    ecount = np.bincount(lab[rows], minlength=ncomp)
+    return vcount[lab], ecount[lab]
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2504_20655_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the pass kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != kernel_source_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, target_core_s: float):
+    import oracle
+    g = wl.graph
+    off, picks = wl.pick_offsets, wl.picks
+    t = time.perf_counter()
+    oracle.dijkstra(g.row_ptr, g.col, g.w, int(picks[0]))
+    per_src = time.perf_counter() - t
+    P = int(off[1] - off[0])
+    k = int(max(1, min(wl.num_orders, round(target_core_s / max(per_src, 1e-4) / P))))
+    threads = oracle.max_threads()
+    sub_off = off[:k + 1]
+    sub_picks = picks[:int(sub_off[-1])]
+    t = time.perf_counter()
+    oracle.order_matrices(g.row_ptr, g.col, g.w, sub_off, sub_picks, nthreads=threads)
+    wall = time.perf_counter() - t
+    n_src = len(np.unique(sub_picks))
+    return {"value": round(k / wall, 3), "unit": "orders/s", "cores": int(min(threads, n_src)),
+            "kind": "oracle",
+            "sample": f"first {k} of {wl.num_orders} orders ({n_src} distinct picks, one "
+                      f"Dijkstra each, {wall:.1f} s wall)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+              "form of this path is a design note, not a runnable configuration.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2504_20655_amd as wr
+    from wgen import make_config
+
+    wl = make_config("medium")
+    g = wl.graph
+    off, picks = wl.pick_offsets, wl.picks
+    n_orders = wl.num_orders
+    total = int((np.diff(off.astype(np.int64)) ** 2).sum())
+
+    ctx = wr.Context(0)
+    G = wr.Graph(ctx, g.row_ptr, g.col, g.w)
+    if args.tile or args.waves or args.passes:
+        G.set_schedule(args.tile, args.waves, args.passes)
+    if args.segment.startswith("grid:"):
+        tw, th = (int(x) for x in args.segment[5:].split("x"))
+        G.segment_grid(g.W, g.H, 1, tw, th)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+
+    # throughput region: passes replayed from captured hipGraphs
+    for _ in range(args.warmup):
+        G.order_matrices(off, picks, out=out, algo=args.algo)
+    torch.cuda.synchronize()
+    lat, relax_ms, passes, items = [], 0.0, 0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        G.order_matrices(off, picks, out=out, algo=args.algo)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        info = G.last_run()
+        relax_ms += info["relax_ms"]
+        passes += info["passes"]
+        items += info["work_items"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    info = G.last_run()
+
+    # kernel-timing region: the same steps with HIP events recorded on the
+    # library's stream around every launch of the relaxation kernel (passes
+    # are launched eagerly so each launch can be bracketed)
+    G.order_matrices(off, picks, out=out, algo=args.algo, time_kernels=True)
+    kern_ms, kern_n = 0.0, 0
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        G.order_matrices(off, picks, out=out, algo=args.algo, time_kernels=True)
+        ti = G.last_run()
+        kern_ms += ti["kernel_ms"]
+        kern_n += ti["kernel_launches"]
+    torch.cuda.synchronize()
+    eager_ms_step = (time.perf_counter() - t1) / args.steps * 1e3
+
+    # useful work of one step: every distinct pick relaxes its reachable arcs
+    vreach, ereach = reach_tables(g)
+    uniq = np.unique(picks)
+    useful_arcs = float(ereach[uniq].sum())
+    # algorithmic HBM bytes: each reached (vertex, source) distance written
+    # once and read once (8 B), and each reached arc's (col, w) streamed once
+    # per block of 64 sources (8 B / 64)
+    alg_bytes = float((8.0 * vreach[uniq] + 8.0 * ereach[uniq] / 64.0).sum())
+
+    ms_per_step = elapsed / args.steps * 1e3
+    orders_per_s = n_orders * args.steps / elapsed
+    kern_ms_step = kern_ms / args.steps
+    launches_step = kern_n / args.steps
+    achieved = alg_bytes / (kern_ms_step * 1e-3) / 1e9 if kern_ms_step > 0 else None
+    traffic = load_traffic()
+    seg = G.segment_info()
+
+    res = {
+        "metric": "routed orders/s",
+        "value": round(orders_per_s, 1),
+        "unit": "orders/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "medium: 512x512 rack-aisle grid (V=262144, E=536188), w in 1..10, "
+                        "256 orders x 32 picks, all orders in one multi-source call",
+            "orders": n_orders, "picks": int(len(picks)), "unique_sources": int(len(uniq)),
+            "algo": info["algo"], "tiles": seg["tiles"], "ports": seg["boundary"],
+        },
+        "gteps": round(useful_arcs / (ms_per_step * 1e-3) / 1e9, 2),
+        "p50_batch_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+        "p99_batch_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+        "relax_ms_per_step": round(relax_ms / args.steps, 3),
+        "ms_per_step_eager_timed": round(eager_ms_step, 3),
+        "passes_per_step": passes / args.steps,
+        "visits_per_step": items / args.steps,
+        "roofline": {
+            "kernel": "k_seg_pass" if info["algo"] == "segmented" else "relaxation pass",
+            "bound": "hbm",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": (round(traffic * launches_step / (kern_ms_step * 1e-3) / 1e9, 1)
+                        if traffic and kern_ms_step > 0 else None),
+            "launches_per_step": launches_step,
+            "avg_launch_us": round(kern_ms_step / max(launches_step, 1) * 1e3, 2),
+            "alg_bytes_per_step": alg_bytes,
+        },
+    }
+    if args.b1_orders > 0:
+        k = min(args.b1_orders, n_orders)
+        sub_off = off[:k + 1]
+        sub_picks = picks[:int(sub_off[-1])]
+        sizes = np.diff(sub_off.astype(np.int64))
+        o1 = torch.empty(int((sizes ** 2).sum()), dtype=torch.int32, device="cuda")
+        t = time.perf_counter()
+        G.order_matrices(sub_off, sub_picks, out=o1, algo="edge_b1")
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t
+        res["baseline_b1"] = {"value": round(k / tb, 3), "unit": "orders/s",
+                              "sample": f"first {k} orders, one order at a time, thread per arc, "
+                                        f"host-checked early exit ({G.last_run()['passes']} rounds)"}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,6 +72,9 @@ typedef enum wr_status {
 #define WR_ALGO_EDGE_B0     0x0050u  /* paper-structured: exactly V-1 rounds         */
 #define WR_ALGO_MASK        0x00F0u
 #define WR_NO_GRAPH_CAPTURE 0x0100u  /* launch passes eagerly instead of replaying a hipGraph */
+#define WR_TIME_KERNELS     0x0200u  /* record HIP events around every launch of the schedule's
+                                        relaxation kernel (wr_run_info.kernel_ms); passes are
+                                        then launched eagerly, not replayed from a hipGraph */
 
 /* ---- opaque handles -------------------------------------------------- */
 typedef struct wr_context wr_context;
@@ -200,6 +203,9 @@ typedef struct wr_run_info {
     uint64_t work_items;       /* visits: (tile, source) or (vertex, block)     */
     double relax_ms;           /* device time of the relaxation passes          */
     double total_ms;           /* wall time of the call                         */
+    double kernel_ms;          /* with WR_TIME_KERNELS: summed duration of the
+                                  relaxation kernel's launches (else 0)         */
+    uint32_t kernel_launches;  /* launches timed into kernel_ms                 */
 } wr_run_info;
 wr_status wr_graph_last_run(const wr_graph *g, wr_run_info *info);
 

@@ -23,6 +23,7 @@ ALGO = {"auto": 0x00, "sweep": 0x10, "frontier": 0x20, "segmented": 0x30,
         "edge_b1": 0x40, "edge_b0": 0x50}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 NO_GRAPH_CAPTURE = 0x0100
+TIME_KERNELS = 0x0200
 
 STATUS = {0: "WR_OK", 1: "WR_E_INVALID", 2: "WR_E_RANGE", 3: "WR_E_NOMEM", 4: "WR_E_DEVICE",
           5: "WR_E_UNSUPPORTED", 6: "WR_E_BUSY", 7: "WR_E_INTERNAL"}
@@ -176,7 +177,8 @@ class Graph:
         return (d, p) if pred else d
 
     def order_matrices(self, pick_offsets, picks, pred: bool = False, algo: str = "auto",
-                       out=None, pred_out=None, graph_capture: bool = True):
+                       out=None, pred_out=None, graph_capture: bool = True,
+                       time_kernels: bool = False):
         """Concatenated per-order P x P matrices (uint32); with pred=True also
         the predecessor row of every pick ([total picks, V])."""
         off, pk = _u32(pick_offsets), _u32(picks)
@@ -184,6 +186,7 @@ class Graph:
         sizes = np.diff(off.astype(np.int64))
         total = int((sizes ** 2).sum())
         flags = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
+        flags |= TIME_KERNELS if time_kernels else 0
         if out is not None:
             flags |= DEVICE_PTRS
             stream = _stream_of(out)

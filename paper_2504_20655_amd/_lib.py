@@ -23,7 +23,8 @@ st = ctypes.c_int  # wr_status
 
 class RunInfo(ctypes.Structure):
     _fields_ = [("algo", u32), ("unique_sources", u32), ("chunks", u32), ("passes", u32),
-                ("work_items", u64), ("relax_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("work_items", u64), ("relax_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("kernel_launches", u32)]
 
 
 class ServerOpts(ctypes.Structure):

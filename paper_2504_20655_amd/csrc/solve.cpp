@@ -25,13 +25,44 @@
 namespace wr {
 
 // --------------------------------------------------------------- workspace
+// Events around each relaxation-kernel launch of one replay (2 per pass).
+struct KernelEvents {
+    std::vector<hipEvent_t> ev;
+    void create(uint32_t K) {
+        ev.assign(2 * K, nullptr);
+        for (auto &e : ev) WR_HIP(hipEventCreate(&e));
+    }
+    ~KernelEvents() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    hipEvent_t b(uint32_t i) const { return ev.empty() ? nullptr : ev[2 * i]; }
+    hipEvent_t e(uint32_t i) const { return ev.empty() ? nullptr : ev[2 * i + 1]; }
+    // Adds the K kernel durations of the replay that just finished; false if
+    // the runtime cannot time these events (then nothing is added).
+    bool collect(uint32_t K, wr_run_info &info) const {
+        if (ev.empty()) return true;
+        double sum = 0;
+        for (uint32_t i = 0; i < K; ++i) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+            sum += ms;
+        }
+        info.kernel_ms += sum;
+        info.kernel_launches += K;
+        return true;
+    }
+};
+
 struct SegWork {
     uint64_t gen = 0;
     uint32_t S_cap = 0, tile_cap = 0, waves = 0, G = 0, K = 0, grid = 0;
-    DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile;
-    DBuf<uint8_t> visited;
-    DBuf<uint2> units;
-    DBuf<unsigned long long> stats;
+    bool timed = false;
+    KernelEvents kev;
+    SegBuffers buf;
     hipGraphExec_t exec = nullptr;
     SegState ss;
     ~SegWork() {
@@ -42,6 +73,8 @@ struct SegWork {
 struct BlkWork {
     uint32_t nb_cap = 0, K = 0, grid = 0;
     bool frontier = false;
+    bool timed = false;
+    KernelEvents kev;
     DBuf<uint32_t> dist, stamps, ctr, src;
     DBuf<uint64_t> list;
     DBuf<unsigned long long> stats;
@@ -132,12 +165,77 @@ uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
     return ts.T * ((S + G - 1) / G) + ts.T;
 }
 
-uint64_t seg_bytes_per_source(const TileSet &ts, uint32_t G) {
+}  // namespace
+
+uint64_t SegBuffers::bytes_per_source(const TileSet &ts, uint32_t G) {
     return 4ull * ts.Vt + 4ull * ts.NP + 1ull * ts.T + 4ull * ts.T + 8ull * ts.T +
            8ull * ts.T / G + 8;
 }
 
-SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode) {
+void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g) {
+    S_cap = S;
+    G = g;
+    gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt);
+    inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u));
+    stamps.alloc(ctx, static_cast<size_t>(S) * ts.T);
+    visited.alloc(ctx, static_cast<size_t>(S) * ts.T);
+    cnt.alloc(ctx, 2ull * ts.T);
+    bucket.alloc(ctx, 2ull * ts.T * S);
+    tiles.alloc(ctx, 2ull * ts.T);
+    ctr.alloc(ctx, 8);
+    units.alloc(ctx, seg_units_cap(ts, S, G));
+    stats.alloc(ctx, 2);
+    src_pos.alloc(ctx, S);
+    src_tile.alloc(ctx, S);
+    ss = SegState{};
+    ss.S = S;
+    ss.gdist = gdist.p;
+    ss.inbox = inbox.p;
+    ss.visited = visited.p;
+    ss.stamps = stamps.p;
+    ss.cnt = cnt.p;
+    ss.bucket = bucket.p;
+    ss.tiles = tiles.p;
+    ss.units = units.p;
+    ss.ntiles = ctr.p + 0;   // [2]
+    ss.nunits = ctr.p + 2;
+    ss.cursor = ctr.p + 3;
+    ss.pass_ctr = ctr.p + 4;
+    ss.stats = stats.p;
+    ss.src_pos = src_pos.p;
+    ss.src_tile = src_tile.p;
+}
+
+uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves) {
+    const uint32_t lds = seg_pass_lds_bytes(tile_cap, waves);
+    uint32_t per_cu = std::max(1u, (160u * 1024u) / lds);
+    per_cu = std::min(per_cu, 32u / waves);
+    return static_cast<uint32_t>(ctx->num_cus) * per_cu;
+}
+
+hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t tile_cap,
+                                  uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st) {
+    hipGraph_t graph;
+    WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+        for (uint32_t i = 0; i < K; ++i) launch_seg_step(ts, ss, i & 1u, tile_cap, waves, G, grid, st);
+    } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(st, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+    }
+    WR_HIP(hipStreamEndCapture(st, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) fail(WR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return exec;
+}
+
+namespace {
+
+SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed) {
     Workspace &ws = workspace(g);
     TileSet &ts = *g->tiles;
     const uint32_t waves = g->waves_per_group;
@@ -145,11 +243,12 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode) {
     const uint32_t K = std::max(2u, g->passes_per_replay & ~1u);
     SegWork *w = ws.seg.get();
     const bool fits = w && w->gen == g->tiles_gen && w->S_cap >= S_need && w->tile_cap == ts.tile_cap &&
-                      w->waves == waves && w->G == G && w->K == K;
+                      w->waves == waves && w->G == G && w->K == K && w->timed == timed &&
+                      (!graph_mode || w->exec);
     if (fits) return *w;
     // size the chunk: the request, bounded by the budget (keep what we hold)
     ws.seg.reset();
-    const uint64_t per = seg_bytes_per_source(ts, G);
+    const uint64_t per = SegBuffers::bytes_per_source(ts, G);
     const uint64_t avail = g->ctx->available();
     uint64_t S_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
     uint32_t S_cap = static_cast<uint32_t>(std::min<uint64_t>(S_need, S_fit));
@@ -161,59 +260,13 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode) {
     nw->waves = waves;
     nw->G = G;
     nw->K = K;
+    nw->timed = timed;
+    if (timed) nw->kev.create(K);
     wr_context *ctx = g->ctx;
-    nw->gdist.alloc(ctx, static_cast<size_t>(S_cap) * ts.Vt);
-    nw->inbox.alloc(ctx, static_cast<size_t>(S_cap) * std::max(ts.NP, 1u));
-    nw->stamps.alloc(ctx, static_cast<size_t>(S_cap) * ts.T);
-    nw->visited.alloc(ctx, static_cast<size_t>(S_cap) * ts.T);
-    nw->cnt.alloc(ctx, 2ull * ts.T);
-    nw->bucket.alloc(ctx, 2ull * ts.T * S_cap);
-    nw->tiles.alloc(ctx, 2ull * ts.T);
-    nw->ctr.alloc(ctx, 8);
-    nw->units.alloc(ctx, seg_units_cap(ts, S_cap, G));
-    nw->stats.alloc(ctx, 2);
-    nw->src_pos.alloc(ctx, S_cap);
-    nw->src_tile.alloc(ctx, S_cap);
-    SegState &ss = nw->ss;
-    ss.S = S_cap;
-    ss.gdist = nw->gdist.p;
-    ss.inbox = nw->inbox.p;
-    ss.visited = nw->visited.p;
-    ss.stamps = nw->stamps.p;
-    ss.cnt = nw->cnt.p;
-    ss.bucket = nw->bucket.p;
-    ss.tiles = nw->tiles.p;
-    ss.units = nw->units.p;
-    ss.ntiles = nw->ctr.p + 0;   // [2]
-    ss.nunits = nw->ctr.p + 2;
-    ss.cursor = nw->ctr.p + 3;
-    ss.pass_ctr = nw->ctr.p + 4;
-    ss.stats = nw->stats.p;
-    ss.src_pos = nw->src_pos.p;
-    ss.src_tile = nw->src_tile.p;
-    // persistent grid: as many workgroups as fit on the chip at once
-    const uint32_t lds = seg_pass_lds_bytes(ts.tile_cap, waves);
-    uint32_t per_cu = std::max(1u, (160u * 1024u) / lds);
-    per_cu = std::min(per_cu, 32u / waves);
-    nw->grid = static_cast<uint32_t>(ctx->num_cus) * per_cu;
-    if (graph_mode) {
-        hipStream_t st = ctx->stream;
-        hipGraph_t graph;
-        WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        try {
-            for (uint32_t i = 0; i < K; ++i)
-                launch_seg_step(ts, ss, i & 1u, ts.tile_cap, waves, G, nw->grid, st);
-        } catch (...) {
-            hipGraph_t dummy;
-            (void)hipStreamEndCapture(st, &dummy);
-            if (dummy) (void)hipGraphDestroy(dummy);
-            throw;
-        }
-        WR_HIP(hipStreamEndCapture(st, &graph));
-        hipError_t e = hipGraphInstantiate(&nw->exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) fail(WR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
+    nw->buf.init(ctx, ts, S_cap, G);
+    nw->ss = nw->buf.ss;
+    nw->grid = seg_pass_grid(ctx, ts.tile_cap, waves);
+    if (graph_mode) nw->exec = capture_seg_passes(ts, nw->ss, K, ts.tile_cap, waves, G, nw->grid, ctx->stream);
     ws.seg = std::move(nw);
     return *ws.seg;
 }
@@ -232,15 +285,15 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
         sp[i] = ts.pos_of[v];
         stl[i] = ts.tile_of[v];
     }
-    WR_HIP(hipMemcpyAsync(w.src_pos.p, sp.data(), n * 4ull, hipMemcpyHostToDevice, st));
-    WR_HIP(hipMemcpyAsync(w.src_tile.p, stl.data(), n * 4ull, hipMemcpyHostToDevice, st));
+    WR_HIP(hipMemcpyAsync(w.buf.src_pos.p, sp.data(), n * 4ull, hipMemcpyHostToDevice, st));
+    WR_HIP(hipMemcpyAsync(w.buf.src_tile.p, stl.data(), n * 4ull, hipMemcpyHostToDevice, st));
     // reset the chunk state (S stays the buffer capacity for indexing)
-    launch_fill_u32(w.inbox.p, static_cast<size_t>(n) * std::max(ts.NP, 1u), INF, st);
-    launch_fill_u32(w.stamps.p, static_cast<size_t>(n) * ts.T, 0u, st);
-    launch_fill_u8(w.visited.p, static_cast<size_t>(n) * ts.T, 0u, st);
-    launch_fill_u32(w.cnt.p, 2ull * ts.T, 0u, st);
-    launch_fill_u32(w.ctr.p, 8, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(w.stats.p), 4, 0u, st);
+    launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(n) * std::max(ts.NP, 1u), INF, st);
+    launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(n) * ts.T, 0u, st);
+    launch_fill_u8(w.buf.visited.p, static_cast<size_t>(n) * ts.T, 0u, st);
+    launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
+    launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
     launch_seg_seed_n(ts, ss, n, st);
     hipEvent_t e0, e1;
     WR_HIP(hipEventCreate(&e0));
@@ -254,17 +307,19 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
             WR_HIP(hipGraphLaunch(w.exec, st));
         } else {
             for (uint32_t i = 0; i < K; ++i)
-                launch_seg_step(ts, ss, i & 1u, ts.tile_cap, w.waves, w.G, w.grid, st);
+                launch_seg_step(ts, ss, i & 1u, ts.tile_cap, w.waves, w.G, w.grid, st, w.kev.b(i),
+                                w.kev.e(i));
         }
         passes += K;
         WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + 0, 4, hipMemcpyDeviceToHost, st));
         WR_HIP(hipStreamSynchronize(st));
+        if (!w.kev.collect(K, info)) fail(WR_E_DEVICE, "kernel event timing failed");
         if (*workspace(g).h_flag == 0) break;
         if (passes > cap) fail(WR_E_INTERNAL, "segmented relaxation exceeded its pass cap");
     }
     WR_HIP(hipEventRecord(e1, st));
     unsigned long long stats[2];
-    WR_HIP(hipMemcpyAsync(stats, w.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
+    WR_HIP(hipMemcpyAsync(stats, w.buf.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
     WR_HIP(hipStreamSynchronize(st));
     float ms = 0;
     WR_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -280,11 +335,37 @@ uint64_t blk_bytes_per_block(uint32_t V, bool frontier) {
     return static_cast<uint64_t>(V) * (LANES * 4ull + (frontier ? 4ull + 16ull : 0ull));
 }
 
-BlkWork &blk_workspace(wr_graph *g, uint32_t nb_need, bool frontier, bool graph_mode) {
+// One replay's worth of passes of the blocked-layout schedule (captured or
+// eager): K frontier passes, or a cleared changed-flag and K sweeps.
+void blk_passes(wr_graph *g, BlkWork &w, hipStream_t st) {
+    const size_t units = static_cast<size_t>(w.nb_cap) * g->V;
+    if (w.frontier) {
+        for (uint32_t i = 0; i < w.K; ++i) {
+            const uint32_t par = i & 1u, nx = par ^ 1u;
+            launch_pass_prologue(w.ctr.p + nx, w.ctr.p + par, w.stats.p, w.ctr.p + 4, st);
+            if (w.kev.b(i)) WR_HIP(hipEventRecord(w.kev.b(i), st));
+            launch_frontier_push(w.dist.p, g->V, g->d_row_ptr.p, g->d_col.p, g->d_w.p,
+                                 w.list.p + par * units, w.ctr.p + par, w.list.p + nx * units,
+                                 w.ctr.p + nx, w.stamps.p, w.ctr.p + 4, w.grid, st);
+            if (w.kev.e(i)) WR_HIP(hipEventRecord(w.kev.e(i), st));
+        }
+    } else {
+        launch_fill_u32(w.ctr.p + 2, 1, 0u, st);
+        for (uint32_t i = 0; i < w.K; ++i) {
+            if (w.kev.b(i)) WR_HIP(hipEventRecord(w.kev.b(i), st));
+            launch_sweep_pull(w.dist.p, g->V, w.nb_cap, g->d_in_ptr.p, g->d_in_src.p, g->d_in_w.p,
+                              w.ctr.p + 2, w.grid, st);
+            if (w.kev.e(i)) WR_HIP(hipEventRecord(w.kev.e(i), st));
+        }
+    }
+}
+
+BlkWork &blk_workspace(wr_graph *g, uint32_t nb_need, bool frontier, bool graph_mode, bool timed) {
     Workspace &ws = workspace(g);
     const uint32_t K = std::max(2u, g->passes_per_replay & ~1u);
     BlkWork *w = ws.blk.get();
-    if (w && w->nb_cap >= nb_need && w->frontier == frontier && w->K == K && (!graph_mode || w->exec))
+    if (w && w->nb_cap >= nb_need && w->frontier == frontier && w->K == K && w->timed == timed &&
+        (!graph_mode || w->exec))
         return *w;
     ws.blk.reset();
     const uint64_t per = blk_bytes_per_block(g->V, frontier);
@@ -296,6 +377,8 @@ BlkWork &blk_workspace(wr_graph *g, uint32_t nb_need, bool frontier, bool graph_
     nw->nb_cap = nb_cap;
     nw->frontier = frontier;
     nw->K = K;
+    nw->timed = timed;
+    if (timed) nw->kev.create(K);
     wr_context *ctx = g->ctx;
     const size_t units = static_cast<size_t>(nb_cap) * g->V;
     nw->dist.alloc(ctx, units * LANES);
@@ -312,21 +395,7 @@ BlkWork &blk_workspace(wr_graph *g, uint32_t nb_need, bool frontier, bool graph_
         hipGraph_t graph;
         WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         try {
-            if (frontier) {
-                for (uint32_t i = 0; i < K; ++i) {
-                    const uint32_t par = i & 1u, nx = par ^ 1u;
-                    launch_pass_prologue(nw->ctr.p + nx, nw->ctr.p + par, nw->stats.p, nw->ctr.p + 4, st);
-                    launch_frontier_push(nw->dist.p, g->V, g->d_row_ptr.p, g->d_col.p, g->d_w.p,
-                                         nw->list.p + par * units, nw->ctr.p + par,
-                                         nw->list.p + nx * units, nw->ctr.p + nx, nw->stamps.p,
-                                         nw->ctr.p + 4, nw->grid, st);
-                }
-            } else {
-                launch_fill_u32(nw->ctr.p + 2, 1, 0u, st);
-                for (uint32_t i = 0; i < K; ++i)
-                    launch_sweep_pull(nw->dist.p, g->V, nb_cap, g->d_in_ptr.p, g->d_in_src.p,
-                                      g->d_in_w.p, nw->ctr.p + 2, nw->grid, st);
-            }
+            blk_passes(g, *nw, st);
         } catch (...) {
             hipGraph_t dummy;
             (void)hipStreamEndCapture(st, &dummy);
@@ -369,25 +438,14 @@ void blk_solve_chunk(wr_graph *g, BlkWork &w, const std::vector<uint32_t> &usrc,
     const uint64_t cap = static_cast<uint64_t>(V) + 2ull * K + 8;
     uint32_t *hf = workspace(g).h_flag;
     for (;;) {
-        if (graph_mode) {
+        if (graph_mode)
             WR_HIP(hipGraphLaunch(w.exec, st));
-        } else if (w.frontier) {
-            for (uint32_t i = 0; i < K; ++i) {
-                const uint32_t par = i & 1u, nx = par ^ 1u;
-                launch_pass_prologue(w.ctr.p + nx, w.ctr.p + par, w.stats.p, w.ctr.p + 4, st);
-                launch_frontier_push(w.dist.p, V, g->d_row_ptr.p, g->d_col.p, g->d_w.p,
-                                     w.list.p + par * units, w.ctr.p + par, w.list.p + nx * units,
-                                     w.ctr.p + nx, w.stamps.p, w.ctr.p + 4, w.grid, st);
-            }
-        } else {
-            launch_fill_u32(w.ctr.p + 2, 1, 0u, st);
-            for (uint32_t i = 0; i < K; ++i)
-                launch_sweep_pull(w.dist.p, V, w.nb_cap, g->d_in_ptr.p, g->d_in_src.p, g->d_in_w.p,
-                                  w.ctr.p + 2, w.grid, st);
-        }
+        else
+            blk_passes(g, w, st);
         passes += K;
         WR_HIP(hipMemcpyAsync(hf, w.frontier ? w.ctr.p + 0 : w.ctr.p + 2, 4, hipMemcpyDeviceToHost, st));
         WR_HIP(hipStreamSynchronize(st));
+        if (!w.kev.collect(K, info)) fail(WR_E_DEVICE, "kernel event timing failed");
         if (!w.frontier && *hf) sweeps_changed += K;
         if (*hf == 0) break;
         if (passes > cap) fail(WR_E_INTERNAL, "relaxation exceeded its pass cap");
@@ -456,10 +514,10 @@ void edge_solve(wr_graph *g, const uint32_t *d_src, uint32_t N, uint32_t *d_rows
 }
 
 // Orders `lo..lo+n)` of usrc that fit one chunk of the chosen schedule.
-uint32_t chunk_sources(wr_graph *g, uint32_t algo, uint32_t total, bool graph_mode) {
-    if (algo == WR_ALGO_SEGMENTED) return seg_workspace(g, total, graph_mode).S_cap;
+uint32_t chunk_sources(wr_graph *g, uint32_t algo, uint32_t total, bool graph_mode, bool timed) {
+    if (algo == WR_ALGO_SEGMENTED) return seg_workspace(g, total, graph_mode, timed).S_cap;
     const uint32_t nb_need = (total + LANES - 1) / LANES;
-    return blk_workspace(g, nb_need, algo == WR_ALGO_FRONTIER, graph_mode).nb_cap * LANES;
+    return blk_workspace(g, nb_need, algo == WR_ALGO_FRONTIER, graph_mode, timed).nb_cap * LANES;
 }
 
 void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, uint32_t lo,
@@ -519,7 +577,10 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
     if (pred && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
     const uint32_t algo = resolve_algo(g, flags);
     const bool dev = (flags & WR_DEVICE_PTRS) != 0;
-    const bool graph_mode = (flags & WR_NO_GRAPH_CAPTURE) == 0;
+    const bool timed = (flags & WR_TIME_KERNELS) != 0;
+    // events around individual kernels are recorded on the stream, so timed
+    // calls launch their passes eagerly instead of replaying a graph
+    const bool graph_mode = (flags & WR_NO_GRAPH_CAPTURE) == 0 && !timed;
     wr_context *ctx = g->ctx;
     WR_HIP(hipSetDevice(ctx->device));
     StreamJoin join(ctx, dev, stream);
@@ -567,7 +628,7 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
     Plan plan = make_plan(g, sources, S, true);
     const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
     info.unique_sources = U;
-    const uint32_t chunk = chunk_sources(g, algo, U, graph_mode);
+    const uint32_t chunk = chunk_sources(g, algo, U, graph_mode, timed);
     // rows of each chunk (output rows whose unique source falls in it)
     std::vector<std::vector<uint32_t>> rows_of(( U + chunk - 1) / chunk);
     for (uint32_t i = 0; i < S; ++i) rows_of[plan.uidx[i] / chunk].push_back(i);
@@ -649,7 +710,10 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
     if (pred_out && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
     const uint32_t algo = resolve_algo(g, flags);
     const bool dev = (flags & WR_DEVICE_PTRS) != 0;
-    const bool graph_mode = (flags & WR_NO_GRAPH_CAPTURE) == 0;
+    const bool timed = (flags & WR_TIME_KERNELS) != 0;
+    // events around individual kernels are recorded on the stream, so timed
+    // calls launch their passes eagerly instead of replaying a graph
+    const bool graph_mode = (flags & WR_NO_GRAPH_CAPTURE) == 0 && !timed;
     wr_context *ctx = g->ctx;
     WR_HIP(hipSetDevice(ctx->device));
     StreamJoin join(ctx, dev, stream);
@@ -713,7 +777,7 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
         const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
         info.unique_sources = U;
         upload(d_sidx, ctx, plan.uidx, st);
-        const uint32_t chunk = chunk_sources(g, algo, U, graph_mode);
+        const uint32_t chunk = chunk_sources(g, algo, U, graph_mode, timed);
         for (uint32_t lo = 0; lo < U; lo += chunk) {
             const uint32_t n = std::min(chunk, U - lo);
             solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <new>
 #include <cstdint>
@@ -184,8 +185,8 @@ struct wr_graph {
     uint32_t user_num_segments = 0;
 
     // schedule
-    uint32_t tile_vertices = 2048;
-    uint32_t waves_per_group = 4;
+    uint32_t tile_vertices = 1024;
+    uint32_t waves_per_group = 8;
     uint32_t sources_per_unit = 0;     // 0 = 4 * waves_per_group
     uint32_t passes_per_replay = 8;
 
@@ -241,12 +242,40 @@ struct SegState {
 // activates (s, tile of source s) for the chunk's sources s < n
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
 // one pass: prologue (zero next counters) + plan (units) + relaxation
+// ev (optional): events recorded right before / after the relaxation kernel
 void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t tile_cap,
-                     uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st);
+                     uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st,
+                     hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves);
 void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t rows,
                      const uint32_t *row_src_idx, const uint32_t *row_src_vertex,
                      const uint32_t *out_row, uint32_t *out, hipStream_t st);
+
+// Device buffers of one segmented state of S_cap sources (see SegState).
+struct SegBuffers {
+    uint32_t S_cap = 0, G = 0;
+    DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile;
+    DBuf<uint8_t> visited;
+    DBuf<uint2> units;
+    DBuf<unsigned long long> stats;
+    SegState ss;
+    void init(wr_context *ctx, const TileSet &ts, uint32_t S_cap, uint32_t G);
+    static uint64_t bytes_per_source(const TileSet &ts, uint32_t G);
+};
+// Persistent grid size of the pass kernel for this schedule.
+uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves);
+// Captures K passes (parities 0,1,0,...) into an instantiated graph.
+hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t tile_cap,
+                                  uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st);
+
+// serving: reset the state rows of new slots, activate their sources for
+// the next pass (parity 0 after an even number of passes), and flag the
+// slots that still have pending (tile, slot) items in the parity-0 lists
+void launch_srv_reset_slots(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
+                            hipStream_t st);
+void launch_srv_seed(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
+                     hipStream_t st);
+void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *active, hipStream_t st);
 
 // order gathers: out[out_base[o] + i*P + j] = d(p_i, p_j)
 void launch_gather_rows(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,

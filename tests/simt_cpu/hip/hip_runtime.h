@@ -198,6 +198,7 @@ enum hipStreamCaptureMode {
 #define hipStreamNonBlocking 1
 #define hipEventDisableTiming 2
 #define hipHostMallocDefault 0
+#define hipEventRecordExternal 0x01
 
 hipError_t hipGetDeviceCount(int *n);
 hipError_t hipSetDevice(int d);
@@ -220,6 +221,7 @@ hipError_t hipDeviceSynchronize();
 hipError_t hipEventCreate(hipEvent_t *e);
 hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned f);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipEventRecordWithFlags(hipEvent_t e, hipStream_t s, unsigned flags);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipEventDestroy(hipEvent_t e);
