@@ -20,7 +20,7 @@ NO_PRED = -1
 
 DEVICE_PTRS = 0x0001
 ALGO = {"auto": 0x00, "sweep": 0x10, "frontier": 0x20, "segmented": 0x30,
-        "edge_b1": 0x40, "edge_b0": 0x50}
+        "edge_b1": 0x40, "edge_b0": 0x50, "overlay": 0x60}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 NO_GRAPH_CAPTURE = 0x0100
 TIME_KERNELS = 0x0200

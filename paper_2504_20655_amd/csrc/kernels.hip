@@ -208,6 +208,9 @@ struct SegPassArgs {
     uint32_t *cursor;
     const uint32_t *pass_ctr;
     uint32_t G;
+    // source-blocked schedule: in-tile in-arcs and the sources of the chunk
+    const uint32_t *li_off, *li_arc;
+    uint32_t nsrc;
 };
 
 __device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
@@ -393,12 +396,500 @@ __global__ __launch_bounds__(NW * 64) void k_seg_pass(SegPassArgs A) {
     }
 }
 
+// Wave 0 turns the set bits of bitmap bm[WORDS] (WORDS <= 64) into list[]
+// (ascending) and stores the count in *len; with clear, the bitmap is
+// zeroed on the way.  The exclusive prefix of the per-word counts is built
+// from readlane broadcasts (uniform loop over the words).
+template <uint32_t WORDS>
+__device__ __forceinline__ void compact_bits(uint32_t *bm, uint16_t *list, uint32_t *len, bool clear) {
+    static_assert(WORDS <= 64, "one word per lane");
+    const uint32_t lane = lane_id();
+    const bool in = lane < WORDS;
+    uint32_t word = in ? bm[lane] : 0u;
+    if (in && clear) bm[lane] = 0u;
+    const uint32_t c = __builtin_popcount(word);
+    uint32_t excl = 0, total = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < WORDS; ++k) {
+        const uint32_t ck = __builtin_amdgcn_readlane(c, k);
+        excl += lane > k ? ck : 0u;
+        total += ck;
+    }
+    uint32_t pos = excl;
+    while (word) {
+        const uint32_t j = __builtin_ctz(word);
+        word &= word - 1u;
+        list[pos++] = static_cast<uint16_t>(lane * 32 + j);
+    }
+    if (lane == 0) *len = total;
+}
+
+// Pull update of candidate v for the 64 lanes: returns whether any lane
+// improved.  The in-arcs of v are read across lanes in one LDS access and
+// broadcast with readlane, so the row reads D[u] of all arcs are independent.
+template <int CAP>
+__device__ __forceinline__ bool pull_row(uint32_t *D, const uint32_t *s_iinfo, const uint32_t *s_iarc,
+                                        uint32_t v, uint32_t lane) {
+    const uint32_t info = uniform(s_iinfo[v]);
+    const uint32_t off = info >> 16, deg = info & 0xFFFFu;
+    const uint32_t old = D[v * 64 + lane];
+    uint32_t m = old;
+    for (uint32_t c0 = 0; c0 < deg; c0 += 64) {
+        const uint32_t mine = c0 + lane < deg ? s_iarc[off + c0 + lane] : 0u;
+        const uint32_t nk = deg - c0 < 64 ? deg - c0 : 64;
+        uint32_t k = 0;
+        for (; k + 4 <= nk; k += 4) {
+            const uint32_t a0 = __builtin_amdgcn_readlane(mine, k);
+            const uint32_t a1 = __builtin_amdgcn_readlane(mine, k + 1);
+            const uint32_t a2 = __builtin_amdgcn_readlane(mine, k + 2);
+            const uint32_t a3 = __builtin_amdgcn_readlane(mine, k + 3);
+            const uint32_t d0 = D[(a0 >> 16) * 64 + lane], d1 = D[(a1 >> 16) * 64 + lane];
+            const uint32_t d2 = D[(a2 >> 16) * 64 + lane], d3 = D[(a3 >> 16) * 64 + lane];
+            m = min(m, min(min(sat_add(d0, a0 & 0xFFFFu), sat_add(d1, a1 & 0xFFFFu)),
+                           min(sat_add(d2, a2 & 0xFFFFu), sat_add(d3, a3 & 0xFFFFu))));
+        }
+        for (; k < nk; ++k) {
+            const uint32_t a = __builtin_amdgcn_readlane(mine, k);
+            m = min(m, sat_add(D[(a >> 16) * 64 + lane], a & 0xFFFFu));
+        }
+    }
+    const bool imp = m < old;
+    if (imp) D[v * 64 + lane] = m;
+    return __builtin_amdgcn_ballot_w64(imp) != 0;
+}
+
+// Marks the in-tile out-neighbours of v in bitmap bm (lanes take one arc each).
+__device__ __forceinline__ void mark_out(uint32_t *bm, const uint32_t *s_oinfo, const uint16_t *s_odst,
+                                         uint32_t v, uint32_t lane) {
+    const uint32_t info = uniform(s_oinfo[v]);
+    const uint32_t off = info >> 16, deg = info & 0xFFFFu;
+    for (uint32_t k = lane; k < deg; k += 64) {
+        const uint32_t x = s_odst[off + k];
+        atomicOr(&bm[x >> 5], 1u << (x & 31));
+    }
+}
+
+// Relaxes the tile held in LDS rows D[v][64] to its local fixpoint.  On
+// entry s_dirty marks the vertices whose rows were lowered from outside (and
+// s_cand is clear); on exit s_dirty marks every row that changed.  Called by
+// the whole workgroup.
+template <int CAP, int NW>
+__device__ __forceinline__ void relax_tile(uint32_t *D, const uint32_t *s_iinfo, const uint32_t *s_iarc,
+                                           const uint32_t *s_oinfo, const uint16_t *s_odst,
+                                           uint32_t (*s_cand)[CAP / 32], uint32_t *s_dirty,
+                                           uint16_t *s_list, uint32_t *s_len, uint32_t wv, uint32_t lane) {
+    constexpr uint32_t WORDS = CAP / 32;
+    // first candidates: out-neighbours of every seeded vertex
+    if (wv == 0) compact_bits<WORDS>(s_dirty, s_list, s_len, false);
+    __syncthreads();
+    {
+        const uint32_t L = uniform(*s_len);
+        for (uint32_t i = wv; i < L; i += NW) mark_out(s_cand[0], s_oinfo, s_odst, uniform(s_list[i]), lane);
+    }
+    __syncthreads();
+    uint32_t cur = 0;
+    for (;;) {
+        if (wv == 0) compact_bits<WORDS>(s_cand[cur], s_list, s_len, true);
+        __syncthreads();
+        const uint32_t L = uniform(*s_len);
+        if (L == 0) break;
+        for (uint32_t i = wv; i < L; i += NW) {
+            const uint32_t v = uniform(s_list[i]);
+            if (pull_row<CAP>(D, s_iinfo, s_iarc, v, lane)) {
+                if (lane == 0) atomicOr(&s_dirty[v >> 5], 1u << (v & 31));
+                mark_out(s_cand[cur ^ 1u], s_oinfo, s_odst, v, lane);
+            }
+        }
+        __syncthreads();
+        cur ^= 1u;
+    }
+}
+
+// Stages the in-tile in-arcs and out-arcs of tile [base, base+n) in LDS.
+__device__ __forceinline__ void stage_tile_arcs(const SegPassArgs &A, uint32_t base, uint32_t n,
+                                                uint32_t *s_iinfo, uint32_t *s_oinfo, uint32_t *s_iarc,
+                                                uint16_t *s_odst) {
+    const uint32_t ai = A.li_off[base], ao = A.l_off[base];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t i0 = A.li_off[base + i] - ai, i1 = A.li_off[base + i + 1] - ai;
+        const uint32_t o0 = A.l_off[base + i] - ao, o1 = A.l_off[base + i + 1] - ao;
+        s_iinfo[i] = (i0 << 16) | (i1 - i0);
+        s_oinfo[i] = (o0 << 16) | (o1 - o0);
+    }
+    const uint32_t ni = A.li_off[base + n] - ai, no = A.l_off[base + n] - ao;
+    for (uint32_t i = threadIdx.x; i < ni; i += blockDim.x) s_iarc[i] = A.li_arc[ai + i];
+    for (uint32_t i = threadIdx.x; i < no; i += blockDim.x)
+        s_odst[i] = static_cast<uint16_t>(A.l_arc[ao + i] >> 16);
+}
+
+// Source-blocked pass: a workgroup relaxes one (tile, block of 64 sources)
+// item at a time.  The tile's distances for the 64 sources sit in LDS as
+// rows D[v][lane] (one 256-byte row per vertex); lanes are sources, so every
+// LDS access of a wave is a whole row.  Relaxation is pull-based over a
+// shared candidate bitmap: a candidate v takes, per lane, the minimum of
+// D[v] and D[u] + w over its in-tile in-arcs; if any lane improved, v's
+// in-tile out-neighbours become candidates of the next sweep and v is marked
+// changed.  Each candidate is handled by one wave, so D[v] has one writer;
+// reads of neighbours racing with their writers only see older upper
+// bounds, which the candidate marking then revisits.  The boundary exchange
+// and the activation of (block, tile) items are those of the one-source
+// schedule, with inbox rows of 64 lanes.
+template <int CAP, int NW>
+__global__ __launch_bounds__(NW * 64) void k_segb_pass(SegPassArgs A) {
+    constexpr uint32_t ACAP = 4u * CAP;
+    constexpr uint32_t WORDS = CAP / 32;
+    __shared__ uint32_t D[CAP * 64];
+    __shared__ uint32_t s_iinfo[CAP];    // (in-arc offset << 16) | in-degree
+    __shared__ uint32_t s_oinfo[CAP];    // (out-arc offset << 16) | out-degree
+    __shared__ uint32_t s_iarc[ACAP];
+    __shared__ uint16_t s_odst[ACAP];
+    __shared__ uint32_t s_cand[2][WORDS];
+    __shared__ uint32_t s_dirty[WORDS];
+    __shared__ uint16_t s_list[CAP];
+    __shared__ uint32_t s_len;
+    __shared__ uint32_t s_unit;
+
+    const uint32_t lane = lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    const uint32_t nunits = uniform(*A.nunits);
+    const uint32_t stamp = uniform(*A.pass_ctr) + 1u;
+    uint32_t staged = NONE;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(A.cursor, 1u);
+        __syncthreads();
+        const uint32_t u = uniform(s_unit);
+        __syncthreads();
+        if (u >= nunits) break;
+        const uint2 unit = A.units[u];
+        const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
+        const uint32_t base = uniform(A.tile_base[t]);
+        const uint32_t n = uniform(A.tile_base[t + 1]) - base;
+        if (t != staged) {
+            stage_tile_arcs(A, base, n, s_iinfo, s_oinfo, s_iarc, s_odst);
+            staged = t;
+            __syncthreads();
+        }
+        const uint32_t total = uniform(A.cnt_cur[t]);
+        const uint32_t first_k = slice * A.G;
+        const uint32_t cnt = min(A.G, total - first_k);
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const uint32_t b = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + k]);
+            const size_t st = static_cast<size_t>(b) * A.T + t;
+            const bool first = A.visited[st] == 0;
+            uint32_t *gd = A.gdist + (static_cast<size_t>(b) * A.Vt + base) * 64;
+            for (uint32_t v = wv; v < n; v += NW) D[v * 64 + lane] = first ? INF : gd[v * 64 + lane];
+            for (uint32_t i = threadIdx.x; i < WORDS; i += blockDim.x) {
+                s_cand[0][i] = 0;
+                s_cand[1][i] = 0;
+                s_dirty[i] = 0;
+            }
+            __syncthreads();
+            // seeds: the block's own sources that lie in this tile
+            if (wv == 0) {
+                const uint32_t s = b * 64 + lane;
+                if (s < A.nsrc && A.src_tile[s] == t) {
+                    const uint32_t loc = A.src_pos[s] - base;
+                    if (D[loc * 64 + lane] != 0) {
+                        D[loc * 64 + lane] = 0;
+                        atomicOr(&s_dirty[loc >> 5], 1u << (loc & 31));
+                    }
+                }
+            }
+            // seeds: inbox values that beat the stored ones
+            const uint32_t p0 = uniform(A.port_base[t]), p1 = uniform(A.port_base[t + 1]);
+            uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64;
+            for (uint32_t kk = p0 + wv; kk < p1; kk += NW) {
+                const uint32_t loc = uniform(A.port_local[kk]);
+                const uint32_t v = ib[static_cast<size_t>(kk) * 64 + lane];
+                const bool imp = v < D[loc * 64 + lane];
+                if (imp) D[loc * 64 + lane] = v;
+                if (__builtin_amdgcn_ballot_w64(imp) != 0 && lane == 0)
+                    atomicOr(&s_dirty[loc >> 5], 1u << (loc & 31));
+            }
+            __syncthreads();
+            relax_tile<CAP, NW>(D, s_iinfo, s_iarc, s_oinfo, s_odst, s_cand, s_dirty, s_list, &s_len, wv, lane);
+            // write back: every row on the first visit, changed rows after
+            for (uint32_t v = wv; v < n; v += NW)
+                if (first || ((s_dirty[v >> 5] >> (v & 31)) & 1u)) gd[v * 64 + lane] = D[v * 64 + lane];
+            if (threadIdx.x == 0 && first) A.visited[st] = 1;
+            // boundary exchange of changed boundary-out vertices
+            const uint32_t b0 = uniform(A.bo_base[t]), b1 = uniform(A.bo_base[t + 1]);
+            for (uint32_t kk = b0 + wv; kk < b1; kk += NW) {
+                const uint32_t loc = uniform(A.bo_local[kk]);
+                if (!((s_dirty[loc >> 5] >> (loc & 31)) & 1u)) continue;
+                const uint32_t dv = D[loc * 64 + lane];
+                const uint32_t pos = base + loc;
+                const uint32_t xe1 = uniform(A.x_off[pos + 1]);
+                for (uint32_t xe = uniform(A.x_off[pos]); xe < xe1; ++xe) {
+                    const uint32_t nd = sat_add(dv, uniform(A.x_w[xe]));
+                    uint32_t *pi = ib + static_cast<size_t>(uniform(A.x_port[xe])) * 64 + lane;
+                    const uint32_t t2 = uniform(A.x_tile[xe]);
+                    bool imp = false;
+                    if (nd < *pi) imp = nd < atomicMin(pi, nd);
+                    if (__builtin_amdgcn_ballot_w64(imp) != 0 && lane == 0) seg_activate(A, b, t2, stamp);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------- overlay schedule
+// The segments' boundary tables: for tile t with E ports (boundary-in
+// vertices, E <= 64), F[pos][i] is the shortest distance from port i to the
+// vertex at position pos using arcs inside t only (INF for lanes i >= E).
+// Customisation (once per weight epoch): one workgroup per tile seeds lane i
+// at port i and relaxes the tile to its local fixpoint.
+template <int CAP, int NW>
+__global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t *__restrict__ F) {
+    constexpr uint32_t ACAP = 4u * CAP;
+    constexpr uint32_t WORDS = CAP / 32;
+    __shared__ uint32_t D[CAP * 64];
+    __shared__ uint32_t s_iinfo[CAP];
+    __shared__ uint32_t s_oinfo[CAP];
+    __shared__ uint32_t s_iarc[ACAP];
+    __shared__ uint16_t s_odst[ACAP];
+    __shared__ uint32_t s_cand[2][WORDS];
+    __shared__ uint32_t s_dirty[WORDS];
+    __shared__ uint16_t s_list[CAP];
+    __shared__ uint32_t s_len;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    for (uint32_t t = blockIdx.x; t < A.T; t += gridDim.x) {
+        const uint32_t base = uniform(A.tile_base[t]);
+        const uint32_t n = uniform(A.tile_base[t + 1]) - base;
+        stage_tile_arcs(A, base, n, s_iinfo, s_oinfo, s_iarc, s_odst);
+        for (uint32_t v = wv; v < n; v += NW) D[v * 64 + lane] = INF;
+        for (uint32_t i = threadIdx.x; i < WORDS; i += blockDim.x) {
+            s_cand[0][i] = 0;
+            s_cand[1][i] = 0;
+            s_dirty[i] = 0;
+        }
+        __syncthreads();
+        const uint32_t p0 = uniform(A.port_base[t]), p1 = uniform(A.port_base[t + 1]);
+        if (wv == 0 && lane < p1 - p0) {
+            const uint32_t loc = A.port_local[p0 + lane];
+            D[loc * 64 + lane] = 0;
+            atomicOr(&s_dirty[loc >> 5], 1u << (loc & 31));
+        }
+        __syncthreads();
+        relax_tile<CAP, NW>(D, s_iinfo, s_iarc, s_oinfo, s_odst, s_cand, s_dirty, s_list, &s_len, wv, lane);
+        uint32_t *Ft = F + static_cast<size_t>(base) * 64;
+        for (uint32_t v = wv; v < n; v += NW) Ft[v * 64 + lane] = D[v * 64 + lane];
+        __syncthreads();
+    }
+}
+
+// Overlay pass: a visit of (tile t, block b) maps the block's entry values
+// (inbox rows of t's ports) through t's table onto t's exits (boundary-out
+// vertices): exit_j = min(exit_j, min_i entry_i + F[exit_j][i]) per lane, a
+// dense min-plus product with no sequential dependency.  Lowered exits are
+// stored in the exits' gdist rows and pushed across their cross-tile arcs
+// into the target tiles' inbox rows, activating (b, target tile).
+//
+// A workgroup stages one tile's exit rows of the table and its cross arcs in
+// LDS, then each of its waves runs a whole visit for one block on its own
+// (no workgroup barrier inside a visit): the entry values sit in registers,
+// exits go in groups of OVL_GRP whose row loads and whose pushes are each
+// issued together, and the visit's activations are made by parallel lanes at
+// its end.  Many independent visits per CU hide the global-memory latency.
+constexpr uint32_t OVL_XCAP = 96;     // exits per tile
+constexpr uint32_t OVL_PCAP = 384;    // cross arcs leaving a tile
+constexpr uint32_t OVL_GRP = 8;       // exits per group
+constexpr uint32_t OVL_ACT = 32;      // activations a wave collects before flushing
+constexpr uint32_t OVL_NW = 4;        // waves per workgroup = blocks per unit
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ F) {
+    __shared__ uint32_t s_M[OVL_XCAP * 64];        // [exit][entry]
+    __shared__ uint32_t s_xpos[OVL_XCAP];          // position of each exit
+    __shared__ uint32_t s_xbeg[OVL_XCAP + 1];      // first cross arc of each exit (tile-relative)
+    __shared__ uint32_t s_xport[OVL_PCAP];
+    __shared__ uint32_t s_xw[OVL_PCAP];
+    __shared__ uint32_t s_xtile[OVL_PCAP];
+    __shared__ uint16_t s_xexit[OVL_PCAP];         // exit of each cross arc
+    __shared__ uint32_t s_m[NW][OVL_GRP * 64];     // new values of the wave's exit group
+    __shared__ uint32_t s_act[NW][OVL_ACT];
+    __shared__ uint32_t s_unit;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    const uint32_t nunits = uniform(*A.nunits);
+    const uint32_t stamp = uniform(*A.pass_ctr) + 1u;
+    uint32_t staged = NONE;
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(A.cursor, 1u);
+        __syncthreads();
+        const uint32_t u = uniform(s_unit);
+        __syncthreads();
+        if (u >= nunits) break;
+        const uint2 unit = A.units[u];
+        const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
+        const uint32_t base = uniform(A.tile_base[t]);
+        const uint32_t p0 = uniform(A.port_base[t]), E = uniform(A.port_base[t + 1]) - p0;
+        const uint32_t b0 = uniform(A.bo_base[t]), X = uniform(A.bo_base[t + 1]) - b0;
+        if (t != staged) {
+            const uint32_t xa0 = A.x_off[base];
+            for (uint32_t j = wv; j < X; j += NW) {
+                const uint32_t pos = base + A.bo_local[b0 + j];
+                s_M[j * 64 + lane] = F[static_cast<size_t>(pos) * 64 + lane];
+                if (lane == 0) {
+                    s_xpos[j] = pos;
+                    s_xbeg[j] = A.x_off[pos] - xa0;
+                }
+            }
+            const uint32_t na = A.x_off[base + uniform(A.tile_base[t + 1]) - base] - xa0;
+            if (threadIdx.x == 0) s_xbeg[X] = na;
+            for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) {
+                s_xport[k] = A.x_port[xa0 + k];
+                s_xw[k] = A.x_w[xa0 + k];
+                s_xtile[k] = A.x_tile[xa0 + k];
+            }
+            __syncthreads();
+            // exit of each cross arc (arcs of consecutive exits are consecutive)
+            for (uint32_t j = threadIdx.x; j < X; j += blockDim.x)
+                for (uint32_t k = s_xbeg[j]; k < s_xbeg[j + 1]; ++k) s_xexit[k] = static_cast<uint16_t>(j);
+            staged = t;
+            __syncthreads();
+        }
+        const uint32_t total = uniform(A.cnt_cur[t]);
+        const uint32_t first_k = slice * A.G;
+        const uint32_t cnt = min(A.G, total - first_k);
+        if (wv < cnt) {
+            const uint32_t b = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + wv]);
+            const size_t st = static_cast<size_t>(b) * A.T + t;
+            const bool first = A.visited[st] == 0;
+            uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64;
+            uint32_t *gd = A.gdist + static_cast<size_t>(b) * A.Vt * 64;
+            uint32_t in[64];
+#pragma unroll
+            for (uint32_t i = 0; i < 64; ++i)
+                in[i] = i < E ? ib[static_cast<size_t>(p0 + i) * 64 + lane] : INF;
+            uint32_t nact = 0;
+            uint32_t *mrow = s_m[wv];
+            for (uint32_t j0 = 0; j0 < X; j0 += OVL_GRP) {
+                const uint32_t ng = X - j0 < OVL_GRP ? X - j0 : OVL_GRP;
+                uint32_t cur[OVL_GRP];
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_GRP; ++r)
+                    cur[r] = (first || r >= ng) ? INF
+                                                : gd[static_cast<size_t>(s_xpos[j0 + r]) * 64 + lane];
+                uint64_t anyimp = 0;
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_GRP; ++r) {
+                    if (r >= ng) break;
+                    const uint32_t *Mj = s_M + (j0 + r) * 64;
+                    uint32_t m = cur[r];
+#pragma unroll
+                    for (uint32_t i = 0; i < 64; ++i)
+                        if (i < E) m = min(m, sat_add(in[i], Mj[i]));
+                    const bool imp = m < cur[r];
+                    if (imp || first) gd[static_cast<size_t>(s_xpos[j0 + r]) * 64 + lane] = m;
+                    mrow[r * 64 + lane] = imp ? m : INF;
+                    anyimp |= __builtin_amdgcn_ballot_w64(imp);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (anyimp == 0) continue;
+                // pushes of the group's cross arcs, four in flight
+                const uint32_t k0 = s_xbeg[j0], k1 = s_xbeg[j0 + ng];
+                for (uint32_t k = k0; k < k1; k += 4) {
+                    uint32_t nd[4], old[4];
+                    uint32_t *pi[4];
+#pragma unroll
+                    for (uint32_t r = 0; r < 4; ++r) {
+                        const uint32_t kk = k + r < k1 ? k + r : k0;
+                        const uint32_t jr = s_xexit[kk] - j0;
+                        const uint32_t mv = mrow[jr * 64 + lane];
+                        nd[r] = (k + r < k1) ? sat_add(mv, s_xw[kk]) : INF;
+                        pi[r] = ib + static_cast<size_t>(s_xport[kk]) * 64 + lane;
+                        old[r] = INF;
+                    }
+#pragma unroll
+                    for (uint32_t r = 0; r < 4; ++r)
+                        if (nd[r] != INF) old[r] = atomicMin(pi[r], nd[r]);
+#pragma unroll
+                    for (uint32_t r = 0; r < 4; ++r) {
+                        if (__builtin_amdgcn_ballot_w64(nd[r] < old[r]) == 0) continue;
+                        const uint32_t t2 = s_xtile[k + r];
+                        if (nact < OVL_ACT) {
+                            if (lane == 0) s_act[wv][nact] = t2;
+                            ++nact;
+                        } else if (lane == 0) {
+                            seg_activate(A, b, t2, stamp);
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nact) seg_activate(A, b, s_act[wv][lane], stamp);
+            if (lane == 0 && first) A.visited[st] = 2;
+        }
+        __syncthreads();
+    }
+}
+
+// Final distance of chunk source s at v under the overlay schedule:
+// min(the source tile's in-tile value when t is a source tile of the block,
+//     min over t's ports i of entry_i + F[v][i]).
+__device__ __forceinline__ uint32_t ovl_value(const uint32_t *tile_of, const uint32_t *pos_of,
+                                              const uint8_t *visited, const uint32_t *gdist,
+                                              const uint32_t *inbox, const uint32_t *F,
+                                              const uint32_t *port_base, uint32_t T, uint32_t Vt,
+                                              uint32_t NP, uint32_t s, uint32_t src_v, uint32_t v) {
+    const uint32_t t = tile_of[v];
+    if (t == NONE) return v == src_v ? 0u : INF;
+    const size_t b = s >> 6, l = s & 63u;
+    const uint32_t pos = pos_of[v];
+    uint32_t m = visited[b * T + t] == 1 ? gdist[(b * Vt + pos) * 64 + l] : INF;
+    const uint32_t p0 = port_base[t], p1 = port_base[t + 1];
+    const uint32_t *ib = inbox + (b * NP) * 64 + l;
+    const uint32_t *Fv = F + static_cast<size_t>(pos) * 64;
+    for (uint32_t p = p0; p < p1; ++p) m = min(m, sat_add(ib[static_cast<size_t>(p) * 64], Fv[p - p0]));
+    return m;
+}
+
+__global__ void k_ovl_emit(const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
+                           const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
+                           const uint32_t *__restrict__ inbox, const uint32_t *__restrict__ F,
+                           const uint32_t *__restrict__ port_base, uint32_t T, uint32_t Vt, uint32_t NP,
+                           uint32_t V, uint32_t rows, const uint32_t *__restrict__ row_src_idx,
+                           const uint32_t *__restrict__ row_src_vertex,
+                           const uint32_t *__restrict__ out_row, uint32_t *__restrict__ out) {
+    for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const uint32_t s = row_src_idx[r], sv = row_src_vertex[r];
+        uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
+        for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
+            o[v] = ovl_value(tile_of, pos_of, visited, gdist, inbox, F, port_base, T, Vt, NP, s, sv, v);
+    }
+}
+
+__global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
+                             const uint32_t *__restrict__ picks, const uint64_t *__restrict__ out_base,
+                             const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n,
+                             const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
+                             const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
+                             const uint32_t *__restrict__ inbox, const uint32_t *__restrict__ F,
+                             const uint32_t *__restrict__ port_base, uint32_t T, uint32_t Vt, uint32_t NP,
+                             uint32_t *__restrict__ out) {
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        const uint64_t ob = out_base[o];
+        for (uint32_t k = threadIdx.x; k < P * P; k += blockDim.x) {
+            const uint32_t i = k / P, j = k - i * P;
+            const uint32_t si = src_idx_of_pick[a + i];
+            if (si < lo || si >= lo + n) continue;
+            out[ob + k] = ovl_value(tile_of, pos_of, visited, gdist, inbox, F, port_base, T, Vt, NP, si - lo,
+                                    picks[a + i], picks[a + j]);
+        }
+    }
+}
+
 // Seeds pass 0: (s, tile of source s) for every source with a tile.
-__global__ void k_seg_seed(SegPassArgs A, uint32_t n) {
+__global__ void k_seg_seed(SegPassArgs A, uint32_t n, uint32_t lanes_log2) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint32_t t = A.src_tile[s];
-    if (t != NONE) seg_activate(A, s, t, 1u);
+    if (t != NONE) seg_activate(A, s >> lanes_log2, t, 1u);
 }
 
 // Splits every active tile's bucket into units of G sources, zeroes the
@@ -434,19 +925,22 @@ __global__ void k_seg_prologue(uint32_t *__restrict__ cnt_next, uint32_t T,
     }
 }
 
+// Final distance of chunk source s at vertex v from the segmented state
+// (lanes_log2 = 0: one source per state row; 6: blocks of 64 sources).
 __device__ __forceinline__ uint32_t seg_value(const uint32_t *tile_of, const uint32_t *pos_of,
                                               const uint8_t *visited, const uint32_t *gdist,
-                                              uint32_t T, uint32_t Vt, uint32_t s, uint32_t src_v,
-                                              uint32_t v) {
+                                              uint32_t T, uint32_t Vt, uint32_t lanes_log2,
+                                              uint32_t s, uint32_t src_v, uint32_t v) {
     const uint32_t t = tile_of[v];
     if (t == NONE) return v == src_v ? 0u : INF;
-    if (!visited[static_cast<size_t>(s) * T + t]) return INF;
-    return gdist[static_cast<size_t>(s) * Vt + pos_of[v]];
+    const size_t b = s >> lanes_log2, l = s & ((1u << lanes_log2) - 1u);
+    if (!visited[b * T + t]) return INF;
+    return gdist[((b * Vt + pos_of[v]) << lanes_log2) + l];
 }
 
 __global__ void k_seg_emit(const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
                            const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
-                           uint32_t T, uint32_t Vt, uint32_t V, uint32_t rows,
+                           uint32_t T, uint32_t Vt, uint32_t lanes_log2, uint32_t V, uint32_t rows,
                            const uint32_t *__restrict__ row_src_idx,
                            const uint32_t *__restrict__ row_src_vertex,
                            const uint32_t *__restrict__ out_row, uint32_t *__restrict__ out) {
@@ -454,7 +948,7 @@ __global__ void k_seg_emit(const uint32_t *__restrict__ tile_of, const uint32_t 
         const uint32_t s = row_src_idx[r], sv = row_src_vertex[r];
         uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
         for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
-            o[v] = seg_value(tile_of, pos_of, visited, gdist, T, Vt, s, sv, v);
+            o[v] = seg_value(tile_of, pos_of, visited, gdist, T, Vt, lanes_log2, s, sv, v);
     }
 }
 
@@ -541,7 +1035,7 @@ __global__ void k_gather_seg(uint32_t num_orders, const uint32_t *__restrict__ p
                              const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n,
                              const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
                              const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
-                             uint32_t T, uint32_t Vt, uint32_t *__restrict__ out) {
+                             uint32_t T, uint32_t Vt, uint32_t lanes_log2, uint32_t *__restrict__ out) {
     for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
         const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
         const uint64_t ob = out_base[o];
@@ -549,8 +1043,8 @@ __global__ void k_gather_seg(uint32_t num_orders, const uint32_t *__restrict__ p
             const uint32_t i = k / P, j = k - i * P;
             const uint32_t si = src_idx_of_pick[a + i];
             if (si < lo || si >= lo + n) continue;
-            out[ob + k] = seg_value(tile_of, pos_of, visited, gdist, T, Vt, si - lo, picks[a + i],
-                                    picks[a + j]);
+            out[ob + k] = seg_value(tile_of, pos_of, visited, gdist, T, Vt, lanes_log2, si - lo,
+                                    picks[a + i], picks[a + j]);
         }
     }
 }
@@ -622,12 +1116,17 @@ __global__ void k_weight_scatter(uint32_t n, const uint32_t *__restrict__ arc,
                                  const uint32_t *__restrict__ neww, uint32_t *__restrict__ w,
                                  uint32_t *__restrict__ in_w, const uint32_t *__restrict__ in_pos,
                                  uint32_t *__restrict__ l_arc, uint32_t *__restrict__ x_w,
-                                 const uint32_t *__restrict__ arc_slot) {
+                                 const uint32_t *__restrict__ arc_slot, uint32_t *__restrict__ li_arc,
+                                 const uint32_t *__restrict__ arc_slot_in) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t a = arc[i], nw = neww[i];
     w[a] = nw;
     in_w[in_pos[a]] = nw;
+    if (arc_slot_in) {
+        const uint32_t si = arc_slot_in[a];
+        if (si != NONE) li_arc[si] = (li_arc[si] & 0xFFFF0000u) | (nw & 0xFFFFu);
+    }
     if (arc_slot) {
         const uint32_t sl = arc_slot[a];
         if (sl == NONE) return;
@@ -737,13 +1236,16 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
     A.cursor = ss.cursor;
     A.pass_ctr = ss.pass_ctr;
     A.G = G;
+    A.li_off = ts.d_li_off.p;
+    A.li_arc = ts.d_li_arc.p;
+    A.nsrc = ss.nsrc;
     return A;
 }
 
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st) {
     // seeds land in parity 0; their stamp is 1 (pass 0's list)
     SegPassArgs A = seg_args(ts, ss, 1u, 1u);
-    hipLaunchKernelGGL(k_seg_seed, blocks_for(n ? n : 1, 256), 256, 0, st, A, n);
+    hipLaunchKernelGGL(k_seg_seed, blocks_for(n ? n : 1, 256), 256, 0, st, A, n, ss.lanes_log2);
     check_launch("seg_seed");
 }
 
@@ -761,6 +1263,23 @@ void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
         ss.cnt + static_cast<size_t>(par) * ts.T, G, ss.units, ss.nunits, ss.stats);
     check_launch("seg_plan");
     SegPassArgs A = seg_args(ts, ss, par, G);
+    if (ss.lanes_log2 == 6) {
+#define WR_SEGB_CASE(CAPV, NWV)                                                          \
+        if (tile_cap == CAPV && waves == NWV) {                                          \
+            if (ev_begin) WR_HIP(hipEventRecord(ev_begin, st));                          \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_segb_pass<CAPV, NWV>), grid, NWV * 64, 0, st, A); \
+            check_launch("segb_pass");                                                   \
+            if (ev_end) WR_HIP(hipEventRecord(ev_end, st));                              \
+            return;                                                                      \
+        }
+        WR_SEGB_CASE(256, 8)
+        WR_SEGB_CASE(256, 16)
+        WR_SEGB_CASE(512, 8)
+        WR_SEGB_CASE(512, 16)
+#undef WR_SEGB_CASE
+        fail(WR_E_UNSUPPORTED, "no source-blocked segment kernel for tile size " +
+                                   std::to_string(tile_cap) + " with " + std::to_string(waves) + " waves");
+    }
 #define WR_SEG_CASE(CAPV, NWV)                                                           \
     if (tile_cap == CAPV && waves == NWV) {                                              \
         if (ev_begin) WR_HIP(hipEventRecord(ev_begin, st));                              \
@@ -779,8 +1298,11 @@ void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
                                " with " + std::to_string(waves) + " waves");
 }
 
-uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves) {
+uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves, uint32_t lanes) {
     const uint32_t words = tile_cap / 32;
+    if (lanes == 64)
+        return tile_cap * 256 + 2 * tile_cap * 4 + 4 * tile_cap * (4 + 2) + 3 * words * 4 +
+               tile_cap * 2 + 8;
     return (tile_cap + 2) * 2 + 4 * tile_cap * 4 +
            waves * (tile_cap * 4 + tile_cap * 2 + 2 * words * 4) + 4;
 }
@@ -790,8 +1312,8 @@ void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t
                      const uint32_t *out_row, uint32_t *out, hipStream_t st) {
     if (!rows) return;
     dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
-    hipLaunchKernelGGL(k_seg_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited, ss.gdist, ts.T,
-                                      ts.Vt, V, rows, row_src_idx, row_src_vertex, out_row, out);
+    hipLaunchKernelGGL(k_seg_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited, ss.gdist,
+                       ts.T, ts.Vt, ss.lanes_log2, V, rows, row_src_idx, row_src_vertex, out_row, out);
     check_launch("seg_emit");
 }
 
@@ -821,7 +1343,7 @@ void launch_gather_seg(uint32_t num_orders, const uint32_t *pick_off, const uint
     if (!num_orders) return;
     hipLaunchKernelGGL(k_gather_seg, blocks_for(num_orders, 1, 65535), 256, 0, st, 
         num_orders, pick_off, picks, out_base, src_idx_of_pick, chunk_lo, chunk_n, ts.d_tile_of.p,
-        ts.d_pos_of.p, ss.visited, ss.gdist, ts.T, ts.Vt, out);
+        ts.d_pos_of.p, ss.visited, ss.gdist, ts.T, ts.Vt, ss.lanes_log2, out);
     check_launch("gather_seg");
 }
 
@@ -856,10 +1378,11 @@ void launch_arc_src(const uint32_t *row_ptr, uint32_t V, uint32_t *arc_src, hipS
 
 void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww, uint32_t *w,
                            uint32_t *in_w, const uint32_t *in_pos, uint32_t *l_arc, uint32_t *x_w,
-                           const uint32_t *arc_slot, hipStream_t st) {
+                           const uint32_t *arc_slot, uint32_t *li_arc, const uint32_t *arc_slot_in,
+                           hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_weight_scatter, blocks_for(n, 256), 256, 0, st, n, arc, neww, w, in_w, in_pos, l_arc, x_w,
-                                                          arc_slot);
+    hipLaunchKernelGGL(k_weight_scatter, blocks_for(n, 256), 256, 0, st, n, arc, neww, w, in_w, in_pos,
+                       l_arc, x_w, arc_slot, li_arc, arc_slot_in);
     check_launch("weight_scatter");
 }
 
@@ -887,5 +1410,66 @@ void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *acti
                        active);
     check_launch("srv_mark_active");
 }
+
+void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st) {
+    SegState dummy;
+    SegPassArgs A = seg_args(ts, dummy, 0u, 1u);
+    if (tile_cap == 256)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_custom<256, 8>), grid, 512, 0, st, A, F);
+    else if (tile_cap == 512)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_custom<512, 8>), grid, 512, 0, st, A, F);
+    else
+        fail(WR_E_UNSUPPORTED, "overlay tables need tiles of at most 512 vertices");
+    check_launch("ovl_custom");
+}
+
+void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t G, uint32_t grid,
+                     const uint32_t *F, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (overlay pass)");
+    const uint32_t nx = par ^ 1u;
+    hipLaunchKernelGGL(k_seg_prologue, blocks_for(ts.T, 256, 64), 256, 0, st,
+                       ss.cnt + static_cast<size_t>(nx) * ts.T, ts.T, ss.ntiles + nx, ss.nunits, ss.cursor,
+                       ss.pass_ctr);
+    check_launch("seg_prologue");
+    hipLaunchKernelGGL(k_seg_plan, blocks_for(ts.T, 256, 64), 256, 0, st,
+                       ss.tiles + static_cast<size_t>(par) * ts.T, ss.ntiles + par,
+                       ss.cnt + static_cast<size_t>(par) * ts.T, G, ss.units, ss.nunits, ss.stats);
+    check_launch("seg_plan");
+    SegPassArgs A = seg_args(ts, ss, par, G);
+    if (ev_begin) WR_HIP(hipEventRecord(ev_begin, st));
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW>), grid, OVL_NW * 64, 0, st, A, F);
+    check_launch("ovl_pass");
+    if (ev_end) WR_HIP(hipEventRecord(ev_end, st));
+}
+
+void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
+                     const uint32_t *row_src_idx, const uint32_t *row_src_vertex, const uint32_t *out_row,
+                     uint32_t *out, hipStream_t st) {
+    if (!rows) return;
+    dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
+    hipLaunchKernelGGL(k_ovl_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited, ss.gdist,
+                       ss.inbox, F, ts.d_port_base.p, ts.T, ts.Vt, std::max(ts.NP, 1u), V, rows, row_src_idx,
+                       row_src_vertex, out_row, out);
+    check_launch("ovl_emit");
+}
+
+void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                       const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
+                       uint32_t chunk_n, const TileSet &ts, const SegState &ss, const uint32_t *F,
+                       uint32_t *out, hipStream_t st) {
+    if (!num_orders) return;
+    hipLaunchKernelGGL(k_gather_ovl, blocks_for(num_orders, 1, 65535), 256, 0, st, num_orders, pick_off, picks,
+                       out_base, src_idx_of_pick, chunk_lo, chunk_n, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited,
+                       ss.gdist, ss.inbox, F, ts.d_port_base.p, ts.T, ts.Vt, std::max(ts.NP, 1u), out);
+    check_launch("gather_ovl");
+}
+
+uint32_t ovl_pass_lds_bytes() {
+    return (OVL_XCAP * 64 + 2 * OVL_XCAP + 1 + 3 * OVL_PCAP + OVL_NW * (OVL_GRP * 64 + OVL_ACT)) * 4 +
+           OVL_PCAP * 2 + 8;
+}
+uint32_t ovl_max_exits() { return OVL_XCAP; }
+uint32_t ovl_max_cross() { return OVL_PCAP; }
+uint32_t ovl_waves() { return OVL_NW; }
 
 }  // namespace wr

@@ -324,6 +324,7 @@ wr_status wr_graph_update_weights(wr_graph *g, uint32_t n, const uint32_t *arc_i
         launch_weight_scatter(static_cast<uint32_t>(arcs.size()), da.p, dv.p, g->d_w.p, g->d_in_w.p,
                               g->d_in_pos_of_arc.p, ts ? ts->d_l_arc.p : nullptr,
                               ts ? ts->d_x_w.p : nullptr, ts ? ts->d_arc_slot.p : nullptr,
+                              ts ? ts->d_li_arc.p : nullptr, ts ? ts->d_arc_slot_in.p : nullptr,
                               ctx->stream);
         if (ts) {
             for (size_t k = 0; k < arcs.size(); ++k) {
@@ -332,6 +333,8 @@ wr_status wr_graph_update_weights(wr_graph *g, uint32_t n, const uint32_t *arc_i
                     ts->x_w[sl & 0x7FFFFFFFu] = vals[k];
                 else
                     ts->l_arc[sl] = (ts->l_arc[sl] & 0xFFFF0000u) | (vals[k] & 0xFFFFu);
+                const uint32_t si = ts->arc_slot_in[arcs[k]];
+                if (si != NONE) ts->li_arc[si] = (ts->li_arc[si] & 0xFFFF0000u) | (vals[k] & 0xFFFFu);
             }
         }
         WR_HIP(hipStreamSynchronize(ctx->stream));

@@ -59,11 +59,13 @@ struct KernelEvents {
 
 struct SegWork {
     uint64_t gen = 0;
-    uint32_t S_cap = 0, tile_cap = 0, waves = 0, G = 0, K = 0, grid = 0;
+    uint32_t S_cap = 0, tile_cap = 0, waves = 0, G = 0, K = 0, grid = 0, lanes = 1;   // S_cap: state rows
     bool timed = false;
+    bool overlay = false;
+    uint32_t grid_ovl = 0;
     KernelEvents kev;
     SegBuffers buf;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;   // K passes of the segment kernel, or of the overlay kernel
     SegState ss;
     ~SegWork() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -110,21 +112,40 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+bool overlay_supported(const wr_graph *g) {
+    const TileSet *ts = g->tiles;
+    return ts && g->lanes == 64 && g->max_w < 65536u && ts->max_ports <= 64 &&
+           ts->max_exits <= ovl_max_exits() && ts->max_cross <= ovl_max_cross() &&
+           (ts->tile_cap == 256 || ts->tile_cap == 512);
+}
+
+// The schedule of a call.  Segment-based schedules build the tile tables on
+// first use; AUTO takes the overlay tables when the tiling allows them, the
+// source-blocked segments otherwise, and the frontier when weights do not fit
+// the 16-bit tile packing.
 uint32_t resolve_algo(wr_graph *g, uint32_t flags) {
     uint32_t a = flags & WR_ALGO_MASK;
-    if (a == WR_ALGO_AUTO) a = g->max_w < 65536u ? WR_ALGO_SEGMENTED : WR_ALGO_FRONTIER;
     switch (a) {
+    case WR_ALGO_AUTO:
     case WR_ALGO_SWEEP:
     case WR_ALGO_FRONTIER:
     case WR_ALGO_SEGMENTED:
     case WR_ALGO_EDGE_B1:
     case WR_ALGO_EDGE_B0:
+    case WR_ALGO_OVERLAY:
         break;
     default:
         fail(WR_E_INVALID, "unknown WR_ALGO value");
     }
-    if (a == WR_ALGO_SEGMENTED && g->max_w >= 65536u)
-        fail(WR_E_UNSUPPORTED, "segmented schedule packs weights in 16 bits; max weight is too large");
+    if ((a == WR_ALGO_SEGMENTED || a == WR_ALGO_OVERLAY) && g->max_w >= 65536u)
+        fail(WR_E_UNSUPPORTED, "segment schedules pack weights in 16 bits; max weight is too large");
+    if (a == WR_ALGO_AUTO && g->max_w >= 65536u) return WR_ALGO_FRONTIER;
+    if (a == WR_ALGO_AUTO || a == WR_ALGO_SEGMENTED || a == WR_ALGO_OVERLAY) rebuild_tiles_if_needed(g);
+    if (a == WR_ALGO_AUTO) a = overlay_supported(g) ? WR_ALGO_OVERLAY : WR_ALGO_SEGMENTED;
+    if (a == WR_ALGO_OVERLAY && !overlay_supported(g))
+        fail(WR_E_UNSUPPORTED, "the tiling does not fit the overlay tables (tiles of at most 512 "
+                               "vertices with at most 64 ports, " + std::to_string(ovl_max_exits()) +
+                               " exits and " + std::to_string(ovl_max_cross()) + " cross arcs each)");
     return a;
 }
 
@@ -167,16 +188,17 @@ uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
 
 }  // namespace
 
-uint64_t SegBuffers::bytes_per_source(const TileSet &ts, uint32_t G) {
-    return 4ull * ts.Vt + 4ull * ts.NP + 1ull * ts.T + 4ull * ts.T + 8ull * ts.T +
+uint64_t SegBuffers::bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes) {
+    return 4ull * lanes * (ts.Vt + ts.NP + 2) + 1ull * ts.T + 4ull * ts.T + 8ull * ts.T +
            8ull * ts.T / G + 8;
 }
 
-void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g) {
+void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g, uint32_t ln) {
     S_cap = S;
     G = g;
-    gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt);
-    inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u));
+    lanes = ln;
+    gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt * lanes);
+    inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u) * lanes);
     stamps.alloc(ctx, static_cast<size_t>(S) * ts.T);
     visited.alloc(ctx, static_cast<size_t>(S) * ts.T);
     cnt.alloc(ctx, 2ull * ts.T);
@@ -185,10 +207,12 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     ctr.alloc(ctx, 8);
     units.alloc(ctx, seg_units_cap(ts, S, G));
     stats.alloc(ctx, 2);
-    src_pos.alloc(ctx, S);
-    src_tile.alloc(ctx, S);
+    src_pos.alloc(ctx, static_cast<size_t>(S) * lanes);
+    src_tile.alloc(ctx, static_cast<size_t>(S) * lanes);
     ss = SegState{};
     ss.S = S;
+    ss.lanes_log2 = lanes == 64 ? 6u : 0u;
+    ss.nsrc = S * lanes;
     ss.gdist = gdist.p;
     ss.inbox = inbox.p;
     ss.visited = visited.p;
@@ -206,11 +230,33 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     ss.src_tile = src_tile.p;
 }
 
-uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves) {
-    const uint32_t lds = seg_pass_lds_bytes(tile_cap, waves);
+uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves, uint32_t lanes) {
+    const uint32_t lds = seg_pass_lds_bytes(tile_cap, waves, lanes);
     uint32_t per_cu = std::max(1u, (160u * 1024u) / lds);
     per_cu = std::min(per_cu, 32u / waves);
     return static_cast<uint32_t>(ctx->num_cus) * per_cu;
+}
+
+// Captures K overlay passes starting at parity 1 (pass 0 of a chunk is the
+// segment kernel over the source tiles), so a replay ends at parity 1.
+hipGraphExec_t capture_ovl_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t G, uint32_t grid,
+                                  const uint32_t *F, hipStream_t st) {
+    hipGraph_t graph;
+    WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+        for (uint32_t i = 0; i < K; ++i) launch_ovl_step(ts, ss, (i + 1) & 1u, G, grid, F, st);
+    } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(st, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+    }
+    WR_HIP(hipStreamEndCapture(st, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) fail(WR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return exec;
 }
 
 hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t tile_cap,
@@ -235,38 +281,59 @@ hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_
 
 namespace {
 
-SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed) {
+// Boundary tables of the current weight epoch (computed on first use and
+// after every weight update).
+void ensure_overlay_tables(wr_graph *g) {
+    TileSet &ts = *g->tiles;
+    if (!ts.d_F.p) ts.d_F.alloc(g->ctx, static_cast<size_t>(ts.Vt) * 64);
+    if (ts.custom_epoch == g->epoch) return;
+    const uint32_t grid = static_cast<uint32_t>(g->ctx->num_cus) * 2;
+    launch_ovl_custom(ts, ts.tile_cap, ts.d_F.p, grid, g->ctx->stream);
+    ts.custom_epoch = g->epoch;
+}
+
+SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed, bool overlay) {
     Workspace &ws = workspace(g);
     TileSet &ts = *g->tiles;
     const uint32_t waves = g->waves_per_group;
-    const uint32_t G = g->sources_per_unit ? g->sources_per_unit : 4 * waves;
+    const uint32_t lanes = g->lanes;
+    const uint32_t G = overlay ? ovl_waves()
+                               : (g->sources_per_unit ? g->sources_per_unit : (lanes == 64 ? 4 : 4 * waves));
     const uint32_t K = std::max(2u, g->passes_per_replay & ~1u);
+    const uint32_t rows_need = (S_need + lanes - 1) / lanes;
     SegWork *w = ws.seg.get();
-    const bool fits = w && w->gen == g->tiles_gen && w->S_cap >= S_need && w->tile_cap == ts.tile_cap &&
-                      w->waves == waves && w->G == G && w->K == K && w->timed == timed &&
-                      (!graph_mode || w->exec);
+    const bool fits = w && w->gen == g->tiles_gen && w->S_cap >= rows_need && w->tile_cap == ts.tile_cap &&
+                      w->waves == waves && w->lanes == lanes && w->G == G && w->K == K &&
+                      w->timed == timed && w->overlay == overlay && (!graph_mode || w->exec);
     if (fits) return *w;
     // size the chunk: the request, bounded by the budget (keep what we hold)
     ws.seg.reset();
-    const uint64_t per = SegBuffers::bytes_per_source(ts, G);
+    const uint64_t per = SegBuffers::bytes_per_row(ts, G, lanes);
     const uint64_t avail = g->ctx->available();
-    uint64_t S_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
-    uint32_t S_cap = static_cast<uint32_t>(std::min<uint64_t>(S_need, S_fit));
-    if (S_cap == 0) fail(WR_E_NOMEM, "not even one source fits the memory budget (segmented)");
+    uint64_t R_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
+    uint32_t R_cap = static_cast<uint32_t>(std::min<uint64_t>(rows_need, R_fit));
+    if (R_cap == 0) fail(WR_E_NOMEM, "not even one source fits the memory budget (segmented)");
     auto nw = std::make_unique<SegWork>();
     nw->gen = g->tiles_gen;
-    nw->S_cap = S_cap;
+    nw->S_cap = R_cap;
     nw->tile_cap = ts.tile_cap;
     nw->waves = waves;
+    nw->lanes = lanes;
     nw->G = G;
     nw->K = K;
     nw->timed = timed;
+    nw->overlay = overlay;
     if (timed) nw->kev.create(K);
     wr_context *ctx = g->ctx;
-    nw->buf.init(ctx, ts, S_cap, G);
+    nw->buf.init(ctx, ts, R_cap, G, lanes);
     nw->ss = nw->buf.ss;
-    nw->grid = seg_pass_grid(ctx, ts.tile_cap, waves);
-    if (graph_mode) nw->exec = capture_seg_passes(ts, nw->ss, K, ts.tile_cap, waves, G, nw->grid, ctx->stream);
+    nw->grid = seg_pass_grid(ctx, ts.tile_cap, waves, lanes);
+    nw->grid_ovl = static_cast<uint32_t>(ctx->num_cus) *
+                   std::min(32u / ovl_waves(), std::max(1u, (160u * 1024u) / ovl_pass_lds_bytes()));
+    if (overlay) ensure_overlay_tables(g);
+    if (graph_mode)
+        nw->exec = overlay ? capture_ovl_passes(ts, nw->ss, K, G, nw->grid_ovl, ts.d_F.p, ctx->stream)
+                           : capture_seg_passes(ts, nw->ss, K, ts.tile_cap, waves, G, nw->grid, ctx->stream);
     ws.seg = std::move(nw);
     return *ws.seg;
 }
@@ -278,19 +345,22 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     wr_context *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     SegState ss = w.ss;
-    // per-source tables
-    std::vector<uint32_t> sp(n), stl(n);
+    // per-source tables, padded with NONE up to the state's capacity
+    const uint32_t lanes = w.lanes;
+    const uint32_t rows = (n + lanes - 1) / lanes;
+    const size_t cap_src = static_cast<size_t>(w.S_cap) * lanes;
+    std::vector<uint32_t> sp(cap_src, NONE), stl(cap_src, NONE);
     for (uint32_t i = 0; i < n; ++i) {
         const uint32_t v = usrc[lo + i];
         sp[i] = ts.pos_of[v];
         stl[i] = ts.tile_of[v];
     }
-    WR_HIP(hipMemcpyAsync(w.buf.src_pos.p, sp.data(), n * 4ull, hipMemcpyHostToDevice, st));
-    WR_HIP(hipMemcpyAsync(w.buf.src_tile.p, stl.data(), n * 4ull, hipMemcpyHostToDevice, st));
-    // reset the chunk state (S stays the buffer capacity for indexing)
-    launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(n) * std::max(ts.NP, 1u), INF, st);
-    launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(n) * ts.T, 0u, st);
-    launch_fill_u8(w.buf.visited.p, static_cast<size_t>(n) * ts.T, 0u, st);
+    WR_HIP(hipMemcpyAsync(w.buf.src_pos.p, sp.data(), cap_src * 4, hipMemcpyHostToDevice, st));
+    WR_HIP(hipMemcpyAsync(w.buf.src_tile.p, stl.data(), cap_src * 4, hipMemcpyHostToDevice, st));
+    // reset the chunk state (the layout keeps the capacity for indexing)
+    launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(rows) * std::max(ts.NP, 1u) * lanes, INF, st);
+    launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(rows) * ts.T, 0u, st);
+    launch_fill_u8(w.buf.visited.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
     launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
@@ -302,16 +372,27 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     const uint32_t K = w.K;
     uint64_t passes = 0;
     const uint64_t cap = static_cast<uint64_t>(g->V) + 2ull * K + 8;
+    // overlay: pass 0 relaxes the source tiles with the segment kernel; the
+    // replayed passes then start at parity 1 and end there
+    const uint32_t par0 = w.overlay ? 1u : 0u;
+    if (w.overlay) {
+        if (ts.custom_epoch != g->epoch) ensure_overlay_tables(g);
+        launch_seg_step(ts, ss, 0u, ts.tile_cap, w.waves, w.G, w.grid, st);
+        passes += 1;
+    }
     for (;;) {
         if (graph_mode) {
             WR_HIP(hipGraphLaunch(w.exec, st));
+        } else if (w.overlay) {
+            for (uint32_t i = 0; i < K; ++i)
+                launch_ovl_step(ts, ss, (i + 1) & 1u, w.G, w.grid_ovl, ts.d_F.p, st, w.kev.b(i), w.kev.e(i));
         } else {
             for (uint32_t i = 0; i < K; ++i)
                 launch_seg_step(ts, ss, i & 1u, ts.tile_cap, w.waves, w.G, w.grid, st, w.kev.b(i),
                                 w.kev.e(i));
         }
         passes += K;
-        WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + 0, 4, hipMemcpyDeviceToHost, st));
+        WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + par0, 4, hipMemcpyDeviceToHost, st));
         WR_HIP(hipStreamSynchronize(st));
         if (!w.kev.collect(K, info)) fail(WR_E_DEVICE, "kernel event timing failed");
         if (*workspace(g).h_flag == 0) break;
@@ -515,14 +596,17 @@ void edge_solve(wr_graph *g, const uint32_t *d_src, uint32_t N, uint32_t *d_rows
 
 // Orders `lo..lo+n)` of usrc that fit one chunk of the chosen schedule.
 uint32_t chunk_sources(wr_graph *g, uint32_t algo, uint32_t total, bool graph_mode, bool timed) {
-    if (algo == WR_ALGO_SEGMENTED) return seg_workspace(g, total, graph_mode, timed).S_cap;
+    if (algo == WR_ALGO_SEGMENTED || algo == WR_ALGO_OVERLAY) {
+        SegWork &w = seg_workspace(g, total, graph_mode, timed, algo == WR_ALGO_OVERLAY);
+        return w.S_cap * w.lanes;
+    }
     const uint32_t nb_need = (total + LANES - 1) / LANES;
     return blk_workspace(g, nb_need, algo == WR_ALGO_FRONTIER, graph_mode, timed).nb_cap * LANES;
 }
 
 void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, uint32_t lo,
                  uint32_t n, bool graph_mode, wr_run_info &info) {
-    if (algo == WR_ALGO_SEGMENTED)
+    if (algo == WR_ALGO_SEGMENTED || algo == WR_ALGO_OVERLAY)
         seg_solve_chunk(g, *workspace(g).seg, usrc, lo, n, graph_mode, info);
     else
         blk_solve_chunk(g, *workspace(g).blk, usrc, lo, n, graph_mode, info);
@@ -549,7 +633,11 @@ struct StreamJoin {
 void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
                const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out) {
     hipStream_t st = g->ctx->stream;
-    if (algo == WR_ALGO_SEGMENTED) {
+    if (algo == WR_ALGO_OVERLAY) {
+        SegWork &w = *workspace(g).seg;
+        launch_ovl_emit(*g->tiles, w.ss, g->tiles->d_F.p, g->V, rows, d_row_idx, d_row_vertex, d_out_row, out,
+                        st);
+    } else if (algo == WR_ALGO_SEGMENTED) {
         SegWork &w = *workspace(g).seg;
         launch_seg_emit(*g->tiles, w.ss, g->V, rows, d_row_idx, d_row_vertex, d_out_row, out, st);
     } else {
@@ -624,7 +712,6 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
         return WR_OK;
     }
 
-    if (algo == WR_ALGO_SEGMENTED) rebuild_tiles_if_needed(g);
     Plan plan = make_plan(g, sources, S, true);
     const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
     info.unique_sources = U;
@@ -772,7 +859,6 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
         info.unique_sources = NPK;
         info.chunks = num_orders;
     } else {
-        if (algo == WR_ALGO_SEGMENTED) rebuild_tiles_if_needed(g);
         Plan plan = make_plan(g, picks, NPK, true);
         const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
         info.unique_sources = U;
@@ -782,7 +868,10 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
             const uint32_t n = std::min(chunk, U - lo);
             solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info);
             info.chunks += 1;
-            if (algo == WR_ALGO_SEGMENTED)
+            if (algo == WR_ALGO_OVERLAY)
+                launch_gather_ovl(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
+                                  workspace(g).seg->ss, g->tiles->d_F.p, dout, st);
+            else if (algo == WR_ALGO_SEGMENTED)
                 launch_gather_seg(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
                                   workspace(g).seg->ss, dout, st);
             else
@@ -849,16 +938,18 @@ wr_status wr_graph_set_schedule(wr_graph *g, uint32_t tile_vertices, uint32_t wa
                                 uint32_t passes_per_replay) {
     WR_API_BEGIN
     if (!g) fail(WR_E_INVALID, "graph is NULL");
-    if (tile_vertices) {
-        if (tile_vertices != 1024 && tile_vertices != 2048 && tile_vertices != 4096)
-            fail(WR_E_INVALID, "tile_vertices must be 1024, 2048 or 4096");
-        g->tile_vertices = tile_vertices;
-    }
-    if (waves_per_group) g->waves_per_group = waves_per_group;
-    const uint32_t t = g->tile_vertices, wv = g->waves_per_group;
-    const bool ok = (t == 1024 && (wv == 4 || wv == 8)) || (t == 2048 && (wv == 4 || wv == 8)) ||
-                    (t == 4096 && wv == 2);
+    uint32_t t = tile_vertices ? tile_vertices : g->tile_vertices;
+    uint32_t wv = waves_per_group ? waves_per_group : g->waves_per_group;
+    // tile sizes up to 512 run the source-blocked kernel (64 sources per
+    // workgroup item); larger tiles run one source per wave
+    const uint32_t lanes = t <= 512 ? 64u : 1u;
+    const bool ok = lanes == 64 ? ((t == 256 || t == 512) && (wv == 8 || wv == 16))
+                                : ((t == 1024 && (wv == 4 || wv == 8)) || (t == 2048 && (wv == 4 || wv == 8)) ||
+                                   (t == 4096 && wv == 2));
     if (!ok) fail(WR_E_INVALID, "unsupported (tile_vertices, waves_per_group) pair");
+    g->tile_vertices = t;
+    g->waves_per_group = wv;
+    g->lanes = lanes;
     if (passes_per_replay) g->passes_per_replay = std::max(2u, passes_per_replay & ~1u);
     destroy_workspace(g->ws);
     g->ws = nullptr;

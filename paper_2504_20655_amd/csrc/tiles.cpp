@@ -43,7 +43,8 @@ void cut_segment(const std::vector<uint32_t> &verts, const std::vector<uint32_t>
 
 }  // namespace
 
-void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, bool bfs_grow) {
+void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, bool bfs_grow,
+                 const uint32_t *sub, uint32_t nsub) {
     const uint32_t V = g->V;
     const auto &row_ptr = g->row_ptr;
     const auto &col = g->col;
@@ -103,19 +104,22 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
         }
         ts->num_segments = T;
     } else {
-        // bucket incident vertices by segment, id order inside a segment
-        std::vector<uint32_t> cnt(nseg + 1, 0);
+        // bucket incident vertices by part (the finer partition if given,
+        // else the segment), id order inside a part, and cut parts to the cap
+        const uint32_t *part = sub ? sub : seg;
+        const uint32_t nparts = sub ? nsub : nseg;
+        std::vector<uint32_t> cnt(nparts + 1, 0);
         for (uint32_t v = 0; v < V; ++v)
-            if (inc[v]) cnt[seg[v] + 1]++;
-        for (uint32_t s = 0; s < nseg; ++s) cnt[s + 1] += cnt[s];
-        std::vector<uint32_t> order(cnt[nseg]);
+            if (inc[v]) cnt[part[v] + 1]++;
+        for (uint32_t s = 0; s < nparts; ++s) cnt[s + 1] += cnt[s];
+        std::vector<uint32_t> order(cnt[nparts]);
         {
             std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
             for (uint32_t v = 0; v < V; ++v)
-                if (inc[v]) order[fill[seg[v]]++] = v;
+                if (inc[v]) order[fill[part[v]]++] = v;
         }
         std::vector<uint32_t> verts;
-        for (uint32_t s = 0; s < nseg; ++s) {
+        for (uint32_t s = 0; s < nparts; ++s) {
             verts.assign(order.begin() + cnt[s], order.begin() + cnt[s + 1]);
             cut_segment(verts, row_ptr, cap, ts->tile_of, T);
         }
@@ -178,6 +182,10 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
     }
     ts->NP = ts->port_base[T];
     ts->NB = ts->bo_base[T];
+    for (uint32_t t = 0; t < T; ++t) {
+        ts->max_ports = std::max(ts->max_ports, ts->port_base[t + 1] - ts->port_base[t]);
+        ts->max_exits = std::max(ts->max_exits, ts->bo_base[t + 1] - ts->bo_base[t]);
+    }
 
     // per-position arc lists
     ts->l_off.assign(Vt + 1, 0);
@@ -214,9 +222,37 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
             }
         }
     }
-    for (uint32_t t = 0; t < T; ++t)
+    for (uint32_t t = 0; t < T; ++t) {
         if (ts->l_off[tsize[t + 1]] - ts->l_off[tsize[t]] > 4ull * cap)
             fail(WR_E_INTERNAL, "tile arc budget exceeded");
+        ts->max_cross = std::max(ts->max_cross, ts->x_off[tsize[t + 1]] - ts->x_off[tsize[t]]);
+    }
+
+    // in-tile in-arcs (pull form): the same arcs grouped by target position
+    ts->li_off.assign(Vt + 1, 0);
+    ts->arc_slot_in.assign(g->E, NONE);
+    for (uint32_t p = 0; p < Vt; ++p) {
+        const uint32_t u = ts->vert_of[p];
+        const uint32_t tu = ts->tile_of[u];
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (ts->tile_of[col[e]] == tu) ts->li_off[ts->pos_of[col[e]] + 1]++;
+    }
+    for (uint32_t p = 0; p < Vt; ++p) ts->li_off[p + 1] += ts->li_off[p];
+    ts->li_arc.resize(ts->li_off[Vt]);
+    {
+        std::vector<uint32_t> fill(ts->li_off.begin(), ts->li_off.end() - 1);
+        for (uint32_t p = 0; p < Vt; ++p) {
+            const uint32_t u = ts->vert_of[p];
+            const uint32_t tu = ts->tile_of[u];
+            const uint32_t uloc = p - tsize[tu];
+            for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                if (ts->tile_of[col[e]] != tu) continue;
+                const uint32_t q = fill[ts->pos_of[col[e]]]++;
+                ts->li_arc[q] = (uloc << 16) | (w[e] & 0xFFFFu);
+                ts->arc_slot_in[e] = q;
+            }
+        }
+    }
 
     // upload
     wr_context *ctx = g->ctx;
@@ -235,6 +271,9 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
     upload(ts->d_bo_base, ctx, ts->bo_base, st);
     upload(ts->d_bo_local, ctx, ts->bo_local, st);
     upload(ts->d_arc_slot, ctx, ts->arc_slot, st);
+    upload(ts->d_li_off, ctx, ts->li_off, st);
+    upload(ts->d_li_arc, ctx, ts->li_arc, st);
+    upload(ts->d_arc_slot_in, ctx, ts->arc_slot_in, st);
     WR_HIP(hipStreamSynchronize(st));
     destroy_workspace(g->ws);
     g->ws = nullptr;
@@ -243,12 +282,49 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
     g->tiles_gen += 1;
 }
 
+namespace {
+
+// Grid segments (tile_w x tile_h cells per level) and, nested in them,
+// sub-rectangles of at most `cap` cells: halve the longer side of the
+// segment rectangle until it fits.
+void grid_maps(uint32_t W, uint32_t H, uint32_t L, uint32_t tw, uint32_t th, uint32_t cap,
+               std::vector<uint32_t> &seg, uint32_t &nseg, std::vector<uint32_t> &sub, uint32_t &nsub) {
+    const uint32_t tx = (W + tw - 1) / tw, ty = (H + th - 1) / th;
+    uint32_t sw = tw, sh = th;
+    while (static_cast<uint64_t>(sw) * sh > cap) {
+        if (sw >= sh) sw = (sw + 1) / 2;
+        else sh = (sh + 1) / 2;
+    }
+    const uint32_t sx = (tw + sw - 1) / sw, sy = (th + sh - 1) / sh;
+    nseg = tx * ty * L;
+    nsub = nseg * sx * sy;
+    seg.resize(static_cast<size_t>(W) * H * L);
+    sub.resize(seg.size());
+    for (uint32_t l = 0; l < L; ++l)
+        for (uint32_t y = 0; y < H; ++y)
+            for (uint32_t x = 0; x < W; ++x) {
+                const size_t v = (static_cast<size_t>(l) * H + y) * W + x;
+                const uint32_t s = (l * ty + y / th) * tx + x / tw;
+                seg[v] = s;
+                sub[v] = (s * sy + (y % th) / sh) * sx + (x % tw) / sw;
+            }
+}
+
+}  // namespace
+
 void rebuild_tiles_if_needed(wr_graph *g) {
     if (g->tiles && g->tiles->tile_cap == g->tile_vertices) return;
-    if (g->tiles_user)
+    if (g->grid_W) {
+        std::vector<uint32_t> seg, sub;
+        uint32_t nseg, nsub;
+        grid_maps(g->grid_W, g->grid_H, g->grid_L, g->grid_tw, g->grid_th, g->tile_vertices, seg, nseg, sub,
+                  nsub);
+        build_tiles(g, seg.data(), nseg, g->tile_vertices, false, sub.data(), nsub);
+    } else if (g->tiles_user) {
         build_tiles(g, g->user_seg.data(), g->user_num_segments, g->tile_vertices, false);
-    else
+    } else {
         build_tiles(g, nullptr, 0, g->tile_vertices, true);
+    }
 }
 
 }  // namespace wr
@@ -270,6 +346,7 @@ wr_status wr_graph_set_segments(wr_graph *g, const uint32_t *segment_of_vertex,
     g->user_seg.swap(seg);
     g->user_num_segments = num_segments;
     g->tiles_user = true;
+    g->grid_W = 0;
     WR_API_END
 }
 
@@ -279,19 +356,21 @@ wr_status wr_graph_segment_grid(wr_graph *g, uint32_t W, uint32_t H, uint32_t le
     if (!g) fail(WR_E_INVALID, "graph is NULL");
     if (!W || !H || !levels || !tile_w || !tile_h) fail(WR_E_INVALID, "sizes must be positive");
     if (static_cast<uint64_t>(W) * H * levels != g->V) fail(WR_E_INVALID, "W*H*levels != V");
-    const uint32_t tx = (W + tile_w - 1) / tile_w, ty = (H + tile_h - 1) / tile_h;
-    const uint64_t nseg = static_cast<uint64_t>(tx) * ty * levels;
-    if (nseg >= 0xFFFFFFFFull) fail(WR_E_INVALID, "too many segments");
-    std::vector<uint32_t> seg(g->V);
-    for (uint32_t l = 0; l < levels; ++l)
-        for (uint32_t y = 0; y < H; ++y)
-            for (uint32_t x = 0; x < W; ++x)
-                seg[(static_cast<size_t>(l) * H + y) * W + x] = (l * ty + y / tile_h) * tx + x / tile_w;
+    const uint64_t nseg64 = static_cast<uint64_t>((W + tile_w - 1) / tile_w) * ((H + tile_h - 1) / tile_h) * levels;
+    if (nseg64 >= 0xFFFFFFFFull / 4) fail(WR_E_INVALID, "too many segments");
     WR_HIP(hipSetDevice(g->ctx->device));
-    build_tiles(g, seg.data(), static_cast<uint32_t>(nseg), g->tile_vertices, false);
+    std::vector<uint32_t> seg, sub;
+    uint32_t nseg, nsub;
+    grid_maps(W, H, levels, tile_w, tile_h, g->tile_vertices, seg, nseg, sub, nsub);
+    build_tiles(g, seg.data(), nseg, g->tile_vertices, false, sub.data(), nsub);
     g->user_seg.swap(seg);
-    g->user_num_segments = static_cast<uint32_t>(nseg);
+    g->user_num_segments = nseg;
     g->tiles_user = true;
+    g->grid_W = W;
+    g->grid_H = H;
+    g->grid_L = levels;
+    g->grid_tw = tile_w;
+    g->grid_th = tile_h;
     WR_API_END
 }
 

@@ -131,6 +131,13 @@ struct TileSet {
     uint32_t NB = 0;              // boundary-out vertices (an arc to another tile starts there)
     uint32_t tile_cap = 0;        // maximum tile size the tables were built for
     uint64_t cross_arcs = 0;
+    uint32_t max_ports = 0;       // most ports of one tile
+    uint32_t max_exits = 0;       // most boundary-out vertices of one tile
+    uint32_t max_cross = 0;       // most cross-tile arcs leaving one tile
+    // overlay boundary tables F[pos][64] (lane i = port i of the tile) and the
+    // weight epoch they were computed for
+    DBuf<uint32_t> d_F;
+    uint64_t custom_epoch = ~0ull;
 
     // host copies
     std::vector<uint32_t> tile_of;      // [V]  tile or NONE
@@ -148,10 +155,14 @@ struct TileSet {
     std::vector<uint32_t> bo_base;      // [T+1]
     std::vector<uint32_t> bo_local;     // local index of each boundary-out vertex
     std::vector<uint32_t> arc_slot;     // [E] where CSR arc e lives: l_arc index, or 0x80000000|x index
+    std::vector<uint32_t> li_off;       // [Vt+1] in-tile in-arc offsets (pull form)
+    std::vector<uint32_t> li_arc;       // packed (local src << 16) | w
+    std::vector<uint32_t> arc_slot_in;  // [E] li_arc index of an in-tile arc, NONE for cross arcs
 
     // device copies
     DBuf<uint32_t> d_tile_of, d_pos_of, d_tile_base, d_l_off, d_l_arc, d_x_off, d_x_port, d_x_w,
-        d_x_tile, d_port_base, d_port_local, d_bo_base, d_bo_local, d_arc_slot;
+        d_x_tile, d_port_base, d_port_local, d_bo_base, d_bo_local, d_arc_slot, d_li_off, d_li_arc,
+        d_arc_slot_in;
 };
 
 }  // namespace wr
@@ -183,10 +194,12 @@ struct wr_graph {
     bool tiles_user = false;           // segmentation given by the caller
     std::vector<uint32_t> user_seg;    // caller's segment map (rebuilt on tile-size change)
     uint32_t user_num_segments = 0;
+    uint32_t grid_W = 0, grid_H = 0, grid_L = 0, grid_tw = 0, grid_th = 0;   // last segment_grid spec
 
     // schedule
-    uint32_t tile_vertices = 1024;
+    uint32_t tile_vertices = 256;
     uint32_t waves_per_group = 8;
+    uint32_t lanes = 64;               // 64: source-blocked segment kernel; 1: one source per wave
     uint32_t sources_per_unit = 0;     // 0 = 4 * waves_per_group
     uint32_t passes_per_replay = 8;
 
@@ -236,8 +249,10 @@ struct SegState {
     uint32_t *cursor = nullptr;     // [1]
     uint32_t *pass_ctr = nullptr;   // [1]
     unsigned long long *stats = nullptr;   // [2]: items, passes with work
-    const uint32_t *src_pos = nullptr;     // [S] position or NONE
-    const uint32_t *src_tile = nullptr;    // [S] tile or NONE
+    const uint32_t *src_pos = nullptr;     // [sources] position or NONE
+    const uint32_t *src_tile = nullptr;    // [sources] tile or NONE
+    uint32_t lanes_log2 = 0;   // 0: a state row per source; 6: per block of 64 sources
+    uint32_t nsrc = 0;         // sources of the chunk (blocked layout: lanes beyond are idle)
 };
 // activates (s, tile of source s) for the chunk's sources s < n
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
@@ -246,24 +261,26 @@ void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStr
 void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t tile_cap,
                      uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st,
                      hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
-uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves);
+uint32_t seg_pass_lds_bytes(uint32_t tile_cap, uint32_t waves, uint32_t lanes);
 void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t rows,
                      const uint32_t *row_src_idx, const uint32_t *row_src_vertex,
                      const uint32_t *out_row, uint32_t *out, hipStream_t st);
 
-// Device buffers of one segmented state of S_cap sources (see SegState).
+// Device buffers of one segmented state of S_cap state rows (sources, or
+// blocks of 64 sources with lanes = 64; see SegState).
 struct SegBuffers {
-    uint32_t S_cap = 0, G = 0;
+    uint32_t S_cap = 0, G = 0, lanes = 1;
     DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile;
     DBuf<uint8_t> visited;
     DBuf<uint2> units;
     DBuf<unsigned long long> stats;
     SegState ss;
-    void init(wr_context *ctx, const TileSet &ts, uint32_t S_cap, uint32_t G);
-    static uint64_t bytes_per_source(const TileSet &ts, uint32_t G);
+    void init(wr_context *ctx, const TileSet &ts, uint32_t S_cap, uint32_t G, uint32_t lanes);
+    // device bytes per state row
+    static uint64_t bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes);
 };
 // Persistent grid size of the pass kernel for this schedule.
-uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves);
+uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves, uint32_t lanes);
 // Captures K passes (parities 0,1,0,...) into an instantiated graph.
 hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t tile_cap,
                                   uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st);
@@ -276,6 +293,24 @@ void launch_srv_reset_slots(const TileSet &ts, const SegState &ss, const uint32_
 void launch_srv_seed(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
                      hipStream_t st);
 void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *active, hipStream_t st);
+
+// overlay schedule: per-epoch boundary tables F[pos][port] of every tile,
+// dense min-plus passes over (tile, block) items, and the read-outs
+void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st);
+void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
+                     const uint32_t *F, hipStream_t st, hipEvent_t ev_begin = nullptr,
+                     hipEvent_t ev_end = nullptr);
+void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
+                     const uint32_t *row_src_idx, const uint32_t *row_src_vertex, const uint32_t *out_row,
+                     uint32_t *out, hipStream_t st);
+void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                       const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
+                       uint32_t chunk_n, const TileSet &ts, const SegState &ss, const uint32_t *F,
+                       uint32_t *out, hipStream_t st);
+uint32_t ovl_pass_lds_bytes();
+uint32_t ovl_max_exits();
+uint32_t ovl_max_cross();
+uint32_t ovl_waves();   // waves (= blocks per unit) of the overlay pass
 
 // order gathers: out[out_base[o] + i*P + j] = d(p_i, p_j)
 void launch_gather_rows(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
@@ -305,11 +340,14 @@ void launch_arc_src(const uint32_t *row_ptr, uint32_t V, uint32_t *arc_src, hipS
 // weight epochs: apply (arc, w) pairs to every weight array of the graph
 void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww, uint32_t *w,
                            uint32_t *in_w, const uint32_t *in_pos, uint32_t *l_arc, uint32_t *x_w,
-                           const uint32_t *arc_slot, hipStream_t st);
+                           const uint32_t *arc_slot, uint32_t *li_arc, const uint32_t *arc_slot_in,
+                           hipStream_t st);
 
 // --------------------------------------------------------------- host side
+// seg: caller's segments (nseg of them); sub (optional): a finer partition
+// nested in the segments whose parts become the tiles (still cut to the cap).
 void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t tile_cap,
-                 bool bfs_grow);
+                 bool bfs_grow, const uint32_t *sub = nullptr, uint32_t nsub = 0);
 void rebuild_tiles_if_needed(wr_graph *g);
 
 }  // namespace wr

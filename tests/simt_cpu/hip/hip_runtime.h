@@ -11,6 +11,7 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <barrier>
 #include <cstddef>
 #include <cstdint>
@@ -62,13 +63,17 @@ struct Lane {
     dim3 tid, bid, bdim, gdim;
     Block *blk = nullptr;
     unsigned wave = 0, lane = 0;
+    volatile int line = 0;    // source line of the last collective entered
+    volatile int waiting = 0; // 1 = in a wave collective, 2 = in __syncthreads
 };
+extern std::atomic<unsigned long> progress;
 
 extern thread_local Lane *cur;
 
 inline Wave &wave() { return cur->blk->waves[cur->wave]; }
 
-inline uint64_t ballot(bool p) {
+inline uint64_t ballot(bool p, int line = 0) {
+    cur->line = line;
     Wave &w = wave();
     w.vals[cur->lane] = p ? 1u : 0u;
     w.bar->arrive_and_wait();
@@ -79,7 +84,8 @@ inline uint64_t ballot(bool p) {
     return m;
 }
 
-inline uint32_t readfirstlane(uint32_t x) {
+inline uint32_t readfirstlane(uint32_t x, int line = 0) {
+    cur->line = line;
     Wave &w = wave();
     w.vals[cur->lane] = x;
     w.bar->arrive_and_wait();
@@ -93,8 +99,37 @@ inline uint32_t readfirstlane(uint32_t x) {
     return r;
 }
 
-inline void wave_barrier() { wave().bar->arrive_and_wait(); }
-inline void syncthreads() { cur->blk->bar->arrive_and_wait(); }
+inline void wave_barrier(int line = 0) {
+    cur->line = line;
+    cur->waiting = 1;
+    wave().bar->arrive_and_wait();
+    cur->waiting = 0;
+    progress++;
+}
+
+// value of `x` held by lane `src` (lanes outside the wave read their own)
+inline uint32_t shfl(uint32_t x, int src, int line = 0) {
+    cur->line = line;
+    Wave &w = wave();
+    w.vals[cur->lane] = x;
+    w.bar->arrive_and_wait();
+    const unsigned s = static_cast<unsigned>(src) & 63u;
+    const uint32_t r = s < w.n ? static_cast<uint32_t>(w.vals[s]) : x;
+    w.bar->arrive_and_wait();
+    return r;
+}
+inline uint32_t shfl_up(uint32_t x, unsigned d) {
+    const unsigned l = cur->lane;
+    const uint32_t r = shfl(x, l >= d ? static_cast<int>(l - d) : static_cast<int>(l));
+    return r;
+}
+inline void syncthreads(int line = 0) {
+    cur->line = line;
+    cur->waiting = 2;
+    cur->blk->bar->arrive_and_wait();
+    cur->waiting = 0;
+    progress++;
+}
 
 inline uint32_t mbcnt_lo(uint32_t m, uint32_t a) {
     const unsigned l = cur->lane;
@@ -127,10 +162,13 @@ void record(void *stream, std::function<void()> fn);
 #define blockIdx (::simt::cur->bid)
 #define blockDim (::simt::cur->bdim)
 #define gridDim (::simt::cur->gdim)
-#define __syncthreads() ::simt::syncthreads()
-#define __builtin_amdgcn_ballot_w64(p) ::simt::ballot(p)
-#define __builtin_amdgcn_readfirstlane(x) ::simt::readfirstlane(x)
-#define __builtin_amdgcn_wave_barrier() ::simt::wave_barrier()
+#define __syncthreads() ::simt::syncthreads(__LINE__)
+#define __shfl(x, src, w) ::simt::shfl((x), (src), __LINE__)
+#define __shfl_up(x, d, w) ::simt::shfl_up((x), (d))
+#define __builtin_amdgcn_ballot_w64(p) ::simt::ballot((p), __LINE__)
+#define __builtin_amdgcn_readfirstlane(x) ::simt::readfirstlane((x), __LINE__)
+#define __builtin_amdgcn_readlane(x, k) ::simt::shfl((x), static_cast<int>(k), __LINE__)
+#define __builtin_amdgcn_wave_barrier() ::simt::wave_barrier(__LINE__)
 #define __builtin_amdgcn_mbcnt_lo(m, a) ::simt::mbcnt_lo(m, a)
 #define __builtin_amdgcn_mbcnt_hi(m, a) ::simt::mbcnt_hi(m, a)
 #define __builtin_elementwise_add_sat(a, b) ::simt::add_sat(a, b)

@@ -9,6 +9,7 @@
 namespace simt {
 
 thread_local Lane *cur = nullptr;
+std::atomic<unsigned long> progress{0};
 
 double now_ms() {
     using namespace std::chrono;
@@ -35,6 +36,26 @@ void run_grid(dim3 g, dim3 b, const std::function<void()> &body) {
                     blk.waves[w].bar = std::make_unique<std::barrier<>>(n);
                     for (unsigned l = 0; l < 64; ++l) blk.waves[w].alive[l] = l < n;
                 }
+                std::vector<Lane *> lanes(nt, nullptr);
+                std::atomic<bool> done{false};
+                std::thread dog([&]() {
+                    unsigned long last = progress.load();
+                    int idle = 0;
+                    while (!done.load()) {
+                        std::this_thread::sleep_for(std::chrono::milliseconds(200));
+                        const unsigned long p = progress.load();
+                        if (p != last) { last = p; idle = 0; continue; }
+                        if (++idle < 25) continue;
+                        std::fprintf(stderr, "[simt] no barrier progress for 5 s in block (%u,%u,%u)\n", bx, by, bz);
+                        std::map<std::pair<int, int>, int> hist;
+                        for (unsigned t = 0; t < nt; ++t)
+                            if (lanes[t]) hist[{lanes[t]->line, lanes[t]->waiting}]++;
+                            else hist[{-1, -1}]++;
+                        for (auto &kv : hist)
+                            std::fprintf(stderr, "[simt]   line %d waiting %d : %d lanes\n", kv.first.first, kv.first.second, kv.second);
+                        std::abort();
+                    }
+                });
                 std::vector<std::thread> th;
                 th.reserve(nt);
                 for (unsigned t = 0; t < nt; ++t) {
@@ -48,15 +69,20 @@ void run_grid(dim3 g, dim3 b, const std::function<void()> &body) {
                         ln.wave = t / 64;
                         ln.lane = t % 64;
                         cur = &ln;
+                        lanes[t] = &ln;
                         body();
                         Wave &w = blk.waves[ln.wave];
                         w.alive[ln.lane] = false;
                         w.bar->arrive_and_drop();
                         blk.bar->arrive_and_drop();
+                        progress++;
+                        lanes[t] = nullptr;
                         cur = nullptr;
                     });
                 }
                 for (auto &x : th) x.join();
+                done = true;
+                dog.join();
             }
 }
 

@@ -21,7 +21,7 @@ def _graph(rt, ctx, row_ptr, col, w):
     return rt.Graph(ctx, row_ptr, col, w)
 
 
-@pytest.mark.parametrize("algo", ALGOS + ["edge_b0"])
+@pytest.mark.parametrize("algo", ALGOS + ["edge_b0", "overlay", "auto"])
 def test_tiny_order_matrix(rt, ctx, algo):
     wl = make_config("tiny")
     g = wl.graph
@@ -29,7 +29,23 @@ def test_tiny_order_matrix(rt, ctx, algo):
     got = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo)
     exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
     assert got.dtype == np.uint32 and (got == exp).all()
-    assert G.last_run()["algo"] == algo
+    if algo != "auto":
+        assert G.last_run()["algo"] == algo
+
+
+# (tile vertices, waves): tiles up to 512 vertices run the source-blocked
+# kernel, larger ones one source per wave
+SCHEDULES = [(256, 8), (512, 16), (1024, 8), (2048, 4)]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_schedules_tiny(rt, ctx, sched):
+    wl = make_config("tiny")
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    G.set_schedule(*sched)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    assert (G.order_matrices(wl.pick_offsets, wl.picks, algo="segmented") == exp).all()
 
 
 @pytest.mark.parametrize("algo", ALGOS)
@@ -39,6 +55,8 @@ def test_random_graph_sssp(rt, ctx, algo, seed):
     V = 300 + 37 * seed
     rp, col, w = random_csr(rng, V, 4 * V, wmax=60, zero_frac=0.1 if seed % 2 else 0.0)
     G = _graph(rt, ctx, rp, col, w)
+    if seed >= 2:
+        G.set_schedule(*SCHEDULES[seed])
     src = rng.choice(V, 70, replace=False).astype(np.uint32)
     src = np.concatenate([src, src[:5]])            # duplicates
     got = G.sssp(src, algo=algo)
@@ -70,11 +88,13 @@ def test_pred_refused_with_zero_weights(rt, ctx):
     assert (G.sssp([0]) == np.asarray([[0, 0]], np.uint32)).all()
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("seg", ["grid32", "grid_rect", "bfs", "user_map"])
-def test_medium_slice_segmented(rt, ctx, seg):
+def test_medium_slice_segmented(rt, ctx, seg, sched):
     wl = make_config("medium", side=128, num_orders=12)
     g = wl.graph
     G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    G.set_schedule(*sched)
     if seg == "grid32":
         G.segment_grid(g.W, g.H, 1, 32, 32)
     elif seg == "grid_rect":
@@ -87,6 +107,8 @@ def test_medium_slice_segmented(rt, ctx, seg):
     assert (got == exp).all()
     info = G.segment_info()
     assert info["tiles"] >= 1
+    if seg.startswith("grid") and sched[0] <= 512:
+        assert (G.order_matrices(wl.pick_offsets, wl.picks, algo="overlay") == exp).all()
 
 
 def test_medium_slice_frontier_and_sweep_agree(rt, ctx):
@@ -127,11 +149,26 @@ def test_graph_capture_matches_eager(rt, ctx):
     wl = make_config("medium", side=64, num_orders=4)
     g = wl.graph
     G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
-    for algo in ("segmented", "frontier"):
+    G.segment_grid(g.W, g.H, 1, 16, 16)
+    for algo in ("segmented", "overlay", "frontier"):
         a = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo)
         b = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo, graph_capture=False)
         c = G.order_matrices(wl.pick_offsets, wl.picks, algo=algo)   # replay again
         assert (a == b).all() and (a == c).all()
+
+
+@pytest.mark.parametrize("algo", ["overlay", "segmented"])
+def test_sssp_full_rows_segmented_schedules(rt, ctx, algo):
+    wl = make_config("medium", side=80, num_orders=2)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    G.segment_grid(g.W, g.H, 1, 16, 16)
+    src = np.concatenate([wl.picks[:40], wl.picks[:3]])     # 43 rows, duplicates
+    d, p = G.sssp(src, pred=True, algo=algo)
+    exp = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)
+    assert (d == exp).all()
+    for i in range(0, len(src), 7):
+        assert (p[i] == oracle.canonical_pred(g.row_ptr, g.col, g.w, int(src[i]), exp[i])).all()
 
 
 def test_device_pointers(rt, ctx):
@@ -170,5 +207,12 @@ def test_weight_update_epochs(rt, ctx):
     w2 = g.w.copy()
     w2[arcs] = vals
     exp = oracle.order_matrices(g.row_ptr, g.col, w2, wl.pick_offsets, wl.picks)
-    for algo in ("segmented", "frontier", "sweep", "edge_b1"):
+    for algo in ("segmented", "overlay", "frontier", "sweep", "edge_b1"):
         assert (G.order_matrices(wl.pick_offsets, wl.picks, algo=algo) == exp).all(), algo
+    # a second update: the overlay tables follow the new epoch
+    w3 = w2.copy()
+    w3[arcs] = np.maximum(vals, 2) - 1
+    assert G.update_weights(arcs, w3[arcs]) == 2
+    exp3 = oracle.order_matrices(g.row_ptr, g.col, w3, wl.pick_offsets, wl.picks)
+    for algo in ("overlay", "segmented"):
+        assert (G.order_matrices(wl.pick_offsets, wl.picks, algo=algo) == exp3).all(), algo
