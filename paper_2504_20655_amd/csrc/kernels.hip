@@ -211,10 +211,16 @@ struct SegPassArgs {
     // source-blocked schedule: in-tile in-arcs and the sources of the chunk
     const uint32_t *li_off, *li_arc;
     uint32_t nsrc;
+    // overlay schedule: activation flags [T][S] instead of stamped lists
+    uint8_t *flags;
 };
 
 __device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
                                              uint32_t stamp) {
+    if (A.flags) {
+        A.flags[static_cast<size_t>(t) * A.S + s] = 1;
+        return;
+    }
     const uint32_t o = atomicMax(&A.stamps[static_cast<size_t>(s) * A.T + t], stamp);
     if (o < stamp) {
         const uint32_t k = atomicAdd(&A.cnt_next[t], 1u);
@@ -683,43 +689,44 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t 
 
 // Overlay pass: a visit of (tile t, block b) maps the block's entry values
 // (inbox rows of t's ports) through t's table onto t's exits (boundary-out
-// vertices): exit_j = min(exit_j, min_i entry_i + F[exit_j][i]) per lane, a
-// dense min-plus product with no sequential dependency.  Lowered exits are
-// stored in the exits' gdist rows and pushed across their cross-tile arcs
-// into the target tiles' inbox rows, activating (b, target tile).
+// vertices), exit_j = min_i entry_i + F[exit_j][i] per lane, a dense
+// min-plus product, and pushes every exit value across the exit's cross
+// arcs into the target tiles' inbox rows with atomicMin.  A push that
+// lowered a target row flags (target tile, b) for the next pass.  Exit
+// values are not stored: the inbox rows of the targets hold them, and the
+// atomic's old value decides the activation.
 //
-// A workgroup stages one tile's exit rows of the table and its cross arcs in
-// LDS, then each of its waves runs a whole visit for one block on its own
-// (no workgroup barrier inside a visit): the entry values sit in registers,
-// exits go in groups of OVL_GRP whose row loads and whose pushes are each
-// issued together, and the visit's activations are made by parallel lanes at
-// its end.  Many independent visits per CU hide the global-memory latency.
-constexpr uint32_t OVL_XCAP = 96;     // exits per tile
-constexpr uint32_t OVL_PCAP = 384;    // cross arcs leaving a tile
-constexpr uint32_t OVL_GRP = 8;       // exits per group
-constexpr uint32_t OVL_ACT = 32;      // activations a wave collects before flushing
-constexpr uint32_t OVL_NW = 4;        // waves per workgroup = blocks per unit
+// A workgroup takes one unit (a tile and up to G of its active blocks),
+// stages the tile's table rows and cross arcs in LDS, and runs the unit's
+// visits one after another: the waves stage the block's entry rows with all
+// loads in flight, then each wave computes four exits at a time from LDS and
+// issues their four pushes together.  A visit thus costs one round trip of
+// loads and one of atomics.  LDS is sized at launch to the tiling's largest
+// tile (XM exits x EM entries, PM cross arcs).
+constexpr uint32_t OVL_XCAP = 128;    // exits per tile
+constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving a tile
+constexpr uint32_t OVL_NW = 8;        // waves per workgroup
+constexpr uint32_t OVL_B = 4;         // exits a wave computes and pushes together
 template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ F) {
-    __shared__ uint32_t s_M[OVL_XCAP * 64];        // [exit][entry]
-    __shared__ uint32_t s_xpos[OVL_XCAP];          // position of each exit
-    __shared__ uint32_t s_xbeg[OVL_XCAP + 1];      // first cross arc of each exit (tile-relative)
-    __shared__ uint32_t s_xport[OVL_PCAP];
-    __shared__ uint32_t s_xw[OVL_PCAP];
-    __shared__ uint32_t s_xtile[OVL_PCAP];
-    __shared__ uint16_t s_xexit[OVL_PCAP];         // exit of each cross arc
-    __shared__ uint32_t s_m[NW][OVL_GRP * 64];     // new values of the wave's exit group
-    __shared__ uint32_t s_act[NW][OVL_ACT];
-    __shared__ uint32_t s_unit;
+__global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ F,
+                                                      uint32_t XM, uint32_t EM, uint32_t PM) {
+    HIP_DYNAMIC_SHARED(uint32_t, lds)
+    uint32_t *s_M = lds;                    // [XM][EM]  table rows of the exits
+    uint32_t *s_in = s_M + XM * EM;         // [EM][64]  entry values of the visit
+    uint32_t *s_xbeg = s_in + EM * 64;      // [XM + 1]  first cross arc of each exit
+    uint32_t *s_xport = s_xbeg + XM + 1;    // [PM]      cross arcs: target port,
+    uint32_t *s_xw = s_xport + PM;          //           weight,
+    uint32_t *s_xtile = s_xw + PM;          //           target tile
+    uint32_t *s_unit = s_xtile + PM;
+    constexpr uint32_t RPW = 64 / NW;       // entry rows a wave stages
     const uint32_t lane = lane_id();
     const uint32_t wv = uniform(threadIdx.x >> 6);
     const uint32_t nunits = uniform(*A.nunits);
-    const uint32_t stamp = uniform(*A.pass_ctr) + 1u;
     uint32_t staged = NONE;
     for (;;) {
-        if (threadIdx.x == 0) s_unit = atomicAdd(A.cursor, 1u);
+        if (threadIdx.x == 0) *s_unit = atomicAdd(A.cursor, 1u);
         __syncthreads();
-        const uint32_t u = uniform(s_unit);
+        const uint32_t u = uniform(*s_unit);
         __syncthreads();
         if (u >= nunits) break;
         const uint2 unit = A.units[u];
@@ -728,104 +735,139 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         const uint32_t p0 = uniform(A.port_base[t]), E = uniform(A.port_base[t + 1]) - p0;
         const uint32_t b0 = uniform(A.bo_base[t]), X = uniform(A.bo_base[t + 1]) - b0;
         if (t != staged) {
-            const uint32_t xa0 = A.x_off[base];
+            const uint32_t xa0 = uniform(A.x_off[base]);
             for (uint32_t j = wv; j < X; j += NW) {
-                const uint32_t pos = base + A.bo_local[b0 + j];
-                s_M[j * 64 + lane] = F[static_cast<size_t>(pos) * 64 + lane];
-                if (lane == 0) {
-                    s_xpos[j] = pos;
-                    s_xbeg[j] = A.x_off[pos] - xa0;
-                }
+                const uint32_t pos = base + uniform(A.bo_local[b0 + j]);
+                if (lane < EM) s_M[j * EM + lane] = lane < E ? F[static_cast<size_t>(pos) * 64 + lane] : INF;
+                if (lane == 0) s_xbeg[j] = A.x_off[pos] - xa0;
             }
-            const uint32_t na = A.x_off[base + uniform(A.tile_base[t + 1]) - base] - xa0;
+            const uint32_t na = uniform(A.x_off[uniform(A.tile_base[t + 1])]) - xa0;
             if (threadIdx.x == 0) s_xbeg[X] = na;
             for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) {
                 s_xport[k] = A.x_port[xa0 + k];
                 s_xw[k] = A.x_w[xa0 + k];
                 s_xtile[k] = A.x_tile[xa0 + k];
             }
-            __syncthreads();
-            // exit of each cross arc (arcs of consecutive exits are consecutive)
-            for (uint32_t j = threadIdx.x; j < X; j += blockDim.x)
-                for (uint32_t k = s_xbeg[j]; k < s_xbeg[j + 1]; ++k) s_xexit[k] = static_cast<uint16_t>(j);
             staged = t;
             __syncthreads();
         }
         const uint32_t total = uniform(A.cnt_cur[t]);
         const uint32_t first_k = slice * A.G;
         const uint32_t cnt = min(A.G, total - first_k);
-        if (wv < cnt) {
-            const uint32_t b = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + wv]);
-            const size_t st = static_cast<size_t>(b) * A.T + t;
-            const bool first = A.visited[st] == 0;
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const uint32_t b = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + k]);
             uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64;
-            uint32_t *gd = A.gdist + static_cast<size_t>(b) * A.Vt * 64;
-            uint32_t in[64];
+            // entry rows of the block, all loads of a wave in flight
+            uint32_t v[RPW];
 #pragma unroll
-            for (uint32_t i = 0; i < 64; ++i)
-                in[i] = i < E ? ib[static_cast<size_t>(p0 + i) * 64 + lane] : INF;
-            uint32_t nact = 0;
-            uint32_t *mrow = s_m[wv];
-            for (uint32_t j0 = 0; j0 < X; j0 += OVL_GRP) {
-                const uint32_t ng = X - j0 < OVL_GRP ? X - j0 : OVL_GRP;
-                uint32_t cur[OVL_GRP];
-#pragma unroll
-                for (uint32_t r = 0; r < OVL_GRP; ++r)
-                    cur[r] = (first || r >= ng) ? INF
-                                                : gd[static_cast<size_t>(s_xpos[j0 + r]) * 64 + lane];
-                uint64_t anyimp = 0;
-#pragma unroll
-                for (uint32_t r = 0; r < OVL_GRP; ++r) {
-                    if (r >= ng) break;
-                    const uint32_t *Mj = s_M + (j0 + r) * 64;
-                    uint32_t m = cur[r];
-#pragma unroll
-                    for (uint32_t i = 0; i < 64; ++i)
-                        if (i < E) m = min(m, sat_add(in[i], Mj[i]));
-                    const bool imp = m < cur[r];
-                    if (imp || first) gd[static_cast<size_t>(s_xpos[j0 + r]) * 64 + lane] = m;
-                    mrow[r * 64 + lane] = imp ? m : INF;
-                    anyimp |= __builtin_amdgcn_ballot_w64(imp);
-                }
-                __builtin_amdgcn_wave_barrier();
-                if (anyimp == 0) continue;
-                // pushes of the group's cross arcs, four in flight
-                const uint32_t k0 = s_xbeg[j0], k1 = s_xbeg[j0 + ng];
-                for (uint32_t k = k0; k < k1; k += 4) {
-                    uint32_t nd[4], old[4];
-                    uint32_t *pi[4];
-#pragma unroll
-                    for (uint32_t r = 0; r < 4; ++r) {
-                        const uint32_t kk = k + r < k1 ? k + r : k0;
-                        const uint32_t jr = s_xexit[kk] - j0;
-                        const uint32_t mv = mrow[jr * 64 + lane];
-                        nd[r] = (k + r < k1) ? sat_add(mv, s_xw[kk]) : INF;
-                        pi[r] = ib + static_cast<size_t>(s_xport[kk]) * 64 + lane;
-                        old[r] = INF;
-                    }
-#pragma unroll
-                    for (uint32_t r = 0; r < 4; ++r)
-                        if (nd[r] != INF) old[r] = atomicMin(pi[r], nd[r]);
-#pragma unroll
-                    for (uint32_t r = 0; r < 4; ++r) {
-                        if (__builtin_amdgcn_ballot_w64(nd[r] < old[r]) == 0) continue;
-                        const uint32_t t2 = s_xtile[k + r];
-                        if (nact < OVL_ACT) {
-                            if (lane == 0) s_act[wv][nact] = t2;
-                            ++nact;
-                        } else if (lane == 0) {
-                            seg_activate(A, b, t2, stamp);
-                        }
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
+            for (uint32_t r = 0; r < RPW; ++r) {
+                const uint32_t i = wv + NW * r;
+                v[r] = i < E ? ib[static_cast<size_t>(p0 + i) * 64 + lane] : INF;
             }
-            __builtin_amdgcn_wave_barrier();
-            if (lane < nact) seg_activate(A, b, s_act[wv][lane], stamp);
-            if (lane == 0 && first) A.visited[st] = 2;
+#pragma unroll
+            for (uint32_t r = 0; r < RPW; ++r) {
+                const uint32_t i = wv + NW * r;
+                if (i < EM) s_in[i * 64 + lane] = v[r];
+            }
+            __syncthreads();
+            for (uint32_t j0 = wv * OVL_B; j0 < X; j0 += NW * OVL_B) {
+                uint32_t m[OVL_B];
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_B; ++r) m[r] = INF;
+                for (uint32_t i = 0; i < E; i += 4) {
+                    const uint32_t e0 = s_in[i * 64 + lane], e1 = s_in[(i + 1) * 64 + lane];
+                    const uint32_t e2 = s_in[(i + 2) * 64 + lane], e3 = s_in[(i + 3) * 64 + lane];
+#pragma unroll
+                    for (uint32_t r = 0; r < OVL_B; ++r) {
+                        const uint4 q = *reinterpret_cast<const uint4 *>(s_M + (j0 + r) * EM + i);
+                        m[r] = min(m[r], min(min(sat_add(e0, q.x), sat_add(e1, q.y)),
+                                             min(sat_add(e2, q.z), sat_add(e3, q.w))));
+                    }
+                }
+                // the first cross arc of each of the four exits, pushed together
+                uint32_t kb[OVL_B], ke[OVL_B], nd[OVL_B], old[OVL_B];
+                uint32_t *pi[OVL_B];
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_B; ++r) {
+                    const bool ok = j0 + r < X;
+                    kb[r] = ok ? uniform(s_xbeg[j0 + r]) : 0u;
+                    ke[r] = ok ? uniform(s_xbeg[j0 + r + 1]) : 0u;
+                    const bool has = kb[r] < ke[r];
+                    const uint32_t kx = has ? kb[r] : 0u;
+                    nd[r] = has ? sat_add(m[r], uniform(s_xw[kx])) : INF;
+                    pi[r] = ib + static_cast<size_t>(has ? uniform(s_xport[kx]) : p0) * 64 + lane;
+                    old[r] = INF;
+                }
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_B; ++r)
+                    if (nd[r] != INF) old[r] = atomicMin(pi[r], nd[r]);
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_B; ++r) {
+                    if (__builtin_amdgcn_ballot_w64(nd[r] < old[r]) != 0 && lane == 0)
+                        A.flags[static_cast<size_t>(s_xtile[kb[r]]) * A.S + b] = 1;
+                }
+                // further cross arcs of exits that have several
+#pragma unroll
+                for (uint32_t r = 0; r < OVL_B; ++r) {
+                    for (uint32_t kx = kb[r] + 1; kx < ke[r]; ++kx) {
+                        const uint32_t d = sat_add(m[r], uniform(s_xw[kx]));
+                        uint32_t *px = ib + static_cast<size_t>(uniform(s_xport[kx])) * 64 + lane;
+                        uint32_t o = INF;
+                        if (d != INF) o = atomicMin(px, d);
+                        if (__builtin_amdgcn_ballot_w64(d < o) != 0 && lane == 0)
+                            A.flags[static_cast<size_t>(s_xtile[kx]) * A.S + b] = 1;
+                    }
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
+}
+
+// Builds the pass's work lists from the activation flags [tile][block]:
+// each tile's active blocks in ascending order, the tile's count, and units
+// of G blocks; clears the flags it consumed and counts work.
+__global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, uint32_t *__restrict__ cnt,
+                           uint32_t *__restrict__ bucket, uint32_t G, uint2 *__restrict__ units,
+                           uint32_t *__restrict__ nunits, unsigned long long *__restrict__ stats) {
+    const uint32_t lane = lane_id();
+    const uint32_t wpb = blockDim.x >> 6;
+    for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < T; t += gridDim.x * wpb) {
+        uint8_t *f = flags + static_cast<size_t>(t) * S;
+        uint32_t *bk = bucket + static_cast<size_t>(t) * S;
+        uint32_t k = 0;
+        for (uint32_t c0 = 0; c0 < S; c0 += 64) {
+            const uint32_t b = c0 + lane;
+            const bool on = b < S && f[b] != 0;
+            const uint64_t msk = __builtin_amdgcn_ballot_w64(on);
+            if (on) {
+                bk[k + mbcnt64(msk)] = b;
+                f[b] = 0;
+            }
+            k += static_cast<uint32_t>(__builtin_popcountll(msk));
+        }
+        if (lane == 0) cnt[t] = k;
+        if (k != 0) {
+            const uint32_t sl = (k + G - 1) / G;
+            uint32_t ub = 0;
+            if (lane == 0) {
+                ub = atomicAdd(nunits, sl);
+                atomicAdd(&stats[0], static_cast<unsigned long long>(k));
+                if (ub == 0) atomicAdd(&stats[1], 1ull);
+            }
+            ub = __builtin_amdgcn_readlane(ub, 0);
+            for (uint32_t q = lane; q < sl; q += 64) units[ub + q] = make_uint2(t, q);
+        }
+    }
+}
+
+// Adds 1 to *out for every wave that sees a set flag (pending work).
+__global__ void k_flags_any(const uint8_t *__restrict__ flags, size_t n, uint32_t *__restrict__ out) {
+    bool any = false;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        any |= flags[i] != 0;
+    if (__builtin_amdgcn_ballot_w64(any) != 0 && lane_id() == 0) atomicAdd(out, 1u);
 }
 
 // Final distance of chunk source s at v under the overlay schedule:
@@ -1232,6 +1274,7 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
     A.tiles_next = ss.tiles + static_cast<size_t>(nx) * ts.T;
     A.ntiles_next = ss.ntiles + nx;
     A.units = ss.units;
+    A.flags = ss.flags;
     A.nunits = ss.nunits;
     A.cursor = ss.cursor;
     A.pass_ctr = ss.pass_ctr;
@@ -1245,6 +1288,7 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st) {
     // seeds land in parity 0; their stamp is 1 (pass 0's list)
     SegPassArgs A = seg_args(ts, ss, 1u, 1u);
+    A.flags = nullptr;
     hipLaunchKernelGGL(k_seg_seed, blocks_for(n ? n : 1, 256), 256, 0, st, A, n, ss.lanes_log2);
     check_launch("seg_seed");
 }
@@ -1423,23 +1467,44 @@ void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32
     check_launch("ovl_custom");
 }
 
+static void ovl_dims(const TileSet &ts, uint32_t &XM, uint32_t &EM, uint32_t &PM) {
+    XM = (std::max(ts.max_exits, 1u) + OVL_B - 1) / OVL_B * OVL_B;
+    EM = (std::max(ts.max_ports, 1u) + 3u) / 4u * 4u;
+    PM = std::max(ts.max_cross, 1u);
+}
+
+uint32_t ovl_pass_lds_bytes(const TileSet &ts) {
+    uint32_t XM, EM, PM;
+    ovl_dims(ts, XM, EM, PM);
+    return (XM * EM + EM * 64 + XM + 1 + 3 * PM + 1) * 4;
+}
+
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t G, uint32_t grid,
-                     const uint32_t *F, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
+                     const uint32_t *F, bool count_after, hipStream_t st, hipEvent_t ev_begin,
+                     hipEvent_t ev_end) {
     if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (overlay pass)");
     const uint32_t nx = par ^ 1u;
     hipLaunchKernelGGL(k_seg_prologue, blocks_for(ts.T, 256, 64), 256, 0, st,
                        ss.cnt + static_cast<size_t>(nx) * ts.T, ts.T, ss.ntiles + nx, ss.nunits, ss.cursor,
                        ss.pass_ctr);
     check_launch("seg_prologue");
-    hipLaunchKernelGGL(k_seg_plan, blocks_for(ts.T, 256, 64), 256, 0, st,
-                       ss.tiles + static_cast<size_t>(par) * ts.T, ss.ntiles + par,
-                       ss.cnt + static_cast<size_t>(par) * ts.T, G, ss.units, ss.nunits, ss.stats);
-    check_launch("seg_plan");
+    hipLaunchKernelGGL(k_ovl_plan, blocks_for(ts.T, 4, 1024), 256, 0, st, ss.flags, ts.T, ss.S,
+                       ss.cnt + static_cast<size_t>(par) * ts.T, ss.bucket + static_cast<size_t>(par) * ts.T * ss.S,
+                       G, ss.units, ss.nunits, ss.stats);
+    check_launch("ovl_plan");
     SegPassArgs A = seg_args(ts, ss, par, G);
+    uint32_t XM, EM, PM;
+    ovl_dims(ts, XM, EM, PM);
     if (ev_begin) WR_HIP(hipEventRecord(ev_begin, st));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW>), grid, OVL_NW * 64, 0, st, A, F);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW>), grid, OVL_NW * 64, ovl_pass_lds_bytes(ts), st, A, F,
+                       XM, EM, PM);
     check_launch("ovl_pass");
     if (ev_end) WR_HIP(hipEventRecord(ev_end, st));
+    if (count_after) {
+        const size_t n = static_cast<size_t>(ts.T) * ss.S;
+        hipLaunchKernelGGL(k_flags_any, blocks_for(n, 256, 512), 256, 0, st, ss.flags, n, ss.ntiles + nx);
+        check_launch("flags_any");
+    }
 }
 
 void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
@@ -1464,10 +1529,6 @@ void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint
     check_launch("gather_ovl");
 }
 
-uint32_t ovl_pass_lds_bytes() {
-    return (OVL_XCAP * 64 + 2 * OVL_XCAP + 1 + 3 * OVL_PCAP + OVL_NW * (OVL_GRP * 64 + OVL_ACT)) * 4 +
-           OVL_PCAP * 2 + 8;
-}
 uint32_t ovl_max_exits() { return OVL_XCAP; }
 uint32_t ovl_max_cross() { return OVL_PCAP; }
 uint32_t ovl_waves() { return OVL_NW; }

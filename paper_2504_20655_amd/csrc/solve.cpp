@@ -189,11 +189,11 @@ uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
 }  // namespace
 
 uint64_t SegBuffers::bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes) {
-    return 4ull * lanes * (ts.Vt + ts.NP + 2) + 1ull * ts.T + 4ull * ts.T + 8ull * ts.T +
+    return 4ull * lanes * (ts.Vt + ts.NP + 2) + 2ull * ts.T + 4ull * ts.T + 8ull * ts.T +
            8ull * ts.T / G + 8;
 }
 
-void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g, uint32_t ln) {
+void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g, uint32_t ln, bool with_flags) {
     S_cap = S;
     G = g;
     lanes = ln;
@@ -201,6 +201,7 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u) * lanes);
     stamps.alloc(ctx, static_cast<size_t>(S) * ts.T);
     visited.alloc(ctx, static_cast<size_t>(S) * ts.T);
+    if (with_flags) flags.alloc(ctx, static_cast<size_t>(S) * ts.T);
     cnt.alloc(ctx, 2ull * ts.T);
     bucket.alloc(ctx, 2ull * ts.T * S);
     tiles.alloc(ctx, 2ull * ts.T);
@@ -228,6 +229,7 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     ss.stats = stats.p;
     ss.src_pos = src_pos.p;
     ss.src_tile = src_tile.p;
+    ss.flags = with_flags ? flags.p : nullptr;
 }
 
 uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves, uint32_t lanes) {
@@ -244,7 +246,7 @@ hipGraphExec_t capture_ovl_passes(const TileSet &ts, const SegState &ss, uint32_
     hipGraph_t graph;
     WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-        for (uint32_t i = 0; i < K; ++i) launch_ovl_step(ts, ss, (i + 1) & 1u, G, grid, F, st);
+        for (uint32_t i = 0; i < K; ++i) launch_ovl_step(ts, ss, (i + 1) & 1u, G, grid, F, i + 1 == K, st);
     } catch (...) {
         hipGraph_t dummy = nullptr;
         (void)hipStreamEndCapture(st, &dummy);
@@ -297,8 +299,7 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
     TileSet &ts = *g->tiles;
     const uint32_t waves = g->waves_per_group;
     const uint32_t lanes = g->lanes;
-    const uint32_t G = overlay ? ovl_waves()
-                               : (g->sources_per_unit ? g->sources_per_unit : (lanes == 64 ? 4 : 4 * waves));
+    const uint32_t G = g->sources_per_unit ? g->sources_per_unit : (lanes == 64 ? 4 : 4 * waves);
     const uint32_t K = std::max(2u, g->passes_per_replay & ~1u);
     const uint32_t rows_need = (S_need + lanes - 1) / lanes;
     SegWork *w = ws.seg.get();
@@ -325,11 +326,11 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
     nw->overlay = overlay;
     if (timed) nw->kev.create(K);
     wr_context *ctx = g->ctx;
-    nw->buf.init(ctx, ts, R_cap, G, lanes);
+    nw->buf.init(ctx, ts, R_cap, G, lanes, overlay);
     nw->ss = nw->buf.ss;
     nw->grid = seg_pass_grid(ctx, ts.tile_cap, waves, lanes);
     nw->grid_ovl = static_cast<uint32_t>(ctx->num_cus) *
-                   std::min(32u / ovl_waves(), std::max(1u, (160u * 1024u) / ovl_pass_lds_bytes()));
+                   std::min(32u / ovl_waves(), std::max(1u, (160u * 1024u) / ovl_pass_lds_bytes(ts)));
     if (overlay) ensure_overlay_tables(g);
     if (graph_mode)
         nw->exec = overlay ? capture_ovl_passes(ts, nw->ss, K, G, nw->grid_ovl, ts.d_F.p, ctx->stream)
@@ -361,6 +362,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(rows) * std::max(ts.NP, 1u) * lanes, INF, st);
     launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u8(w.buf.visited.p, static_cast<size_t>(rows) * ts.T, 0u, st);
+    if (w.overlay) launch_fill_u8(w.buf.flags.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
     launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
@@ -385,7 +387,8 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
             WR_HIP(hipGraphLaunch(w.exec, st));
         } else if (w.overlay) {
             for (uint32_t i = 0; i < K; ++i)
-                launch_ovl_step(ts, ss, (i + 1) & 1u, w.G, w.grid_ovl, ts.d_F.p, st, w.kev.b(i), w.kev.e(i));
+                launch_ovl_step(ts, ss, (i + 1) & 1u, w.G, w.grid_ovl, ts.d_F.p, i + 1 == K, st, w.kev.b(i),
+                                w.kev.e(i));
         } else {
             for (uint32_t i = 0; i < K; ++i)
                 launch_seg_step(ts, ss, i & 1u, ts.tile_cap, w.waves, w.G, w.grid, st, w.kev.b(i),

@@ -253,6 +253,7 @@ struct SegState {
     const uint32_t *src_tile = nullptr;    // [sources] tile or NONE
     uint32_t lanes_log2 = 0;   // 0: a state row per source; 6: per block of 64 sources
     uint32_t nsrc = 0;         // sources of the chunk (blocked layout: lanes beyond are idle)
+    uint8_t *flags = nullptr;  // [T][S] activation flags (overlay schedule), else null
 };
 // activates (s, tile of source s) for the chunk's sources s < n
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
@@ -271,11 +272,12 @@ void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t
 struct SegBuffers {
     uint32_t S_cap = 0, G = 0, lanes = 1;
     DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile;
-    DBuf<uint8_t> visited;
+    DBuf<uint8_t> visited, flags;
     DBuf<uint2> units;
     DBuf<unsigned long long> stats;
     SegState ss;
-    void init(wr_context *ctx, const TileSet &ts, uint32_t S_cap, uint32_t G, uint32_t lanes);
+    // with_flags: activation by flags [T][S_cap] (overlay schedule)
+    void init(wr_context *ctx, const TileSet &ts, uint32_t S_cap, uint32_t G, uint32_t lanes, bool with_flags);
     // device bytes per state row
     static uint64_t bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes);
 };
@@ -297,8 +299,10 @@ void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *acti
 // overlay schedule: per-epoch boundary tables F[pos][port] of every tile,
 // dense min-plus passes over (tile, block) items, and the read-outs
 void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st);
+// one overlay pass: prologue + plan from the flags + the pass; count_after
+// adds the number of waves that still see set flags to ntiles[parity ^ 1]
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
-                     const uint32_t *F, hipStream_t st, hipEvent_t ev_begin = nullptr,
+                     const uint32_t *F, bool count_after, hipStream_t st, hipEvent_t ev_begin = nullptr,
                      hipEvent_t ev_end = nullptr);
 void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
                      const uint32_t *row_src_idx, const uint32_t *row_src_vertex, const uint32_t *out_row,
@@ -307,7 +311,7 @@ void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint
                        const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
                        uint32_t chunk_n, const TileSet &ts, const SegState &ss, const uint32_t *F,
                        uint32_t *out, hipStream_t st);
-uint32_t ovl_pass_lds_bytes();
+uint32_t ovl_pass_lds_bytes(const TileSet &ts);
 uint32_t ovl_max_exits();
 uint32_t ovl_max_cross();
 uint32_t ovl_waves();   // waves (= blocks per unit) of the overlay pass

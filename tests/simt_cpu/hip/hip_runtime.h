@@ -275,11 +275,15 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 namespace simt {
 void trace(const char *name, dim3 g, dim3 b, double ms);
 double now_ms();
+// dynamic LDS of the running launch (blocks run one after another)
+void set_dynamic_lds(size_t bytes);
+void *dynamic_lds();
 template <class... P, class... A>
-void launch(const char *name, void (*k)(P...), dim3 g, dim3 b, hipStream_t st, A &&...a) {
+void launch(const char *name, void (*k)(P...), dim3 g, dim3 b, size_t sh, hipStream_t st, A &&...a) {
     std::tuple<std::decay_t<P>...> args(static_cast<std::decay_t<P>>(a)...);
-    std::function<void()> job = [name, k, g, b, args]() {
+    std::function<void()> job = [name, k, g, b, sh, args]() {
         const double t0 = now_ms();
+        set_dynamic_lds(sh);
         run_grid(g, b, [&]() { std::apply(k, args); });
         trace(name, g, b, now_ms() - t0);
     };
@@ -291,4 +295,6 @@ void launch(const char *name, void (*k)(P...), dim3 g, dim3 b, hipStream_t st, A
 }  // namespace simt
 
 #define HIP_KERNEL_NAME(...) __VA_ARGS__
-#define hipLaunchKernelGGL(k, g, b, sh, st, ...) ::simt::launch(#k, k, ::dim3(g), ::dim3(b), (st), ##__VA_ARGS__)
+#define hipLaunchKernelGGL(k, g, b, sh, st, ...) \
+    ::simt::launch(#k, k, ::dim3(g), ::dim3(b), static_cast<size_t>(sh), (st), ##__VA_ARGS__)
+#define HIP_DYNAMIC_SHARED(type, var) type *var = static_cast<type *>(::simt::dynamic_lds());

@@ -21,6 +21,14 @@ void trace(const char *name, dim3 g, dim3 b, double ms) {
     if (on) std::fprintf(stderr, "[simt] %s grid=(%u,%u,%u) block=%u %.1f ms\n", name, g.x, g.y, g.z, b.x * b.y * b.z, ms);
 }
 
+namespace {
+std::vector<uint64_t> g_dyn_lds;
+}
+void set_dynamic_lds(size_t bytes) {
+    g_dyn_lds.assign((bytes + 7) / 8, 0xDEADBEEFDEADBEEFull);
+}
+void *dynamic_lds() { return g_dyn_lds.empty() ? nullptr : g_dyn_lds.data(); }
+
 void run_grid(dim3 g, dim3 b, const std::function<void()> &body) {
     const unsigned nt = b.x * b.y * b.z;
     for (unsigned bz = 0; bz < g.z; ++bz)
