@@ -10,7 +10,7 @@ C ABI defines them.
 
 Prints ONE JSON line:
   value        routed orders/s (whole job; one GPU)
-  roofline     dominant kernel (the segment relaxation pass) against HBM:
+  roofline     dominant kernel (the relaxation pass of the schedule) against HBM:
                algorithmic bytes per launch / its average launch duration,
                timed live with HIP events recorded around each launch
   cpu_baseline the CPU oracle (Dijkstra per distinct pick, all host cores)
@@ -32,7 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "seg_pass_medium_traffic.json")
+PASS_KERNEL = {"overlay": "k_ovl_pass", "segmented": "k_segb_pass"}
 
 
 def parse():
@@ -40,16 +40,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--algo", default="segmented")
-    ap.add_argument("--tile", type=int, default=0, help="tile vertices (0 = library default)")
+    ap.add_argument("--algo", default="overlay")
+    ap.add_argument("--tile", type=int, default=512, help="tile vertices (0 = library default)")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--passes", type=int, default=0)
-    ap.add_argument("--segment", default="auto", help="auto | grid:TWxTH")
+    ap.add_argument("--segment", default="grid:24x20", help="auto | grid:TWxTH")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work of the oracle sample (core-seconds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--b1-orders", type=int, default=2,
                     help="orders of the paper-structured B1 baseline to time (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device once (a dispatch of known "
+                         "traffic that scales the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -73,11 +76,11 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(kernel: str):
     """HBM bytes per launch of the pass kernel from the committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(os.path.join(ROOT, "profiles", f"{kernel}_medium_traffic.json")))
     except (OSError, ValueError):
         return None
     if t.get("kernel_src_sha") != kernel_source_sha():
@@ -179,7 +182,8 @@ def main():
     kern_ms_step = kern_ms / args.steps
     launches_step = kern_n / args.steps
     achieved = alg_bytes / (kern_ms_step * 1e-3) / 1e9 if kern_ms_step > 0 else None
-    traffic = load_traffic()
+    kernel = PASS_KERNEL.get(info["algo"], "relaxation pass")
+    traffic = load_traffic(kernel)
     seg = G.segment_info()
 
     res = {
@@ -209,7 +213,7 @@ def main():
         "passes_per_step": passes / args.steps,
         "visits_per_step": items / args.steps,
         "roofline": {
-            "kernel": "k_seg_pass" if info["algo"] == "segmented" else "relaxation pass",
+            "kernel": kernel,
             "bound": "hbm",
             "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS,
@@ -235,6 +239,14 @@ def main():
         res["baseline_b1"] = {"value": round(k / tb, 3), "unit": "orders/s",
                               "sample": f"first {k} orders, one order at a time, thread per arc, "
                                         f"host-checked early exit ({G.last_run()['passes']} rounds)"}
+    if args.copy_probe > 0:
+        n = args.copy_probe << 18
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = int(n) * 4
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -697,7 +697,7 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t 
 // atomic's old value decides the activation.
 //
 // A workgroup takes one unit (a tile and up to G of its active blocks),
-// stages the tile's table rows and cross arcs in LDS, and runs the unit's
+// stages the tile's packed table rows and cross arcs in LDS, and runs the unit's
 // visits one after another: the waves stage the block's entry rows with all
 // loads in flight, then each wave computes four exits at a time from LDS and
 // issues their four pushes together.  A visit thus costs one round trip of
@@ -708,8 +708,10 @@ constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving a tile
 constexpr uint32_t OVL_NW = 8;        // waves per workgroup
 constexpr uint32_t OVL_B = 4;         // exits a wave computes and pushes together
 template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ F,
-                                                      uint32_t XM, uint32_t EM, uint32_t PM) {
+__global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ Fx,
+                                                      const uint4 *__restrict__ hdr,
+                                                      const uint32_t *__restrict__ bo_xbeg, uint32_t XM,
+                                                      uint32_t EM, uint32_t PM) {
     HIP_DYNAMIC_SHARED(uint32_t, lds)
     uint32_t *s_M = lds;                    // [XM][EM]  table rows of the exits
     uint32_t *s_in = s_M + XM * EM;         // [EM][64]  entry values of the visit
@@ -731,18 +733,16 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         if (u >= nunits) break;
         const uint2 unit = A.units[u];
         const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
-        const uint32_t base = uniform(A.tile_base[t]);
-        const uint32_t p0 = uniform(A.port_base[t]), E = uniform(A.port_base[t + 1]) - p0;
-        const uint32_t b0 = uniform(A.bo_base[t]), X = uniform(A.bo_base[t + 1]) - b0;
+        const uint4 h = hdr[t];
+        const uint32_t p0 = uniform(h.x), b0 = uniform(h.y), xa0 = uniform(h.z), hw = uniform(h.w);
+        const uint32_t E = hw & 0xFFu, X = (hw >> 8) & 0xFFu, na = hw >> 16;
         if (t != staged) {
-            const uint32_t xa0 = uniform(A.x_off[base]);
-            for (uint32_t j = wv; j < X; j += NW) {
-                const uint32_t pos = base + uniform(A.bo_local[b0 + j]);
-                if (lane < EM) s_M[j * EM + lane] = lane < E ? F[static_cast<size_t>(pos) * 64 + lane] : INF;
-                if (lane == 0) s_xbeg[j] = A.x_off[pos] - xa0;
-            }
-            const uint32_t na = uniform(A.x_off[uniform(A.tile_base[t + 1])]) - xa0;
-            if (threadIdx.x == 0) s_xbeg[X] = na;
+            // all staging loads are independent: one round trip
+            const uint32_t *rows = Fx + static_cast<size_t>(b0) * EM;
+            const uint32_t nM = X * EM;
+#pragma unroll 4
+            for (uint32_t q = threadIdx.x; q < nM; q += blockDim.x) s_M[q] = rows[q];
+            for (uint32_t j = threadIdx.x; j <= X; j += blockDim.x) s_xbeg[j] = bo_xbeg[b0 + t + j];
             for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) {
                 s_xport[k] = A.x_port[xa0 + k];
                 s_xw[k] = A.x_w[xa0 + k];
@@ -754,16 +754,18 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         const uint32_t total = uniform(A.cnt_cur[t]);
         const uint32_t first_k = slice * A.G;
         const uint32_t cnt = min(A.G, total - first_k);
-        for (uint32_t k = 0; k < cnt; ++k) {
+        for (uint32_t k = 0; E != 0 && k < cnt; ++k) {
             const uint32_t b = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + k]);
             uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64;
-            // entry rows of the block, all loads of a wave in flight
+            // entry rows of the block, all loads of a wave in flight: the
+            // loads are unconditional (rows past the tile's ports re-read its
+            // last port; their table entries are INF, so they add nothing)
+            const uint32_t *ie = ib + static_cast<size_t>(p0) * 64;   // uniform: row i at ie + 64 i
+            const uint32_t elast = E - 1;
             uint32_t v[RPW];
 #pragma unroll
-            for (uint32_t r = 0; r < RPW; ++r) {
-                const uint32_t i = wv + NW * r;
-                v[r] = i < E ? ib[static_cast<size_t>(p0 + i) * 64 + lane] : INF;
-            }
+            for (uint32_t r = 0; r < RPW; ++r)
+                v[r] = ie[static_cast<size_t>(min(wv + NW * r, elast)) * 64 + lane];
 #pragma unroll
             for (uint32_t r = 0; r < RPW; ++r) {
                 const uint32_t i = wv + NW * r;
@@ -826,12 +828,21 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
 
 // Builds the pass's work lists from the activation flags [tile][block]:
 // each tile's active blocks in ascending order, the tile's count, and units
-// of G blocks; clears the flags it consumed and counts work.
+// of G blocks counted in *nunits (zeroed by the previous pass's plan); clears
+// the flags it consumed, counts work, and zeroes the next pass's unit count,
+// unit cursor and pending-work counter.
 __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, uint32_t *__restrict__ cnt,
                            uint32_t *__restrict__ bucket, uint32_t G, uint2 *__restrict__ units,
-                           uint32_t *__restrict__ nunits, unsigned long long *__restrict__ stats) {
+                           uint32_t *__restrict__ nunits, uint32_t *__restrict__ next_nunits,
+                           uint32_t *__restrict__ next_cursor, uint32_t *__restrict__ next_pending,
+                           unsigned long long *__restrict__ stats) {
     const uint32_t lane = lane_id();
     const uint32_t wpb = blockDim.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *next_nunits = 0;
+        *next_cursor = 0;
+        *next_pending = 0;
+    }
     for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < T; t += gridDim.x * wpb) {
         uint8_t *f = flags + static_cast<size_t>(t) * S;
         uint32_t *bk = bucket + static_cast<size_t>(t) * S;
@@ -857,6 +868,25 @@ __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, 
             }
             ub = __builtin_amdgcn_readlane(ub, 0);
             for (uint32_t q = lane; q < sl; q += 64) units[ub + q] = make_uint2(t, q);
+        }
+    }
+}
+
+// Packs the exits' rows of the boundary tables: Fx[exit][i] = F[pos][i]
+// for the tile's ports i, INF for i up to the row length EM.
+__global__ void k_ovl_pack(const uint32_t *__restrict__ F, const uint32_t *__restrict__ tile_base,
+                           const uint32_t *__restrict__ bo_local, const uint4 *__restrict__ hdr, uint32_t T,
+                           uint32_t EM, uint32_t *__restrict__ Fx) {
+    const uint32_t lane = lane_id();
+    const uint32_t wpb = blockDim.x >> 6;
+    for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < T; t += gridDim.x * wpb) {
+        const uint32_t base = tile_base[t];
+        const uint4 h = hdr[t];
+        const uint32_t b0 = h.y, E = h.w & 0xFFu, X = (h.w >> 8) & 0xFFu;
+        for (uint32_t j = 0; j < X; ++j) {
+            const uint32_t pos = base + bo_local[b0 + j];
+            for (uint32_t i = lane; i < EM; i += 64)
+                Fx[static_cast<size_t>(b0 + j) * EM + i] = i < E ? F[static_cast<size_t>(pos) * 64 + i] : INF;
         }
     }
 }
@@ -1473,31 +1503,50 @@ static void ovl_dims(const TileSet &ts, uint32_t &XM, uint32_t &EM, uint32_t &PM
     PM = std::max(ts.max_cross, 1u);
 }
 
+uint32_t ovl_row_entries(const TileSet &ts) {
+    uint32_t XM, EM, PM;
+    ovl_dims(ts, XM, EM, PM);
+    return EM;
+}
+
 uint32_t ovl_pass_lds_bytes(const TileSet &ts) {
     uint32_t XM, EM, PM;
     ovl_dims(ts, XM, EM, PM);
     return (XM * EM + EM * 64 + XM + 1 + 3 * PM + 1) * 4;
 }
 
+void launch_ovl_pack(const TileSet &ts, hipStream_t st) {
+    hipLaunchKernelGGL(k_ovl_pack, blocks_for(ts.T, 4, 4096), 256, 0, st, ts.d_F.p, ts.d_tile_base.p,
+                       ts.d_bo_local.p, reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), ts.T, ts.ovl_em,
+                       ts.d_Fx.p);
+    check_launch("ovl_pack");
+}
+
+// The overlay steps keep the unit count and cursor per parity (parity 0 in
+// nunits[0] / cursor[0], parity 1 three words further), so a step's plan
+// can zero the next step's pair while its own pass runs on the current one.
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t G, uint32_t grid,
                      const uint32_t *F, bool count_after, hipStream_t st, hipEvent_t ev_begin,
                      hipEvent_t ev_end) {
+    (void)F;
     if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (overlay pass)");
     const uint32_t nx = par ^ 1u;
-    hipLaunchKernelGGL(k_seg_prologue, blocks_for(ts.T, 256, 64), 256, 0, st,
-                       ss.cnt + static_cast<size_t>(nx) * ts.T, ts.T, ss.ntiles + nx, ss.nunits, ss.cursor,
-                       ss.pass_ctr);
-    check_launch("seg_prologue");
+    uint32_t *nunits_cur = ss.nunits + 3u * par, *cursor_cur = ss.cursor + 3u * par;
+    uint32_t *nunits_nx = ss.nunits + 3u * nx, *cursor_nx = ss.cursor + 3u * nx;
     hipLaunchKernelGGL(k_ovl_plan, blocks_for(ts.T, 4, 1024), 256, 0, st, ss.flags, ts.T, ss.S,
                        ss.cnt + static_cast<size_t>(par) * ts.T, ss.bucket + static_cast<size_t>(par) * ts.T * ss.S,
-                       G, ss.units, ss.nunits, ss.stats);
+                       G, ss.units, nunits_cur, nunits_nx, cursor_nx, ss.ntiles + nx, ss.stats);
     check_launch("ovl_plan");
     SegPassArgs A = seg_args(ts, ss, par, G);
+    A.nunits = nunits_cur;
+    A.cursor = cursor_cur;
     uint32_t XM, EM, PM;
     ovl_dims(ts, XM, EM, PM);
+    const uint32_t lds = ovl_pass_lds_bytes(ts);
+    const uint4 *hd = reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p);
     if (ev_begin) WR_HIP(hipEventRecord(ev_begin, st));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW>), grid, OVL_NW * 64, ovl_pass_lds_bytes(ts), st, A, F,
-                       XM, EM, PM);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW>), grid, OVL_NW * 64, lds, st, A, ts.d_Fx.p, hd,
+                       ts.d_bo_xbeg.p, XM, EM, PM);
     check_launch("ovl_pass");
     if (ev_end) WR_HIP(hipEventRecord(ev_end, st));
     if (count_after) {

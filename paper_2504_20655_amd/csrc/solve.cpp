@@ -288,9 +288,32 @@ namespace {
 void ensure_overlay_tables(wr_graph *g) {
     TileSet &ts = *g->tiles;
     if (!ts.d_F.p) ts.d_F.alloc(g->ctx, static_cast<size_t>(ts.Vt) * 64);
+    if (!ts.d_ovl_hdr.p) {
+        // staging headers and per-exit arc offsets (fixed for the tiling)
+        std::vector<uint32_t> &hdr = ts.ovl_hdr, &xb = ts.bo_xbeg;
+        hdr.assign(4ull * ts.T, 0u);
+        xb.assign(static_cast<size_t>(ts.NB) + ts.T, 0u);
+        for (uint32_t t = 0; t < ts.T; ++t) {
+            const uint32_t base = ts.tile_base[t], next = ts.tile_base[t + 1];
+            const uint32_t p0 = ts.port_base[t], E = ts.port_base[t + 1] - p0;
+            const uint32_t b0 = ts.bo_base[t], X = ts.bo_base[t + 1] - b0;
+            const uint32_t xa0 = ts.x_off[base], na = ts.x_off[next] - xa0;
+            hdr[4ull * t + 0] = p0;
+            hdr[4ull * t + 1] = b0;
+            hdr[4ull * t + 2] = xa0;
+            hdr[4ull * t + 3] = E | (X << 8) | (na << 16);
+            for (uint32_t j = 0; j < X; ++j) xb[b0 + t + j] = ts.x_off[base + ts.bo_local[b0 + j]] - xa0;
+            xb[b0 + t + X] = na;
+        }
+        upload(ts.d_ovl_hdr, g->ctx, hdr, g->ctx->stream);
+        upload(ts.d_bo_xbeg, g->ctx, xb, g->ctx->stream);
+        ts.ovl_em = ovl_row_entries(ts);
+        ts.d_Fx.alloc(g->ctx, std::max<size_t>(1, static_cast<size_t>(ts.NB) * ts.ovl_em));
+    }
     if (ts.custom_epoch == g->epoch) return;
     const uint32_t grid = static_cast<uint32_t>(g->ctx->num_cus) * 2;
     launch_ovl_custom(ts, ts.tile_cap, ts.d_F.p, grid, g->ctx->stream);
+    launch_ovl_pack(ts, g->ctx->stream);
     ts.custom_epoch = g->epoch;
 }
 

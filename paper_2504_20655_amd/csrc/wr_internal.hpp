@@ -138,6 +138,14 @@ struct TileSet {
     // weight epoch they were computed for
     DBuf<uint32_t> d_F;
     uint64_t custom_epoch = ~0ull;
+    // overlay pass staging.  Per tile a header {first port, first exit, first
+    // cross arc, ports | exits << 8 | cross arcs << 16}; per tile t, X_t + 1
+    // entries from bo_base[t] + t: each exit's first cross arc relative to
+    // the tile's; and the exits' table rows packed [NB][ovl_em] (entries
+    // beyond the tile's ports INF) for the epoch of d_F.
+    uint32_t ovl_em = 0;
+    std::vector<uint32_t> ovl_hdr, bo_xbeg;
+    DBuf<uint32_t> d_ovl_hdr, d_bo_xbeg, d_Fx;
 
     // host copies
     std::vector<uint32_t> tile_of;      // [V]  tile or NONE
@@ -245,8 +253,8 @@ struct SegState {
     uint32_t *tiles = nullptr;      // [2][T]
     uint32_t *ntiles = nullptr;     // [2]
     uint2 *units = nullptr;         // [max units]
-    uint32_t *nunits = nullptr;     // [1]
-    uint32_t *cursor = nullptr;     // [1]
+    uint32_t *nunits = nullptr;     // [1]; the overlay steps use nunits[3] for parity 1
+    uint32_t *cursor = nullptr;     // [1]; the overlay steps use cursor[3] for parity 1
     uint32_t *pass_ctr = nullptr;   // [1]
     unsigned long long *stats = nullptr;   // [2]: items, passes with work
     const uint32_t *src_pos = nullptr;     // [sources] position or NONE
@@ -299,6 +307,10 @@ void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *acti
 // overlay schedule: per-epoch boundary tables F[pos][port] of every tile,
 // dense min-plus passes over (tile, block) items, and the read-outs
 void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st);
+// entries per packed table row of the overlay pass (ports rounded up to 4)
+uint32_t ovl_row_entries(const TileSet &ts);
+// packs the exits' rows of F into d_Fx
+void launch_ovl_pack(const TileSet &ts, hipStream_t st);
 // one overlay pass: prologue + plan from the flags + the pass; count_after
 // adds the number of waves that still see set flags to ntiles[parity ^ 1]
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
