@@ -264,7 +264,10 @@ wr_status wr_server_submit(wr_server *srv, uint32_t P, const uint32_t *picks, ui
 wr_status wr_server_poll(wr_server *srv, uint64_t ticket, uint32_t *dist_out, wr_req_info *info);
 
 /* Queues a weight update; it is applied between scheduler steps, and every
- * request admitted after that point is solved on the new epoch. */
+ * request admitted after that point is solved on the new epoch.  Arc
+ * indices are checked here (WR_E_INVALID); an update that the graph would
+ * refuse at application time (WR_E_RANGE, see wr_graph_update_weights) is
+ * dropped and the epoch does not advance. */
 wr_status wr_server_update_weights(wr_server *srv, uint32_t n, const uint32_t *arc_index,
                                    const uint32_t *new_w);
 

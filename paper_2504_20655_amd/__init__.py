@@ -27,6 +27,7 @@ TIME_KERNELS = 0x0200
 
 STATUS = {0: "WR_OK", 1: "WR_E_INVALID", 2: "WR_E_RANGE", 3: "WR_E_NOMEM", 4: "WR_E_DEVICE",
           5: "WR_E_UNSUPPORTED", 6: "WR_E_BUSY", 7: "WR_E_INTERNAL"}
+BUSY = 6
 
 
 class WrError(RuntimeError):
@@ -198,6 +199,67 @@ class Graph:
         _check(lib().wr_order_matrices(self.h, n, _ptr(off), _ptr(pk), _ptr(d), _ptr(p), flags, None))
         d = d[:total]
         return (d, p) if pred else d
+
+
+class Server:
+    """Continuous-batching server over a graph (wr_server_*).  The graph must
+    stay alive, and must not be used directly, while the server runs."""
+
+    def __init__(self, graph: Graph, max_source_slots: int = 0, mem_budget_bytes: int = 0,
+                 max_queue: int = 0, passes_per_step: int = 0):
+        from ._lib import ServerOpts
+        self.graph = graph
+        o = ServerOpts(max_source_slots, mem_budget_bytes, max_queue, passes_per_step)
+        h = ctypes.c_void_p()
+        _check(lib().wr_server_create(graph.h, ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._P = {}
+
+    def submit(self, picks) -> int:
+        pk = _u32(picks)
+        t = ctypes.c_uint64()
+        _check(lib().wr_server_submit(self.h, len(pk), _ptr(pk), ctypes.byref(t)))
+        self._P[t.value] = len(pk)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(P x P matrix, info) once done, (None, None) while pending."""
+        from ._lib import ReqInfo
+        P = self._P[ticket]
+        d = np.empty(max(P * P, 1), dtype=np.uint32)
+        info = ReqInfo()
+        rc = lib().wr_server_poll(self.h, ticket, _ptr(d), ctypes.byref(info))
+        if rc == BUSY:
+            return None, None
+        del self._P[ticket]
+        _check(rc)
+        return d[:P * P].reshape(P, P), {"epoch": info.epoch, "t_arrive": info.t_arrive,
+                                          "t_admit": info.t_admit, "t_done": info.t_done,
+                                          "P": info.P, "status": info.status}
+
+    def update_weights(self, arc_index, new_w):
+        a, v = _u32(arc_index), _u32(new_w)
+        _check(lib().wr_server_update_weights(self.h, len(a), _ptr(a), _ptr(v)))
+
+    def stats(self) -> dict:
+        from ._lib import Stats
+        s = Stats()
+        _check(lib().wr_server_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def drain(self):
+        _check(lib().wr_server_drain(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wr_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def split_matrices(flat, pick_offsets):

@@ -1024,43 +1024,6 @@ __global__ void k_seg_emit(const uint32_t *__restrict__ tile_of, const uint32_t 
     }
 }
 
-// ------------------------------------------------------- serving kernels
-// Clears the per-slot state of newly admitted sources.
-__global__ void k_srv_reset_slots(const uint32_t *__restrict__ slots, uint32_t n, uint32_t T,
-                                  uint32_t NP, uint32_t *__restrict__ inbox,
-                                  uint32_t *__restrict__ stamps, uint8_t *__restrict__ visited) {
-    for (uint32_t i = blockIdx.y; i < n; i += gridDim.y) {
-        const size_t s = slots[i];
-        for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < NP; k += gridDim.x * blockDim.x)
-            inbox[s * NP + k] = INF;
-        for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < T; k += gridDim.x * blockDim.x) {
-            stamps[s * T + k] = 0;
-            visited[s * T + k] = 0;
-        }
-    }
-}
-
-// Activates (slot, tile of its source) for the next pass of a running state.
-__global__ void k_srv_seed(SegPassArgs A, const uint32_t *__restrict__ slots, uint32_t n) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t s = slots[i];
-    const uint32_t t = A.src_tile[s];
-    if (t != NONE) seg_activate(A, s, t, *A.pass_ctr + 1u);
-}
-
-// active[s] = 1 for every slot with a pending (tile, slot) item.
-__global__ void k_srv_mark_active(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ ntiles,
-                                  const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ bucket,
-                                  uint32_t S, uint8_t *__restrict__ active) {
-    const uint32_t nt = *ntiles;
-    for (uint32_t j = blockIdx.y; j < nt; j += gridDim.y) {
-        const uint32_t t = tiles[j];
-        const uint32_t c = cnt[t];
-        for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x)
-            active[bucket[static_cast<size_t>(t) * S + k]] = 1;
-    }
-}
 
 // ---------------------------------------------------------- order gathers
 // One workgroup per order; entry (i, j) of order o is written at
@@ -1458,31 +1421,6 @@ void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww
     hipLaunchKernelGGL(k_weight_scatter, blocks_for(n, 256), 256, 0, st, n, arc, neww, w, in_w, in_pos,
                        l_arc, x_w, arc_slot, li_arc, arc_slot_in);
     check_launch("weight_scatter");
-}
-
-void launch_srv_reset_slots(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
-                            hipStream_t st) {
-    if (!n) return;
-    dim3 grid(blocks_for(std::max(ts.NP, ts.T), 256, 64), n < 65535u ? n : 65535u);
-    hipLaunchKernelGGL(k_srv_reset_slots, grid, 256, 0, st, slots, n, ts.T, ts.NP, ss.inbox, ss.stamps,
-                       ss.visited);
-    check_launch("srv_reset_slots");
-}
-
-void launch_srv_seed(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
-                     hipStream_t st) {
-    if (!n) return;
-    SegPassArgs A = seg_args(ts, ss, 1u, 1u);
-    hipLaunchKernelGGL(k_srv_seed, blocks_for(n, 256), 256, 0, st, A, slots, n);
-    check_launch("srv_seed");
-}
-
-void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *active, hipStream_t st) {
-    launch_fill_u8(active, ss.S, 0, st);
-    dim3 grid(blocks_for(ss.S, 256, 16), ts.T < 4096u ? ts.T : 4096u);
-    hipLaunchKernelGGL(k_srv_mark_active, grid, 256, 0, st, ss.tiles, ss.ntiles, ss.cnt, ss.bucket, ss.S,
-                       active);
-    check_launch("srv_mark_active");
 }
 
 void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st) {

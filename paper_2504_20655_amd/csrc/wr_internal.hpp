@@ -295,15 +295,6 @@ uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves,
 hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t tile_cap,
                                   uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st);
 
-// serving: reset the state rows of new slots, activate their sources for
-// the next pass (parity 0 after an even number of passes), and flag the
-// slots that still have pending (tile, slot) items in the parity-0 lists
-void launch_srv_reset_slots(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
-                            hipStream_t st);
-void launch_srv_seed(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t n,
-                     hipStream_t st);
-void launch_srv_mark_active(const TileSet &ts, const SegState &ss, uint8_t *active, hipStream_t st);
-
 // overlay schedule: per-epoch boundary tables F[pos][port] of every tile,
 // dense min-plus passes over (tile, block) items, and the read-outs
 void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st);

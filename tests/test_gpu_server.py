@@ -1,0 +1,179 @@
+"""GPU tests of the continuous-batching server and the autotuner against the
+CPU oracle: every order's matrix is exact whether it is solved alone or in
+a mix, results are pinned to the weight epoch current at admission, a
+request that can never fit the memory budget fails alone, and every
+autotuner choice gives the default's bits."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from wgen import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(rt):
+    return rt.Context(0)
+
+
+def _small(rt, ctx, side=48, orders=12):
+    wl = make_config("medium", side=side, num_orders=orders)
+    g = wl.graph
+    G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
+    G.segment_grid(g.W, g.H, 1, 12, 10)
+    return wl, G
+
+
+def _orders(wl):
+    off = wl.pick_offsets
+    return [wl.picks[off[o]:off[o + 1]].copy() for o in range(len(off) - 1)]
+
+
+def _expect(g, picks, w=None):
+    off = np.array([0, len(picks)], dtype=np.uint32)
+    P = len(picks)
+    return oracle.order_matrices(g.row_ptr, g.col, g.w if w is None else w, off, picks).reshape(P, P)
+
+
+def _wait(srv, tickets, timeout=120.0):
+    res = {}
+    t_end = time.time() + timeout
+    while len(res) < len(tickets):
+        assert time.time() < t_end, "server did not finish in time"
+        for t in tickets:
+            if t in res:
+                continue
+            m, info = srv.poll(t)
+            if m is not None:
+                res[t] = (m, info)
+        time.sleep(0.002)
+    return res
+
+
+def test_server_alone_equals_mix(rt, ctx):
+    wl, G = _small(rt, ctx)
+    g = wl.graph
+    orders = _orders(wl)
+    srv = rt.Server(G, max_source_slots=256)
+    try:
+        alone = []
+        for pk in orders[:4]:
+            t = srv.submit(pk)
+            srv.drain()
+            alone.append(_wait(srv, [t])[t][0])
+        tickets = [srv.submit(pk) for pk in orders]
+        got = _wait(srv, tickets)
+        for i, pk in enumerate(orders):
+            m, info = got[tickets[i]]
+            exp = _expect(g, pk)
+            assert (m == exp).all(), f"order {i}"
+            assert info["status"] == 0 and info["P"] == len(pk)
+            assert info["t_arrive"] <= info["t_admit"] <= info["t_done"]
+            if i < 4:
+                assert (alone[i] == m).all()
+        st = srv.stats()
+        assert st["completed"] == 4 + len(orders) and st["failed"] == 0
+        assert st["p99_ms"] >= st["p50_ms"] > 0 and st["throughput_per_s"] > 0
+    finally:
+        srv.close()
+
+
+def test_server_empty_order_and_duplicates(rt, ctx):
+    wl, G = _small(rt, ctx, side=32, orders=2)
+    g = wl.graph
+    srv = rt.Server(G)
+    try:
+        t0 = srv.submit(np.zeros(0, dtype=np.uint32))
+        pk = np.array([wl.picks[0], wl.picks[1], wl.picks[0]], dtype=np.uint32)
+        t1 = srv.submit(pk)
+        res = _wait(srv, [t0, t1])
+        assert res[t0][0].shape == (0, 0)
+        m = res[t1][0]
+        assert (m == _expect(g, pk)).all()
+        assert m[0, 2] == 0 and (m[0] == m[2]).all()
+    finally:
+        srv.close()
+
+
+def test_server_weight_epochs(rt, ctx):
+    wl, G = _small(rt, ctx, side=40, orders=6)
+    g = wl.graph
+    orders = _orders(wl)
+    srv = rt.Server(G)
+    try:
+        t_before = [srv.submit(pk) for pk in orders[:3]]
+        first = _wait(srv, t_before)
+        rng = np.random.default_rng(77)
+        arcs = rng.choice(g.E, g.E // 20, replace=False).astype(np.uint32)
+        new_w = rng.integers(1, 30, len(arcs)).astype(np.uint32)
+        srv.update_weights(arcs, new_w)
+        w2 = g.w.copy()
+        w2[arcs] = new_w
+        t_after = [srv.submit(pk) for pk in orders]
+        after = _wait(srv, t_after)
+        e0 = {first[t][1]["epoch"] for t in t_before}
+        e1 = {after[t][1]["epoch"] for t in t_after}
+        assert len(e0) == 1 and len(e1) == 1 and min(e1) == max(e0) + 1
+        for i, t in enumerate(t_before):
+            assert (first[t][0] == _expect(g, orders[i])).all()
+        for i, t in enumerate(t_after):
+            assert (after[t][0] == _expect(g, orders[i], w2)).all()
+    finally:
+        srv.close()
+
+
+def test_server_memory_admission(rt, ctx):
+    wl, G = _small(rt, ctx, side=32, orders=2)
+    srv = rt.Server(G, mem_budget_bytes=1)
+    try:
+        t_empty = srv.submit(np.zeros(0, dtype=np.uint32))
+        t_big = srv.submit(wl.picks[:8])
+        m, _ = _wait(srv, [t_empty])[t_empty]
+        assert m.shape == (0, 0)
+        t_end = time.time() + 60
+        while True:
+            try:
+                m, info = srv.poll(t_big)
+            except rt.WrError as e:
+                assert e.name == "WR_E_NOMEM"
+                break
+            assert m is None and time.time() < t_end
+            time.sleep(0.002)
+        st = srv.stats()
+        assert st["failed"] == 1 and st["completed"] == 1
+    finally:
+        srv.close()
+
+
+def test_server_rejects_bad_input(rt, ctx):
+    wl, G = _small(rt, ctx, side=24, orders=1)
+    srv = rt.Server(G)
+    try:
+        with pytest.raises(rt.WrError) as e:
+            srv.submit(np.array([wl.graph.V], dtype=np.uint32))
+        assert e.value.name == "WR_E_INVALID"
+        with pytest.raises(rt.WrError):
+            srv.update_weights(np.array([wl.graph.E], dtype=np.uint32), np.array([1], dtype=np.uint32))
+    finally:
+        srv.close()
+
+
+def test_autotune_identical_results(rt, ctx, tmp_path):
+    wl, G = _small(rt, ctx, side=48, orders=6)
+    g = wl.graph
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    assert (G.order_matrices(wl.pick_offsets, wl.picks) == exp).all()
+    cache = tmp_path / "tune.json"
+    G.autotune(sources_hint=64, cache_path=str(cache))
+    assert cache.exists()
+    assert (G.order_matrices(wl.pick_offsets, wl.picks) == exp).all()
+    # a second graph of the same structure reads the cache and gets the same bits
+    G2 = rt.Graph(ctx, g.row_ptr, g.col, g.w)
+    G2.segment_grid(g.W, g.H, 1, 12, 10)
+    t = time.time()
+    G2.autotune(sources_hint=64, cache_path=str(cache))
+    assert time.time() - t < 5.0
+    assert (G2.order_matrices(wl.pick_offsets, wl.picks) == exp).all()
