@@ -830,12 +830,12 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
 // each tile's active blocks in ascending order, the tile's count, and units
 // of G blocks counted in *nunits (zeroed by the previous pass's plan); clears
 // the flags it consumed, counts work, and zeroes the next pass's unit count,
-// unit cursor and pending-work counter.
+// unit cursor and pending-work counters (total and per block).
 __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, uint32_t *__restrict__ cnt,
                            uint32_t *__restrict__ bucket, uint32_t G, uint2 *__restrict__ units,
                            uint32_t *__restrict__ nunits, uint32_t *__restrict__ next_nunits,
                            uint32_t *__restrict__ next_cursor, uint32_t *__restrict__ next_pending,
-                           unsigned long long *__restrict__ stats) {
+                           uint32_t *__restrict__ row_pending, unsigned long long *__restrict__ stats) {
     const uint32_t lane = lane_id();
     const uint32_t wpb = blockDim.x >> 6;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -843,6 +843,8 @@ __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, 
         *next_cursor = 0;
         *next_pending = 0;
     }
+    if (blockIdx.x == 0)
+        for (uint32_t b = threadIdx.x; b < S; b += blockDim.x) row_pending[b] = 0;
     for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < T; t += gridDim.x * wpb) {
         uint8_t *f = flags + static_cast<size_t>(t) * S;
         uint32_t *bk = bucket + static_cast<size_t>(t) * S;
@@ -891,12 +893,18 @@ __global__ void k_ovl_pack(const uint32_t *__restrict__ F, const uint32_t *__res
     }
 }
 
-// Adds 1 to *out for every wave that sees a set flag (pending work).
-__global__ void k_flags_any(const uint8_t *__restrict__ flags, size_t n, uint32_t *__restrict__ out) {
+// Adds 1 to *out for every wave that sees a set flag (pending work) and
+// marks row_pending[b] for every block b with a set flag (flags are [T][S]).
+__global__ void k_flags_any(const uint8_t *__restrict__ flags, size_t n, uint32_t S, uint32_t *__restrict__ out,
+                            uint32_t *__restrict__ row_pending) {
     bool any = false;
     for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        any |= flags[i] != 0;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        if (flags[i] != 0) {
+            any = true;
+            row_pending[i % S] = 1;
+        }
+    }
     if (__builtin_amdgcn_ballot_w64(any) != 0 && lane_id() == 0) atomicAdd(out, 1u);
 }
 
@@ -962,6 +970,16 @@ __global__ void k_seg_seed(SegPassArgs A, uint32_t n, uint32_t lanes_log2) {
     if (s >= n) return;
     const uint32_t t = A.src_tile[s];
     if (t != NONE) seg_activate(A, s >> lanes_log2, t, 1u);
+}
+
+// Seeds pass 0 for the sources of the listed blocks of 64 (blocked layout):
+// (block, tile of the source) for every lane with a source.
+__global__ void k_seg_seed_blocks(SegPassArgs A, const uint32_t *__restrict__ blocks, uint32_t nb) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb * 64u) return;
+    const uint32_t b = blocks[i >> 6];
+    const uint32_t t = A.src_tile[static_cast<size_t>(b) * 64u + (i & 63u)];
+    if (t != NONE) seg_activate(A, b, t, 1u);
 }
 
 // Splits every active tile's bucket into units of G sources, zeroes the
@@ -1286,6 +1304,15 @@ void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStr
     check_launch("seg_seed");
 }
 
+void launch_seg_seed_blocks(const TileSet &ts, const SegState &ss, const uint32_t *blocks, uint32_t nb,
+                            hipStream_t st) {
+    if (!nb) return;
+    SegPassArgs A = seg_args(ts, ss, 1u, 1u);
+    A.flags = nullptr;
+    hipLaunchKernelGGL(k_seg_seed_blocks, blocks_for(static_cast<size_t>(nb) * 64, 256), 256, 0, st, A, blocks, nb);
+    check_launch("seg_seed_blocks");
+}
+
 void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t tile_cap,
                      uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st, hipEvent_t ev_begin,
                      hipEvent_t ev_end) {
@@ -1473,7 +1500,7 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     uint32_t *nunits_nx = ss.nunits + 3u * nx, *cursor_nx = ss.cursor + 3u * nx;
     hipLaunchKernelGGL(k_ovl_plan, blocks_for(ts.T, 4, 1024), 256, 0, st, ss.flags, ts.T, ss.S,
                        ss.cnt + static_cast<size_t>(par) * ts.T, ss.bucket + static_cast<size_t>(par) * ts.T * ss.S,
-                       G, ss.units, nunits_cur, nunits_nx, cursor_nx, ss.ntiles + nx, ss.stats);
+                       G, ss.units, nunits_cur, nunits_nx, cursor_nx, ss.ntiles + nx, ss.pending, ss.stats);
     check_launch("ovl_plan");
     SegPassArgs A = seg_args(ts, ss, par, G);
     A.nunits = nunits_cur;
@@ -1489,7 +1516,8 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     if (ev_end) WR_HIP(hipEventRecord(ev_end, st));
     if (count_after) {
         const size_t n = static_cast<size_t>(ts.T) * ss.S;
-        hipLaunchKernelGGL(k_flags_any, blocks_for(n, 256, 512), 256, 0, st, ss.flags, n, ss.ntiles + nx);
+        hipLaunchKernelGGL(k_flags_any, blocks_for(n, 256, 512), 256, 0, st, ss.flags, n, ss.S, ss.ntiles + nx,
+                           ss.pending);
         check_launch("flags_any");
     }
 }

@@ -1,10 +1,16 @@
-// Continuous-batching server: orders arrive at any time, a scheduler thread
-// admits as many queued orders as the source slots and the memory budget
-// allow, solves the admitted batch in one multi-source call (distinct picks
-// relaxed once, 64 sources per block), hands every order its P x P matrix,
-// and admits the next batch.  Weight updates queue and are applied between
-// steps, so each admitted order is solved entirely on one weight epoch (the
-// epoch current at its admission), and an order's matrix is the same alone
+// Continuous-batching server.  Orders arrive at any time; a scheduler thread
+// owns the GPU.  In the streaming mode (graphs whose tiling runs the overlay
+// schedule) the device holds a fixed set of block rows of 64 source lanes.
+// Each scheduler step admits queued orders into free rows (their distinct
+// picks seeded while the other rows keep relaxing), replays one group of
+// relaxation passes over every row, retires the orders whose rows have all
+// converged (their P x P matrices gathered and copied to the host) and frees
+// rows no order uses any more.  Other graphs fall back to step batching: the
+// admitted orders are solved together in one multi-source call.
+//
+// Weight updates queue; admission pauses until the rows in flight have
+// converged, then the update is applied, so every order is solved entirely
+// on the epoch current at its admission.  An order's matrix is the same alone
 // or in any mix, because every schedule reaches the exact fixpoint.
 #include <algorithm>
 #include <atomic>
@@ -62,6 +68,8 @@ struct wr_server {
     std::vector<double> lat_ms;
     double t0 = 0;
     std::thread worker;
+    // streaming mode
+    StreamSolver *stream = nullptr;
 };
 
 namespace {
@@ -93,8 +101,19 @@ void finish(wr_server *s, Request *r, wr_status st, double t_done) {
     }
 }
 
-void scheduler(wr_server *s) {
-    (void)hipSetDevice(s->g->ctx->device);
+// Applies queued weight updates (caller: nothing in flight).
+void apply_updates(wr_server *s, std::vector<WeightBatch> &ups) {
+    for (WeightBatch &u : ups) {
+        uint64_t ep = 0;
+        const wr_status st = wr_graph_update_weights(s->g, static_cast<uint32_t>(u.arc.size()), u.arc.data(),
+                                                     u.w.data(), &ep);
+        if (st != WR_OK) set_last_error(std::string("server weight update rejected: ") + wr_status_str(st));
+    }
+    ups.clear();
+}
+
+// Step batching: every admitted order in one multi-source call.
+void run_step_mode(wr_server *s) {
     const uint32_t slots = s->opts.max_source_slots;
     std::vector<Request *> batch;
     std::vector<uint32_t> off, picks, out;
@@ -110,12 +129,7 @@ void scheduler(wr_server *s) {
                 s->updates.pop_front();
             }
         }
-        for (WeightBatch &u : ups) {
-            uint64_t ep = 0;
-            const wr_status st = wr_graph_update_weights(s->g, static_cast<uint32_t>(u.arc.size()), u.arc.data(),
-                                                         u.w.data(), &ep);
-            if (st != WR_OK) set_last_error(std::string("server weight update rejected: ") + wr_status_str(st));
-        }
+        apply_updates(s, ups);
         // admission: queued orders in arrival order while slots and memory allow
         batch.clear();
         {
@@ -144,7 +158,6 @@ void scheduler(wr_server *s) {
             s->max_inflight = std::max<uint32_t>(s->max_inflight, static_cast<uint32_t>(batch.size()));
         }
         if (batch.empty()) continue;
-        // one step: every admitted order in one call
         off.assign(1, 0u);
         picks.clear();
         for (Request *r : batch) {
@@ -168,6 +181,200 @@ void scheduler(wr_server *s) {
         }
         s->cv_done.notify_all();
     }
+}
+
+// An admitted order of the streaming mode: the source slot of every pick and
+// the rows it waits for.
+struct Live {
+    Request *r = nullptr;
+    std::vector<uint32_t> slot;   // per pick: row * 64 + lane
+    std::vector<uint32_t> rows;   // distinct rows
+};
+
+// Streaming mode; returns false (nothing admitted yet) if the state cannot
+// be built, and then the caller falls back to step batching.
+bool run_stream_mode(wr_server *s) {
+    wr_graph *g = s->g;
+    uint32_t want = (s->opts.max_source_slots + 63) / 64;
+    try {
+        const uint64_t per = stream_bytes_per_block(g);
+        const uint64_t fit = s->budget > (8ull << 20) ? (s->budget - (8ull << 20)) / per : 0;
+        want = static_cast<uint32_t>(std::min<uint64_t>(want, fit));
+        if (!want) return false;
+        s->stream = stream_create(g, want);
+    } catch (const Error &) {
+        return false;
+    }
+    const uint32_t R = stream_blocks(s->stream);
+    std::vector<uint32_t> refcnt(R, 0);       // admitted orders using the row
+    std::vector<uint8_t> busy(R, 0);          // row still relaxing
+    std::vector<uint32_t> free_rows;
+    for (uint32_t b = R; b-- > 0;) free_rows.push_back(b);
+    std::vector<Live> live;
+    std::vector<uint32_t> pending;
+    std::vector<WeightBatch> ups;
+    auto fail_all = [&](wr_status st) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        const double t = clock_s();
+        for (Live &L : live) finish(s, L.r, st, t);
+        live.clear();
+        s->cv_done.notify_all();
+    };
+    for (;;) {
+        std::vector<Request *> adm;
+        std::vector<uint32_t> rows, srcv;
+        std::vector<Live> fresh;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (live.empty())
+                s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->updates.empty(); });
+            if (s->stop && s->queue.empty() && s->updates.empty() && live.empty()) return true;
+            const bool update_waiting = !s->updates.empty();
+            if (update_waiting && live.empty()) {
+                while (!s->updates.empty()) {
+                    ups.push_back(std::move(s->updates.front()));
+                    s->updates.pop_front();
+                }
+            }
+            if (!update_waiting) {
+                // admission in arrival order while free rows last; the picks
+                // of the orders admitted together share source lanes
+                std::unordered_map<uint32_t, uint32_t> slot_of;
+                const double now = clock_s() - s->t0;
+                while (!s->queue.empty()) {
+                    Request *r = s->queue.front();
+                    // distinct picks of the order, and those new to this group
+                    std::unordered_map<uint32_t, uint32_t> seen;
+                    uint32_t add = 0;
+                    for (uint32_t v : r->picks)
+                        if (seen.emplace(v, 0u).second && !slot_of.count(v)) ++add;
+                    if ((seen.size() + 63) / 64 > R) {
+                        // larger than the whole state: can never be admitted
+                        s->queue.pop_front();
+                        r->info.t_admit = now;
+                        finish(s, r, WR_E_NOMEM, clock_s());
+                        s->cv_done.notify_all();
+                        continue;
+                    }
+                    const size_t used = slot_of.size();
+                    const size_t rows_after = (used + add + 63) / 64;
+                    if (rows_after - rows.size() > free_rows.size()) break;
+                    s->queue.pop_front();
+                    Live L;
+                    L.r = r;
+                    for (uint32_t v : r->picks) {
+                        auto it = slot_of.find(v);
+                        if (it == slot_of.end()) {
+                            const uint32_t k = static_cast<uint32_t>(slot_of.size());
+                            if (k % 64 == 0) {
+                                rows.push_back(free_rows.back());
+                                free_rows.pop_back();
+                                srcv.insert(srcv.end(), 64, NONE);
+                            }
+                            const uint32_t slot = rows[k / 64] * 64 + k % 64;
+                            srcv[k] = v;
+                            it = slot_of.emplace(v, slot).first;
+                        }
+                        L.slot.push_back(it->second);
+                    }
+                    for (uint32_t sl : L.slot) L.rows.push_back(sl / 64);
+                    std::sort(L.rows.begin(), L.rows.end());
+                    L.rows.erase(std::unique(L.rows.begin(), L.rows.end()), L.rows.end());
+                    r->info.t_admit = now;
+                    r->info.epoch = g->epoch;
+                    fresh.push_back(std::move(L));
+                }
+            }
+        }
+        if (!ups.empty()) {
+            apply_updates(s, ups);
+            // nothing is in flight; weights beyond the overlay tables' range
+            // move serving to step batching
+            try {
+                (void)stream_bytes_per_block(g);
+            } catch (const Error &) {
+                stream_destroy(s->stream);
+                s->stream = nullptr;
+                run_step_mode(s);
+                return true;
+            }
+        }
+        try {
+            if (!rows.empty()) {
+                stream_admit(s->stream, rows, srcv);
+                for (uint32_t b : rows) busy[b] = 1;
+                for (Live &L : fresh) {
+                    for (uint32_t b : L.rows) ++refcnt[b];
+                    live.push_back(std::move(L));
+                }
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->max_inflight = std::max<uint32_t>(s->max_inflight, static_cast<uint32_t>(live.size()));
+            }
+            if (live.empty()) continue;
+            stream_step(s->stream, pending);
+            for (uint32_t b = 0; b < R; ++b)
+                if (busy[b] && !pending[b]) busy[b] = 0;
+            // retire the orders whose rows have all converged
+            std::vector<uint32_t> off(1, 0u), picks, slots;
+            std::vector<size_t> done;
+            for (size_t i = 0; i < live.size(); ++i) {
+                bool ok = true;
+                for (uint32_t b : live[i].rows) ok = ok && !busy[b];
+                if (!ok) continue;
+                done.push_back(i);
+                picks.insert(picks.end(), live[i].r->picks.begin(), live[i].r->picks.end());
+                slots.insert(slots.end(), live[i].slot.begin(), live[i].slot.end());
+                off.push_back(static_cast<uint32_t>(picks.size()));
+            }
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                ++s->steps;
+            }
+            if (done.empty()) continue;
+            uint64_t total = 0;
+            for (size_t o = 0; o + 1 < off.size(); ++o)
+                total += static_cast<uint64_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
+            std::vector<uint32_t> out(total);
+            stream_gather(s->stream, off, picks, slots, out.data());
+            const double t_done = clock_s();
+            std::lock_guard<std::mutex> lk(s->mu);
+            uint64_t at = 0;
+            for (size_t k = 0; k < done.size(); ++k) {
+                Live &L = live[done[k]];
+                const uint64_t n = static_cast<uint64_t>(L.r->picks.size()) * L.r->picks.size();
+                L.r->dist.assign(out.begin() + at, out.begin() + at + n);
+                at += n;
+                finish(s, L.r, WR_OK, t_done);
+                for (uint32_t b : L.rows)
+                    if (--refcnt[b] == 0) free_rows.push_back(b);
+                L.r = nullptr;
+            }
+            live.erase(std::remove_if(live.begin(), live.end(), [](const Live &L) { return !L.r; }), live.end());
+            s->cv_done.notify_all();
+        } catch (const Error &e) {
+            // a failed step fails the orders in flight and the state is built
+            // afresh; serving goes on (in step batching if that fails too)
+            set_last_error(e.msg);
+            fail_all(e.st);
+            std::fill(refcnt.begin(), refcnt.end(), 0u);
+            std::fill(busy.begin(), busy.end(), 0);
+            free_rows.clear();
+            for (uint32_t b = R; b-- > 0;) free_rows.push_back(b);
+            stream_destroy(s->stream);
+            s->stream = nullptr;
+            try {
+                s->stream = stream_create(g, R);
+            } catch (const Error &) {
+                run_step_mode(s);
+                return true;
+            }
+        }
+    }
+}
+
+void scheduler(wr_server *s) {
+    (void)hipSetDevice(s->g->ctx->device);
+    if (!run_stream_mode(s)) run_step_mode(s);
 }
 
 Request *find(wr_server *s, uint64_t ticket) {
@@ -315,6 +522,7 @@ wr_status wr_server_destroy(wr_server *srv) {
         srv->cv_work.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
+    if (srv->stream) stream_destroy(srv->stream);
     for (auto &kv : srv->reqs) delete kv.second;
     delete srv;
     WR_API_END

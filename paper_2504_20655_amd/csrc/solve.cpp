@@ -201,7 +201,10 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u) * lanes);
     stamps.alloc(ctx, static_cast<size_t>(S) * ts.T);
     visited.alloc(ctx, static_cast<size_t>(S) * ts.T);
-    if (with_flags) flags.alloc(ctx, static_cast<size_t>(S) * ts.T);
+    if (with_flags) {
+        flags.alloc(ctx, static_cast<size_t>(S) * ts.T);
+        pending.alloc(ctx, S);
+    }
     cnt.alloc(ctx, 2ull * ts.T);
     bucket.alloc(ctx, 2ull * ts.T * S);
     tiles.alloc(ctx, 2ull * ts.T);
@@ -230,6 +233,7 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     ss.src_pos = src_pos.p;
     ss.src_tile = src_tile.p;
     ss.flags = with_flags ? flags.p : nullptr;
+    ss.pending = with_flags ? pending.p : nullptr;
 }
 
 uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves, uint32_t lanes) {
@@ -672,6 +676,134 @@ void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_
     }
 }
 
+}  // namespace
+
+// ------------------------------------------------------ streaming overlay
+struct StreamSolver {
+    wr_graph *g = nullptr;
+    uint64_t gen = 0;
+    uint32_t blocks = 0;
+};
+
+namespace {
+
+SegWork &stream_work(StreamSolver *s) {
+    SegWork &w = seg_workspace(s->g, s->blocks * 64u, true, false, true);
+    if (w.gen != s->gen || w.S_cap < s->blocks)
+        fail(WR_E_INTERNAL, "the streaming state was rebuilt while requests were in flight");
+    return w;
+}
+
+}  // namespace
+
+uint64_t stream_bytes_per_block(wr_graph *g) {
+    (void)resolve_algo(g, WR_ALGO_OVERLAY);
+    return SegBuffers::bytes_per_row(*g->tiles, 4, 64);
+}
+
+StreamSolver *stream_create(wr_graph *g, uint32_t blocks) {
+    (void)hipSetDevice(g->ctx->device);
+    (void)resolve_algo(g, WR_ALGO_OVERLAY);
+    if (!blocks) fail(WR_E_NOMEM, "no block row fits the memory budget");
+    SegWork &w = seg_workspace(g, blocks * 64u, true, false, true);
+    const TileSet &ts = *g->tiles;
+    hipStream_t st = g->ctx->stream;
+    launch_fill_u8(w.buf.flags.p, static_cast<size_t>(w.S_cap) * ts.T, 0u, st);
+    launch_fill_u32(w.buf.pending.p, w.S_cap, 0u, st);
+    launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
+    launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    launch_fill_u32(w.buf.src_tile.p, static_cast<size_t>(w.S_cap) * 64, NONE, st);
+    ensure_overlay_tables(g);
+    WR_HIP(hipStreamSynchronize(st));
+    auto *s = new StreamSolver();
+    s->g = g;
+    s->gen = w.gen;
+    s->blocks = w.S_cap;
+    return s;
+}
+
+void stream_destroy(StreamSolver *s) { delete s; }
+
+uint32_t stream_blocks(const StreamSolver *s) { return s->blocks; }
+
+void stream_admit(StreamSolver *s, const std::vector<uint32_t> &blocks, const std::vector<uint32_t> &srcv) {
+    wr_graph *g = s->g;
+    SegWork &w = stream_work(s);
+    const TileSet &ts = *g->tiles;
+    const SegState &ss = w.ss;
+    hipStream_t st = g->ctx->stream;
+    ensure_overlay_tables(g);   // the epoch may have moved since the last admission
+    const uint32_t nb = static_cast<uint32_t>(blocks.size());
+    if (!nb) return;
+    std::vector<uint32_t> sp(64), stl(64);
+    for (uint32_t i = 0; i < nb; ++i) {
+        const uint32_t b = blocks[i];
+        for (uint32_t l = 0; l < 64; ++l) {
+            const uint32_t v = srcv[static_cast<size_t>(i) * 64 + l];
+            sp[l] = v == NONE ? NONE : ts.pos_of[v];
+            stl[l] = v == NONE ? NONE : ts.tile_of[v];
+        }
+        WR_HIP(hipMemcpyAsync(w.buf.src_pos.p + static_cast<size_t>(b) * 64, sp.data(), 256,
+                              hipMemcpyHostToDevice, st));
+        WR_HIP(hipMemcpyAsync(w.buf.src_tile.p + static_cast<size_t>(b) * 64, stl.data(), 256,
+                              hipMemcpyHostToDevice, st));
+        WR_HIP(hipStreamSynchronize(st));   // sp / stl are reused for the next row
+        launch_fill_u32(w.buf.inbox.p + static_cast<size_t>(b) * std::max(ts.NP, 1u) * 64,
+                        static_cast<size_t>(std::max(ts.NP, 1u)) * 64, INF, st);
+        launch_fill_u8(w.buf.visited.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
+        launch_fill_u32(w.buf.stamps.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
+    }
+    // pass 0 of the new rows: seeds into the parity-0 lists, then the
+    // segment kernel relaxes the sources' own tiles and flags what it pushed
+    launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
+    launch_fill_u32(w.buf.ctr.p, 2, 0u, st);   // ntiles[0], ntiles[1]
+    DBuf<uint32_t> d_blocks;
+    upload(d_blocks, g->ctx, blocks, st);
+    launch_seg_seed_blocks(ts, ss, d_blocks.p, nb, st);
+    launch_seg_step(ts, ss, 0u, ts.tile_cap, w.waves, w.G, w.grid, st);
+    WR_HIP(hipStreamSynchronize(st));
+}
+
+void stream_step(StreamSolver *s, std::vector<uint32_t> &pending) {
+    wr_graph *g = s->g;
+    SegWork &w = stream_work(s);
+    hipStream_t st = g->ctx->stream;
+    WR_HIP(hipGraphLaunch(w.exec, st));
+    pending.resize(s->blocks);
+    WR_HIP(hipMemcpyAsync(pending.data(), w.buf.pending.p, static_cast<size_t>(s->blocks) * 4,
+                          hipMemcpyDeviceToHost, st));
+    WR_HIP(hipStreamSynchronize(st));
+}
+
+void stream_gather(StreamSolver *s, const std::vector<uint32_t> &off, const std::vector<uint32_t> &picks,
+                   const std::vector<uint32_t> &slot_of_pick, uint32_t *host_out) {
+    wr_graph *g = s->g;
+    SegWork &w = stream_work(s);
+    wr_context *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    const uint32_t n = static_cast<uint32_t>(off.size()) - 1;
+    std::vector<uint64_t> base(n);
+    uint64_t total = 0;
+    for (uint32_t o = 0; o < n; ++o) {
+        base[o] = total;
+        total += static_cast<uint64_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
+    }
+    if (!total) return;
+    DBuf<uint32_t> d_off, d_picks, d_slot, d_out;
+    DBuf<uint64_t> d_base;
+    upload(d_off, ctx, off, st);
+    upload(d_picks, ctx, picks, st);
+    upload(d_slot, ctx, slot_of_pick, st);
+    upload(d_base, ctx, base, st);
+    d_out.alloc(ctx, total);
+    launch_gather_ovl(n, d_off.p, d_picks.p, d_base.p, d_slot.p, 0u, s->blocks * 64u, *g->tiles, w.ss,
+                      g->tiles->d_F.p, d_out.p, st);
+    WR_HIP(hipMemcpyAsync(host_out, d_out.p, total * 4, hipMemcpyDeviceToHost, st));
+    WR_HIP(hipStreamSynchronize(st));
+}
+
+namespace {
 }  // namespace
 }  // namespace wr
 

@@ -262,9 +262,13 @@ struct SegState {
     uint32_t lanes_log2 = 0;   // 0: a state row per source; 6: per block of 64 sources
     uint32_t nsrc = 0;         // sources of the chunk (blocked layout: lanes beyond are idle)
     uint8_t *flags = nullptr;  // [T][S] activation flags (overlay schedule), else null
+    uint32_t *pending = nullptr;   // [S] blocks with set flags after a replay (overlay schedule)
 };
 // activates (s, tile of source s) for the chunk's sources s < n
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
+// the same for the sources of the listed blocks (device array of nb block rows)
+void launch_seg_seed_blocks(const TileSet &ts, const SegState &ss, const uint32_t *blocks, uint32_t nb,
+                            hipStream_t st);
 // one pass: prologue (zero next counters) + plan (units) + relaxation
 // ev (optional): events recorded right before / after the relaxation kernel
 void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t tile_cap,
@@ -279,7 +283,7 @@ void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t
 // blocks of 64 sources with lanes = 64; see SegState).
 struct SegBuffers {
     uint32_t S_cap = 0, G = 0, lanes = 1;
-    DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile;
+    DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile, pending;
     DBuf<uint8_t> visited, flags;
     DBuf<uint2> units;
     DBuf<unsigned long long> stats;
@@ -289,6 +293,27 @@ struct SegBuffers {
     // device bytes per state row
     static uint64_t bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes);
 };
+// Streaming overlay state for continuous batching: a fixed set of block rows
+// (64 source lanes each) that are seeded, relaxed and read out independently,
+// so new sources join between replays while older ones are still relaxing.
+struct StreamSolver;
+// Throws WR_E_UNSUPPORTED when the graph's tiling cannot run the overlay
+// schedule; `blocks` is the number of rows wanted (bounded by the budget).
+StreamSolver *stream_create(wr_graph *g, uint32_t blocks);
+void stream_destroy(StreamSolver *s);
+uint32_t stream_blocks(const StreamSolver *s);
+// Bytes of device state per block row of the streaming schedule.
+uint64_t stream_bytes_per_block(wr_graph *g);
+// Resets the listed rows and seeds them with srcv[i * 64 + lane] (NONE for
+// an empty lane), then runs their first pass (the sources' own tiles).
+void stream_admit(StreamSolver *s, const std::vector<uint32_t> &blocks, const std::vector<uint32_t> &srcv);
+// One replay of passes over every row; pending[b] != 0 while row b has work.
+void stream_step(StreamSolver *s, std::vector<uint32_t> &pending);
+// Order matrices of converged rows into host memory: picks of order o are
+// picks[off[o] .. off[o+1]) with source slot (row * 64 + lane) slot_of_pick.
+void stream_gather(StreamSolver *s, const std::vector<uint32_t> &off, const std::vector<uint32_t> &picks,
+                   const std::vector<uint32_t> &slot_of_pick, uint32_t *host_out);
+
 // Persistent grid size of the pass kernel for this schedule.
 uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves, uint32_t lanes);
 // Captures K passes (parities 0,1,0,...) into an instantiated graph.

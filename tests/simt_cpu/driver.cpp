@@ -1,8 +1,12 @@
 // Runs one wr_sssp / wr_order_matrices request read from a file through the
-// C ABI under the CPU executor -- TEST INFRASTRUCTURE ONLY.
+// C ABI under the CPU executor -- TEST INFRASTRUCTURE ONLY.  Mode 2 sends
+// the orders through the request server instead, one every `flags`
+// milliseconds, so later orders arrive while earlier ones are relaxing.
 //   wr_cpu_driver <request.bin> <result.bin>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <thread>
 #include <vector>
 
 #include "wroute.h"
@@ -54,6 +58,32 @@ int main(int argc, char **argv) {
         if (want_pred) pred.assign(static_cast<size_t>(S) * V, 0);
         if (st == WR_OK)
             st = wr_sssp(g, S, src.data(), out.data(), want_pred ? pred.data() : nullptr, flags, nullptr);
+    } else if (mode == 2) {
+        const uint32_t no = rd();
+        auto off = rdv(no + 1);
+        auto picks = rdv(off[no]);
+        wr_server *srv = nullptr;
+        wr_server_opts opts{};
+        opts.max_source_slots = 128;
+        if (st == WR_OK) st = wr_server_create(g, &opts, &srv);
+        std::vector<uint64_t> tickets(no);
+        for (uint32_t o = 0; o < no && st == WR_OK; ++o) {
+            st = wr_server_submit(srv, off[o + 1] - off[o], picks.data() + off[o], &tickets[o]);
+            std::this_thread::sleep_for(std::chrono::milliseconds(flags));
+        }
+        if (st == WR_OK) st = wr_server_drain(srv);
+        for (uint32_t o = 0; o < no && st == WR_OK; ++o) {
+            const uint32_t P = off[o + 1] - off[o];
+            std::vector<uint32_t> m(static_cast<size_t>(P) * P);
+            st = wr_server_poll(srv, tickets[o], m.data(), nullptr);
+            out.insert(out.end(), m.begin(), m.end());
+        }
+        wr_stats ss{};
+        if (srv) wr_server_stats(srv, &ss);
+        std::fprintf(stderr, "server: completed %llu steps %llu max_inflight %u\n",
+                     static_cast<unsigned long long>(ss.completed), static_cast<unsigned long long>(ss.steps),
+                     ss.max_inflight_requests);
+        wr_server_destroy(srv);
     } else {
         const uint32_t no = rd();
         auto off = rdv(no + 1);

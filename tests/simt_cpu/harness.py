@@ -22,14 +22,16 @@ def driver(rebuild=False) -> str:
 
 
 def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="auto",
-        pred=False, graph_capture=True, seg=None, schedule=(0, 0, 0), updates=None, timeout=600):
-    """seg: None | ("grid", W, H, L, tw, th) | ("map", nseg, map).  Returns
-    (status, out, pred_or_None, stderr)."""
+        pred=False, graph_capture=True, seg=None, schedule=(0, 0, 0), updates=None, timeout=600,
+        server_gap_ms=None):
+    """seg: None | ("grid", W, H, L, tw, th) | ("map", nseg, map).  With
+    server_gap_ms the orders go through the request server, one every
+    server_gap_ms milliseconds.  Returns (status, out, pred_or_None, stderr)."""
     V = len(row_ptr) - 1
     E = len(col)
-    parts = [np.asarray([0x57524F55, 0 if sources is not None else 1,
-                         ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE),
-                         1 if pred else 0, V, E], np.uint32),
+    mode = 0 if sources is not None else (2 if server_gap_ms is not None else 1)
+    flags = server_gap_ms if mode == 2 else ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
+    parts = [np.asarray([0x57524F55, mode, flags, 1 if pred else 0, V, E], np.uint32),
              np.asarray(row_ptr, np.uint32), np.asarray(col, np.uint32), np.asarray(w, np.uint32)]
     if seg is None:
         parts.append(np.asarray([0], np.uint32))

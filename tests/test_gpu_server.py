@@ -177,3 +177,31 @@ def test_autotune_identical_results(rt, ctx, tmp_path):
     G2.autotune(sources_hint=64, cache_path=str(cache))
     assert time.time() - t < 5.0
     assert (G2.order_matrices(wl.pick_offsets, wl.picks) == exp).all()
+
+
+def test_server_admits_while_others_relax(rt, ctx):
+    """Continuous batching: an order that arrives while another is relaxing is
+    admitted before that one finishes (step batching could only admit it
+    afterwards), and both results stay exact."""
+    wl = make_config("medium", side=256, num_orders=24)
+    g = wl.graph
+    G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
+    G.segment_grid(g.W, g.H, 1, 24, 20)
+    G.set_schedule(512, 8, 0)
+    orders = _orders(wl)
+    srv = rt.Server(G, passes_per_step=2)
+    try:
+        tickets = []
+        for pk in orders:
+            tickets.append(srv.submit(pk))
+            time.sleep(0.0005)
+        res = _wait(srv, tickets)
+        info = [res[t][1] for t in tickets]
+        overlap = any(info[i]["t_admit"] < info[j]["t_admit"] < info[i]["t_done"]
+                      for i in range(len(info)) for j in range(len(info)))
+        assert overlap, "no order was admitted while another was in flight"
+        for i, t in enumerate(tickets):
+            assert (res[t][0] == _expect(g, orders[i])).all(), f"order {i}"
+        assert srv.stats()["max_inflight_requests"] > 1
+    finally:
+        srv.close()
