@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--b1-orders", type=int, default=2,
                     help="orders of the paper-structured B1 baseline to time (0 = skip)")
+    ap.add_argument("--serve-rates", default="500,2000",
+                    help="Poisson arrival rates (orders/s) of the serving leg, comma-separated ('' = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device once (a dispatch of known "
                          "traffic that scales the HBM byte counters of a profiler run)")
@@ -86,6 +89,75 @@ def load_traffic(kernel: str):
     if t.get("kernel_src_sha") != kernel_source_sha():
         return None
     return t.get("bytes_per_launch")
+
+
+def serving_leg(wr, ctx, rates, seconds, tile):
+    """Continuous-batching server on the serving warehouse (3 levels of
+    1024x1024 joined by lifts): Poisson order arrivals with sizes uniform in
+    2..128, and 1% congestion updates every 100 ms applied between steps.
+    Latency is arrival to result ready on the host."""
+    from wgen import make_config
+    from wgen.orders import CongestionTicker
+    wl = make_config("serving")
+    g = wl.graph
+    ex = wl.extra
+    G = wr.Graph(ctx, g.row_ptr, g.col, g.w)
+    G.set_schedule(tile, 8, 0)
+    G.segment_grid(g.W, g.H, g.levels, 24, 20)
+    rng = np.random.default_rng(wl.seed + 7)
+    cand = g.aisle_adjacent_vertices()
+
+    def draw(n):
+        sizes = rng.integers(ex["pick_lo"], ex["pick_hi"] + 1, n)
+        return [cand[rng.choice(len(cand), size=int(P), replace=False)].astype(np.uint32) for P in sizes]
+
+    # warm-up server: builds the tiles, the boundary tables and the captured passes
+    srv = wr.Server(G)
+    ts = [srv.submit(o) for o in draw(16)]
+    srv.drain()
+    for t in ts:
+        srv.poll(t)
+    srv.close()
+    out = []
+    for rate in rates:
+        n = max(1, int(rate * seconds))
+        orders = draw(n)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+        ticker = CongestionTicker(np.random.default_rng(wl.seed + 11), g.edge_arc_a, g.edge_arc_b,
+                                  g.edge_base_w, g.edge_is_lift, ex["congestion"], ex["congestion_extra"])
+        srv = wr.Server(G)
+        tickets, ticks = [], 0
+        t0 = time.perf_counter()
+        next_tick = ex["tick_s"]
+        for i in range(n):
+            target = t0 + arrivals[i]
+            while True:
+                now = time.perf_counter()
+                if now - t0 >= next_tick:
+                    srv.update_weights(*ticker.tick())
+                    ticks += 1
+                    next_tick += ex["tick_s"]
+                if now >= target:
+                    break
+                time.sleep(min(target - now, 0.0005))
+            tickets.append(srv.submit(orders[i]))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        for t in tickets:
+            srv.poll(t)
+        srv.close()
+        out.append({"rate": rate, "orders": n, "weight_ticks": ticks,
+                    "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                    "mean_ms": round(st["mean_ms"], 3), "orders_per_s": round(n / wall, 1),
+                    "max_inflight": st["max_inflight_requests"], "steps": st["steps"],
+                    "failed": st["failed"]})
+        print(f"serving rate {rate}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
+              f"({n} orders, {ticks} weight ticks)", file=sys.stderr, flush=True)
+    G.close()
+    return {"workload": "serving: 3 levels of 1024x1024 (V=3,145,728, E=6,422,650), 64 lifts (w=50), "
+                        "P ~ U{2..128}, 1% congestion per 100 ms",
+            "seconds_per_rate": seconds, "runs": out}
 
 
 def cpu_baseline(wl, target_core_s: float):
@@ -239,6 +311,9 @@ def main():
         res["baseline_b1"] = {"value": round(k / tb, 3), "unit": "orders/s",
                               "sample": f"first {k} orders, one order at a time, thread per arc, "
                                         f"host-checked early exit ({G.last_run()['passes']} rounds)"}
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+    if rates:
+        res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds, args.tile or 512)
     if args.copy_probe > 0:
         n = args.copy_probe << 18
         a = torch.ones(n, dtype=torch.int32, device="cuda")

@@ -16,6 +16,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -70,6 +72,9 @@ struct wr_server {
     std::thread worker;
     // streaming mode
     StreamSolver *stream = nullptr;
+    // phase timers (seconds), printed at destroy when WR_TRACE is set
+    double t_update = 0, t_admit = 0, t_step = 0, t_gather = 0, t_wait = 0;
+    uint64_t rows_admitted = 0;
 };
 
 namespace {
@@ -226,8 +231,10 @@ bool run_stream_mode(wr_server *s) {
         std::vector<Live> fresh;
         {
             std::unique_lock<std::mutex> lk(s->mu);
+            const double tw0 = clock_s();
             if (live.empty())
                 s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->updates.empty(); });
+            s->t_wait += clock_s() - tw0;
             if (s->stop && s->queue.empty() && s->updates.empty() && live.empty()) return true;
             const bool update_waiting = !s->updates.empty();
             if (update_waiting && live.empty()) {
@@ -240,6 +247,7 @@ bool run_stream_mode(wr_server *s) {
                 // admission in arrival order while free rows last; the picks
                 // of the orders admitted together share source lanes
                 std::unordered_map<uint32_t, uint32_t> slot_of;
+                std::vector<uint32_t> group;   // distinct picks of the group
                 const double now = clock_s() - s->t0;
                 while (!s->queue.empty()) {
                     Request *r = s->queue.front();
@@ -256,38 +264,46 @@ bool run_stream_mode(wr_server *s) {
                         s->cv_done.notify_all();
                         continue;
                     }
-                    const size_t used = slot_of.size();
-                    const size_t rows_after = (used + add + 63) / 64;
-                    if (rows_after - rows.size() > free_rows.size()) break;
+                    if ((group.size() + add + 63) / 64 > free_rows.size()) break;
                     s->queue.pop_front();
+                    for (uint32_t v : r->picks)
+                        if (slot_of.emplace(v, 0u).second) group.push_back(v);
                     Live L;
                     L.r = r;
-                    for (uint32_t v : r->picks) {
-                        auto it = slot_of.find(v);
-                        if (it == slot_of.end()) {
-                            const uint32_t k = static_cast<uint32_t>(slot_of.size());
-                            if (k % 64 == 0) {
-                                rows.push_back(free_rows.back());
-                                free_rows.pop_back();
-                                srcv.insert(srcv.end(), 64, NONE);
-                            }
-                            const uint32_t slot = rows[k / 64] * 64 + k % 64;
-                            srcv[k] = v;
-                            it = slot_of.emplace(v, slot).first;
-                        }
-                        L.slot.push_back(it->second);
-                    }
-                    for (uint32_t sl : L.slot) L.rows.push_back(sl / 64);
-                    std::sort(L.rows.begin(), L.rows.end());
-                    L.rows.erase(std::unique(L.rows.begin(), L.rows.end()), L.rows.end());
                     r->info.t_admit = now;
                     r->info.epoch = g->epoch;
                     fresh.push_back(std::move(L));
                 }
+                if (!group.empty()) {
+                    // lanes in tile order: a row's sources start close together,
+                    // so their wavefronts share tile visits
+                    const std::vector<uint32_t> &tile_of = g->tiles->tile_of;
+                    std::sort(group.begin(), group.end(), [&](uint32_t x, uint32_t y) {
+                        return tile_of[x] != tile_of[y] ? tile_of[x] < tile_of[y] : x < y;
+                    });
+                    const size_t nrows = (group.size() + 63) / 64;
+                    for (size_t i = 0; i < nrows; ++i) {
+                        rows.push_back(free_rows.back());
+                        free_rows.pop_back();
+                    }
+                    srcv.assign(nrows * 64, NONE);
+                    for (size_t k = 0; k < group.size(); ++k) {
+                        srcv[k] = group[k];
+                        slot_of[group[k]] = rows[k / 64] * 64 + static_cast<uint32_t>(k % 64);
+                    }
+                    for (Live &L : fresh) {
+                        for (uint32_t v : L.r->picks) L.slot.push_back(slot_of[v]);
+                        for (uint32_t sl : L.slot) L.rows.push_back(sl / 64);
+                        std::sort(L.rows.begin(), L.rows.end());
+                        L.rows.erase(std::unique(L.rows.begin(), L.rows.end()), L.rows.end());
+                    }
+                }
             }
         }
         if (!ups.empty()) {
+            const double tu0 = clock_s();
             apply_updates(s, ups);
+            s->t_update += clock_s() - tu0;
             // nothing is in flight; weights beyond the overlay tables' range
             // move serving to step batching
             try {
@@ -301,7 +317,10 @@ bool run_stream_mode(wr_server *s) {
         }
         try {
             if (!rows.empty()) {
+                const double ta0 = clock_s();
                 stream_admit(s->stream, rows, srcv);
+                s->t_admit += clock_s() - ta0;
+                s->rows_admitted += rows.size();
                 for (uint32_t b : rows) busy[b] = 1;
                 for (Live &L : fresh) {
                     for (uint32_t b : L.rows) ++refcnt[b];
@@ -311,7 +330,9 @@ bool run_stream_mode(wr_server *s) {
                 s->max_inflight = std::max<uint32_t>(s->max_inflight, static_cast<uint32_t>(live.size()));
             }
             if (live.empty()) continue;
+            const double ts0 = clock_s();
             stream_step(s->stream, pending);
+            s->t_step += clock_s() - ts0;
             for (uint32_t b = 0; b < R; ++b)
                 if (busy[b] && !pending[b]) busy[b] = 0;
             // retire the orders whose rows have all converged
@@ -335,7 +356,9 @@ bool run_stream_mode(wr_server *s) {
             for (size_t o = 0; o + 1 < off.size(); ++o)
                 total += static_cast<uint64_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
             std::vector<uint32_t> out(total);
+            const double tg0 = clock_s();
             stream_gather(s->stream, off, picks, slots, out.data());
+            s->t_gather += clock_s() - tg0;
             const double t_done = clock_s();
             std::lock_guard<std::mutex> lk(s->mu);
             uint64_t at = 0;
@@ -523,6 +546,12 @@ wr_status wr_server_destroy(wr_server *srv) {
     }
     if (srv->worker.joinable()) srv->worker.join();
     if (srv->stream) stream_destroy(srv->stream);
+    if (std::getenv("WR_TRACE"))
+        std::fprintf(stderr,
+                     "[wroute server] steps %llu rows admitted %llu | seconds: update %.3f admit %.3f "
+                     "step %.3f gather %.3f idle %.3f\n",
+                     static_cast<unsigned long long>(srv->steps), static_cast<unsigned long long>(srv->rows_admitted),
+                     srv->t_update, srv->t_admit, srv->t_step, srv->t_gather, srv->t_wait);
     for (auto &kv : srv->reqs) delete kv.second;
     delete srv;
     WR_API_END

@@ -736,19 +736,18 @@ void stream_admit(StreamSolver *s, const std::vector<uint32_t> &blocks, const st
     ensure_overlay_tables(g);   // the epoch may have moved since the last admission
     const uint32_t nb = static_cast<uint32_t>(blocks.size());
     if (!nb) return;
-    std::vector<uint32_t> sp(64), stl(64);
+    std::vector<uint32_t> sp(static_cast<size_t>(nb) * 64), stl(static_cast<size_t>(nb) * 64);
+    for (size_t k = 0; k < sp.size(); ++k) {
+        const uint32_t v = srcv[k];
+        sp[k] = v == NONE ? NONE : ts.pos_of[v];
+        stl[k] = v == NONE ? NONE : ts.tile_of[v];
+    }
     for (uint32_t i = 0; i < nb; ++i) {
         const uint32_t b = blocks[i];
-        for (uint32_t l = 0; l < 64; ++l) {
-            const uint32_t v = srcv[static_cast<size_t>(i) * 64 + l];
-            sp[l] = v == NONE ? NONE : ts.pos_of[v];
-            stl[l] = v == NONE ? NONE : ts.tile_of[v];
-        }
-        WR_HIP(hipMemcpyAsync(w.buf.src_pos.p + static_cast<size_t>(b) * 64, sp.data(), 256,
-                              hipMemcpyHostToDevice, st));
-        WR_HIP(hipMemcpyAsync(w.buf.src_tile.p + static_cast<size_t>(b) * 64, stl.data(), 256,
-                              hipMemcpyHostToDevice, st));
-        WR_HIP(hipStreamSynchronize(st));   // sp / stl are reused for the next row
+        WR_HIP(hipMemcpyAsync(w.buf.src_pos.p + static_cast<size_t>(b) * 64, sp.data() + static_cast<size_t>(i) * 64,
+                              256, hipMemcpyHostToDevice, st));
+        WR_HIP(hipMemcpyAsync(w.buf.src_tile.p + static_cast<size_t>(b) * 64, stl.data() + static_cast<size_t>(i) * 64,
+                              256, hipMemcpyHostToDevice, st));
         launch_fill_u32(w.buf.inbox.p + static_cast<size_t>(b) * std::max(ts.NP, 1u) * 64,
                         static_cast<size_t>(std::max(ts.NP, 1u)) * 64, INF, st);
         launch_fill_u8(w.buf.visited.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
