@@ -528,6 +528,24 @@ __device__ __forceinline__ void stage_tile_arcs(const SegPassArgs &A, uint32_t b
         s_odst[i] = static_cast<uint16_t>(A.l_arc[ao + i] >> 16);
 }
 
+// The same with the arcs reversed: a pull over out-arcs and marking over
+// in-arcs, so relax_tile computes distances *to* the seeded vertices.
+__device__ __forceinline__ void stage_tile_arcs_rev(const SegPassArgs &A, uint32_t base, uint32_t n,
+                                                    uint32_t *s_iinfo, uint32_t *s_oinfo, uint32_t *s_iarc,
+                                                    uint16_t *s_odst) {
+    const uint32_t ai = A.l_off[base], ao = A.li_off[base];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t i0 = A.l_off[base + i] - ai, i1 = A.l_off[base + i + 1] - ai;
+        const uint32_t o0 = A.li_off[base + i] - ao, o1 = A.li_off[base + i + 1] - ao;
+        s_iinfo[i] = (i0 << 16) | (i1 - i0);
+        s_oinfo[i] = (o0 << 16) | (o1 - o0);
+    }
+    const uint32_t ni = A.l_off[base + n] - ai, no = A.li_off[base + n] - ao;
+    for (uint32_t i = threadIdx.x; i < ni; i += blockDim.x) s_iarc[i] = A.l_arc[ai + i];
+    for (uint32_t i = threadIdx.x; i < no; i += blockDim.x)
+        s_odst[i] = static_cast<uint16_t>(A.li_arc[ao + i] >> 16);
+}
+
 // Source-blocked pass: a workgroup relaxes one (tile, block of 64 sources)
 // item at a time.  The tile's distances for the 64 sources sit in LDS as
 // rows D[v][lane] (one 256-byte row per vertex); lanes are sources, so every
@@ -642,12 +660,12 @@ __global__ __launch_bounds__(NW * 64) void k_segb_pass(SegPassArgs A) {
 }
 
 // ---------------------------------------------------------- overlay schedule
-// The segments' boundary tables: for tile t with E ports (boundary-in
-// vertices, E <= 64), F[pos][i] is the shortest distance from port i to the
-// vertex at position pos using arcs inside t only (INF for lanes i >= E).
-// Customisation (once per weight epoch): one workgroup per tile seeds lane i
-// at port i and relaxes the tile to its local fixpoint.
-template <int CAP, int NW>
+// Boundary tables of one weight epoch, a workgroup per tile with lanes as
+// seeds.  REV = false: F[pos][i] = in-tile distance from port i of the tile
+// to pos (lanes = ports).  REV = true: B[pos][j] = in-tile distance from pos
+// to exit j of the tile (lanes = exits, arcs reversed).  Lanes beyond the
+// tile's ports / exits stay INF.
+template <int CAP, int NW, bool REV>
 __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t *__restrict__ F) {
     constexpr uint32_t ACAP = 4u * CAP;
     constexpr uint32_t WORDS = CAP / 32;
@@ -665,6 +683,98 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t 
     for (uint32_t t = blockIdx.x; t < A.T; t += gridDim.x) {
         const uint32_t base = uniform(A.tile_base[t]);
         const uint32_t n = uniform(A.tile_base[t + 1]) - base;
+        if (REV)
+            stage_tile_arcs_rev(A, base, n, s_iinfo, s_oinfo, s_iarc, s_odst);
+        else
+            stage_tile_arcs(A, base, n, s_iinfo, s_oinfo, s_iarc, s_odst);
+        for (uint32_t v = wv; v < n; v += NW) D[v * 64 + lane] = INF;
+        for (uint32_t i = threadIdx.x; i < WORDS; i += blockDim.x) {
+            s_cand[0][i] = 0;
+            s_cand[1][i] = 0;
+            s_dirty[i] = 0;
+        }
+        __syncthreads();
+        const uint32_t k0 = uniform(REV ? A.bo_base[t] : A.port_base[t]);
+        const uint32_t k1 = uniform(REV ? A.bo_base[t + 1] : A.port_base[t + 1]);
+        if (wv == 0 && lane < k1 - k0) {
+            const uint32_t loc = REV ? A.bo_local[k0 + lane] : A.port_local[k0 + lane];
+            D[loc * 64 + lane] = 0;
+            atomicOr(&s_dirty[loc >> 5], 1u << (loc & 31));
+        }
+        __syncthreads();
+        relax_tile<CAP, NW>(D, s_iinfo, s_iarc, s_oinfo, s_odst, s_cand, s_dirty, s_list, &s_len, wv, lane);
+        uint32_t *Ft = F + static_cast<size_t>(base) * 64;
+        for (uint32_t v = wv; v < n; v += NW) Ft[v * 64 + lane] = D[v * 64 + lane];
+        __syncthreads();
+    }
+}
+
+// First pass of the overlay schedule: a wave per source slot s (block
+// s / 64, lane s % 64) pushes the source's in-tile distance to each exit j
+// of its tile (lane j reads B[pos][j]) across the exit's cross arcs into the
+// block's inbox rows, flagging (target tile, block) where a row dropped.
+__global__ void k_ovl_seed_push(SegPassArgs A, const uint32_t *__restrict__ B, const uint4 *__restrict__ hdr,
+                                const uint32_t *__restrict__ bo_xbeg, const uint32_t *__restrict__ slots,
+                                uint32_t nslots) {
+    const uint32_t lane = lane_id();
+    const uint32_t wpb = blockDim.x >> 6;
+    for (uint32_t q = blockIdx.x * wpb + (threadIdx.x >> 6); q < nslots; q += gridDim.x * wpb) {
+        const uint32_t s = uniform(slots ? slots[q] : q);
+        const uint32_t t = uniform(A.src_tile[s]);
+        if (t == NONE) continue;
+        const uint32_t b = s >> 6, l = s & 63u;
+        const uint32_t pos = uniform(A.src_pos[s]);
+        const uint4 h = hdr[t];
+        const uint32_t b0 = uniform(h.y), xa0 = uniform(h.z), X = (uniform(h.w) >> 8) & 0xFFu;
+        if (lane >= X) continue;
+        const uint32_t d = B[static_cast<size_t>(pos) * 64 + lane];
+        if (d == INF) continue;
+        uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64 + l;
+        const uint32_t k1 = bo_xbeg[b0 + t + lane + 1];
+        for (uint32_t k = bo_xbeg[b0 + t + lane]; k < k1; ++k) {
+            const uint32_t nd = sat_add(d, A.x_w[xa0 + k]);
+            if (nd < atomicMin(ib + static_cast<size_t>(A.x_port[xa0 + k]) * 64, nd))
+                A.flags[static_cast<size_t>(A.x_tile[xa0 + k]) * A.S + b] = 1;
+        }
+    }
+}
+
+// In-tile distances for sources that share a tile with some target: a
+// workgroup per group of up to 64 sources in one tile (lanes = sources)
+// relaxes the tile from them in LDS and lowers out[...] to the in-tile value
+// (paths that leave the tile are in out[...] already).  pairs mode: the
+// group's entries (lane << 16 | target local index, output index);
+// full mode (pairs == NULL): every vertex of the tile for every lane, at
+// out[row[lane] * V + vertex].
+struct IntileGroup {
+    uint32_t tile, lanes, p0, p1;
+};
+template <int CAP, int NW>
+__global__ __launch_bounds__(NW * 64) void k_intile_fix(SegPassArgs A, const IntileGroup *__restrict__ groups,
+                                                         uint32_t ngroups, const uint32_t *__restrict__ src_local,
+                                                         const uint32_t *__restrict__ pair_key,
+                                                         const uint64_t *__restrict__ pair_out,
+                                                         const uint32_t *__restrict__ row,
+                                                         const uint32_t *__restrict__ vert_of, uint32_t V,
+                                                         uint32_t *__restrict__ out) {
+    constexpr uint32_t ACAP = 4u * CAP;
+    constexpr uint32_t WORDS = CAP / 32;
+    __shared__ uint32_t D[CAP * 64];
+    __shared__ uint32_t s_iinfo[CAP];
+    __shared__ uint32_t s_oinfo[CAP];
+    __shared__ uint32_t s_iarc[ACAP];
+    __shared__ uint16_t s_odst[ACAP];
+    __shared__ uint32_t s_cand[2][WORDS];
+    __shared__ uint32_t s_dirty[WORDS];
+    __shared__ uint16_t s_list[CAP];
+    __shared__ uint32_t s_len;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    for (uint32_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+        const IntileGroup G = groups[gi];
+        const uint32_t t = uniform(G.tile), nl = uniform(G.lanes);
+        const uint32_t base = uniform(A.tile_base[t]);
+        const uint32_t n = uniform(A.tile_base[t + 1]) - base;
         stage_tile_arcs(A, base, n, s_iinfo, s_oinfo, s_iarc, s_odst);
         for (uint32_t v = wv; v < n; v += NW) D[v * 64 + lane] = INF;
         for (uint32_t i = threadIdx.x; i < WORDS; i += blockDim.x) {
@@ -673,16 +783,27 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t 
             s_dirty[i] = 0;
         }
         __syncthreads();
-        const uint32_t p0 = uniform(A.port_base[t]), p1 = uniform(A.port_base[t + 1]);
-        if (wv == 0 && lane < p1 - p0) {
-            const uint32_t loc = A.port_local[p0 + lane];
+        if (wv == 0 && lane < nl) {
+            const uint32_t loc = src_local[static_cast<size_t>(gi) * 64 + lane];
             D[loc * 64 + lane] = 0;
             atomicOr(&s_dirty[loc >> 5], 1u << (loc & 31));
         }
         __syncthreads();
         relax_tile<CAP, NW>(D, s_iinfo, s_iarc, s_oinfo, s_odst, s_cand, s_dirty, s_list, &s_len, wv, lane);
-        uint32_t *Ft = F + static_cast<size_t>(base) * 64;
-        for (uint32_t v = wv; v < n; v += NW) Ft[v * 64 + lane] = D[v * 64 + lane];
+        if (pair_key) {
+            for (uint32_t q = G.p0 + threadIdx.x; q < G.p1; q += blockDim.x) {
+                const uint32_t key = pair_key[q];
+                const uint32_t d = D[(key & 0xFFFFu) * 64 + (key >> 16)];
+                uint32_t *o = out + pair_out[q];
+                *o = min(*o, d);
+            }
+        } else if (lane < nl) {
+            const uint64_t r = static_cast<uint64_t>(row[static_cast<size_t>(gi) * 64 + lane]) * V;
+            for (uint32_t v = wv; v < n; v += NW) {
+                uint32_t *o = out + r + vert_of[base + v];
+                *o = min(*o, D[v * 64 + lane]);
+            }
+        }
         __syncthreads();
     }
 }
@@ -703,7 +824,7 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t 
 // issues their four pushes together.  A visit thus costs one round trip of
 // loads and one of atomics.  LDS is sized at launch to the tiling's largest
 // tile (XM exits x EM entries, PM cross arcs).
-constexpr uint32_t OVL_XCAP = 128;    // exits per tile
+constexpr uint32_t OVL_XCAP = 64;     // exits per tile (one 64-lane row of the exit table)
 constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving a tile
 constexpr uint32_t OVL_NW = 8;        // waves per workgroup
 constexpr uint32_t OVL_B = 4;         // exits a wave computes and pushes together
@@ -908,38 +1029,37 @@ __global__ void k_flags_any(const uint8_t *__restrict__ flags, size_t n, uint32_
     if (__builtin_amdgcn_ballot_w64(any) != 0 && lane_id() == 0) atomicAdd(out, 1u);
 }
 
-// Final distance of chunk source s at v under the overlay schedule:
-// min(the source tile's in-tile value when t is a source tile of the block,
-//     min over t's ports i of entry_i + F[v][i]).
+// Distance of chunk source s (vertex src_v) to v under the overlay schedule
+// over paths that leave the source's tile: min over the ports i of v's tile
+// of entry_i + F[v][i].  The source itself is 0; paths that stay inside the
+// source's tile are added by k_intile_fix.
 __device__ __forceinline__ uint32_t ovl_value(const uint32_t *tile_of, const uint32_t *pos_of,
-                                              const uint8_t *visited, const uint32_t *gdist,
                                               const uint32_t *inbox, const uint32_t *F,
-                                              const uint32_t *port_base, uint32_t T, uint32_t Vt,
-                                              uint32_t NP, uint32_t s, uint32_t src_v, uint32_t v) {
+                                              const uint32_t *port_base, uint32_t NP, uint32_t s,
+                                              uint32_t src_v, uint32_t v) {
+    if (v == src_v) return 0u;
     const uint32_t t = tile_of[v];
-    if (t == NONE) return v == src_v ? 0u : INF;
+    if (t == NONE) return INF;
     const size_t b = s >> 6, l = s & 63u;
     const uint32_t pos = pos_of[v];
-    uint32_t m = visited[b * T + t] == 1 ? gdist[(b * Vt + pos) * 64 + l] : INF;
     const uint32_t p0 = port_base[t], p1 = port_base[t + 1];
     const uint32_t *ib = inbox + (b * NP) * 64 + l;
     const uint32_t *Fv = F + static_cast<size_t>(pos) * 64;
+    uint32_t m = INF;
     for (uint32_t p = p0; p < p1; ++p) m = min(m, sat_add(ib[static_cast<size_t>(p) * 64], Fv[p - p0]));
     return m;
 }
 
 __global__ void k_ovl_emit(const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
-                           const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
                            const uint32_t *__restrict__ inbox, const uint32_t *__restrict__ F,
-                           const uint32_t *__restrict__ port_base, uint32_t T, uint32_t Vt, uint32_t NP,
-                           uint32_t V, uint32_t rows, const uint32_t *__restrict__ row_src_idx,
-                           const uint32_t *__restrict__ row_src_vertex,
+                           const uint32_t *__restrict__ port_base, uint32_t NP, uint32_t V, uint32_t rows,
+                           const uint32_t *__restrict__ row_src_idx, const uint32_t *__restrict__ row_src_vertex,
                            const uint32_t *__restrict__ out_row, uint32_t *__restrict__ out) {
     for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
         const uint32_t s = row_src_idx[r], sv = row_src_vertex[r];
         uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
         for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
-            o[v] = ovl_value(tile_of, pos_of, visited, gdist, inbox, F, port_base, T, Vt, NP, s, sv, v);
+            o[v] = ovl_value(tile_of, pos_of, inbox, F, port_base, NP, s, sv, v);
     }
 }
 
@@ -947,10 +1067,8 @@ __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ p
                              const uint32_t *__restrict__ picks, const uint64_t *__restrict__ out_base,
                              const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n,
                              const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
-                             const uint8_t *__restrict__ visited, const uint32_t *__restrict__ gdist,
                              const uint32_t *__restrict__ inbox, const uint32_t *__restrict__ F,
-                             const uint32_t *__restrict__ port_base, uint32_t T, uint32_t Vt, uint32_t NP,
-                             uint32_t *__restrict__ out) {
+                             const uint32_t *__restrict__ port_base, uint32_t NP, uint32_t *__restrict__ out) {
     for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
         const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
         const uint64_t ob = out_base[o];
@@ -958,8 +1076,7 @@ __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ p
             const uint32_t i = k / P, j = k - i * P;
             const uint32_t si = src_idx_of_pick[a + i];
             if (si < lo || si >= lo + n) continue;
-            out[ob + k] = ovl_value(tile_of, pos_of, visited, gdist, inbox, F, port_base, T, Vt, NP, si - lo,
-                                    picks[a + i], picks[a + j]);
+            out[ob + k] = ovl_value(tile_of, pos_of, inbox, F, port_base, NP, si - lo, picks[a + i], picks[a + j]);
         }
     }
 }
@@ -970,16 +1087,6 @@ __global__ void k_seg_seed(SegPassArgs A, uint32_t n, uint32_t lanes_log2) {
     if (s >= n) return;
     const uint32_t t = A.src_tile[s];
     if (t != NONE) seg_activate(A, s >> lanes_log2, t, 1u);
-}
-
-// Seeds pass 0 for the sources of the listed blocks of 64 (blocked layout):
-// (block, tile of the source) for every lane with a source.
-__global__ void k_seg_seed_blocks(SegPassArgs A, const uint32_t *__restrict__ blocks, uint32_t nb) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb * 64u) return;
-    const uint32_t b = blocks[i >> 6];
-    const uint32_t t = A.src_tile[static_cast<size_t>(b) * 64u + (i & 63u)];
-    if (t != NONE) seg_activate(A, b, t, 1u);
 }
 
 // Splits every active tile's bucket into units of G sources, zeroes the
@@ -1304,15 +1411,6 @@ void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStr
     check_launch("seg_seed");
 }
 
-void launch_seg_seed_blocks(const TileSet &ts, const SegState &ss, const uint32_t *blocks, uint32_t nb,
-                            hipStream_t st) {
-    if (!nb) return;
-    SegPassArgs A = seg_args(ts, ss, 1u, 1u);
-    A.flags = nullptr;
-    hipLaunchKernelGGL(k_seg_seed_blocks, blocks_for(static_cast<size_t>(nb) * 64, 256), 256, 0, st, A, blocks, nb);
-    check_launch("seg_seed_blocks");
-}
-
 void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t tile_cap,
                      uint32_t waves, uint32_t G, uint32_t grid, hipStream_t st, hipEvent_t ev_begin,
                      hipEvent_t ev_end) {
@@ -1450,16 +1548,23 @@ void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww
     check_launch("weight_scatter");
 }
 
-void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st) {
+void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st,
+                       bool reverse) {
     SegState dummy;
     SegPassArgs A = seg_args(ts, dummy, 0u, 1u);
-    if (tile_cap == 256)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_custom<256, 8>), grid, 512, 0, st, A, F);
-    else if (tile_cap == 512)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_custom<512, 8>), grid, 512, 0, st, A, F);
-    else
-        fail(WR_E_UNSUPPORTED, "overlay tables need tiles of at most 512 vertices");
-    check_launch("ovl_custom");
+#define WR_CUSTOM_CASE(CAPV)                                                                          \
+    if (tile_cap == CAPV) {                                                                           \
+        if (reverse)                                                                                  \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_custom<CAPV, 8, true>), grid, 512, 0, st, A, F);  \
+        else                                                                                          \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_custom<CAPV, 8, false>), grid, 512, 0, st, A, F); \
+        check_launch("ovl_custom");                                                                   \
+        return;                                                                                       \
+    }
+    WR_CUSTOM_CASE(256)
+    WR_CUSTOM_CASE(512)
+#undef WR_CUSTOM_CASE
+    fail(WR_E_UNSUPPORTED, "overlay tables need tiles of at most 512 vertices");
 }
 
 static void ovl_dims(const TileSet &ts, uint32_t &XM, uint32_t &EM, uint32_t &PM) {
@@ -1527,9 +1632,8 @@ void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, u
                      uint32_t *out, hipStream_t st) {
     if (!rows) return;
     dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
-    hipLaunchKernelGGL(k_ovl_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited, ss.gdist,
-                       ss.inbox, F, ts.d_port_base.p, ts.T, ts.Vt, std::max(ts.NP, 1u), V, rows, row_src_idx,
-                       row_src_vertex, out_row, out);
+    hipLaunchKernelGGL(k_ovl_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.inbox, F,
+                       ts.d_port_base.p, std::max(ts.NP, 1u), V, rows, row_src_idx, row_src_vertex, out_row, out);
     check_launch("ovl_emit");
 }
 
@@ -1539,9 +1643,50 @@ void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint
                        uint32_t *out, hipStream_t st) {
     if (!num_orders) return;
     hipLaunchKernelGGL(k_gather_ovl, blocks_for(num_orders, 1, 65535), 256, 0, st, num_orders, pick_off, picks,
-                       out_base, src_idx_of_pick, chunk_lo, chunk_n, ts.d_tile_of.p, ts.d_pos_of.p, ss.visited,
-                       ss.gdist, ss.inbox, F, ts.d_port_base.p, ts.T, ts.Vt, std::max(ts.NP, 1u), out);
+                       out_base, src_idx_of_pick, chunk_lo, chunk_n, ts.d_tile_of.p, ts.d_pos_of.p, ss.inbox, F,
+                       ts.d_port_base.p, std::max(ts.NP, 1u), out);
     check_launch("gather_ovl");
+}
+
+void launch_ovl_seed_push(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t nslots,
+                          hipStream_t st) {
+    if (!nslots) return;
+    SegPassArgs A = seg_args(ts, ss, 0u, 1u);
+    hipLaunchKernelGGL(k_ovl_seed_push, blocks_for(nslots, 4, 4096), 256, 0, st, A, ts.d_B.p,
+                       reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), ts.d_bo_xbeg.p, slots, nslots);
+    check_launch("ovl_seed_push");
+}
+
+void launch_intile_fix(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
+                       uint32_t *out, hipStream_t st) {
+    const uint32_t ng = static_cast<uint32_t>(w.grp.size() / 4);
+    if (!ng) return;
+    DBuf<uint32_t> d_grp, d_src, d_row, d_key;
+    DBuf<uint64_t> d_out;
+    upload(d_grp, ctx, w.grp, st);
+    upload(d_src, ctx, w.src_local, st);
+    if (full)
+        upload(d_row, ctx, w.row, st);
+    else {
+        upload(d_key, ctx, w.pair_key, st);
+        upload(d_out, ctx, w.pair_out, st);
+    }
+    SegState dummy;
+    SegPassArgs A = seg_args(ts, dummy, 0u, 1u);
+    const IntileGroup *G = reinterpret_cast<const IntileGroup *>(d_grp.p);
+    const uint32_t grid = std::min<uint32_t>(ng, 4096u);
+    if (ts.tile_cap == 256)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_intile_fix<256, 8>), grid, 512, 0, st, A, G, ng, d_src.p,
+                           full ? nullptr : d_key.p, full ? nullptr : d_out.p, full ? d_row.p : nullptr,
+                           ts.d_vert_of.p, V, out);
+    else if (ts.tile_cap == 512)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_intile_fix<512, 8>), grid, 512, 0, st, A, G, ng, d_src.p,
+                           full ? nullptr : d_key.p, full ? nullptr : d_out.p, full ? d_row.p : nullptr,
+                           ts.d_vert_of.p, V, out);
+    else
+        fail(WR_E_UNSUPPORTED, "in-tile fix-up needs tiles of at most 512 vertices");
+    check_launch("intile_fix");
+    WR_HIP(hipStreamSynchronize(st));   // the uploaded tables are freed on return
 }
 
 uint32_t ovl_max_exits() { return OVL_XCAP; }

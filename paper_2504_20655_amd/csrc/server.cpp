@@ -86,7 +86,7 @@ uint64_t batch_bytes(const wr_graph *g, uint64_t sources, uint64_t out_entries) 
     const uint64_t blocks = (sources + 63) / 64;
     uint64_t per_block;
     if (ts)
-        per_block = SegBuffers::bytes_per_row(*ts, 4, 64);
+        per_block = SegBuffers::bytes_per_row(*ts, 4, 64, false);
     else
         per_block = 64ull * 4ull * g->V * 2ull;
     return out_entries * 4ull + blocks * per_block + (8ull << 20);

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cstdio>
 #include <fstream>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <sstream>
@@ -188,8 +189,8 @@ uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
 
 }  // namespace
 
-uint64_t SegBuffers::bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes) {
-    return 4ull * lanes * (ts.Vt + ts.NP + 2) + 2ull * ts.T + 4ull * ts.T + 8ull * ts.T +
+uint64_t SegBuffers::bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes, bool overlay) {
+    return 4ull * lanes * ((overlay ? 0u : ts.Vt) + ts.NP + 2) + 2ull * ts.T + 4ull * ts.T + 8ull * ts.T +
            8ull * ts.T / G + 8;
 }
 
@@ -197,7 +198,8 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     S_cap = S;
     G = g;
     lanes = ln;
-    gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt * lanes);
+    // the overlay schedule keeps boundary values only (inbox rows)
+    if (!with_flags) gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt * lanes);
     inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u) * lanes);
     stamps.alloc(ctx, static_cast<size_t>(S) * ts.T);
     visited.alloc(ctx, static_cast<size_t>(S) * ts.T);
@@ -311,12 +313,15 @@ void ensure_overlay_tables(wr_graph *g) {
         }
         upload(ts.d_ovl_hdr, g->ctx, hdr, g->ctx->stream);
         upload(ts.d_bo_xbeg, g->ctx, xb, g->ctx->stream);
+        upload(ts.d_vert_of, g->ctx, ts.vert_of, g->ctx->stream);
+        ts.d_B.alloc(g->ctx, static_cast<size_t>(ts.Vt) * 64);
         ts.ovl_em = ovl_row_entries(ts);
         ts.d_Fx.alloc(g->ctx, std::max<size_t>(1, static_cast<size_t>(ts.NB) * ts.ovl_em));
     }
     if (ts.custom_epoch == g->epoch) return;
     const uint32_t grid = static_cast<uint32_t>(g->ctx->num_cus) * 2;
-    launch_ovl_custom(ts, ts.tile_cap, ts.d_F.p, grid, g->ctx->stream);
+    launch_ovl_custom(ts, ts.tile_cap, ts.d_F.p, grid, g->ctx->stream, false);
+    launch_ovl_custom(ts, ts.tile_cap, ts.d_B.p, grid, g->ctx->stream, true);
     launch_ovl_pack(ts, g->ctx->stream);
     ts.custom_epoch = g->epoch;
 }
@@ -336,7 +341,7 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
     if (fits) return *w;
     // size the chunk: the request, bounded by the budget (keep what we hold)
     ws.seg.reset();
-    const uint64_t per = SegBuffers::bytes_per_row(ts, G, lanes);
+    const uint64_t per = SegBuffers::bytes_per_row(ts, G, lanes, overlay);
     const uint64_t avail = g->ctx->available();
     uint64_t R_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
     uint32_t R_cap = static_cast<uint32_t>(std::min<uint64_t>(rows_need, R_fit));
@@ -393,7 +398,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
     launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
-    launch_seg_seed_n(ts, ss, n, st);
+    if (!w.overlay) launch_seg_seed_n(ts, ss, n, st);
     hipEvent_t e0, e1;
     WR_HIP(hipEventCreate(&e0));
     WR_HIP(hipEventCreate(&e1));
@@ -406,7 +411,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     const uint32_t par0 = w.overlay ? 1u : 0u;
     if (w.overlay) {
         if (ts.custom_epoch != g->epoch) ensure_overlay_tables(g);
-        launch_seg_step(ts, ss, 0u, ts.tile_cap, w.waves, w.G, w.grid, st);
+        launch_ovl_seed_push(ts, ss, nullptr, rows * 64, st);
         passes += 1;
     }
     for (;;) {
@@ -645,7 +650,8 @@ void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, 
 // Source-major rows of the current chunk's state: out + out_row[r]*V gets the
 // row of chunk source row_idx[r].
 void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
-               const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out);
+               const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out,
+               const std::vector<uint32_t> &row_vertex, const std::vector<uint32_t> &out_row);
 
 struct StreamJoin {
     // The library works on its own stream; with caller (device) buffers it
@@ -660,13 +666,90 @@ struct StreamJoin {
     }
 };
 
+// Overlay read-outs hold paths that leave the source's tile; these add the
+// in-tile distances of the source's own tile (groups of up to 64 sources of
+// one tile).  Full rows: every vertex of the tile of each row's source.
+IntileWork intile_rows(const TileSet &ts, const std::vector<uint32_t> &src_vertex,
+                       const std::vector<uint32_t> &out_row) {
+    std::map<uint32_t, std::vector<uint32_t>> by_tile;
+    for (uint32_t i = 0; i < src_vertex.size(); ++i) {
+        const uint32_t t = ts.tile_of[src_vertex[i]];
+        if (t != NONE) by_tile[t].push_back(i);
+    }
+    IntileWork w;
+    for (auto &kv : by_tile) {
+        const uint32_t t = kv.first;
+        for (size_t c = 0; c < kv.second.size(); c += 64) {
+            const uint32_t nl = static_cast<uint32_t>(std::min<size_t>(64, kv.second.size() - c));
+            w.grp.insert(w.grp.end(), {t, nl, 0u, 0u});
+            for (uint32_t l = 0; l < 64; ++l) {
+                const uint32_t i = l < nl ? kv.second[c + l] : kv.second[c];
+                w.src_local.push_back(ts.pos_of[src_vertex[i]] - ts.tile_base[t]);
+                w.row.push_back(out_row[i]);
+            }
+        }
+    }
+    return w;
+}
+
+// Order matrices: the entries (i, j) whose picks lie in one tile, for the
+// picks whose source index passes `take` (out index = out_base[o] + i*P + j).
+template <class Take>
+IntileWork intile_pairs(const TileSet &ts, uint32_t num_orders, const uint32_t *off, const uint32_t *picks,
+                        const uint64_t *out_base, Take take) {
+    struct Entry {
+        uint32_t t, src, tgt;
+        uint64_t out;
+    };
+    std::vector<Entry> e;
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        const uint32_t a = off[o], P = off[o + 1] - a;
+        for (uint32_t i = 0; i < P; ++i) {
+            const uint32_t si = picks[a + i];
+            const uint32_t t = ts.tile_of[si];
+            if (t == NONE || !take(a + i)) continue;
+            for (uint32_t j = 0; j < P; ++j) {
+                const uint32_t v = picks[a + j];
+                if (v == si || ts.tile_of[v] != t) continue;
+                e.push_back({t, si, ts.pos_of[v] - ts.tile_base[t], out_base[o] + static_cast<uint64_t>(i) * P + j});
+            }
+        }
+    }
+    std::sort(e.begin(), e.end(), [](const Entry &x, const Entry &y) {
+        return x.t != y.t ? x.t < y.t : x.src < y.src;
+    });
+    IntileWork w;
+    size_t k = 0;
+    while (k < e.size()) {
+        // one group: up to 64 distinct sources of tile e[k].t
+        const uint32_t t = e[k].t;
+        const size_t g0 = w.pair_key.size();
+        std::vector<uint32_t> lanes;
+        while (k < e.size() && e[k].t == t) {
+            if (lanes.empty() || lanes.back() != e[k].src) {
+                if (lanes.size() == 64) break;
+                lanes.push_back(e[k].src);
+            }
+            w.pair_key.push_back((static_cast<uint32_t>(lanes.size() - 1) << 16) | e[k].tgt);
+            w.pair_out.push_back(e[k].out);
+            ++k;
+        }
+        const uint32_t nl = static_cast<uint32_t>(lanes.size());
+        w.grp.insert(w.grp.end(), {t, nl, static_cast<uint32_t>(g0), static_cast<uint32_t>(w.pair_key.size())});
+        for (uint32_t l = 0; l < 64; ++l) w.src_local.push_back(ts.pos_of[lanes[l < nl ? l : 0]] - ts.tile_base[t]);
+    }
+    return w;
+}
+
 void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
-               const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out) {
+               const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out,
+               const std::vector<uint32_t> &row_vertex, const std::vector<uint32_t> &out_row) {
     hipStream_t st = g->ctx->stream;
     if (algo == WR_ALGO_OVERLAY) {
         SegWork &w = *workspace(g).seg;
         launch_ovl_emit(*g->tiles, w.ss, g->tiles->d_F.p, g->V, rows, d_row_idx, d_row_vertex, d_out_row, out,
                         st);
+        launch_intile_fix(g->ctx, *g->tiles, intile_rows(*g->tiles, row_vertex, out_row), true, g->V, out, st);
     } else if (algo == WR_ALGO_SEGMENTED) {
         SegWork &w = *workspace(g).seg;
         launch_seg_emit(*g->tiles, w.ss, g->V, rows, d_row_idx, d_row_vertex, d_out_row, out, st);
@@ -698,7 +781,7 @@ SegWork &stream_work(StreamSolver *s) {
 
 uint64_t stream_bytes_per_block(wr_graph *g) {
     (void)resolve_algo(g, WR_ALGO_OVERLAY);
-    return SegBuffers::bytes_per_row(*g->tiles, 4, 64);
+    return SegBuffers::bytes_per_row(*g->tiles, 4, 64, true);
 }
 
 StreamSolver *stream_create(wr_graph *g, uint32_t blocks) {
@@ -753,14 +836,15 @@ void stream_admit(StreamSolver *s, const std::vector<uint32_t> &blocks, const st
         launch_fill_u8(w.buf.visited.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
         launch_fill_u32(w.buf.stamps.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
     }
-    // pass 0 of the new rows: seeds into the parity-0 lists, then the
-    // segment kernel relaxes the sources' own tiles and flags what it pushed
-    launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
-    launch_fill_u32(w.buf.ctr.p, 2, 0u, st);   // ntiles[0], ntiles[1]
-    DBuf<uint32_t> d_blocks;
-    upload(d_blocks, g->ctx, blocks, st);
-    launch_seg_seed_blocks(ts, ss, d_blocks.p, nb, st);
-    launch_seg_step(ts, ss, 0u, ts.tile_cap, w.waves, w.G, w.grid, st);
+    // first pass of the new rows: each source pushes its exits' in-tile
+    // distances into its row's inbox and flags the targets
+    std::vector<uint32_t> slots;
+    for (uint32_t i = 0; i < nb; ++i)
+        for (uint32_t l = 0; l < 64; ++l)
+            if (srcv[static_cast<size_t>(i) * 64 + l] != NONE) slots.push_back(blocks[i] * 64 + l);
+    DBuf<uint32_t> d_slots;
+    upload(d_slots, g->ctx, slots, st);
+    launch_ovl_seed_push(ts, ss, d_slots.p, static_cast<uint32_t>(slots.size()), st);
     WR_HIP(hipStreamSynchronize(st));
 }
 
@@ -798,6 +882,9 @@ void stream_gather(StreamSolver *s, const std::vector<uint32_t> &off, const std:
     d_out.alloc(ctx, total);
     launch_gather_ovl(n, d_off.p, d_picks.p, d_base.p, d_slot.p, 0u, s->blocks * 64u, *g->tiles, w.ss,
                       g->tiles->d_F.p, d_out.p, st);
+    launch_intile_fix(ctx, *g->tiles, intile_pairs(*g->tiles, n, off.data(), picks.data(), base.data(),
+                                                   [](uint32_t) { return true; }),
+                      false, g->V, d_out.p, st);
     WR_HIP(hipMemcpyAsync(host_out, d_out.p, total * 4, hipMemcpyDeviceToHost, st));
     WR_HIP(hipStreamSynchronize(st));
 }
@@ -897,7 +984,7 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
             tmp.alloc(ctx, static_cast<size_t>(R) * V);
             out = tmp.p;
         }
-        emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, out);
+        emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, out, rvert, orow);
         if (pred) {
             DBuf<int32_t> ptmp;
             int32_t *pp = pred;
@@ -1025,9 +1112,13 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
             const uint32_t n = std::min(chunk, U - lo);
             solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info);
             info.chunks += 1;
-            if (algo == WR_ALGO_OVERLAY)
+            if (algo == WR_ALGO_OVERLAY) {
                 launch_gather_ovl(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
                                   workspace(g).seg->ss, g->tiles->d_F.p, dout, st);
+                const IntileWork iw = intile_pairs(*g->tiles, num_orders, pick_offsets, picks, out_base.data(),
+                                                   [&](uint32_t k) { return plan.uidx[k] >= lo && plan.uidx[k] < lo + n; });
+                launch_intile_fix(ctx, *g->tiles, iw, false, g->V, dout, st);
+            }
             else if (algo == WR_ALGO_SEGMENTED)
                 launch_gather_seg(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
                                   workspace(g).seg->ss, dout, st);
@@ -1060,7 +1151,7 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
                     upload(d_rvert, ctx, rvert, st);
                     upload(d_orow, ctx, orow, st);
                     upload(d_prow, ctx, prow, st);
-                    emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, rtmp.p);
+                    emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, rtmp.p, rvert, orow);
                     int32_t *pp = dev ? pred_out : ptmp.p;
                     launch_pred_rows(rtmp.p, R, V, d_rvert.p, g->d_in_ptr.p, g->d_in_src.p,
                                      g->d_in_w.p, d_orow.p, d_prow.p, pp, st);

@@ -146,6 +146,9 @@ struct TileSet {
     uint32_t ovl_em = 0;
     std::vector<uint32_t> ovl_hdr, bo_xbeg;
     DBuf<uint32_t> d_ovl_hdr, d_bo_xbeg, d_Fx;
+    // exit tables B[pos][64] of the epoch of d_F (lane j: in-tile distance to
+    // exit j of the tile), and positions' vertices on the device
+    DBuf<uint32_t> d_B, d_vert_of;
 
     // host copies
     std::vector<uint32_t> tile_of;      // [V]  tile or NONE
@@ -266,9 +269,6 @@ struct SegState {
 };
 // activates (s, tile of source s) for the chunk's sources s < n
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
-// the same for the sources of the listed blocks (device array of nb block rows)
-void launch_seg_seed_blocks(const TileSet &ts, const SegState &ss, const uint32_t *blocks, uint32_t nb,
-                            hipStream_t st);
 // one pass: prologue (zero next counters) + plan (units) + relaxation
 // ev (optional): events recorded right before / after the relaxation kernel
 void launch_seg_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t tile_cap,
@@ -291,7 +291,7 @@ struct SegBuffers {
     // with_flags: activation by flags [T][S_cap] (overlay schedule)
     void init(wr_context *ctx, const TileSet &ts, uint32_t S_cap, uint32_t G, uint32_t lanes, bool with_flags);
     // device bytes per state row
-    static uint64_t bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes);
+    static uint64_t bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes, bool overlay);
 };
 // Streaming overlay state for continuous batching: a fixed set of block rows
 // (64 source lanes each) that are seeded, relaxed and read out independently,
@@ -322,7 +322,26 @@ hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_
 
 // overlay schedule: per-epoch boundary tables F[pos][port] of every tile,
 // dense min-plus passes over (tile, block) items, and the read-outs
-void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st);
+// reverse = false: F (from ports); reverse = true: B[pos][j] = in-tile
+// distance from pos to exit j of its tile
+void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st,
+                       bool reverse);
+// first overlay pass: pushes each source slot's exit distances (B rows) into
+// the inbox rows of its block and flags the targets; slots == NULL means the
+// slots 0 .. nslots-1
+void launch_ovl_seed_push(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t nslots,
+                          hipStream_t st);
+// In-tile fix-ups after an overlay read-out: groups of up to 64 sources of one
+// tile (4 words per group: tile, lanes, first pair, end pair; 64 source local
+// indices per group).  Pair mode: pair_key = lane << 16 | target local index,
+// pair_out = output index.  Full mode: row = output row per lane, every tile
+// vertex written.  out[...] becomes min(out[...], in-tile distance).
+struct IntileWork {
+    std::vector<uint32_t> grp, src_local, row, pair_key;
+    std::vector<uint64_t> pair_out;
+};
+void launch_intile_fix(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
+                       uint32_t *out, hipStream_t st);
 // entries per packed table row of the overlay pass (ports rounded up to 4)
 uint32_t ovl_row_entries(const TileSet &ts);
 // packs the exits' rows of F into d_Fx
