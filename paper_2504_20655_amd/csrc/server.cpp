@@ -278,8 +278,12 @@ bool run_stream_mode(wr_server *s) {
                     // lanes in tile order: a row's sources start close together,
                     // so their wavefronts share tile visits
                     const std::vector<uint32_t> &tile_of = g->tiles->tile_of;
+                    const std::vector<uint64_t> &tkey = tile_order_keys(g);
+                    auto k = [&](uint32_t x) { return tile_of[x] == NONE ? ~0ull : tkey[tile_of[x]]; };
                     std::sort(group.begin(), group.end(), [&](uint32_t x, uint32_t y) {
-                        return tile_of[x] != tile_of[y] ? tile_of[x] < tile_of[y] : x < y;
+                        if (k(x) != k(y)) return k(x) < k(y);
+                        if (tile_of[x] != tile_of[y]) return tile_of[x] < tile_of[y];
+                        return x < y;
                     });
                     const size_t nrows = (group.size() + 63) / 64;
                     for (size_t i = 0; i < nrows; ++i) {

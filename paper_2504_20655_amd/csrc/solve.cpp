@@ -163,11 +163,16 @@ Plan make_plan(wr_graph *g, const uint32_t *verts, size_t n, bool by_tile) {
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
     if (by_tile && g->tiles) {
+        // blocks of 64 consecutive sources should start close together: order
+        // by the tile's key (a compact patch order for grid tilings), then id
         const auto &tof = g->tiles->tile_of;
+        const auto &key = tile_order_keys(g);
+        auto k = [&](uint32_t x) { return tof[x] == NONE ? ~0ull : key[tof[x]]; };
         std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) {
-            const uint64_t ka = (static_cast<uint64_t>(tof[a]) << 32) | a;
-            const uint64_t kb = (static_cast<uint64_t>(tof[b]) << 32) | b;
-            return ka < kb;
+            const uint64_t ka = k(a), kb = k(b);
+            if (ka != kb) return ka < kb;
+            if (tof[a] != tof[b]) return tof[a] < tof[b];
+            return a < b;
         });
     }
     p.usrc = v;

@@ -312,6 +312,43 @@ void grid_maps(uint32_t W, uint32_t H, uint32_t L, uint32_t tw, uint32_t th, uin
 
 }  // namespace
 
+namespace {
+// interleaves the low 21 bits of x and y (x in the even bits)
+uint64_t morton2(uint32_t x, uint32_t y) {
+    uint64_t k = 0;
+    for (uint32_t b = 0; b < 21; ++b)
+        k |= (static_cast<uint64_t>((x >> b) & 1u) << (2 * b)) | (static_cast<uint64_t>((y >> b) & 1u) << (2 * b + 1));
+    return k;
+}
+}  // namespace
+
+const std::vector<uint64_t> &tile_order_keys(wr_graph *g) {
+    TileSet &ts = *g->tiles;
+    if (ts.order_key.size() == ts.T) return ts.order_key;
+    ts.order_key.assign(ts.T, 0);
+    const uint64_t plane = static_cast<uint64_t>(g->grid_W) * g->grid_H;
+    const bool grid = g->tiles_user && g->grid_W && g->grid_H &&
+                      plane * std::max(g->grid_L, 1u) == static_cast<uint64_t>(g->V);
+    for (uint32_t t = 0; t < ts.T; ++t) {
+        if (!grid) {
+            ts.order_key[t] = t;
+            continue;
+        }
+        uint64_t sx = 0, sy = 0, n = 0, lv = 0;
+        for (uint32_t p = ts.tile_base[t]; p < ts.tile_base[t + 1]; ++p) {
+            const uint64_t v = ts.vert_of[p];
+            const uint64_t r = v % plane;
+            sx += r % g->grid_W;
+            sy += r / g->grid_W;
+            lv = v / plane;
+            ++n;
+        }
+        const uint32_t cx = n ? static_cast<uint32_t>(sx / n) : 0, cy = n ? static_cast<uint32_t>(sy / n) : 0;
+        ts.order_key[t] = (lv << 42) | morton2(cx, cy);
+    }
+    return ts.order_key;
+}
+
 void rebuild_tiles_if_needed(wr_graph *g) {
     if (g->tiles && g->tiles->tile_cap == g->tile_vertices) return;
     if (g->grid_W) {

@@ -145,6 +145,8 @@ struct TileSet {
     // beyond the tile's ports INF) for the epoch of d_F.
     uint32_t ovl_em = 0;
     std::vector<uint32_t> ovl_hdr, bo_xbeg;
+    // per tile, the key sources are ordered by (see tile_order_keys)
+    std::vector<uint64_t> order_key;
     DBuf<uint32_t> d_ovl_hdr, d_bo_xbeg, d_Fx;
     // exit tables B[pos][64] of the epoch of d_F (lane j: in-tile distance to
     // exit j of the tile), and positions' vertices on the device
@@ -399,6 +401,11 @@ void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww
 // nested in the segments whose parts become the tiles (still cut to the cap).
 void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t tile_cap,
                  bool bfs_grow, const uint32_t *sub = nullptr, uint32_t nsub = 0);
+// Sort keys of the tiles for grouping sources into blocks: for a grid
+// segmentation, the Z-order (Morton) code of the tile's centroid cell per
+// level, so that consecutive tiles form compact patches; otherwise the
+// tile id.  Computed on first use and kept with the tiles.
+const std::vector<uint64_t> &tile_order_keys(wr_graph *g);
 void rebuild_tiles_if_needed(wr_graph *g);
 
 }  // namespace wr
