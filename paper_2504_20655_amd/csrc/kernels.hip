@@ -745,7 +745,8 @@ __global__ void k_ovl_seed_push(SegPassArgs A, const uint32_t *__restrict__ B, c
 // (paths that leave the tile are in out[...] already).  pairs mode: the
 // group's entries (lane << 16 | target local index, output index);
 // full mode (pairs == NULL): every vertex of the tile for every lane, at
-// out[row[lane] * V + vertex].
+// out[row[lane] * V + vertex].  With pair_val, pairs mode stores the in-tile
+// values there instead (k_min_scatter applies them later).
 struct IntileGroup {
     uint32_t tile, lanes, p0, p1;
 };
@@ -756,7 +757,7 @@ __global__ __launch_bounds__(NW * 64) void k_intile_fix(SegPassArgs A, const Int
                                                          const uint64_t *__restrict__ pair_out,
                                                          const uint32_t *__restrict__ row,
                                                          const uint32_t *__restrict__ vert_of, uint32_t V,
-                                                         uint32_t *__restrict__ out) {
+                                                         uint32_t *__restrict__ out, uint32_t *__restrict__ pair_val) {
     constexpr uint32_t ACAP = 4u * CAP;
     constexpr uint32_t WORDS = CAP / 32;
     __shared__ uint32_t D[CAP * 64];
@@ -794,8 +795,12 @@ __global__ __launch_bounds__(NW * 64) void k_intile_fix(SegPassArgs A, const Int
             for (uint32_t q = G.p0 + threadIdx.x; q < G.p1; q += blockDim.x) {
                 const uint32_t key = pair_key[q];
                 const uint32_t d = D[(key & 0xFFFFu) * 64 + (key >> 16)];
-                uint32_t *o = out + pair_out[q];
-                *o = min(*o, d);
+                if (pair_val) {
+                    pair_val[q] = d;
+                } else {
+                    uint32_t *o = out + pair_out[q];
+                    *o = min(*o, d);
+                }
             }
         } else if (lane < nl) {
             const uint64_t r = static_cast<uint64_t>(row[static_cast<size_t>(gi) * 64 + lane]) * V;
@@ -806,6 +811,13 @@ __global__ __launch_bounds__(NW * 64) void k_intile_fix(SegPassArgs A, const Int
         }
         __syncthreads();
     }
+}
+
+// out[idx[q]] = min(out[idx[q]], val[q]) for every q < n.
+__global__ void k_min_scatter(const uint64_t *__restrict__ idx, const uint32_t *__restrict__ val, uint32_t n,
+                              uint32_t *__restrict__ out) {
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
+        out[idx[q]] = min(out[idx[q]], val[q]);
 }
 
 // Overlay pass: a visit of (tile t, block b) maps the block's entry values
@@ -1657,36 +1669,49 @@ void launch_ovl_seed_push(const TileSet &ts, const SegState &ss, const uint32_t 
     check_launch("ovl_seed_push");
 }
 
-void launch_intile_fix(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
-                       uint32_t *out, hipStream_t st) {
-    const uint32_t ng = static_cast<uint32_t>(w.grp.size() / 4);
+void IntileJob::upload_and_launch(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
+                                  uint32_t *out, hipStream_t st) {
+    ng = static_cast<uint32_t>(w.grp.size() / 4);
+    npairs = static_cast<uint32_t>(w.pair_key.size());
     if (!ng) return;
-    DBuf<uint32_t> d_grp, d_src, d_row, d_key;
-    DBuf<uint64_t> d_out;
-    upload(d_grp, ctx, w.grp, st);
-    upload(d_src, ctx, w.src_local, st);
-    if (full)
-        upload(d_row, ctx, w.row, st);
-    else {
-        upload(d_key, ctx, w.pair_key, st);
-        upload(d_out, ctx, w.pair_out, st);
+    upload_reuse(d_grp, ctx, w.grp, st);
+    upload_reuse(d_src, ctx, w.src_local, st);
+    if (full) {
+        upload_reuse(d_row, ctx, w.row, st);
+    } else {
+        upload_reuse(d_key, ctx, w.pair_key, st);
+        upload_reuse(d_out, ctx, w.pair_out, st);
+        if (!out) reserve(d_val, ctx, npairs);
     }
     SegState dummy;
     SegPassArgs A = seg_args(ts, dummy, 0u, 1u);
     const IntileGroup *G = reinterpret_cast<const IntileGroup *>(d_grp.p);
     const uint32_t grid = std::min<uint32_t>(ng, 4096u);
+    uint32_t *val = (!full && !out) ? d_val.p : nullptr;
     if (ts.tile_cap == 256)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_intile_fix<256, 8>), grid, 512, 0, st, A, G, ng, d_src.p,
                            full ? nullptr : d_key.p, full ? nullptr : d_out.p, full ? d_row.p : nullptr,
-                           ts.d_vert_of.p, V, out);
+                           ts.d_vert_of.p, V, out, val);
     else if (ts.tile_cap == 512)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_intile_fix<512, 8>), grid, 512, 0, st, A, G, ng, d_src.p,
                            full ? nullptr : d_key.p, full ? nullptr : d_out.p, full ? d_row.p : nullptr,
-                           ts.d_vert_of.p, V, out);
+                           ts.d_vert_of.p, V, out, val);
     else
         fail(WR_E_UNSUPPORTED, "in-tile fix-up needs tiles of at most 512 vertices");
     check_launch("intile_fix");
-    WR_HIP(hipStreamSynchronize(st));   // the uploaded tables are freed on return
+}
+
+void IntileJob::apply(uint32_t *out, hipStream_t st) const {
+    if (!npairs || !d_val.p) return;
+    hipLaunchKernelGGL(k_min_scatter, blocks_for(npairs, 256, 1024), 256, 0, st, d_out.p, d_val.p, npairs, out);
+    check_launch("min_scatter");
+}
+
+void launch_intile_fix(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
+                       uint32_t *out, hipStream_t st) {
+    IntileJob job;
+    job.upload_and_launch(ctx, ts, w, full, V, out, st);
+    if (job.ng) WR_HIP(hipStreamSynchronize(st));   // the uploaded tables are freed on return
 }
 
 uint32_t ovl_max_exits() { return OVL_XCAP; }

@@ -127,7 +127,9 @@ wr_status wr_context_create(int device, uint64_t mem_budget_bytes, wr_context **
     WR_HIP(hipMemGetInfo(&freeb, &totalb));
     ctx->budget = mem_budget_bytes ? mem_budget_bytes : static_cast<uint64_t>(freeb * 0.9);
     hipError_t se = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+    if (se == hipSuccess) se = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
     if (se != hipSuccess) {
+        if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
         fail(WR_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(se));
     }
@@ -139,6 +141,7 @@ wr_status wr_context_destroy(wr_context *ctx) {
     WR_API_BEGIN
     if (!ctx) return WR_OK;
     (void)hipSetDevice(ctx->device);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     WR_API_END

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cstdio>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <numeric>
@@ -91,6 +92,16 @@ struct Workspace {
     std::unique_ptr<SegWork> seg;
     std::unique_ptr<BlkWork> blk;
     uint32_t *h_flag = nullptr;   // pinned host word for termination checks
+    // per-call index arrays of wr_order_matrices and the in-tile job, reused
+    DBuf<uint32_t> call_off, call_picks, call_sidx;
+    // source dedup: per-vertex stamp of the last call that saw it, and its slot
+    std::vector<uint32_t> stamp, slot;
+    uint32_t stamp_id = 0;
+    // passes the last segmented / overlay solve needed (replays launched
+    // before the first convergence check)
+    uint64_t last_passes = 0;
+    DBuf<uint64_t> call_base;
+    IntileJob intile;
     ~Workspace() {
         if (h_flag) (void)hipHostFree(h_flag);
     }
@@ -107,6 +118,28 @@ Workspace &workspace(wr_graph *g) {
     }
     return *g->ws;
 }
+
+// Host timeline of a call, printed to stderr when WR_TRACE is set.
+struct CallTrace {
+    bool on = std::getenv("WR_TRACE") != nullptr;
+    double t0 = 0, last = 0;
+    std::string line;
+    void start(double t) {
+        t0 = last = t;
+        line.clear();
+    }
+    void mark(const char *what, double t) {
+        if (!on) return;
+        char b[64];
+        std::snprintf(b, sizeof b, " %s %.3f", what, t - last);
+        line += b;
+        last = t;
+    }
+    void flush(const char *call) const {
+        if (on) std::fprintf(stderr, "[wroute %s] ms:%s | total %.3f\n", call, line.c_str(), last - t0);
+    }
+};
+CallTrace g_trace;
 
 double now_ms() {
     using namespace std::chrono;
@@ -157,33 +190,56 @@ struct Plan {
     std::vector<uint32_t> uidx;
 };
 
+// Distinct sources of a call in block order, and each input's index among
+// them.  Linear apart from one sort of the distinct sources: duplicates are
+// found with a per-vertex stamp kept in the workspace.
 Plan make_plan(wr_graph *g, const uint32_t *verts, size_t n, bool by_tile) {
-    Plan p;
-    std::vector<uint32_t> v(verts, verts + n);
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    if (by_tile && g->tiles) {
-        // blocks of 64 consecutive sources should start close together: order
-        // by the tile's key (a compact patch order for grid tilings), then id
-        const auto &tof = g->tiles->tile_of;
-        const auto &key = tile_order_keys(g);
-        auto k = [&](uint32_t x) { return tof[x] == NONE ? ~0ull : key[tof[x]]; };
-        std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) {
-            const uint64_t ka = k(a), kb = k(b);
-            if (ka != kb) return ka < kb;
-            if (tof[a] != tof[b]) return tof[a] < tof[b];
-            return a < b;
-        });
+    Workspace &ws = workspace(g);
+    if (ws.stamp.size() != g->V) {
+        ws.stamp.assign(g->V, 0u);
+        ws.slot.assign(g->V, 0u);
+        ws.stamp_id = 0;
     }
-    p.usrc = v;
-    std::vector<std::pair<uint32_t, uint32_t>> key(v.size());
-    for (uint32_t i = 0; i < v.size(); ++i) key[i] = {v[i], i};
-    std::sort(key.begin(), key.end());
-    p.uidx.resize(n);
+    if (++ws.stamp_id == 0) {   // wrapped: clear the stamps
+        std::fill(ws.stamp.begin(), ws.stamp.end(), 0u);
+        ws.stamp_id = 1;
+    }
+    const uint32_t id = ws.stamp_id;
+    struct Item {
+        uint64_t key;
+        uint32_t tile, v;
+    };
+    std::vector<Item> items;
+    items.reserve(n);
+    const bool tiled = by_tile && g->tiles;
+    const std::vector<uint64_t> *key = tiled ? &tile_order_keys(g) : nullptr;
     for (size_t k = 0; k < n; ++k) {
-        auto it = std::lower_bound(key.begin(), key.end(), std::make_pair(verts[k], 0u));
-        p.uidx[k] = it->second;
+        const uint32_t v = verts[k];
+        if (ws.stamp[v] == id) continue;
+        ws.stamp[v] = id;
+        uint32_t t = NONE;
+        uint64_t kk = 0;
+        if (tiled) {
+            t = g->tiles->tile_of[v];
+            kk = t == NONE ? ~0ull : (*key)[t];
+        }
+        items.push_back({kk, t, v});
     }
+    // blocks of 64 consecutive sources should start close together: order by
+    // the tile's key (a compact patch order for grid tilings), tile, vertex
+    std::sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
+        if (x.key != y.key) return x.key < y.key;
+        if (x.tile != y.tile) return x.tile < y.tile;
+        return x.v < y.v;
+    });
+    Plan p;
+    p.usrc.resize(items.size());
+    for (uint32_t i = 0; i < items.size(); ++i) {
+        p.usrc[i] = items[i].v;
+        ws.slot[items[i].v] = i;
+    }
+    p.uidx.resize(n);
+    for (size_t k = 0; k < n; ++k) p.uidx[k] = ws.slot[verts[k]];
     return p;
 }
 
@@ -377,8 +433,10 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
 }
 
 // Relaxes sources usrc[lo .. lo+n) to the fixpoint in the segmented state.
+// `overlap` (may be empty) runs on the host once the first passes are on the
+// GPU, so host work of the caller overlaps the relaxation.
 void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc, uint32_t lo,
-                     uint32_t n, bool graph_mode, wr_run_info &info) {
+                     uint32_t n, bool graph_mode, wr_run_info &info, const std::function<void()> &overlap) {
     const TileSet &ts = *g->tiles;
     wr_context *ctx = g->ctx;
     hipStream_t st = ctx->stream;
@@ -403,6 +461,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
     launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    g_trace.mark("chunk_reset", now_ms());
     if (!w.overlay) launch_seg_seed_n(ts, ss, n, st);
     hipEvent_t e0, e1;
     WR_HIP(hipEventCreate(&e0));
@@ -419,9 +478,16 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
         launch_ovl_seed_push(ts, ss, nullptr, rows * 64, st);
         passes += 1;
     }
+    // replays launched before the first convergence check: as many as the
+    // previous solve needed (surplus passes find nothing to do and are cheap)
+    Workspace &wsp = workspace(g);
+    uint32_t batch = graph_mode ? static_cast<uint32_t>(std::max<uint64_t>(1, wsp.last_passes / K)) : 1u;
+    bool first = true;
     for (;;) {
         if (graph_mode) {
-            WR_HIP(hipGraphLaunch(w.exec, st));
+            for (uint32_t r = 0; r < batch; ++r) WR_HIP(hipGraphLaunch(w.exec, st));
+            passes += static_cast<uint64_t>(K) * (batch - 1);
+            batch = 1;
         } else if (w.overlay) {
             for (uint32_t i = 0; i < K; ++i)
                 launch_ovl_step(ts, ss, (i + 1) & 1u, w.G, w.grid_ovl, ts.d_F.p, i + 1 == K, st, w.kev.b(i),
@@ -432,12 +498,16 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
                                 w.kev.e(i));
         }
         passes += K;
+        if (first && overlap) overlap();
+        first = false;
         WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + par0, 4, hipMemcpyDeviceToHost, st));
         WR_HIP(hipStreamSynchronize(st));
         if (!w.kev.collect(K, info)) fail(WR_E_DEVICE, "kernel event timing failed");
         if (*workspace(g).h_flag == 0) break;
         if (passes > cap) fail(WR_E_INTERNAL, "segmented relaxation exceeded its pass cap");
     }
+    g_trace.mark("replays", now_ms());
+    wsp.last_passes = passes;
     WR_HIP(hipEventRecord(e1, st));
     unsigned long long stats[2];
     WR_HIP(hipMemcpyAsync(stats, w.buf.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
@@ -645,11 +715,14 @@ uint32_t chunk_sources(wr_graph *g, uint32_t algo, uint32_t total, bool graph_mo
 }
 
 void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, uint32_t lo,
-                 uint32_t n, bool graph_mode, wr_run_info &info) {
-    if (algo == WR_ALGO_SEGMENTED || algo == WR_ALGO_OVERLAY)
-        seg_solve_chunk(g, *workspace(g).seg, usrc, lo, n, graph_mode, info);
-    else
+                 uint32_t n, bool graph_mode, wr_run_info &info,
+                 const std::function<void()> &overlap = std::function<void()>()) {
+    if (algo == WR_ALGO_SEGMENTED || algo == WR_ALGO_OVERLAY) {
+        seg_solve_chunk(g, *workspace(g).seg, usrc, lo, n, graph_mode, info, overlap);
+    } else {
         blk_solve_chunk(g, *workspace(g).blk, usrc, lo, n, graph_mode, info);
+        if (overlap) overlap();
+    }
 }
 
 // Source-major rows of the current chunk's state: out + out_row[r]*V gets the
@@ -707,17 +780,30 @@ IntileWork intile_pairs(const TileSet &ts, uint32_t num_orders, const uint32_t *
         uint64_t out;
     };
     std::vector<Entry> e;
+    std::vector<std::pair<uint32_t, uint32_t>> by;   // (tile, index in the order)
     for (uint32_t o = 0; o < num_orders; ++o) {
         const uint32_t a = off[o], P = off[o + 1] - a;
+        by.clear();
         for (uint32_t i = 0; i < P; ++i) {
-            const uint32_t si = picks[a + i];
-            const uint32_t t = ts.tile_of[si];
-            if (t == NONE || !take(a + i)) continue;
-            for (uint32_t j = 0; j < P; ++j) {
-                const uint32_t v = picks[a + j];
-                if (v == si || ts.tile_of[v] != t) continue;
-                e.push_back({t, si, ts.pos_of[v] - ts.tile_base[t], out_base[o] + static_cast<uint64_t>(i) * P + j});
+            const uint32_t t = ts.tile_of[picks[a + i]];
+            if (t != NONE) by.push_back({t, i});
+        }
+        std::sort(by.begin(), by.end());
+        // pairs only within runs of one tile
+        for (size_t r0 = 0; r0 < by.size();) {
+            size_t r1 = r0 + 1;
+            while (r1 < by.size() && by[r1].first == by[r0].first) ++r1;
+            const uint32_t t = by[r0].first;
+            for (size_t x = r0; x < r1; ++x) {
+                const uint32_t i = by[x].second, si = picks[a + i];
+                if (!take(a + i)) continue;
+                for (size_t y = r0; y < r1; ++y) {
+                    const uint32_t j = by[y].second, v = picks[a + j];
+                    if (v == si) continue;
+                    e.push_back({t, si, ts.pos_of[v] - ts.tile_base[t], out_base[o] + static_cast<uint64_t>(i) * P + j});
+                }
             }
+            r0 = r1;
         }
     }
     std::sort(e.begin(), e.end(), [](const Entry &x, const Entry &y) {
@@ -801,6 +887,7 @@ StreamSolver *stream_create(wr_graph *g, uint32_t blocks) {
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
     launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    g_trace.mark("chunk_reset", now_ms());
     launch_fill_u32(w.buf.src_tile.p, static_cast<size_t>(w.S_cap) * 64, NONE, st);
     ensure_overlay_tables(g);
     WR_HIP(hipStreamSynchronize(st));
@@ -1058,13 +1145,16 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
     wr_run_info info{};
     info.algo = algo;
 
+    g_trace.start(t0);
+    g_trace.mark("validate", now_ms());
     std::vector<uint32_t> hoff(pick_offsets, pick_offsets + num_orders + 1);
     std::vector<uint32_t> hpicks(picks, picks + NPK);
-    DBuf<uint32_t> d_off, d_picks, d_sidx;
-    DBuf<uint64_t> d_base;
-    upload(d_off, ctx, hoff, st);
-    upload(d_picks, ctx, hpicks, st);
-    upload(d_base, ctx, out_base, st);
+    Workspace &cws = workspace(g);
+    DBuf<uint32_t> &d_off = cws.call_off, &d_picks = cws.call_picks, &d_sidx = cws.call_sidx;
+    DBuf<uint64_t> &d_base = cws.call_base;
+    upload_reuse(d_off, ctx, hoff, st);
+    upload_reuse(d_picks, ctx, hpicks, st);
+    upload_reuse(d_base, ctx, out_base, st);
     DBuf<uint32_t> dout_tmp;
     uint32_t *dout = dist_out;
     if (!dev) {
@@ -1108,21 +1198,49 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
         info.unique_sources = NPK;
         info.chunks = num_orders;
     } else {
+        g_trace.mark("uploads", now_ms());
         Plan plan = make_plan(g, picks, NPK, true);
+        g_trace.mark("plan", now_ms());
         const uint32_t U = static_cast<uint32_t>(plan.usrc.size());
         info.unique_sources = U;
-        upload(d_sidx, ctx, plan.uidx, st);
+        upload_reuse(d_sidx, ctx, plan.uidx, st);
         const uint32_t chunk = chunk_sources(g, algo, U, graph_mode, timed);
         for (uint32_t lo = 0; lo < U; lo += chunk) {
             const uint32_t n = std::min(chunk, U - lo);
-            solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info);
+            // overlay: the in-tile values of entries whose picks share a tile
+            // depend only on the tiles, so they are computed on the side
+            // stream while the chunk relaxes, and applied after the gather
+            IntileJob &job = workspace(g).intile;
+            hipEvent_t ev_side = nullptr;
+            std::function<void()> overlap;
+            hipEvent_t ev_ready = nullptr;
+            if (algo == WR_ALGO_OVERLAY) {
+                // the fix-up reads only the tiles' arc tables, which are on the
+                // device once the work queued on st so far is done
+                WR_HIP(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
+                WR_HIP(hipEventRecord(ev_ready, st));
+                // runs once the first passes are queued, so the host builds the
+                // pair list while the GPU relaxes
+                overlap = [&]() {
+                    const IntileWork iw = intile_pairs(*g->tiles, num_orders, pick_offsets, picks, out_base.data(),
+                                                       [&](uint32_t k) { return plan.uidx[k] >= lo && plan.uidx[k] < lo + n; });
+                    WR_HIP(hipStreamWaitEvent(ctx->side, ev_ready, 0));
+                    job.upload_and_launch(ctx, *g->tiles, iw, false, g->V, nullptr, ctx->side);
+                    WR_HIP(hipEventCreateWithFlags(&ev_side, hipEventDisableTiming));
+                    WR_HIP(hipEventRecord(ev_side, ctx->side));
+                    g_trace.mark("intile_setup", now_ms());
+                };
+            }
+            solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info, overlap);
+            g_trace.mark("solve", now_ms());
             info.chunks += 1;
             if (algo == WR_ALGO_OVERLAY) {
                 launch_gather_ovl(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
                                   workspace(g).seg->ss, g->tiles->d_F.p, dout, st);
-                const IntileWork iw = intile_pairs(*g->tiles, num_orders, pick_offsets, picks, out_base.data(),
-                                                   [&](uint32_t k) { return plan.uidx[k] >= lo && plan.uidx[k] < lo + n; });
-                launch_intile_fix(ctx, *g->tiles, iw, false, g->V, dout, st);
+                WR_HIP(hipStreamWaitEvent(st, ev_side, 0));
+                (void)hipEventDestroy(ev_side);
+                (void)hipEventDestroy(ev_ready);
+                job.apply(dout, st);
             }
             else if (algo == WR_ALGO_SEGMENTED)
                 launch_gather_seg(num_orders, d_off.p, d_picks.p, d_base.p, d_sidx.p, lo, n, *g->tiles,
@@ -1173,9 +1291,12 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
             }
         }
     }
+    g_trace.mark("gather", now_ms());
     if (!dev) WR_HIP(hipMemcpyAsync(dist_out, dout, static_cast<size_t>(total) * 4, hipMemcpyDeviceToHost, st));
     WR_HIP(hipStreamSynchronize(st));
     info.total_ms = now_ms() - t0;
+    g_trace.mark("sync", now_ms());
+    g_trace.flush("order_matrices");
     g->last = info;
     WR_API_END
 }

@@ -72,6 +72,7 @@ struct wr_context {
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
     hipStream_t stream = nullptr;   // internal stream for host-pointer calls
+    hipStream_t side = nullptr;     // second internal stream (work that overlaps the relaxation)
 
     void *alloc(size_t bytes);      // throws WR_E_NOMEM / WR_E_DEVICE
     void release(void *p, size_t bytes);
@@ -116,6 +117,19 @@ struct DBuf {
 template <class T>
 void upload(DBuf<T> &d, wr_context *ctx, const std::vector<T> &h, hipStream_t st) {
     d.alloc(ctx, h.size());
+    if (!h.empty()) WR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+// Grow-only buffers for per-call arrays: reallocated only when too small, so
+// repeated calls do not allocate (the caller orders reuse on its stream).
+template <class T>
+void reserve(DBuf<T> &d, wr_context *ctx, size_t count) {
+    if (d.n >= count && d.p) return;
+    d.alloc(ctx, std::max<size_t>(count, d.n * 2));
+}
+template <class T>
+void upload_reuse(DBuf<T> &d, wr_context *ctx, const std::vector<T> &h, hipStream_t st) {
+    reserve(d, ctx, std::max<size_t>(h.size(), 1));
     if (!h.empty()) WR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
@@ -344,6 +358,18 @@ struct IntileWork {
 };
 void launch_intile_fix(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
                        uint32_t *out, hipStream_t st);
+// The pairs form split in two, so it can run beside the relaxation: launch
+// with out == NULL computes the in-tile values into a device buffer (its
+// inputs live as long as the job, whose buffers are reused by later jobs);
+// apply() lowers out[...] by them.
+struct IntileJob {
+    uint32_t ng = 0, npairs = 0;
+    DBuf<uint32_t> d_grp, d_src, d_row, d_key, d_val;
+    DBuf<uint64_t> d_out;
+    void upload_and_launch(wr_context *ctx, const TileSet &ts, const IntileWork &w, bool full, uint32_t V,
+                           uint32_t *out, hipStream_t st);
+    void apply(uint32_t *out, hipStream_t st) const;
+};
 // entries per packed table row of the overlay pass (ports rounded up to 4)
 uint32_t ovl_row_entries(const TileSet &ts);
 // packs the exits' rows of F into d_Fx
