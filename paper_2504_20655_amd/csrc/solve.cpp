@@ -400,8 +400,10 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
                       w->waves == waves && w->lanes == lanes && w->G == G && w->K == K &&
                       w->timed == timed && w->overlay == overlay && (!graph_mode || w->exec);
     if (fits) return *w;
-    // size the chunk: the request, bounded by the budget (keep what we hold)
+    // size the chunk: the request, bounded by the budget (keep what we hold;
+    // the overlay's epoch tables are allocated first, the state takes the rest)
     ws.seg.reset();
+    if (overlay) ensure_overlay_tables(g);
     const uint64_t per = SegBuffers::bytes_per_row(ts, G, lanes, overlay);
     const uint64_t avail = g->ctx->available();
     uint64_t R_fit = avail > (64ull << 20) ? (avail - (64ull << 20)) / per : 0;
