@@ -216,3 +216,25 @@ def test_weight_update_epochs(rt, ctx):
     exp3 = oracle.order_matrices(g.row_ptr, g.col, w3, wl.pick_offsets, wl.picks)
     for algo in ("overlay", "segmented"):
         assert (G.order_matrices(wl.pick_offsets, wl.picks, algo=algo) == exp3).all(), algo
+
+
+def test_overlay_chunks_under_small_budget(rt):
+    """A memory budget too small for every source block at once: the batch
+    is solved chunk by chunk, and the matrices stay exact."""
+    wl = make_config("medium", side=128, num_orders=16)
+    g = wl.graph
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    for budget_mb in (66, 68, 70, 72, 76, 80, 96):
+        try:
+            ctx = rt.Context(0, budget_mb << 20)
+            G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
+            G.set_schedule(512, 8, 0)
+            G.segment_grid(g.W, g.H, 1, 24, 20)
+            got = G.order_matrices(wl.pick_offsets, wl.picks, algo="overlay")
+        except rt.WrError as e:
+            assert e.name == "WR_E_NOMEM"
+            continue
+        if G.last_run()["chunks"] > 1:
+            assert (got == exp).all()
+            return
+    pytest.fail("no budget produced a chunked run")
