@@ -211,8 +211,16 @@ struct SegPassArgs {
     // source-blocked schedule: in-tile in-arcs and the sources of the chunk
     const uint32_t *li_off, *li_arc;
     uint32_t nsrc;
-    // overlay schedule: activation flags [T][S] instead of stamped lists
+    // overlay schedule: activation flags [T][S] instead of stamped lists;
+    // per block the value of every exit, xval[S][NB][64]; per port p its
+    // incoming cross arcs k in [pin_off[p], pin_off[p+1]) with their source
+    // exits pin_exit[k] and weights pin_w[k]; per tile {first incoming arc,
+    // incoming arcs} in hdr2
     uint8_t *flags;
+    uint32_t *xval;
+    uint32_t NB;
+    const uint32_t *pin_off, *pin_exit, *pin_w;
+    const uint2 *hdr2;
 };
 
 __device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
@@ -710,9 +718,9 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_custom(SegPassArgs A, uint32_t 
 }
 
 // First pass of the overlay schedule: a wave per source slot s (block
-// s / 64, lane s % 64) pushes the source's in-tile distance to each exit j
-// of its tile (lane j reads B[pos][j]) across the exit's cross arcs into the
-// block's inbox rows, flagging (target tile, block) where a row dropped.
+// s / 64, lane s % 64) sets the source's exit values to its in-tile distance
+// to each exit j of its tile (lane j reads B[pos][j]) and flags the tiles the
+// exit's cross arcs lead to.
 __global__ void k_ovl_seed_push(SegPassArgs A, const uint32_t *__restrict__ B, const uint4 *__restrict__ hdr,
                                 const uint32_t *__restrict__ bo_xbeg, const uint32_t *__restrict__ slots,
                                 uint32_t nslots) {
@@ -729,13 +737,10 @@ __global__ void k_ovl_seed_push(SegPassArgs A, const uint32_t *__restrict__ B, c
         if (lane >= X) continue;
         const uint32_t d = B[static_cast<size_t>(pos) * 64 + lane];
         if (d == INF) continue;
-        uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64 + l;
+        A.xval[(static_cast<size_t>(b) * A.NB + b0 + lane) * 64 + l] = d;
         const uint32_t k1 = bo_xbeg[b0 + t + lane + 1];
-        for (uint32_t k = bo_xbeg[b0 + t + lane]; k < k1; ++k) {
-            const uint32_t nd = sat_add(d, A.x_w[xa0 + k]);
-            if (nd < atomicMin(ib + static_cast<size_t>(A.x_port[xa0 + k]) * 64, nd))
-                A.flags[static_cast<size_t>(A.x_tile[xa0 + k]) * A.S + b] = 1;
-        }
+        for (uint32_t k = bo_xbeg[b0 + t + lane]; k < k1; ++k)
+            A.flags[static_cast<size_t>(A.x_tile[xa0 + k]) * A.S + b] = 1;
     }
 }
 
@@ -820,27 +825,32 @@ __global__ void k_min_scatter(const uint64_t *__restrict__ idx, const uint32_t *
         out[idx[q]] = min(out[idx[q]], val[q]);
 }
 
-// Overlay pass: a visit of (tile t, block b) maps the block's entry values
-// (inbox rows of t's ports) through t's table onto t's exits (boundary-out
-// vertices), exit_j = min_i entry_i + F[exit_j][i] per lane, a dense
-// min-plus product, and pushes every exit value across the exit's cross
-// arcs into the target tiles' inbox rows with atomicMin.  A push that
-// lowered a target row flags (target tile, b) for the next pass.  Exit
-// values are not stored: the inbox rows of the targets hold them, and the
-// atomic's old value decides the activation.
+// Overlay pass: a visit of (tile t, block b) computes the block's entry
+// values at t's ports from the exit values of the neighbouring tiles
+// (entry_p = min over cross arcs e -> p of xval[e] + w), maps them through
+// t's table onto t's exits (exit_j = min_p entry_p + F[exit_j][p], a dense
+// min-plus product), and stores each exit value that dropped, flagging the
+// tiles that exit's cross arcs lead to for the next pass.  All traffic is
+// plain loads and stores: a pass reads the exit values the previous passes
+// wrote (kernel boundaries order them), and a flag set during a pass brings
+// its tile back in the next one.
 //
 // A workgroup takes one unit (a tile and up to G of its active blocks),
-// stages the tile's packed table rows and cross arcs in LDS, and runs the unit's
-// visits one after another: the waves stage the block's entry rows with all
-// loads in flight, then each wave computes four exits at a time from LDS and
-// issues their four pushes together.  A visit thus costs one round trip of
-// loads and one of atomics.  LDS is sized at launch to the tiling's largest
-// tile (XM exits x EM entries, PM cross arcs).
+// stages the tile's packed table rows, its ports' incoming arcs and its
+// exits' outgoing arcs in LDS, and runs the unit's visits one after another.
+// Wave w owns entry rows w, w + NW, ... (R of them) and exits w R .. w R +
+// R - 1: per visit it loads its entry rows (the first incoming arc of each
+// port; a port's further arcs follow in a short loop) and the current values
+// of its exits with all loads in flight, and computes its exits against LDS
+// while the loads of the unit's next visit are in flight.  Rows and exits
+// past the tile's last are clamped to it (loaded again, never stored), so
+// every load is unconditional.  LDS is sized at launch to the tiling's
+// largest tile (XM exits x EM entries, PM arcs in or out); R is the smallest
+// instance with NW R >= max(EM, XM).
 constexpr uint32_t OVL_XCAP = 64;     // exits per tile (one 64-lane row of the exit table)
-constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving a tile
+constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving or entering a tile
 constexpr uint32_t OVL_NW = 8;        // waves per workgroup
-constexpr uint32_t OVL_B = 4;         // exits a wave computes and pushes together
-template <int NW>
+template <int NW, int R>
 __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ Fx,
                                                       const uint4 *__restrict__ hdr,
                                                       const uint32_t *__restrict__ bo_xbeg, uint32_t XM,
@@ -848,12 +858,12 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
     HIP_DYNAMIC_SHARED(uint32_t, lds)
     uint32_t *s_M = lds;                    // [XM][EM]  table rows of the exits
     uint32_t *s_in = s_M + XM * EM;         // [EM][64]  entry values of the visit
-    uint32_t *s_xbeg = s_in + EM * 64;      // [XM + 1]  first cross arc of each exit
-    uint32_t *s_xport = s_xbeg + XM + 1;    // [PM]      cross arcs: target port,
-    uint32_t *s_xw = s_xport + PM;          //           weight,
-    uint32_t *s_xtile = s_xw + PM;          //           target tile
-    uint32_t *s_unit = s_xtile + PM;
-    constexpr uint32_t RPW = 64 / NW;       // entry rows a wave stages
+    uint32_t *s_xbeg = s_in + EM * 64;      // [XM + 1]  first outgoing arc of each exit
+    uint32_t *s_xtile = s_xbeg + XM + 1;    // [PM]      outgoing arcs: target tile
+    uint32_t *s_pbeg = s_xtile + PM;        // [EM + 1]  first incoming arc of each port
+    uint32_t *s_pexit = s_pbeg + EM + 1;    // [PM]      incoming arcs: source exit,
+    uint32_t *s_pw = s_pexit + PM;          //           weight
+    uint32_t *s_unit = s_pw + PM;
     const uint32_t lane = lane_id();
     const uint32_t wv = uniform(threadIdx.x >> 6);
     const uint32_t nunits = uniform(*A.nunits);
@@ -876,86 +886,103 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
 #pragma unroll 4
             for (uint32_t q = threadIdx.x; q < nM; q += blockDim.x) s_M[q] = rows[q];
             for (uint32_t j = threadIdx.x; j <= X; j += blockDim.x) s_xbeg[j] = bo_xbeg[b0 + t + j];
-            for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) {
-                s_xport[k] = A.x_port[xa0 + k];
-                s_xw[k] = A.x_w[xa0 + k];
-                s_xtile[k] = A.x_tile[xa0 + k];
+            for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) s_xtile[k] = A.x_tile[xa0 + k];
+            const uint2 h2 = A.hdr2[t];
+            const uint32_t pa0 = uniform(h2.x), npa = uniform(h2.y);
+            for (uint32_t i = threadIdx.x; i <= E; i += blockDim.x) s_pbeg[i] = A.pin_off[p0 + i] - pa0;
+            for (uint32_t k = threadIdx.x; k < npa; k += blockDim.x) {
+                s_pexit[k] = A.pin_exit[pa0 + k];
+                s_pw[k] = A.pin_w[pa0 + k];
             }
             staged = t;
             __syncthreads();
         }
         const uint32_t total = uniform(A.cnt_cur[t]);
         const uint32_t first_k = slice * A.G;
-        const uint32_t cnt = min(A.G, total - first_k);
-        for (uint32_t k = 0; E != 0 && k < cnt; ++k) {
-            const uint32_t b = uniform(A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + k]);
-            uint32_t *ib = A.inbox + static_cast<size_t>(b) * A.NP * 64;
-            // entry rows of the block, all loads of a wave in flight: the
-            // loads are unconditional (rows past the tile's ports re-read its
-            // last port; their table entries are INF, so they add nothing)
-            const uint32_t *ie = ib + static_cast<size_t>(p0) * 64;   // uniform: row i at ie + 64 i
-            const uint32_t elast = E - 1;
-            uint32_t v[RPW];
+        const uint32_t cnt = (E != 0 && X != 0) ? min(A.G, total - first_k) : 0u;
+        if (cnt == 0) continue;
+        const uint32_t elast = E - 1, xlast = X - 1;
+        // per entry row of this wave: row offset of its first arc's source
+        // exit, and that arc's weight (the same for every visit of the unit)
+        uint32_t eoff[R], ew[R];
 #pragma unroll
-            for (uint32_t r = 0; r < RPW; ++r)
-                v[r] = ie[static_cast<size_t>(min(wv + NW * r, elast)) * 64 + lane];
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint32_t k0 = s_pbeg[min(wv + NW * r, elast)];
+            eoff[r] = s_pexit[k0] * 64u + lane;
+            ew[r] = s_pw[k0];
+        }
+        // the unit's block ids, one per lane (cnt <= G <= 64)
+        const uint32_t blk = A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + min(lane, cnt - 1)];
+        uint32_t nb = __builtin_amdgcn_readfirstlane(blk);
+        uint32_t vn[R], cn[R];
+#define OVL_ISSUE_LOADS(BLK)                                                                 \
+        {                                                                                    \
+            const uint32_t *xb_ = A.xval + static_cast<size_t>(BLK) * A.NB * 64;             \
+            const uint32_t *xv_ = xb_ + static_cast<size_t>(b0) * 64;                        \
+            _Pragma("unroll") for (uint32_t r = 0; r < R; ++r) vn[r] = xb_[eoff[r]];         \
+            _Pragma("unroll") for (uint32_t r = 0; r < R; ++r)                               \
+                cn[r] = xv_[static_cast<size_t>(min(wv * R + r, xlast)) * 64 + lane];        \
+        }
+        OVL_ISSUE_LOADS(nb)
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const uint32_t b = nb;
+            const uint32_t *xb = A.xval + static_cast<size_t>(b) * A.NB * 64;   // uniform: exit e at xb + 64 e
+            uint32_t *xv = A.xval + (static_cast<size_t>(b) * A.NB + b0) * 64;  // uniform: own exit j at xv + 64 j
+            uint32_t c[R];
 #pragma unroll
-            for (uint32_t r = 0; r < RPW; ++r) {
+            for (uint32_t r = 0; r < R; ++r) c[r] = cn[r];
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) {
                 const uint32_t i = wv + NW * r;
-                if (i < EM) s_in[i * 64 + lane] = v[r];
+                if (i < E) {
+                    uint32_t e = sat_add(vn[r], ew[r]);
+                    // further incoming arcs of ports that have several
+                    const uint32_t k1 = s_pbeg[i + 1];
+                    for (uint32_t kx = s_pbeg[i] + 1; kx < k1; ++kx)
+                        e = min(e, sat_add(xb[static_cast<size_t>(s_pexit[kx]) * 64 + lane], s_pw[kx]));
+                    s_in[i * 64 + lane] = e;
+                }
             }
             __syncthreads();
-            for (uint32_t j0 = wv * OVL_B; j0 < X; j0 += NW * OVL_B) {
-                uint32_t m[OVL_B];
+            if (k + 1 < cnt) {
+                nb = __builtin_amdgcn_readlane(blk, k + 1);
+                OVL_ISSUE_LOADS(nb)
+            }
+            // this wave's exits (rows past the tile's last repeat it): min-plus
+            // over the entry rows; rows past the tile's ports are not written
+            // this visit, their table entries are INF and a saturating add
+            // with INF is INF whatever the row holds
+            const uint32_t j0 = wv * R;
+            if (j0 < X) {
+                uint32_t m[R];
 #pragma unroll
-                for (uint32_t r = 0; r < OVL_B; ++r) m[r] = INF;
+                for (uint32_t r = 0; r < R; ++r) m[r] = INF;
                 for (uint32_t i = 0; i < E; i += 4) {
                     const uint32_t e0 = s_in[i * 64 + lane], e1 = s_in[(i + 1) * 64 + lane];
                     const uint32_t e2 = s_in[(i + 2) * 64 + lane], e3 = s_in[(i + 3) * 64 + lane];
 #pragma unroll
-                    for (uint32_t r = 0; r < OVL_B; ++r) {
-                        const uint4 q = *reinterpret_cast<const uint4 *>(s_M + (j0 + r) * EM + i);
-                        m[r] = min(m[r], min(min(sat_add(e0, q.x), sat_add(e1, q.y)),
-                                             min(sat_add(e2, q.z), sat_add(e3, q.w))));
+                    for (uint32_t r = 0; r < R; ++r) {
+                        const uint4 f = *reinterpret_cast<const uint4 *>(s_M + min(j0 + r, xlast) * EM + i);
+                        m[r] = min(m[r], min(min(sat_add(e0, f.x), sat_add(e1, f.y)),
+                                             min(sat_add(e2, f.z), sat_add(e3, f.w))));
                     }
                 }
-                // the first cross arc of each of the four exits, pushed together
-                uint32_t kb[OVL_B], ke[OVL_B], nd[OVL_B], old[OVL_B];
-                uint32_t *pi[OVL_B];
+                // exits that dropped: store the value, flag the arcs' targets
 #pragma unroll
-                for (uint32_t r = 0; r < OVL_B; ++r) {
-                    const bool ok = j0 + r < X;
-                    kb[r] = ok ? uniform(s_xbeg[j0 + r]) : 0u;
-                    ke[r] = ok ? uniform(s_xbeg[j0 + r + 1]) : 0u;
-                    const bool has = kb[r] < ke[r];
-                    const uint32_t kx = has ? kb[r] : 0u;
-                    nd[r] = has ? sat_add(m[r], uniform(s_xw[kx])) : INF;
-                    pi[r] = ib + static_cast<size_t>(has ? uniform(s_xport[kx]) : p0) * 64 + lane;
-                    old[r] = INF;
-                }
-#pragma unroll
-                for (uint32_t r = 0; r < OVL_B; ++r)
-                    if (nd[r] != INF) old[r] = atomicMin(pi[r], nd[r]);
-#pragma unroll
-                for (uint32_t r = 0; r < OVL_B; ++r) {
-                    if (__builtin_amdgcn_ballot_w64(nd[r] < old[r]) != 0 && lane == 0)
-                        A.flags[static_cast<size_t>(s_xtile[kb[r]]) * A.S + b] = 1;
-                }
-                // further cross arcs of exits that have several
-#pragma unroll
-                for (uint32_t r = 0; r < OVL_B; ++r) {
-                    for (uint32_t kx = kb[r] + 1; kx < ke[r]; ++kx) {
-                        const uint32_t d = sat_add(m[r], uniform(s_xw[kx]));
-                        uint32_t *px = ib + static_cast<size_t>(uniform(s_xport[kx])) * 64 + lane;
-                        uint32_t o = INF;
-                        if (d != INF) o = atomicMin(px, d);
-                        if (__builtin_amdgcn_ballot_w64(d < o) != 0 && lane == 0)
-                            A.flags[static_cast<size_t>(s_xtile[kx]) * A.S + b] = 1;
-                    }
+                for (uint32_t r = 0; r < R; ++r) {
+                    const uint32_t j = j0 + r;
+                    if (j >= X) break;
+                    const bool imp = m[r] < c[r];
+                    if (imp) xv[static_cast<size_t>(j) * 64 + lane] = m[r];
+                    if (__builtin_amdgcn_ballot_w64(imp) == 0) continue;
+                    const uint32_t kb = uniform(s_xbeg[j]), ke = uniform(s_xbeg[j + 1]);
+                    for (uint32_t kx = kb + lane; kx < ke; kx += 64)
+                        A.flags[static_cast<size_t>(s_xtile[kx]) * A.S + b] = 1;
                 }
             }
             __syncthreads();
         }
+#undef OVL_ISSUE_LOADS
     }
 }
 
@@ -1042,45 +1069,48 @@ __global__ void k_flags_any(const uint8_t *__restrict__ flags, size_t n, uint32_
 }
 
 // Distance of chunk source s (vertex src_v) to v under the overlay schedule
-// over paths that leave the source's tile: min over the ports i of v's tile
-// of entry_i + F[v][i].  The source itself is 0; paths that stay inside the
+// over paths that leave the source's tile: min over the ports p of v's tile
+// of entry_p + F[v][p], with entry_p = min over the cross arcs e -> p of the
+// exit value xval[e] + w.  The source itself is 0; paths that stay inside the
 // source's tile are added by k_intile_fix.
-__device__ __forceinline__ uint32_t ovl_value(const uint32_t *tile_of, const uint32_t *pos_of,
-                                              const uint32_t *inbox, const uint32_t *F,
-                                              const uint32_t *port_base, uint32_t NP, uint32_t s,
-                                              uint32_t src_v, uint32_t v) {
+struct OvlRead {
+    const uint32_t *tile_of, *pos_of, *port_base, *pin_off, *pin_exit, *pin_w, *xval, *F;
+    uint32_t NB;
+};
+__device__ __forceinline__ uint32_t ovl_value(const OvlRead &R, uint32_t s, uint32_t src_v, uint32_t v) {
     if (v == src_v) return 0u;
-    const uint32_t t = tile_of[v];
+    const uint32_t t = R.tile_of[v];
     if (t == NONE) return INF;
     const size_t b = s >> 6, l = s & 63u;
-    const uint32_t pos = pos_of[v];
-    const uint32_t p0 = port_base[t], p1 = port_base[t + 1];
-    const uint32_t *ib = inbox + (b * NP) * 64 + l;
-    const uint32_t *Fv = F + static_cast<size_t>(pos) * 64;
+    const uint32_t pos = R.pos_of[v];
+    const uint32_t p0 = R.port_base[t], p1 = R.port_base[t + 1];
+    const uint32_t *xb = R.xval + (b * R.NB) * 64 + l;
+    const uint32_t *Fv = R.F + static_cast<size_t>(pos) * 64;
     uint32_t m = INF;
-    for (uint32_t p = p0; p < p1; ++p) m = min(m, sat_add(ib[static_cast<size_t>(p) * 64], Fv[p - p0]));
+    for (uint32_t p = p0; p < p1; ++p) {
+        uint32_t e = INF;
+        for (uint32_t k = R.pin_off[p]; k < R.pin_off[p + 1]; ++k)
+            e = min(e, sat_add(xb[static_cast<size_t>(R.pin_exit[k]) * 64], R.pin_w[k]));
+        m = min(m, sat_add(e, Fv[p - p0]));
+    }
     return m;
 }
 
-__global__ void k_ovl_emit(const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
-                           const uint32_t *__restrict__ inbox, const uint32_t *__restrict__ F,
-                           const uint32_t *__restrict__ port_base, uint32_t NP, uint32_t V, uint32_t rows,
-                           const uint32_t *__restrict__ row_src_idx, const uint32_t *__restrict__ row_src_vertex,
-                           const uint32_t *__restrict__ out_row, uint32_t *__restrict__ out) {
+__global__ void k_ovl_emit(OvlRead R, uint32_t V, uint32_t rows, const uint32_t *__restrict__ row_src_idx,
+                           const uint32_t *__restrict__ row_src_vertex, const uint32_t *__restrict__ out_row,
+                           uint32_t *__restrict__ out) {
     for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
         const uint32_t s = row_src_idx[r], sv = row_src_vertex[r];
         uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
         for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
-            o[v] = ovl_value(tile_of, pos_of, inbox, F, port_base, NP, s, sv, v);
+            o[v] = ovl_value(R, s, sv, v);
     }
 }
 
 __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
                              const uint32_t *__restrict__ picks, const uint64_t *__restrict__ out_base,
-                             const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n,
-                             const uint32_t *__restrict__ tile_of, const uint32_t *__restrict__ pos_of,
-                             const uint32_t *__restrict__ inbox, const uint32_t *__restrict__ F,
-                             const uint32_t *__restrict__ port_base, uint32_t NP, uint32_t *__restrict__ out) {
+                             const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n, OvlRead R,
+                             uint32_t *__restrict__ out) {
     for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
         const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
         const uint64_t ob = out_base[o];
@@ -1088,7 +1118,7 @@ __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ p
             const uint32_t i = k / P, j = k - i * P;
             const uint32_t si = src_idx_of_pick[a + i];
             if (si < lo || si >= lo + n) continue;
-            out[ob + k] = ovl_value(tile_of, pos_of, inbox, F, port_base, NP, si - lo, picks[a + i], picks[a + j]);
+            out[ob + k] = ovl_value(R, si - lo, picks[a + i], picks[a + j]);
         }
     }
 }
@@ -1405,6 +1435,12 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
     A.ntiles_next = ss.ntiles + nx;
     A.units = ss.units;
     A.flags = ss.flags;
+    A.xval = ss.xval;
+    A.NB = ts.NB;
+    A.pin_off = ts.d_pin_off.p;
+    A.pin_exit = ts.d_pin_exit.p;
+    A.pin_w = ts.d_pin_w.p;
+    A.hdr2 = reinterpret_cast<const uint2 *>(ts.d_ovl_hdr2.p);
     A.nunits = ss.nunits;
     A.cursor = ss.cursor;
     A.pass_ctr = ss.pass_ctr;
@@ -1580,9 +1616,9 @@ void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32
 }
 
 static void ovl_dims(const TileSet &ts, uint32_t &XM, uint32_t &EM, uint32_t &PM) {
-    XM = (std::max(ts.max_exits, 1u) + OVL_B - 1) / OVL_B * OVL_B;
+    XM = std::max(ts.max_exits, 1u);
     EM = (std::max(ts.max_ports, 1u) + 3u) / 4u * 4u;
-    PM = std::max(ts.max_cross, 1u);
+    PM = std::max(std::max(ts.max_cross, ts.max_cross_in), 1u);
 }
 
 uint32_t ovl_row_entries(const TileSet &ts) {
@@ -1594,7 +1630,19 @@ uint32_t ovl_row_entries(const TileSet &ts) {
 uint32_t ovl_pass_lds_bytes(const TileSet &ts) {
     uint32_t XM, EM, PM;
     ovl_dims(ts, XM, EM, PM);
-    return (XM * EM + EM * 64 + XM + 1 + 3 * PM + 1) * 4;
+    return (XM * EM + EM * 64 + XM + 1 + PM + EM + 1 + 2 * PM + 1) * 4;
+}
+
+__global__ void k_gather_u32(uint32_t *__restrict__ out, const uint32_t *__restrict__ idx,
+                             const uint32_t *__restrict__ src, uint32_t n) {
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+        out[k] = src[idx[k]];
+}
+
+void launch_gather_u32(uint32_t *out, const uint32_t *idx, const uint32_t *src, uint32_t n, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_gather_u32, blocks_for(n, 256, 4096), 256, 0, st, out, idx, src, n);
+    check_launch("gather_u32");
 }
 
 void launch_ovl_pack(const TileSet &ts, hipStream_t st) {
@@ -1627,8 +1675,16 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     const uint32_t lds = ovl_pass_lds_bytes(ts);
     const uint4 *hd = reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p);
     if (ev_begin) WR_HIP(hipEventRecord(ev_begin, st));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW>), grid, OVL_NW * 64, lds, st, A, ts.d_Fx.p, hd,
-                       ts.d_bo_xbeg.p, XM, EM, PM);
+    // rows (and exits) per wave: the smallest instance covering the tiling
+    const uint32_t need = (std::max(XM, EM) + OVL_NW - 1) / OVL_NW;
+#define WR_OVL_PASS(RR)                                                                                  \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ovl_pass<OVL_NW, RR>), grid, OVL_NW * 64, lds, st, A, ts.d_Fx.p, \
+                       hd, ts.d_bo_xbeg.p, XM, EM, PM)
+    if (need <= 4) WR_OVL_PASS(4);
+    else if (need <= 5) WR_OVL_PASS(5);
+    else if (need <= 6) WR_OVL_PASS(6);
+    else WR_OVL_PASS(8);
+#undef WR_OVL_PASS
     check_launch("ovl_pass");
     if (ev_end) WR_HIP(hipEventRecord(ev_end, st));
     if (count_after) {
@@ -1639,13 +1695,27 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     }
 }
 
+static OvlRead ovl_read(const TileSet &ts, const SegState &ss, const uint32_t *F) {
+    OvlRead R{};
+    R.tile_of = ts.d_tile_of.p;
+    R.pos_of = ts.d_pos_of.p;
+    R.port_base = ts.d_port_base.p;
+    R.pin_off = ts.d_pin_off.p;
+    R.pin_exit = ts.d_pin_exit.p;
+    R.pin_w = ts.d_pin_w.p;
+    R.xval = ss.xval;
+    R.F = F;
+    R.NB = ts.NB;
+    return R;
+}
+
 void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
                      const uint32_t *row_src_idx, const uint32_t *row_src_vertex, const uint32_t *out_row,
                      uint32_t *out, hipStream_t st) {
     if (!rows) return;
     dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
-    hipLaunchKernelGGL(k_ovl_emit, grid, 256, 0, st, ts.d_tile_of.p, ts.d_pos_of.p, ss.inbox, F,
-                       ts.d_port_base.p, std::max(ts.NP, 1u), V, rows, row_src_idx, row_src_vertex, out_row, out);
+    hipLaunchKernelGGL(k_ovl_emit, grid, 256, 0, st, ovl_read(ts, ss, F), V, rows, row_src_idx, row_src_vertex,
+                       out_row, out);
     check_launch("ovl_emit");
 }
 
@@ -1655,8 +1725,7 @@ void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint
                        uint32_t *out, hipStream_t st) {
     if (!num_orders) return;
     hipLaunchKernelGGL(k_gather_ovl, blocks_for(num_orders, 1, 65535), 256, 0, st, num_orders, pick_off, picks,
-                       out_base, src_idx_of_pick, chunk_lo, chunk_n, ts.d_tile_of.p, ts.d_pos_of.p, ss.inbox, F,
-                       ts.d_port_base.p, std::max(ts.NP, 1u), out);
+                       out_base, src_idx_of_pick, chunk_lo, chunk_n, ovl_read(ts, ss, F), out);
     check_launch("gather_ovl");
 }
 

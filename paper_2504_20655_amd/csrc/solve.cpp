@@ -150,6 +150,7 @@ bool overlay_supported(const wr_graph *g) {
     const TileSet *ts = g->tiles;
     return ts && g->lanes == 64 && g->max_w < 65536u && ts->max_ports <= 64 &&
            ts->max_exits <= ovl_max_exits() && ts->max_cross <= ovl_max_cross() &&
+           ts->max_cross_in <= ovl_max_cross() &&
            (ts->tile_cap == 256 || ts->tile_cap == 512);
 }
 
@@ -179,7 +180,7 @@ uint32_t resolve_algo(wr_graph *g, uint32_t flags) {
     if (a == WR_ALGO_OVERLAY && !overlay_supported(g))
         fail(WR_E_UNSUPPORTED, "the tiling does not fit the overlay tables (tiles of at most 512 "
                                "vertices with at most 64 ports, " + std::to_string(ovl_max_exits()) +
-                               " exits and " + std::to_string(ovl_max_cross()) + " cross arcs each)");
+                               " exits and " + std::to_string(ovl_max_cross()) + " cross arcs leaving and entering each)");
     return a;
 }
 
@@ -251,7 +252,7 @@ uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
 }  // namespace
 
 uint64_t SegBuffers::bytes_per_row(const TileSet &ts, uint32_t G, uint32_t lanes, bool overlay) {
-    return 4ull * lanes * ((overlay ? 0u : ts.Vt) + ts.NP + 2) + 2ull * ts.T + 4ull * ts.T + 8ull * ts.T +
+    return 4ull * lanes * ((overlay ? ts.NB : ts.Vt + ts.NP) + 2) + 2ull * ts.T + 4ull * ts.T + 8ull * ts.T +
            8ull * ts.T / G + 8;
 }
 
@@ -259,9 +260,13 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     S_cap = S;
     G = g;
     lanes = ln;
-    // the overlay schedule keeps boundary values only (inbox rows)
-    if (!with_flags) gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt * lanes);
-    inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u) * lanes);
+    // the overlay schedule keeps the exits' values only
+    if (with_flags) {
+        xval.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NB, 1u) * lanes);
+    } else {
+        gdist.alloc(ctx, static_cast<size_t>(S) * ts.Vt * lanes);
+        inbox.alloc(ctx, static_cast<size_t>(S) * std::max(ts.NP, 1u) * lanes);
+    }
     stamps.alloc(ctx, static_cast<size_t>(S) * ts.T);
     visited.alloc(ctx, static_cast<size_t>(S) * ts.T);
     if (with_flags) {
@@ -282,6 +287,7 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     ss.nsrc = S * lanes;
     ss.gdist = gdist.p;
     ss.inbox = inbox.p;
+    ss.xval = xval.p;
     ss.visited = visited.p;
     ss.stamps = stamps.p;
     ss.cnt = cnt.p;
@@ -372,6 +378,36 @@ void ensure_overlay_tables(wr_graph *g) {
             for (uint32_t j = 0; j < X; ++j) xb[b0 + t + j] = ts.x_off[base + ts.bo_local[b0 + j]] - xa0;
             xb[b0 + t + X] = na;
         }
+        // pull form: incoming cross arcs per port with their source exits
+        std::vector<uint32_t> xsrc_exit(ts.x_port.size(), NONE);
+        for (uint32_t t = 0; t < ts.T; ++t)
+            for (uint32_t b = ts.bo_base[t]; b < ts.bo_base[t + 1]; ++b) {
+                const uint32_t pos = ts.tile_base[t] + ts.bo_local[b];
+                for (uint32_t k = ts.x_off[pos]; k < ts.x_off[pos + 1]; ++k) xsrc_exit[k] = b;
+            }
+        ts.pin_off.assign(static_cast<size_t>(ts.NP) + 1, 0u);
+        for (uint32_t p : ts.x_port) ts.pin_off[p + 1]++;
+        for (uint32_t p = 0; p < ts.NP; ++p) ts.pin_off[p + 1] += ts.pin_off[p];
+        ts.pin_xa.assign(ts.x_port.size(), 0u);
+        ts.pin_exit.assign(ts.x_port.size(), 0u);
+        {
+            std::vector<uint32_t> fill(ts.pin_off.begin(), ts.pin_off.end() - 1);
+            for (uint32_t k = 0; k < ts.x_port.size(); ++k) {
+                const uint32_t slot = fill[ts.x_port[k]]++;
+                ts.pin_xa[slot] = k;
+                ts.pin_exit[slot] = xsrc_exit[k];
+            }
+        }
+        ts.ovl_hdr2.assign(2ull * ts.T, 0u);
+        for (uint32_t t = 0; t < ts.T; ++t) {
+            ts.ovl_hdr2[2ull * t] = ts.pin_off[ts.port_base[t]];
+            ts.ovl_hdr2[2ull * t + 1] = ts.pin_off[ts.port_base[t + 1]] - ts.pin_off[ts.port_base[t]];
+        }
+        upload(ts.d_pin_off, g->ctx, ts.pin_off, g->ctx->stream);
+        upload(ts.d_pin_xa, g->ctx, ts.pin_xa, g->ctx->stream);
+        upload(ts.d_pin_exit, g->ctx, ts.pin_exit, g->ctx->stream);
+        upload(ts.d_ovl_hdr2, g->ctx, ts.ovl_hdr2, g->ctx->stream);
+        ts.d_pin_w.alloc(g->ctx, std::max<size_t>(1, ts.pin_xa.size()));
         upload(ts.d_ovl_hdr, g->ctx, hdr, g->ctx->stream);
         upload(ts.d_bo_xbeg, g->ctx, xb, g->ctx->stream);
         upload(ts.d_vert_of, g->ctx, ts.vert_of, g->ctx->stream);
@@ -384,6 +420,8 @@ void ensure_overlay_tables(wr_graph *g) {
     launch_ovl_custom(ts, ts.tile_cap, ts.d_F.p, grid, g->ctx->stream, false);
     launch_ovl_custom(ts, ts.tile_cap, ts.d_B.p, grid, g->ctx->stream, true);
     launch_ovl_pack(ts, g->ctx->stream);
+    launch_gather_u32(ts.d_pin_w.p, ts.d_pin_xa.p, ts.d_x_w.p, static_cast<uint32_t>(ts.pin_xa.size()),
+                      g->ctx->stream);
     ts.custom_epoch = g->epoch;
 }
 
@@ -456,7 +494,10 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     WR_HIP(hipMemcpyAsync(w.buf.src_pos.p, sp.data(), cap_src * 4, hipMemcpyHostToDevice, st));
     WR_HIP(hipMemcpyAsync(w.buf.src_tile.p, stl.data(), cap_src * 4, hipMemcpyHostToDevice, st));
     // reset the chunk state (the layout keeps the capacity for indexing)
-    launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(rows) * std::max(ts.NP, 1u) * lanes, INF, st);
+    if (w.overlay)
+        launch_fill_u32(w.buf.xval.p, static_cast<size_t>(rows) * std::max(ts.NB, 1u) * lanes, INF, st);
+    else
+        launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(rows) * std::max(ts.NP, 1u) * lanes, INF, st);
     launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u8(w.buf.visited.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     if (w.overlay) launch_fill_u8(w.buf.flags.p, static_cast<size_t>(rows) * ts.T, 0u, st);
@@ -925,13 +966,13 @@ void stream_admit(StreamSolver *s, const std::vector<uint32_t> &blocks, const st
                               256, hipMemcpyHostToDevice, st));
         WR_HIP(hipMemcpyAsync(w.buf.src_tile.p + static_cast<size_t>(b) * 64, stl.data() + static_cast<size_t>(i) * 64,
                               256, hipMemcpyHostToDevice, st));
-        launch_fill_u32(w.buf.inbox.p + static_cast<size_t>(b) * std::max(ts.NP, 1u) * 64,
-                        static_cast<size_t>(std::max(ts.NP, 1u)) * 64, INF, st);
+        launch_fill_u32(w.buf.xval.p + static_cast<size_t>(b) * std::max(ts.NB, 1u) * 64,
+                        static_cast<size_t>(std::max(ts.NB, 1u)) * 64, INF, st);
         launch_fill_u8(w.buf.visited.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
         launch_fill_u32(w.buf.stamps.p + static_cast<size_t>(b) * ts.T, ts.T, 0u, st);
     }
-    // first pass of the new rows: each source pushes its exits' in-tile
-    // distances into its row's inbox and flags the targets
+    // first pass of the new rows: each source stores its in-tile distances to
+    // its tile's exits as its row's exit values and flags the tiles they lead to
     std::vector<uint32_t> slots;
     for (uint32_t i = 0; i < nb; ++i)
         for (uint32_t l = 0; l < 64; ++l)

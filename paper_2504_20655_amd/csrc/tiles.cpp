@@ -227,6 +227,11 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
             fail(WR_E_INTERNAL, "tile arc budget exceeded");
         ts->max_cross = std::max(ts->max_cross, ts->x_off[tsize[t + 1]] - ts->x_off[tsize[t]]);
     }
+    {
+        std::vector<uint32_t> in_cnt(T, 0u);
+        for (uint32_t tx : ts->x_tile) in_cnt[tx]++;
+        for (uint32_t t = 0; t < T; ++t) ts->max_cross_in = std::max(ts->max_cross_in, in_cnt[t]);
+    }
 
     // in-tile in-arcs (pull form): the same arcs grouped by target position
     ts->li_off.assign(Vt + 1, 0);

@@ -148,6 +148,7 @@ struct TileSet {
     uint32_t max_ports = 0;       // most ports of one tile
     uint32_t max_exits = 0;       // most boundary-out vertices of one tile
     uint32_t max_cross = 0;       // most cross-tile arcs leaving one tile
+    uint32_t max_cross_in = 0;    // most cross-tile arcs entering one tile
     // overlay boundary tables F[pos][64] (lane i = port i of the tile) and the
     // weight epoch they were computed for
     DBuf<uint32_t> d_F;
@@ -162,6 +163,13 @@ struct TileSet {
     // per tile, the key sources are ordered by (see tile_order_keys)
     std::vector<uint64_t> order_key;
     DBuf<uint32_t> d_ovl_hdr, d_bo_xbeg, d_Fx;
+    // pull form of the overlay: per port p its incoming cross arcs
+    // k in [pin_off[p], pin_off[p + 1]): the arc's index in the x_ arrays
+    // (pin_xa), its source exit (pin_exit, an index of the exit tables) and,
+    // for the epoch of d_F, its weight (d_pin_w); per tile {first incoming
+    // arc, incoming arcs} (ovl_hdr2)
+    std::vector<uint32_t> pin_off, pin_xa, pin_exit, ovl_hdr2;
+    DBuf<uint32_t> d_pin_off, d_pin_xa, d_pin_exit, d_pin_w, d_ovl_hdr2;
     // exit tables B[pos][64] of the epoch of d_F (lane j: in-tile distance to
     // exit j of the tile), and positions' vertices on the device
     DBuf<uint32_t> d_B, d_vert_of;
@@ -265,6 +273,7 @@ struct SegState {
     uint32_t S = 0;
     uint32_t *gdist = nullptr;      // [S][Vt]
     uint32_t *inbox = nullptr;      // [S][NP]
+    uint32_t *xval = nullptr;       // [S][NB][64] exit values (overlay schedule)
     uint8_t *visited = nullptr;     // [S][T]
     uint32_t *stamps = nullptr;     // [S][T]
     uint32_t *cnt = nullptr;        // [2][T]
@@ -299,7 +308,7 @@ void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t
 // blocks of 64 sources with lanes = 64; see SegState).
 struct SegBuffers {
     uint32_t S_cap = 0, G = 0, lanes = 1;
-    DBuf<uint32_t> gdist, inbox, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile, pending;
+    DBuf<uint32_t> gdist, inbox, xval, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile, pending;
     DBuf<uint8_t> visited, flags;
     DBuf<uint2> units;
     DBuf<unsigned long long> stats;
@@ -342,9 +351,9 @@ hipGraphExec_t capture_seg_passes(const TileSet &ts, const SegState &ss, uint32_
 // distance from pos to exit j of its tile
 void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32_t grid, hipStream_t st,
                        bool reverse);
-// first overlay pass: pushes each source slot's exit distances (B rows) into
-// the inbox rows of its block and flags the targets; slots == NULL means the
-// slots 0 .. nslots-1
+// first overlay pass: stores each source slot's in-tile distances to its
+// tile's exits (B rows) as the exit values of its block and flags the tiles
+// the exits lead to; slots == NULL means the slots 0 .. nslots-1
 void launch_ovl_seed_push(const TileSet &ts, const SegState &ss, const uint32_t *slots, uint32_t nslots,
                           hipStream_t st);
 // In-tile fix-ups after an overlay read-out: groups of up to 64 sources of one
@@ -374,6 +383,8 @@ struct IntileJob {
 uint32_t ovl_row_entries(const TileSet &ts);
 // packs the exits' rows of F into d_Fx
 void launch_ovl_pack(const TileSet &ts, hipStream_t st);
+// out[k] = src[idx[k]] for k < n
+void launch_gather_u32(uint32_t *out, const uint32_t *idx, const uint32_t *src, uint32_t n, hipStream_t st);
 // one overlay pass: prologue + plan from the flags + the pass; count_after
 // adds the number of waves that still see set flags to ntiles[parity ^ 1]
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
