@@ -213,13 +213,14 @@ struct SegPassArgs {
     uint32_t nsrc;
     // overlay schedule: activation flags [T][S] instead of stamped lists;
     // per block the value of every exit, xval[S][NB][64]; per port p its
-    // incoming cross arcs k in [pin_off[p], pin_off[p+1]) with their source
-    // exits pin_exit[k] and weights pin_w[k]; per tile {first incoming arc,
-    // incoming arcs} in hdr2
+    // incoming cross arcs k in [pin_off[p], pin_off[p+1]) with their records
+    // pin_rec[k] = {source exit, w | local port << 16}; per tile {first
+    // incoming arc, incoming arcs} in hdr2
     uint8_t *flags;
     uint32_t *xval;
     uint32_t NB;
-    const uint32_t *pin_off, *pin_exit, *pin_w;
+    const uint32_t *pin_off;
+    const uint2 *pin_rec;
     const uint2 *hdr2;
 };
 
@@ -891,8 +892,9 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
             const uint32_t pa0 = uniform(h2.x), npa = uniform(h2.y);
             for (uint32_t i = threadIdx.x; i <= E; i += blockDim.x) s_pbeg[i] = A.pin_off[p0 + i] - pa0;
             for (uint32_t k = threadIdx.x; k < npa; k += blockDim.x) {
-                s_pexit[k] = A.pin_exit[pa0 + k];
-                s_pw[k] = A.pin_w[pa0 + k];
+                const uint2 rec = A.pin_rec[pa0 + k];
+                s_pexit[k] = rec.x;
+                s_pw[k] = rec.y & 0xFFFFu;
             }
             staged = t;
             __syncthreads();
@@ -1069,12 +1071,14 @@ __global__ void k_flags_any(const uint8_t *__restrict__ flags, size_t n, uint32_
 }
 
 // Distance of chunk source s (vertex src_v) to v under the overlay schedule
-// over paths that leave the source's tile: min over the ports p of v's tile
-// of entry_p + F[v][p], with entry_p = min over the cross arcs e -> p of the
-// exit value xval[e] + w.  The source itself is 0; paths that stay inside the
-// source's tile are added by k_intile_fix.
+// over paths that leave the source's tile: the minimum, over the cross arcs
+// e -> p into v's tile, of the arc's source exit value xval[e] + w + F[v][p]
+// (the per-port minimum of the pass, folded into one loop over the tile's
+// contiguous arc records).  The source itself is 0; paths that stay inside
+// the source's tile are added by k_intile_fix.
 struct OvlRead {
-    const uint32_t *tile_of, *pos_of, *port_base, *pin_off, *pin_exit, *pin_w, *xval, *F;
+    const uint32_t *tile_of, *pos_of, *xval, *F;
+    const uint2 *hdr2, *pin_rec;
     uint32_t NB;
 };
 __device__ __forceinline__ uint32_t ovl_value(const OvlRead &R, uint32_t s, uint32_t src_v, uint32_t v) {
@@ -1083,15 +1087,15 @@ __device__ __forceinline__ uint32_t ovl_value(const OvlRead &R, uint32_t s, uint
     if (t == NONE) return INF;
     const size_t b = s >> 6, l = s & 63u;
     const uint32_t pos = R.pos_of[v];
-    const uint32_t p0 = R.port_base[t], p1 = R.port_base[t + 1];
+    const uint2 h2 = R.hdr2[t];
+    const uint2 *rec = R.pin_rec + h2.x;
     const uint32_t *xb = R.xval + (b * R.NB) * 64 + l;
     const uint32_t *Fv = R.F + static_cast<size_t>(pos) * 64;
     uint32_t m = INF;
-    for (uint32_t p = p0; p < p1; ++p) {
-        uint32_t e = INF;
-        for (uint32_t k = R.pin_off[p]; k < R.pin_off[p + 1]; ++k)
-            e = min(e, sat_add(xb[static_cast<size_t>(R.pin_exit[k]) * 64], R.pin_w[k]));
-        m = min(m, sat_add(e, Fv[p - p0]));
+#pragma unroll 4
+    for (uint32_t k = 0; k < h2.y; ++k) {
+        const uint2 r = rec[k];
+        m = min(m, sat_add(sat_add(xb[static_cast<size_t>(r.x) * 64], r.y & 0xFFFFu), Fv[r.y >> 16]));
     }
     return m;
 }
@@ -1107,6 +1111,8 @@ __global__ void k_ovl_emit(OvlRead R, uint32_t V, uint32_t rows, const uint32_t 
     }
 }
 
+// One order per blockIdx.x (strided), its P x P pairs spread over the
+// threads of gridDim.y workgroups.
 __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
                              const uint32_t *__restrict__ picks, const uint64_t *__restrict__ out_base,
                              const uint32_t *__restrict__ src_idx_of_pick, uint32_t lo, uint32_t n, OvlRead R,
@@ -1114,7 +1120,7 @@ __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ p
     for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
         const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
         const uint64_t ob = out_base[o];
-        for (uint32_t k = threadIdx.x; k < P * P; k += blockDim.x) {
+        for (uint32_t k = blockIdx.y * blockDim.x + threadIdx.x; k < P * P; k += gridDim.y * blockDim.x) {
             const uint32_t i = k / P, j = k - i * P;
             const uint32_t si = src_idx_of_pick[a + i];
             if (si < lo || si >= lo + n) continue;
@@ -1438,8 +1444,7 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
     A.xval = ss.xval;
     A.NB = ts.NB;
     A.pin_off = ts.d_pin_off.p;
-    A.pin_exit = ts.d_pin_exit.p;
-    A.pin_w = ts.d_pin_w.p;
+    A.pin_rec = ts.d_pin_rec.p;
     A.hdr2 = reinterpret_cast<const uint2 *>(ts.d_ovl_hdr2.p);
     A.nunits = ss.nunits;
     A.cursor = ss.cursor;
@@ -1633,16 +1638,19 @@ uint32_t ovl_pass_lds_bytes(const TileSet &ts) {
     return (XM * EM + EM * 64 + XM + 1 + PM + EM + 1 + 2 * PM + 1) * 4;
 }
 
-__global__ void k_gather_u32(uint32_t *__restrict__ out, const uint32_t *__restrict__ idx,
-                             const uint32_t *__restrict__ src, uint32_t n) {
+__global__ void k_ovl_pin_rec(uint2 *__restrict__ rec, const uint32_t *__restrict__ pin_xa,
+                              const uint32_t *__restrict__ pin_exit, const uint32_t *__restrict__ pin_lport,
+                              const uint32_t *__restrict__ x_w, uint32_t n) {
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-        out[k] = src[idx[k]];
+        rec[k] = make_uint2(pin_exit[k], (x_w[pin_xa[k]] & 0xFFFFu) | (pin_lport[k] << 16));
 }
 
-void launch_gather_u32(uint32_t *out, const uint32_t *idx, const uint32_t *src, uint32_t n, hipStream_t st) {
+void launch_ovl_pin_rec(const TileSet &ts, hipStream_t st) {
+    const uint32_t n = static_cast<uint32_t>(ts.pin_xa.size());
     if (!n) return;
-    hipLaunchKernelGGL(k_gather_u32, blocks_for(n, 256, 4096), 256, 0, st, out, idx, src, n);
-    check_launch("gather_u32");
+    hipLaunchKernelGGL(k_ovl_pin_rec, blocks_for(n, 256, 4096), 256, 0, st, ts.d_pin_rec.p, ts.d_pin_xa.p,
+                       ts.d_pin_exit.p, ts.d_pin_lport.p, ts.d_x_w.p, n);
+    check_launch("ovl_pin_rec");
 }
 
 void launch_ovl_pack(const TileSet &ts, hipStream_t st) {
@@ -1699,10 +1707,8 @@ static OvlRead ovl_read(const TileSet &ts, const SegState &ss, const uint32_t *F
     OvlRead R{};
     R.tile_of = ts.d_tile_of.p;
     R.pos_of = ts.d_pos_of.p;
-    R.port_base = ts.d_port_base.p;
-    R.pin_off = ts.d_pin_off.p;
-    R.pin_exit = ts.d_pin_exit.p;
-    R.pin_w = ts.d_pin_w.p;
+    R.hdr2 = reinterpret_cast<const uint2 *>(ts.d_ovl_hdr2.p);
+    R.pin_rec = ts.d_pin_rec.p;
     R.xval = ss.xval;
     R.F = F;
     R.NB = ts.NB;
@@ -1724,8 +1730,11 @@ void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint
                        uint32_t chunk_n, const TileSet &ts, const SegState &ss, const uint32_t *F,
                        uint32_t *out, hipStream_t st) {
     if (!num_orders) return;
-    hipLaunchKernelGGL(k_gather_ovl, blocks_for(num_orders, 1, 65535), 256, 0, st, num_orders, pick_off, picks,
-                       out_base, src_idx_of_pick, chunk_lo, chunk_n, ovl_read(ts, ss, F), out);
+    // four workgroups per order: one pair per thread for orders of up to 32
+    // picks, larger orders loop
+    dim3 grid(std::min(num_orders, 65535u), 4);
+    hipLaunchKernelGGL(k_gather_ovl, grid, 256, 0, st, num_orders, pick_off, picks, out_base, src_idx_of_pick,
+                       chunk_lo, chunk_n, ovl_read(ts, ss, F), out);
     check_launch("gather_ovl");
 }
 

@@ -69,7 +69,14 @@ struct SegWork {
     SegBuffers buf;
     hipGraphExec_t exec = nullptr;   // K passes of the segment kernel, or of the overlay kernel
     SegState ss;
+    // overlay: every exit value of all S_cap rows is INF (state_clean), else
+    // the rows a call may have left dirty; a call that ends cleanly resets
+    // its rows behind the host's wait, so the next call can skip the reset
+    bool state_clean = false;
+    uint32_t dirty_rows = 0;
+    hipStream_t st = nullptr;        // stream the state's kernels run on
     ~SegWork() {
+        if (st) (void)hipStreamSynchronize(st);   // a trailing reset may still run
         if (exec) (void)hipGraphExecDestroy(exec);
     }
 };
@@ -94,15 +101,19 @@ struct Workspace {
     uint32_t *h_flag = nullptr;   // pinned host word for termination checks
     // per-call index arrays of wr_order_matrices and the in-tile job, reused
     DBuf<uint32_t> call_off, call_picks, call_sidx;
-    // source dedup: per-vertex stamp of the last call that saw it, and its slot
-    std::vector<uint32_t> stamp, slot;
+    // source dedup: per-vertex stamp of the last call that saw it, its slot,
+    // and the bucket counts of the source ordering
+    std::vector<uint32_t> stamp, slot, plan_cnt;
     uint32_t stamp_id = 0;
     // passes the last segmented / overlay solve needed (replays launched
     // before the first convergence check)
     uint64_t last_passes = 0;
     DBuf<uint64_t> call_base;
     IntileJob intile;
+    hipEvent_t ev_done = nullptr;   // end of a call's results, ahead of a trailing reset
     ~Workspace() {
+        seg.reset();
+        if (ev_done) (void)hipEventDestroy(ev_done);
         if (h_flag) (void)hipHostFree(h_flag);
     }
 };
@@ -192,8 +203,9 @@ struct Plan {
 };
 
 // Distinct sources of a call in block order, and each input's index among
-// them.  Linear apart from one sort of the distinct sources: duplicates are
-// found with a per-vertex stamp kept in the workspace.
+// them.  Duplicates are found with a per-vertex stamp kept in the workspace
+// and the order is a counting sort over tile ranks (sorting by vertex only
+// inside a tile), so the cost is linear in the picks plus the tiles.
 Plan make_plan(wr_graph *g, const uint32_t *verts, size_t n, bool by_tile) {
     Workspace &ws = workspace(g);
     if (ws.stamp.size() != g->V) {
@@ -206,39 +218,45 @@ Plan make_plan(wr_graph *g, const uint32_t *verts, size_t n, bool by_tile) {
         ws.stamp_id = 1;
     }
     const uint32_t id = ws.stamp_id;
-    struct Item {
-        uint64_t key;
-        uint32_t tile, v;
-    };
-    std::vector<Item> items;
-    items.reserve(n);
-    const bool tiled = by_tile && g->tiles;
-    const std::vector<uint64_t> *key = tiled ? &tile_order_keys(g) : nullptr;
+    Plan p;
+    std::vector<uint32_t> &u = p.usrc;
+    u.reserve(n);
     for (size_t k = 0; k < n; ++k) {
         const uint32_t v = verts[k];
         if (ws.stamp[v] == id) continue;
         ws.stamp[v] = id;
-        uint32_t t = NONE;
-        uint64_t kk = 0;
-        if (tiled) {
-            t = g->tiles->tile_of[v];
-            kk = t == NONE ? ~0ull : (*key)[t];
+        u.push_back(v);
+    }
+    if (by_tile && g->tiles) {
+        // blocks of 64 consecutive sources should start close together: a
+        // counting sort by the tile's rank in key order (a compact patch
+        // order for grid tilings; untiled vertices last), vertex id inside a
+        // tile
+        const TileSet &ts = *g->tiles;
+        const std::vector<uint32_t> &rank = tile_order_rank(g);
+        std::vector<uint32_t> &cnt = ws.plan_cnt;
+        cnt.assign(static_cast<size_t>(ts.T) + 2, 0u);
+        std::vector<uint32_t> rk(u.size());
+        for (size_t i = 0; i < u.size(); ++i) {
+            const uint32_t t = ts.tile_of[u[i]];
+            rk[i] = t == NONE ? ts.T : rank[t];
+            cnt[rk[i] + 1]++;
         }
-        items.push_back({kk, t, v});
+        for (uint32_t r = 0; r <= ts.T; ++r) cnt[r + 1] += cnt[r];
+        std::vector<uint32_t> sorted(u.size());
+        for (size_t i = 0; i < u.size(); ++i) sorted[cnt[rk[i]]++] = u[i];
+        // cnt[r] is now the end of bucket r; buckets are small
+        uint32_t beg = 0;
+        for (uint32_t r = 0; r <= ts.T; ++r) {
+            const uint32_t end = cnt[r];
+            if (end - beg > 1) std::sort(sorted.begin() + beg, sorted.begin() + end);
+            beg = end;
+        }
+        u.swap(sorted);
+    } else {
+        std::sort(u.begin(), u.end());
     }
-    // blocks of 64 consecutive sources should start close together: order by
-    // the tile's key (a compact patch order for grid tilings), tile, vertex
-    std::sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
-        if (x.key != y.key) return x.key < y.key;
-        if (x.tile != y.tile) return x.tile < y.tile;
-        return x.v < y.v;
-    });
-    Plan p;
-    p.usrc.resize(items.size());
-    for (uint32_t i = 0; i < items.size(); ++i) {
-        p.usrc[i] = items[i].v;
-        ws.slot[items[i].v] = i;
-    }
+    for (uint32_t i = 0; i < u.size(); ++i) ws.slot[u[i]] = i;
     p.uidx.resize(n);
     for (size_t k = 0; k < n; ++k) p.uidx[k] = ws.slot[verts[k]];
     return p;
@@ -390,12 +408,15 @@ void ensure_overlay_tables(wr_graph *g) {
         for (uint32_t p = 0; p < ts.NP; ++p) ts.pin_off[p + 1] += ts.pin_off[p];
         ts.pin_xa.assign(ts.x_port.size(), 0u);
         ts.pin_exit.assign(ts.x_port.size(), 0u);
+        ts.pin_lport.assign(ts.x_port.size(), 0u);
         {
             std::vector<uint32_t> fill(ts.pin_off.begin(), ts.pin_off.end() - 1);
             for (uint32_t k = 0; k < ts.x_port.size(); ++k) {
-                const uint32_t slot = fill[ts.x_port[k]]++;
+                const uint32_t p = ts.x_port[k];
+                const uint32_t slot = fill[p]++;
                 ts.pin_xa[slot] = k;
                 ts.pin_exit[slot] = xsrc_exit[k];
+                ts.pin_lport[slot] = p - ts.port_base[ts.x_tile[k]];
             }
         }
         ts.ovl_hdr2.assign(2ull * ts.T, 0u);
@@ -406,8 +427,9 @@ void ensure_overlay_tables(wr_graph *g) {
         upload(ts.d_pin_off, g->ctx, ts.pin_off, g->ctx->stream);
         upload(ts.d_pin_xa, g->ctx, ts.pin_xa, g->ctx->stream);
         upload(ts.d_pin_exit, g->ctx, ts.pin_exit, g->ctx->stream);
+        upload(ts.d_pin_lport, g->ctx, ts.pin_lport, g->ctx->stream);
         upload(ts.d_ovl_hdr2, g->ctx, ts.ovl_hdr2, g->ctx->stream);
-        ts.d_pin_w.alloc(g->ctx, std::max<size_t>(1, ts.pin_xa.size()));
+        ts.d_pin_rec.alloc(g->ctx, std::max<size_t>(1, ts.pin_xa.size()));
         upload(ts.d_ovl_hdr, g->ctx, hdr, g->ctx->stream);
         upload(ts.d_bo_xbeg, g->ctx, xb, g->ctx->stream);
         upload(ts.d_vert_of, g->ctx, ts.vert_of, g->ctx->stream);
@@ -420,8 +442,7 @@ void ensure_overlay_tables(wr_graph *g) {
     launch_ovl_custom(ts, ts.tile_cap, ts.d_F.p, grid, g->ctx->stream, false);
     launch_ovl_custom(ts, ts.tile_cap, ts.d_B.p, grid, g->ctx->stream, true);
     launch_ovl_pack(ts, g->ctx->stream);
-    launch_gather_u32(ts.d_pin_w.p, ts.d_pin_xa.p, ts.d_x_w.p, static_cast<uint32_t>(ts.pin_xa.size()),
-                      g->ctx->stream);
+    launch_ovl_pin_rec(ts, g->ctx->stream);
     ts.custom_epoch = g->epoch;
 }
 
@@ -448,6 +469,7 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
     uint32_t R_cap = static_cast<uint32_t>(std::min<uint64_t>(rows_need, R_fit));
     if (R_cap == 0) fail(WR_E_NOMEM, "not even one source fits the memory budget (segmented)");
     auto nw = std::make_unique<SegWork>();
+    nw->st = g->ctx->stream;
     nw->gen = g->tiles_gen;
     nw->S_cap = R_cap;
     nw->tile_cap = ts.tile_cap;
@@ -494,9 +516,12 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     WR_HIP(hipMemcpyAsync(w.buf.src_pos.p, sp.data(), cap_src * 4, hipMemcpyHostToDevice, st));
     WR_HIP(hipMemcpyAsync(w.buf.src_tile.p, stl.data(), cap_src * 4, hipMemcpyHostToDevice, st));
     // reset the chunk state (the layout keeps the capacity for indexing)
-    if (w.overlay)
-        launch_fill_u32(w.buf.xval.p, static_cast<size_t>(rows) * std::max(ts.NB, 1u) * lanes, INF, st);
-    else
+    if (w.overlay) {
+        if (!w.state_clean)
+            launch_fill_u32(w.buf.xval.p, static_cast<size_t>(w.S_cap) * std::max(ts.NB, 1u) * lanes, INF, st);
+        w.state_clean = false;
+        w.dirty_rows = rows;
+    } else
         launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(rows) * std::max(ts.NP, 1u) * lanes, INF, st);
     launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u8(w.buf.visited.p, static_cast<size_t>(rows) * ts.T, 0u, st);
@@ -923,6 +948,7 @@ StreamSolver *stream_create(wr_graph *g, uint32_t blocks) {
     (void)resolve_algo(g, WR_ALGO_OVERLAY);
     if (!blocks) fail(WR_E_NOMEM, "no block row fits the memory budget");
     SegWork &w = seg_workspace(g, blocks * 64u, true, false, true);
+    w.state_clean = false;   // rows are reset one by one at admission
     const TileSet &ts = *g->tiles;
     hipStream_t st = g->ctx->stream;
     launch_fill_u8(w.buf.flags.p, static_cast<size_t>(w.S_cap) * ts.T, 0u, st);
@@ -948,6 +974,7 @@ uint32_t stream_blocks(const StreamSolver *s) { return s->blocks; }
 void stream_admit(StreamSolver *s, const std::vector<uint32_t> &blocks, const std::vector<uint32_t> &srcv) {
     wr_graph *g = s->g;
     SegWork &w = stream_work(s);
+    w.state_clean = false;
     const TileSet &ts = *g->tiles;
     const SegState &ss = w.ss;
     hipStream_t st = g->ctx->stream;
@@ -1336,7 +1363,20 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
     }
     g_trace.mark("gather", now_ms());
     if (!dev) WR_HIP(hipMemcpyAsync(dist_out, dout, static_cast<size_t>(total) * 4, hipMemcpyDeviceToHost, st));
-    WR_HIP(hipStreamSynchronize(st));
+    SegWork *sw = workspace(g).seg.get();
+    if (algo == WR_ALGO_OVERLAY && sw && sw->overlay && !sw->state_clean) {
+        // the results are complete at ev_done; the exit values of the rows
+        // this call used are reset behind it, while the host moves on
+        Workspace &ws = workspace(g);
+        if (!ws.ev_done) WR_HIP(hipEventCreateWithFlags(&ws.ev_done, hipEventDisableTiming));
+        WR_HIP(hipEventRecord(ws.ev_done, st));
+        launch_fill_u32(sw->buf.xval.p, static_cast<size_t>(sw->dirty_rows) * std::max(g->tiles->NB, 1u) * 64,
+                        INF, st);
+        sw->state_clean = true;
+        WR_HIP(hipEventSynchronize(ws.ev_done));
+    } else {
+        WR_HIP(hipStreamSynchronize(st));
+    }
     info.total_ms = now_ms() - t0;
     g_trace.mark("sync", now_ms());
     g_trace.flush("order_matrices");

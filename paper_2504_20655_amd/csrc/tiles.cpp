@@ -354,6 +354,18 @@ const std::vector<uint64_t> &tile_order_keys(wr_graph *g) {
     return ts.order_key;
 }
 
+const std::vector<uint32_t> &tile_order_rank(wr_graph *g) {
+    TileSet &ts = *g->tiles;
+    if (ts.order_rank.size() == ts.T) return ts.order_rank;
+    const std::vector<uint64_t> &key = tile_order_keys(g);
+    std::vector<uint32_t> by(ts.T);
+    for (uint32_t t = 0; t < ts.T; ++t) by[t] = t;
+    std::sort(by.begin(), by.end(), [&](uint32_t a, uint32_t b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
+    ts.order_rank.assign(ts.T, 0u);
+    for (uint32_t r = 0; r < ts.T; ++r) ts.order_rank[by[r]] = r;
+    return ts.order_rank;
+}
+
 void rebuild_tiles_if_needed(wr_graph *g) {
     if (g->tiles && g->tiles->tile_cap == g->tile_vertices) return;
     if (g->grid_W) {

@@ -160,16 +160,20 @@ struct TileSet {
     // beyond the tile's ports INF) for the epoch of d_F.
     uint32_t ovl_em = 0;
     std::vector<uint32_t> ovl_hdr, bo_xbeg;
-    // per tile, the key sources are ordered by (see tile_order_keys)
+    // per tile, the key sources are ordered by (see tile_order_keys), and
+    // the tile's rank in (key, tile) order
     std::vector<uint64_t> order_key;
+    std::vector<uint32_t> order_rank;
     DBuf<uint32_t> d_ovl_hdr, d_bo_xbeg, d_Fx;
     // pull form of the overlay: per port p its incoming cross arcs
     // k in [pin_off[p], pin_off[p + 1]): the arc's index in the x_ arrays
-    // (pin_xa), its source exit (pin_exit, an index of the exit tables) and,
-    // for the epoch of d_F, its weight (d_pin_w); per tile {first incoming
-    // arc, incoming arcs} (ovl_hdr2)
-    std::vector<uint32_t> pin_off, pin_xa, pin_exit, ovl_hdr2;
-    DBuf<uint32_t> d_pin_off, d_pin_xa, d_pin_exit, d_pin_w, d_ovl_hdr2;
+    // (pin_xa), its source exit (pin_exit, an index of the exit tables) and
+    // the port's index in its tile (pin_lport); for the epoch of d_F the
+    // packed records d_pin_rec[k] = {source exit, w | local port << 16}; per
+    // tile {first incoming arc, incoming arcs} (ovl_hdr2)
+    std::vector<uint32_t> pin_off, pin_xa, pin_exit, pin_lport, ovl_hdr2;
+    DBuf<uint32_t> d_pin_off, d_pin_xa, d_pin_exit, d_pin_lport, d_ovl_hdr2;
+    DBuf<uint2> d_pin_rec;
     // exit tables B[pos][64] of the epoch of d_F (lane j: in-tile distance to
     // exit j of the tile), and positions' vertices on the device
     DBuf<uint32_t> d_B, d_vert_of;
@@ -383,8 +387,8 @@ struct IntileJob {
 uint32_t ovl_row_entries(const TileSet &ts);
 // packs the exits' rows of F into d_Fx
 void launch_ovl_pack(const TileSet &ts, hipStream_t st);
-// out[k] = src[idx[k]] for k < n
-void launch_gather_u32(uint32_t *out, const uint32_t *idx, const uint32_t *src, uint32_t n, hipStream_t st);
+// packs d_pin_rec from the current cross-arc weights
+void launch_ovl_pin_rec(const TileSet &ts, hipStream_t st);
 // one overlay pass: prologue + plan from the flags + the pass; count_after
 // adds the number of waves that still see set flags to ntiles[parity ^ 1]
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
@@ -443,6 +447,8 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t tile_
 // level, so that consecutive tiles form compact patches; otherwise the
 // tile id.  Computed on first use and kept with the tiles.
 const std::vector<uint64_t> &tile_order_keys(wr_graph *g);
+// Rank of each tile in (key, tile) order.
+const std::vector<uint32_t> &tile_order_rank(wr_graph *g);
 void rebuild_tiles_if_needed(wr_graph *g);
 
 }  // namespace wr

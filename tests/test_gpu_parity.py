@@ -238,3 +238,27 @@ def test_overlay_chunks_under_small_budget(rt):
             assert (got == exp).all()
             return
     pytest.fail("no budget produced a chunked run")
+
+
+def test_overlay_back_to_back_calls(rt, ctx):
+    """Consecutive overlay calls on one graph reuse the per-call state (reset
+    after each call): batches of growing and shrinking source counts, with
+    a weight update in between, all stay exact."""
+    wl = make_config("medium", side=96, num_orders=24)
+    g = wl.graph
+    G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
+    G.segment_grid(g.W, g.H, 1, 12, 10)
+    off, picks = wl.pick_offsets, wl.picks
+    w = g.w.copy()
+    rng = np.random.default_rng(5)
+    for n_orders in (24, 3, 17, 1, 24):
+        o_off = off[:n_orders + 1]
+        o_picks = picks[:int(o_off[-1])]
+        got = G.order_matrices(o_off, o_picks, algo="overlay")
+        exp = oracle.order_matrices(g.row_ptr, g.col, w, o_off, o_picks)
+        assert (got == exp).all(), f"{n_orders} orders"
+        if n_orders == 17:
+            arcs = rng.choice(g.E, g.E // 10, replace=False).astype(np.uint32)
+            neww = rng.integers(1, 25, len(arcs)).astype(np.uint32)
+            G.update_weights(arcs, neww)
+            w[arcs] = neww
