@@ -5,8 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and shares no code with it.
 
 The C part (``oracle.c`` -> ``liboracle.so``) holds Dijkstra, Jacobi
-Bellman-Ford, canonical predecessors, order gathers, CSR validation and the
-optimality certificate; ``brute.py`` enumerates simple paths on tiny graphs
+Bellman-Ford, canonical predecessors, order gathers, CSR validation, the
+optimality certificate and the optimal open route over an order's matrix
+(Held and Karp's subset programme); ``brute.py`` enumerates simple paths on tiny graphs
 and ``closed_forms.py`` holds the grid distance formulas used as pins.
 """
 from __future__ import annotations
@@ -60,6 +61,11 @@ def lib():
         L.orc_certificate.restype = i32
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = i32
+        _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+        L.orc_route_held_karp.argtypes = [u32, _u32p, _u64p, _u32p]
+        L.orc_route_held_karp.restype = i32
+        L.orc_order_routes.argtypes = [u32, _u32p, _u32p, _u64p, _u32p, i32]
+        L.orc_order_routes.restype = i32
         _lib = L
     return _lib
 
@@ -159,6 +165,38 @@ def order_matrices(row_ptr, col, w, pick_offsets, picks, nthreads: int = 0) -> n
     lib().orc_gather_orders(V, n_orders, off, pk, row_of.astype(np.uint32),
                             rows.reshape(-1), out)
     return out[:total]
+
+
+ROUTE_INF = 0xFFFFFFFFFFFFFFFF
+
+
+def route(D) -> tuple[int, np.ndarray]:
+    """Optimal open route over the stops of one n x n matrix (n <= 20):
+    (length, lexicographically smallest optimal ordering).  Length is the
+    exact sum of the n-1 steps, ROUTE_INF when every ordering meets an INF
+    entry.  Held and Karp's programme over stop subsets (C)."""
+    M = np.ascontiguousarray(D, dtype=np.uint32)
+    n = M.shape[0] if M.ndim == 2 else int(round(len(M) ** 0.5))
+    cost = np.zeros(1, dtype=np.uint64)
+    r = np.zeros(max(n, 1), dtype=np.uint32)
+    if lib().orc_route_held_karp(n, M.reshape(-1) if n else np.zeros(1, np.uint32), cost, r) != 0:
+        raise ValueError("route oracle: n out of range or out of memory")
+    return int(cost[0]), r[:n]
+
+
+def order_routes(pick_offsets, dist, nthreads: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """route() of every order: dist holds the concatenated P_o x P_o
+    matrices; returns (lengths u64[num_orders], orderings u32[total picks])
+    with order o's ordering at pick_offsets[o]."""
+    off = np.ascontiguousarray(pick_offsets, dtype=np.uint32)
+    n_orders = len(off) - 1
+    D = np.ascontiguousarray(dist, dtype=np.uint32)
+    cost = np.zeros(max(n_orders, 1), dtype=np.uint64)
+    rt = np.zeros(max(int(off[-1]) if n_orders else 0, 1), dtype=np.uint32)
+    if n_orders and lib().orc_order_routes(n_orders, off, D if D.size else np.zeros(1, np.uint32),
+                                           cost, rt, nthreads) != 0:
+        raise ValueError("route oracle: an order is out of range")
+    return cost[:n_orders], rt[:int(off[-1]) if n_orders else 0]
 
 
 def max_threads() -> int:

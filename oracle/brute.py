@@ -32,3 +32,25 @@ def all_pairs_by_enumeration(V: int, arcs) -> list[list[int]]:
 
         walk(s, 0)
     return D
+
+
+def route_by_enumeration(D) -> tuple[int, list[int]]:
+    """Optimal open route over the stops of a tiny n x n matrix by trying
+    every ordering (n <= 8): the length is the sum of the n-1 steps along the
+    ordering (infinite if a step is INF), and among the shortest orderings
+    the lexicographically smallest is kept -- permutations() yields them in
+    lexicographic order, so the first strict improvement wins.  Returns
+    (length or None when every ordering is infinite, ordering)."""
+    import itertools
+    n = len(D)
+    best, best_p = None, list(range(n))
+    for p in itertools.permutations(range(n)):
+        length = 0
+        for a, b in zip(p, p[1:]):
+            if D[a][b] == INF:
+                length = None
+                break
+            length += D[a][b]
+        if length is not None and (best is None or length < best):
+            best, best_p = length, list(p)
+    return best, best_p

@@ -353,3 +353,111 @@ int orc_certificate(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
     free(stack); free(seen); free(reach);
     return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Optimal open route over an order's stops (Route Optimization section:
+ * the entrance/exit is not part of the route, so a route is an ordering of
+ * the n stops with any first and any last stop, and its length is the sum
+ * of the n-1 stop-to-stop distances along it; the section counts n!/2
+ * routes by identifying the two travel directions, which for a directed
+ * matrix are kept apart here).  The result is the minimum over all n!
+ * orderings; among orderings of that length the lexicographically smallest
+ * index sequence is returned.  Lengths are exact 64-bit sums; an INF entry
+ * makes every ordering that uses it infinite (ORC_ROUTE_INF).
+ *
+ * The minimum is reached with Held and Karp's dynamic programme over stop
+ * subsets, which the section names as the exact alternative to enumerating
+ * orderings: h(S, i) = shortest path that starts at stop i and visits exactly
+ * the stops of S (i in S), h({i}, i) = 0, h(S, i) = min over j in S\{i} of
+ * D[i][j] + h(S\{i}, j).  The optimum is min_i h(all, i), and the
+ * lexicographically smallest optimal ordering is read greedily: the smallest
+ * i with h(all, i) optimal, then repeatedly the smallest j whose step
+ * D[i][j] + h(rest, j) equals h(current, i).                              */
+#define ORC_ROUTE_INF UINT64_MAX
+
+static uint64_t route_add(uint64_t a, uint32_t d)
+{
+    if (a == ORC_ROUTE_INF || d == ORC_INF) return ORC_ROUTE_INF;
+    return a + d;
+}
+
+/* n <= 20; D row-major n x n; route gets n indices.  Returns 0, or -1 when
+ * n is out of range or memory is short. */
+int orc_route_held_karp(uint32_t n, const uint32_t *D, uint64_t *cost, uint32_t *route)
+{
+    if (n == 0) {
+        *cost = 0;
+        return 0;
+    }
+    if (n > 20) return -1;
+    const size_t nsub = (size_t)1 << n;
+    uint64_t *h = (uint64_t *)malloc(nsub * n * sizeof(uint64_t));
+    if (!h) return -1;
+    for (size_t k = 0; k < nsub * n; ++k) h[k] = ORC_ROUTE_INF;
+    for (uint32_t i = 0; i < n; ++i) h[((size_t)1 << i) * n + i] = 0;
+    /* subsets in increasing numeric order: S \ {i} < S, so it is final */
+    for (size_t S = 1; S < nsub; ++S) {
+        if ((S & (S - 1)) == 0) continue;   /* singletons are set */
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!(S & ((size_t)1 << i))) continue;
+            const size_t R = S & ~((size_t)1 << i);
+            uint64_t best = ORC_ROUTE_INF;
+            for (uint32_t j = 0; j < n; ++j) {
+                if (!(R & ((size_t)1 << j))) continue;
+                const uint64_t v = route_add(h[R * n + j], D[(size_t)i * n + j]);
+                if (v < best) best = v;
+            }
+            h[S * n + i] = best;
+        }
+    }
+    const size_t all = nsub - 1;
+    uint64_t opt = ORC_ROUTE_INF;
+    for (uint32_t i = 0; i < n; ++i)
+        if (h[all * n + i] < opt) opt = h[all * n + i];
+    uint32_t cur = 0;
+    while (h[all * n + cur] != opt) ++cur;
+    size_t S = all;
+    route[0] = cur;
+    for (uint32_t k = 1; k < n; ++k) {
+        const size_t R = S & ~((size_t)1 << cur);
+        uint32_t nxt = 0;
+        for (uint32_t j = 0; j < n; ++j) {
+            if (!(R & ((size_t)1 << j))) continue;
+            if (route_add(h[R * n + j], D[(size_t)cur * n + j]) == h[S * n + cur]) {
+                nxt = j;
+                break;
+            }
+        }
+        route[k] = nxt;
+        S = R;
+        cur = nxt;
+    }
+    *cost = opt;
+    free(h);
+    return 0;
+}
+
+/* Every order of a batch: matrices concatenated (order o is P_o x P_o at the
+ * running offset sum of P^2), routes concatenated at pick_off[o]. */
+int orc_order_routes(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *D, uint64_t *cost,
+                     uint32_t *route, int nthreads)
+{
+    uint64_t *base = (uint64_t *)malloc(((size_t)num_orders + 1) * sizeof(uint64_t));
+    if (!base) return -1;
+    base[0] = 0;
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        const uint64_t P = pick_off[o + 1] - pick_off[o];
+        base[o + 1] = base[o] + P * P;
+    }
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+#endif
+    for (int64_t o = 0; o < (int64_t)num_orders; ++o) {
+        const uint32_t P = pick_off[o + 1] - pick_off[o];
+        if (orc_route_held_karp(P, D + base[o], cost + o, route + pick_off[o]) != 0) bad |= 1;
+    }
+    free(base);
+    return bad ? -1 : 0;
+}

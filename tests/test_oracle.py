@@ -316,3 +316,68 @@ def test_generators_are_deterministic():
     for o in range(4):
         pk = a.picks[a.pick_offsets[o]:a.pick_offsets[o + 1]].tolist()
         assert len(set(pk)) == len(pk) and set(pk) <= adj
+
+
+# ----------------------------------------------------------- optimal routes
+def _route_cases():
+    """Matrices that expose plausible mistakes: asymmetric entries (a
+    transposed step), heavy ties (the tie-break), INF entries (saturation),
+    and metric closures of random points (the hot path's matrices)."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for n in range(1, 8):
+        cases.append(rng.integers(0, 50, (n, n)))                    # asymmetric
+        cases.append(rng.integers(0, 3, (n, n)))                     # many ties
+        m = rng.integers(1, 40, (n, n))
+        m[rng.random((n, n)) < 0.3] = INF                            # unreachable steps
+        cases.append(m)
+        pts = rng.integers(0, 20, (n, 2))
+        cases.append(np.abs(pts[:, None, :] - pts[None, :, :]).sum(-1))   # L1 metric
+    for m in cases:
+        np.fill_diagonal(m, 0)
+    return [m.astype(np.uint32) for m in cases]
+
+
+def test_route_matches_enumeration():
+    from oracle.brute import route_by_enumeration
+    for D in _route_cases():
+        cost, r = oracle.route(D)
+        best, p = route_by_enumeration(D.tolist())
+        assert cost == (oracle.ROUTE_INF if best is None else best), D
+        assert r.tolist() == p, D
+
+
+def test_route_closed_forms():
+    # stops on a line: the best open route sweeps from one end to the other,
+    # length max - min, visiting the stops in coordinate order
+    rng = np.random.default_rng(12)
+    for n in (2, 5, 9, 13):
+        x = rng.choice(1000, n, replace=False)
+        D = np.abs(x[:, None] - x[None, :]).astype(np.uint32)
+        cost, r = oracle.route(D)
+        assert cost == x.max() - x.min()
+        xs = x[r]
+        assert (np.diff(xs) > 0).all() or (np.diff(xs) < 0).all()
+        # lexicographically smallest of the two sweeps
+        asc, desc = np.argsort(x), np.argsort(-x)
+        assert r.tolist() == min(asc.tolist(), desc.tolist())
+    # degenerate sizes and an infeasible matrix
+    assert oracle.route(np.zeros((0, 0), np.uint32))[0] == 0
+    c, r = oracle.route(np.zeros((1, 1), np.uint32))
+    assert c == 0 and r.tolist() == [0]
+    c, r = oracle.route(np.array([[0, 7], [3, 0]], np.uint32))
+    assert c == 3 and r.tolist() == [1, 0]
+    D = np.full((4, 4), INF, np.uint32)
+    np.fill_diagonal(D, 0)
+    c, r = oracle.route(D)
+    assert c == oracle.ROUTE_INF and r.tolist() == [0, 1, 2, 3]
+
+
+def test_order_routes_batches_orders():
+    mats = _route_cases()[:12]
+    sizes = [m.shape[0] for m in mats]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    cost, rt = oracle.order_routes(off, np.concatenate([m.ravel() for m in mats]))
+    for o, m in enumerate(mats):
+        c, r = oracle.route(m)
+        assert cost[o] == c and rt[off[o]:off[o + 1]].tolist() == r.tolist()
