@@ -15,6 +15,9 @@ Prints ONE JSON line:
                timed live with HIP events recorded around each launch
   cpu_baseline the CPU oracle (Dijkstra per distinct pick, all host cores)
                on a bounded sample of the same orders
+  route_leg    the next step on the path: exact open routes (wr_order_routes)
+               over 12-stop windows of the batch's own matrices, routes/s,
+               with its ALU roofline and the CPU oracle beside it
 """
 from __future__ import annotations
 
@@ -53,6 +56,8 @@ def parse():
     ap.add_argument("--serve-rates", default="500,2000",
                     help="Poisson arrival rates (orders/s) of the serving leg, comma-separated ('' = skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
+    ap.add_argument("--route-stops", type=int, default=12,
+                    help="stops per route in the exact-route leg (0 = skip the leg)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device once (a dispatch of known "
                          "traffic that scales the HBM byte counters of a profiler run)")
@@ -158,6 +163,53 @@ def serving_leg(wr, ctx, rates, seconds, tile):
     return {"workload": "serving: 3 levels of 1024x1024 (V=3,145,728, E=6,422,650), 64 lifts (w=50), "
                         "P ~ U{2..128}, 1% congestion per 100 ms",
             "seconds_per_rate": seconds, "runs": out}
+
+
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit integer VALU ops: CUs x SIMDs x lanes x clock
+
+
+def route_leg(wr, ctx, D_host, n_orders, P, stops, steps, warmup, with_cpu):
+    """Exact open routes (wr_order_routes) over windows of `stops` picks of
+    every order of the batch, cut from the batch's own P x P matrices
+    (offsets 0, 4, 8, ... while a window fits): routes/s with the matrices
+    resident in HBM, the kernel's ALU roofline (each candidate step of the
+    subset programme is an add and a min, n(n-1)2^(n-2) per route), and the
+    CPU oracle on a bounded sample."""
+    import torch
+    mats = [D_host[o * P * P:(o + 1) * P * P].reshape(P, P) for o in range(n_orders)]
+    wins = [m[s:s + stops, s:s + stops] for m in mats for s in range(0, P - stops + 1, 4)]
+    woff = np.arange(len(wins) + 1, dtype=np.uint32) * stops
+    flat = np.concatenate([w.ravel() for w in wins]).astype(np.uint32)
+    dev = torch.device("cuda:0")
+    d_dist = torch.from_numpy(flat.view(np.int32).copy()).to(dev)
+    d_len = torch.zeros(len(wins), dtype=torch.int64, device=dev)
+    d_rt = torch.zeros(len(wins) * stops, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        ctx.order_routes(woff, d_dist, d_len, d_rt)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.order_routes(woff, d_dist, d_len, d_rt)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    n = stops
+    ops = 2.0 * n * (n - 1) * 2 ** (n - 2) * len(wins)
+    achieved = ops / dt / 1e12
+    res = {"workload": f"{len(wins)} routes of {stops} stops: windows of the medium batch's order matrices",
+           "value": round(len(wins) / dt, 1), "unit": "routes/s", "ms_per_call": round(dt * 1e3, 4),
+           "roofline": {"kernel": "k_route_hk", "bound": "alu", "achieved": round(achieved, 3),
+                        "peak": round(ALU_PEAK_TOPS, 1), "unit": "Tops/s",
+                        "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None}}
+    if with_cpu:
+        import oracle
+        k = len(wins)
+        t = time.perf_counter()
+        oracle.order_routes(woff[:k + 1], flat[:k * stops * stops], nthreads=oracle.max_threads())
+        tc = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": round(k / tc, 1), "unit": "routes/s", "cores": oracle.max_threads(),
+                               "kind": "oracle",
+                               "sample": f"first {k} of {len(wins)} routes (Held-Karp in C), {tc:.2f} s wall"}
+    return res
 
 
 def cpu_baseline(wl, target_core_s: float):
@@ -311,6 +363,12 @@ def main():
         res["baseline_b1"] = {"value": round(k / tb, 3), "unit": "orders/s",
                               "sample": f"first {k} orders, one order at a time, thread per arc, "
                                         f"host-checked early exit ({G.last_run()['passes']} rounds)"}
+    if args.route_stops > 0:
+        P0 = int(off[1] - off[0])
+        if all(int(off[o + 1] - off[o]) == P0 for o in range(n_orders)) and args.route_stops <= P0:
+            D_host = out.cpu().numpy().view(np.uint32)[:n_orders * P0 * P0]
+            res["route_leg"] = route_leg(wr, ctx, D_host, n_orders, P0, args.route_stops, args.steps,
+                                         args.warmup, not args.no_cpu_baseline)
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
         res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds, args.tile or 512)

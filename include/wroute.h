@@ -196,6 +196,42 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
                             const uint32_t *picks, uint32_t *dist_out, int32_t *pred_out,
                             uint32_t flags, void *stream);
 
+/* Optimal open route over each order's stops, from its distance matrix
+ * (Route Optimization section: the entrance/exit is not part of a route, so
+ * a route is an ordering of the order's P stops with any first and any last
+ * stop, and its length is the sum of the P-1 matrix entries along it; the
+ * section names Held and Karp's subset programme as the exact method,
+ * which the kernel runs, one workgroup per order with its states in LDS).
+ * Orderings are directed (D[i][j] is the step from stop i to stop j), so an
+ * asymmetric matrix is served too; for a symmetric one the two travel
+ * directions of a route tie and the smaller ordering is returned.
+ *
+ * pick_offsets: uint32[num_orders+1] (host), non-decreasing, first 0; order
+ *               o has P_o = pick_offsets[o+1] - pick_offsets[o] stops,
+ *               P_o <= WR_ROUTE_MAX_STOPS.
+ * dist:         uint32[sum_o P_o^2]: the concatenated row-major P_o x P_o
+ *               matrices, as wr_order_matrices writes them; WR_INF marks a
+ *               step that cannot be taken.
+ * length_out:   uint64[num_orders]: the shortest route's length,
+ *               WR_ROUTE_INF when every ordering takes a WR_INF step (0 for
+ *               orders of 0 or 1 stops).
+ * route_out:    uint32[pick_offsets[num_orders]]: order o's ordering at
+ *               pick_offsets[o], as indices 0..P_o-1 into its picks; among
+ *               shortest orderings the lexicographically smallest.
+ * flags:        WR_DEVICE_PTRS: dist, length_out and route_out are device
+ *               pointers, read and written by work ordered after `stream`
+ *               (pick_offsets stays a host array).
+ * Errors: WR_E_INVALID (NULL, bad offsets, unknown flags), WR_E_UNSUPPORTED
+ * (an order with more than WR_ROUTE_MAX_STOPS stops), WR_E_RANGE (the
+ * length of some partial route of an order reaches 2^32-1: lengths are
+ * accumulated in 32 bits; outputs are then unspecified), WR_E_NOMEM,
+ * WR_E_DEVICE. */
+#define WR_ROUTE_MAX_STOPS 12u
+#define WR_ROUTE_INF 0xFFFFFFFFFFFFFFFFull
+wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
+                          const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
+                          uint32_t flags, void *stream);
+
 /* Statistics of the last wr_sssp / wr_order_matrices call on this graph. */
 typedef struct wr_run_info {
     uint32_t algo;             /* WR_ALGO_* value that ran                      */

@@ -80,6 +80,24 @@ class Context:
         _check(lib().wr_context_memory(self.h, ctypes.byref(used), ctypes.byref(budget)))
         return used.value, budget.value
 
+    def order_routes(self, pick_offsets, dist, lengths=None, routes=None):
+        """Shortest open route over each order's stops (wr_order_routes):
+        dist holds the concatenated P x P matrices (numpy uint32, or a device
+        tensor with lengths/routes device tensors as well).  Returns
+        (lengths uint64[num_orders], orderings uint32[total picks])."""
+        off = _u32(pick_offsets)
+        n = len(off) - 1
+        total = int(off[-1]) if n > 0 else 0
+        if lengths is not None:
+            _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(dist), _ptr(lengths), _ptr(routes),
+                                         DEVICE_PTRS, _stream_of(lengths)))
+            return lengths, routes
+        d = _u32(dist)
+        ln = np.zeros(max(n, 1), dtype=np.uint64)
+        rt = np.zeros(max(total, 1), dtype=np.uint32)
+        _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(d), _ptr(ln), _ptr(rt), 0, None))
+        return ln[:max(n, 0)], rt[:total]
+
     def close(self):
         if getattr(self, "h", None):
             lib().wr_context_destroy(self.h)

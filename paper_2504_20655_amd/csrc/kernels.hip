@@ -1796,4 +1796,166 @@ uint32_t ovl_max_exits() { return OVL_XCAP; }
 uint32_t ovl_max_cross() { return OVL_PCAP; }
 uint32_t ovl_waves() { return OVL_NW; }
 
+
+// ------------------------------------------------------------ order routes
+// Optimal open route over each order's stops (Route Optimization section:
+// an ordering of the P stops with free ends, length = sum of its P-1 matrix
+// steps), by Held and Karp's programme over stop subsets, which that section
+// names as the exact alternative to enumerating orderings:
+//   h(S, i) = shortest path that starts at stop i and visits exactly S,
+//   h({i}, i) = 0,  h(S, i) = min_{j in S\{i}} D[i][j] + h(S\{i}, j).
+// One workgroup per order keeps the matrix and every state in LDS: only the
+// states with i in S exist, P * 2^(P-1) words, state (S, i) at
+// sbase(S) + |S below i| where sbase(S) = sum of |T| over T < S.  Subsets are
+// processed layer by layer (|S| = 2..P, a barrier between layers); a thread
+// takes one state at a time: a per-order table lists the subsets by size
+// (each at its layer's start plus its colex rank among subsets of that
+// size), so the thread's item index gives the subset with one lookup, i is
+// the subset's m-th member, and the minimum runs over the members of S\{i}
+// only.  Lengths accumulate in 32
+// bits with WR_INF absorbing; a finite sum that would reach WR_INF raises
+// *overflow and the call fails.  The route is read greedily by one thread:
+// the smallest first stop that reaches the optimum, then repeatedly the
+// smallest next stop whose step keeps it, which is the lexicographically
+// smallest shortest ordering.
+constexpr uint32_t RT_NMAX = 12;
+constexpr uint32_t RT_THREADS = 1024;
+
+// number of stops summed over all subsets T < S (n <= 31)
+__device__ __forceinline__ uint32_t rt_sbase(uint32_t S, uint32_t n) {
+    uint32_t t = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        t += (S >> (b + 1)) << b;
+        const uint32_t r = S & ((2u << b) - 1u);
+        t += r > (1u << b) ? r - (1u << b) : 0u;
+    }
+    return t;
+}
+
+__device__ __forceinline__ uint32_t rt_step(uint32_t h, uint32_t d, bool &ovf) {
+    if (h == INF || d == INF) return INF;
+    const uint32_t s = h + d;
+    if (s < h || s == INF) {
+        ovf = true;
+        return INF;
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, const uint32_t *__restrict__ off,
+                                                         const uint64_t *__restrict__ mbase,
+                                                         const uint32_t *__restrict__ dist,
+                                                         uint64_t *__restrict__ len_out,
+                                                         uint32_t *__restrict__ route_out,
+                                                         uint32_t *__restrict__ overflow, uint32_t nmax) {
+    HIP_DYNAMIC_SHARED(uint32_t, lds)
+    uint32_t *sBin = lds;                          // [(RT_NMAX+1)^2] binomials C(c, t)
+    uint32_t *sD = sBin + (RT_NMAX + 1) * (RT_NMAX + 1);   // [nmax * nmax]
+    uint32_t *sBase = sD + nmax * nmax;            // [2^nmax]
+    uint32_t *sOrd = sBase + (1u << nmax);         // [2^nmax] subsets by size, colex within a size
+    uint32_t *sH = sOrd + (1u << nmax);            // [nmax * 2^(nmax-1)]
+    constexpr uint32_t NB1 = RT_NMAX + 1;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t q = tid; q < NB1 * NB1; q += blockDim.x) {
+        const uint32_t c = q / NB1, t = q % NB1;
+        uint32_t v = t <= c ? 1u : 0u;   // C(c, t) by the product formula
+        for (uint32_t x = 1; x <= t && t <= c; ++x) v = v * (c - t + x) / x;
+        sBin[q] = v;
+    }
+    __syncthreads();   // the table is read by every thread from here on
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = off[o], n = off[o + 1] - a;
+        if (n == 0) {
+            if (tid == 0) len_out[o] = 0;
+            continue;
+        }
+        const uint32_t *Dg = dist + mbase[o];
+        const uint32_t nsub = 1u << n;
+        for (uint32_t q = tid; q < n * n; q += blockDim.x) sD[q] = Dg[q];
+        for (uint32_t S = tid; S < nsub; S += blockDim.x) {
+            sBase[S] = rt_sbase(S, n);
+            // subsets smaller than |S|, then S's colex rank among its size
+            const uint32_t k = __builtin_popcount(S);
+            uint32_t pos = 0;
+            for (uint32_t x = 0; x < k; ++x) pos += sBin[n * NB1 + x];
+            uint32_t t = 1;
+            for (uint32_t U = S; U != 0; U &= U - 1u, ++t) pos += sBin[__builtin_ctz(U) * NB1 + t];
+            sOrd[pos] = S;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += blockDim.x) sH[sBase[1u << i]] = 0u;
+        __syncthreads();
+        bool ovf = false;
+        uint32_t lstart = 1 + n;   // the empty set and the singletons come first
+        for (uint32_t k = 2; k <= n; ++k) {
+            const uint32_t items = sBin[n * NB1 + k] * k;
+            for (uint32_t q = tid; q < items; q += blockDim.x) {
+                const uint32_t r = q / k, m = q - r * k;
+                const uint32_t S = sOrd[lstart + r];
+                uint32_t T = S;
+                for (uint32_t x = 0; x < m; ++x) T &= T - 1u;
+                const uint32_t i = __builtin_ctz(T);
+                const uint32_t R = S & ~(1u << i);
+                const uint32_t bR = sBase[R];
+                const uint32_t *Di = sD + i * n;
+                uint32_t best = INF, rj = 0;
+                for (uint32_t U = R; U != 0; U &= U - 1u) {
+                    best = min(best, rt_step(sH[bR + rj], Di[__builtin_ctz(U)], ovf));
+                    ++rj;
+                }
+                sH[sBase[S] + m] = best;
+            }
+            lstart += sBin[n * NB1 + k];
+            __syncthreads();
+        }
+        if (ovf) atomicOr(overflow, 1u);
+        if (tid == 0) {
+            const uint32_t all = nsub - 1u, bA = sBase[all];
+            uint32_t opt = INF;
+            for (uint32_t i = 0; i < n; ++i) opt = min(opt, sH[bA + i]);
+            uint32_t cur = 0;
+            while (sH[bA + cur] != opt) ++cur;
+            uint32_t S = all;
+            route_out[a] = cur;
+            for (uint32_t k = 1; k < n; ++k) {
+                const uint32_t hS = sH[sBase[S] + __builtin_popcount(S & ((1u << cur) - 1u))];
+                const uint32_t R = S & ~(1u << cur);
+                const uint32_t bR = sBase[R];
+                uint32_t nxt = 0, rj = 0;
+                bool dummy = false;
+                for (uint32_t j = 0; j < n; ++j) {
+                    if (!((R >> j) & 1u)) continue;
+                    if (rt_step(sH[bR + rj], sD[cur * n + j], dummy) == hS) {
+                        nxt = j;
+                        break;
+                    }
+                    ++rj;
+                }
+                route_out[a + k] = nxt;
+                S = R;
+                cur = nxt;
+            }
+            len_out[o] = opt == INF ? ~0ull : static_cast<uint64_t>(opt);
+        }
+        __syncthreads();   // the next order reuses the LDS
+    }
+}
+
+uint32_t route_max_stops() { return RT_NMAX; }
+
+uint32_t route_lds_bytes(uint32_t nmax) {
+    return ((RT_NMAX + 1) * (RT_NMAX + 1) + nmax * nmax + 2u * (1u << nmax) +
+            nmax * (1u << (nmax ? nmax - 1 : 0))) * 4u;
+}
+
+void launch_route_hk(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
+                     uint64_t *len_out, uint32_t *route_out, uint32_t *overflow, uint32_t nmax, uint32_t grid,
+                     hipStream_t st) {
+    if (!num_orders) return;
+    const uint32_t n = std::max(nmax, 1u);
+    hipLaunchKernelGGL(k_route_hk, std::min(grid, num_orders), RT_THREADS, route_lds_bytes(n), st, num_orders,
+                       off, mbase, dist, len_out, route_out, overflow, n);
+    check_launch("route_hk");
+}
+
 }  // namespace wr

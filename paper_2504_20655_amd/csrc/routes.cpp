@@ -1,0 +1,82 @@
+// wr_order_routes: the optimal open route over each order's stops, from the
+// order's distance matrix (Route Optimization section; Held and Karp's
+// subset programme, run by k_route_hk with one workgroup per order).
+#include <algorithm>
+#include <vector>
+
+#include "wr_internal.hpp"
+
+using namespace wr;
+
+extern "C" wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
+                                     const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
+                                     uint32_t flags, void *stream) {
+    WR_API_BEGIN
+    if (!ctx) fail(WR_E_INVALID, "context is NULL");
+    if (flags & ~static_cast<uint32_t>(WR_DEVICE_PTRS)) fail(WR_E_INVALID, "unknown flags for wr_order_routes");
+    if (num_orders == 0) return WR_OK;
+    if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
+    if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
+    uint32_t nmax = 0;
+    uint64_t cells = 0;
+    std::vector<uint64_t> mbase(num_orders);
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        if (pick_offsets[o + 1] < pick_offsets[o]) fail(WR_E_INVALID, "pick_offsets must be non-decreasing");
+        const uint32_t P = pick_offsets[o + 1] - pick_offsets[o];
+        if (P > route_max_stops())
+            fail(WR_E_UNSUPPORTED, "order " + std::to_string(o) + " has " + std::to_string(P) +
+                                       " stops; exact routes are served for at most " +
+                                       std::to_string(route_max_stops()));
+        mbase[o] = cells;
+        cells += static_cast<uint64_t>(P) * P;
+        nmax = std::max(nmax, P);
+    }
+    const uint32_t total = pick_offsets[num_orders];
+    if (!length_out) fail(WR_E_INVALID, "length_out is NULL");
+    if (total && !route_out) fail(WR_E_INVALID, "route_out is NULL");
+    if (cells && !dist) fail(WR_E_INVALID, "dist is NULL");
+    const bool dev = flags & WR_DEVICE_PTRS;
+    WR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (dev) {
+        // caller buffers: start after the work the caller queued on `stream`
+        hipEvent_t ev;
+        WR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        WR_HIP(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
+        WR_HIP(hipStreamWaitEvent(st, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
+    std::vector<uint32_t> hoff(pick_offsets, pick_offsets + num_orders + 1);
+    DBuf<uint32_t> d_off, d_flag, d_dist, d_route;
+    DBuf<uint64_t> d_base, d_len;
+    upload(d_off, ctx, hoff, st);
+    upload(d_base, ctx, mbase, st);
+    d_flag.alloc(ctx, 1);
+    launch_fill_u32(d_flag.p, 1, 0u, st);
+    const uint32_t *ddist = dist;
+    uint64_t *dlen = length_out;
+    uint32_t *droute = route_out;
+    if (!dev) {
+        d_dist.alloc(ctx, std::max<uint64_t>(cells, 1));
+        if (cells) WR_HIP(hipMemcpyAsync(d_dist.p, dist, cells * 4, hipMemcpyHostToDevice, st));
+        d_len.alloc(ctx, num_orders);
+        d_route.alloc(ctx, std::max(total, 1u));
+        ddist = d_dist.p;
+        dlen = d_len.p;
+        droute = d_route.p;
+    }
+    // the LDS of the largest order bounds the workgroups per CU
+    const uint32_t lds = route_lds_bytes(std::max(nmax, 1u));
+    const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / lds));
+    launch_route_hk(num_orders, d_off.p, d_base.p, ddist, dlen, droute, d_flag.p, nmax,
+                    static_cast<uint32_t>(ctx->num_cus) * per_cu, st);
+    uint32_t ovf = 0;
+    WR_HIP(hipMemcpyAsync(&ovf, d_flag.p, 4, hipMemcpyDeviceToHost, st));
+    if (!dev) {
+        WR_HIP(hipMemcpyAsync(length_out, dlen, static_cast<size_t>(num_orders) * 8, hipMemcpyDeviceToHost, st));
+        if (total) WR_HIP(hipMemcpyAsync(route_out, droute, static_cast<size_t>(total) * 4, hipMemcpyDeviceToHost, st));
+    }
+    WR_HIP(hipStreamSynchronize(st));
+    if (ovf) fail(WR_E_RANGE, "a partial route length reached 2^32-1 (lengths are accumulated in 32 bits)");
+    WR_API_END
+}

@@ -406,6 +406,16 @@ uint32_t ovl_max_exits();
 uint32_t ovl_max_cross();
 uint32_t ovl_waves();   // waves (= blocks per unit) of the overlay pass
 
+// optimal open route per order (Held and Karp over stop subsets, one
+// workgroup per order): orders of at most route_max_stops() stops; the
+// matrices start at dist + mbase[o]; *overflow is raised when a partial
+// length reaches WR_INF in 32 bits
+uint32_t route_max_stops();
+uint32_t route_lds_bytes(uint32_t nmax);
+void launch_route_hk(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
+                     uint64_t *len_out, uint32_t *route_out, uint32_t *overflow, uint32_t nmax, uint32_t grid,
+                     hipStream_t st);
+
 // order gathers: out[out_base[o] + i*P + j] = d(p_i, p_j)
 void launch_gather_rows(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
                         const uint64_t *out_base, const uint32_t *row_of_pick, const uint32_t *rows,

@@ -95,6 +95,18 @@ int main(int argc, char **argv) {
         if (st == WR_OK)
             st = wr_order_matrices(g, no, off.data(), picks.data(), out.data(),
                                    want_pred ? pred.data() : nullptr, flags, nullptr);
+        if (mode == 3) {
+            // routes over the matrices just computed: lengths (two words
+            // each, low first) and orderings follow the matrices
+            std::vector<uint64_t> len(no);
+            std::vector<uint32_t> rt(off[no]);
+            if (st == WR_OK) st = wr_order_routes(ctx, no, off.data(), out.data(), len.data(), rt.data(), 0, nullptr);
+            for (uint64_t l : len) {
+                out.push_back(static_cast<uint32_t>(l));
+                out.push_back(static_cast<uint32_t>(l >> 32));
+            }
+            out.insert(out.end(), rt.begin(), rt.end());
+        }
     }
     if (st != WR_OK) std::fprintf(stderr, "status %s: %s\n", wr_status_str(st), wr_last_error());
     FILE *o = std::fopen(argv[2], "wb");

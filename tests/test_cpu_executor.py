@@ -45,3 +45,27 @@ def test_segmented_rows_and_pred_random_graph(harness):
         ed = oracle.dijkstra(rp, col, w, int(s))
         assert (d[i] == ed).all()
         assert (p[i] == oracle.canonical_pred(rp, col, w, int(s), ed)).all()
+
+
+def test_order_routes_over_executor_matrices(harness):
+    """wr_order_routes (subset programme in LDS) over the library's own
+    matrices for orders of 0..12 stops with duplicate picks: lengths and
+    orderings equal the oracle's, with every LDS and global access checked."""
+    wl = make_config("medium", side=40, num_orders=8)
+    g = wl.graph
+    rng = np.random.default_rng(3)
+    sizes = [0, 1, 2, 3, 5, 8, 12, 7, 12, 4]
+    picks = np.concatenate([rng.choice(wl.picks, s) for s in sizes]).astype(np.uint32)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    st, out, _, err = harness.run(g.row_ptr, g.col, g.w, pick_offsets=off, picks=picks, algo="overlay",
+                                  seg=("grid", g.W, g.H, 1, 12, 10), routes=True)
+    assert st == 0, err[-2000:]
+    ncell = int((np.diff(off.astype(np.int64)) ** 2).sum())
+    mats = out[:ncell]
+    words = out[ncell:ncell + 2 * len(sizes)].astype(np.uint64)
+    lens = words[0::2] | (words[1::2] << np.uint64(32))
+    rts = out[ncell + 2 * len(sizes):]
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, off, picks)
+    assert (mats == exp).all()
+    el, er = oracle.order_routes(off, exp)
+    assert (lens == el).all() and (rts == er).all()
