@@ -66,6 +66,12 @@ def lib():
         L.orc_route_held_karp.restype = i32
         L.orc_order_routes.argtypes = [u32, _u32p, _u32p, _u64p, _u32p, i32]
         L.orc_order_routes.restype = i32
+        L.orc_kmeans.argtypes = [u32, _i32p, u32, _u32p]
+        L.orc_kmeans.restype = None
+        L.orc_route_clustered.argtypes = [u32, _u32p, _i32p, u32, u32, u32, _u64p, _u32p, _u32p]
+        L.orc_route_clustered.restype = i32
+        L.orc_order_routes_clustered.argtypes = [u32, _u32p, _u32p, _i32p, u32, u32, u32, _u64p, _u32p, _u32p, i32]
+        L.orc_order_routes_clustered.restype = i32
         _lib = L
     return _lib
 
@@ -197,6 +203,49 @@ def order_routes(pick_offsets, dist, nthreads: int = 0) -> tuple[np.ndarray, np.
                                            cost, rt, nthreads) != 0:
         raise ValueError("route oracle: an order is out of range")
     return cost[:n_orders], rt[:int(off[-1]) if n_orders else 0]
+
+
+def kmeans(xy, m: int) -> np.ndarray:
+    """Cluster of every point (K-means with farthest-point initial centres,
+    exact integer comparisons; see orc_route_clustered)."""
+    P = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    asg = np.zeros(max(len(P), 1), dtype=np.uint32)
+    if len(P):
+        lib().orc_kmeans(len(P), P.reshape(-1), m, asg)
+    return asg[:len(P)]
+
+
+def route_clustered(D, xy, m: int, max_cluster: int = 12, m_max: int = 8):
+    """Cluster-decomposed route over one order (the Route Optimization
+    section's theorem): (length, ordering, clusters used)."""
+    M = np.ascontiguousarray(D, dtype=np.uint32)
+    n = M.shape[0]
+    P = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1)
+    cost = np.zeros(1, dtype=np.uint64)
+    r = np.zeros(max(n, 1), dtype=np.uint32)
+    mu = np.zeros(1, dtype=np.uint32)
+    if lib().orc_route_clustered(n, M.reshape(-1) if n else np.zeros(1, np.uint32),
+                                 P if n else np.zeros(2, np.int32), m, max_cluster, m_max, cost, r, mu) != 0:
+        raise ValueError("clustered route oracle: no cluster count keeps every cluster small")
+    return int(cost[0]), r[:n], int(mu[0])
+
+
+def order_routes_clustered(pick_offsets, dist, xy, m: int, max_cluster: int = 12, m_max: int = 8,
+                           nthreads: int = 0):
+    """route_clustered() of every order: (lengths u64, orderings u32,
+    clusters used u32 per order)."""
+    off = np.ascontiguousarray(pick_offsets, dtype=np.uint32)
+    n_orders = len(off) - 1
+    D = np.ascontiguousarray(dist, dtype=np.uint32)
+    P = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1)
+    cost = np.zeros(max(n_orders, 1), dtype=np.uint64)
+    rt = np.zeros(max(int(off[-1]) if n_orders else 0, 1), dtype=np.uint32)
+    mu = np.zeros(max(n_orders, 1), dtype=np.uint32)
+    if n_orders and lib().orc_order_routes_clustered(n_orders, off, D if D.size else np.zeros(1, np.uint32),
+                                                     P if P.size else np.zeros(2, np.int32), m, max_cluster,
+                                                     m_max, cost, rt, mu, nthreads) != 0:
+        raise ValueError("clustered route oracle: an order cannot be split into small clusters")
+    return cost[:n_orders], rt[:int(off[-1]) if n_orders else 0], mu[:n_orders]
 
 
 def max_threads() -> int:

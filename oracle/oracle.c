@@ -461,3 +461,239 @@ int orc_order_routes(uint32_t num_orders, const uint32_t *pick_off, const uint32
     free(base);
     return bad ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Cluster-decomposed route (Route Optimization section, the theorem on
+ * m clusters): the order's stops are split into m clusters by K-means on
+ * their positions (clusters of an order, routes-and-clusters subsection;
+ * a cluster's centre is the mean position of its picks, so a stop picked
+ * twice weighs twice), an optimal open route is found inside every cluster,
+ * and the global route is the cheapest way to chain the cluster routes:
+ * every order of the clusters and every orientation of each cluster's
+ * route, adding the steps between consecutive clusters' ends.
+ *
+ * Readings where the section is silent (the product library follows the
+ * same ones):
+ *  - positions are integer (x, y) pairs; squared Euclidean distances to a
+ *    centre sum/c are compared exactly as |c*p - sum|^2 scaled by the other
+ *    cluster's c^2 (64-bit integers);
+ *  - initial centres by farthest-point selection: the first pick, then
+ *    repeatedly the pick farthest (squared distance) from every chosen
+ *    centre, ties to the smaller index; Lloyd iterations assign each pick
+ *    to its nearest centre (ties to the smaller cluster index) and move
+ *    every non-empty cluster's centre to its mean, until no assignment
+ *    changes or 100 iterations;
+ *  - a cluster's route is the optimal directed open route of orc_route_
+ *    held_karp over its picks in increasing index order; a reversed cluster
+ *    route costs its reversed steps;
+ *  - chaining: non-empty clusters are ordered by cluster index; every
+ *    permutation of them (lexicographic order) and every orientation mask
+ *    (bit c set = cluster c reversed, ascending) is tried; the first
+ *    strictly cheaper candidate wins;
+ *  - if K-means leaves a cluster with more than max_cluster picks, m grows
+ *    by one and the clustering restarts (up to m_max).
+ * Lengths are exact 64-bit sums with ORC_ROUTE_INF absorbing.             */
+static int64_t km_cmp(int64_t px, int64_t py, int64_t sxa, int64_t sya, int64_t ca, int64_t sxb, int64_t syb,
+                      int64_t cb)
+{
+    /* sign of |p - s_a/c_a|^2 - |p - s_b/c_b|^2 */
+    const int64_t dxa = ca * px - sxa, dya = ca * py - sya;
+    const int64_t dxb = cb * px - sxb, dyb = cb * py - syb;
+    const __int128 a = (__int128)(dxa * dxa + dya * dya) * (cb * cb);
+    const __int128 b = (__int128)(dxb * dxb + dyb * dyb) * (ca * ca);
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* K-means of n points into m clusters; asg[i] = cluster of point i */
+void orc_kmeans(uint32_t n, const int32_t *xy, uint32_t m, uint32_t *asg)
+{
+    int64_t sx[16], sy[16], cnt[16];
+    uint32_t cen[16];
+    uint32_t nc = 0;
+    /* farthest-point initial centres (point indices) */
+    cen[nc++] = 0;
+    while (nc < m && nc < n) {
+        int64_t best = -1;
+        uint32_t bi = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            int64_t dmin = INT64_MAX;
+            for (uint32_t c = 0; c < nc; ++c) {
+                const int64_t dx = (int64_t)xy[2 * i] - xy[2 * cen[c]], dy = (int64_t)xy[2 * i + 1] - xy[2 * cen[c] + 1];
+                const int64_t d = dx * dx + dy * dy;
+                if (d < dmin) dmin = d;
+            }
+            if (dmin > best) {
+                best = dmin;
+                bi = i;
+            }
+        }
+        cen[nc++] = bi;
+    }
+    for (uint32_t c = 0; c < nc; ++c) {
+        sx[c] = xy[2 * cen[c]];
+        sy[c] = xy[2 * cen[c] + 1];
+        cnt[c] = 1;
+    }
+    for (uint32_t i = 0; i < n; ++i) asg[i] = 0xFFFFFFFFu;
+    for (int it = 0; it < 100; ++it) {
+        int changed = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            uint32_t b = 0;
+            for (uint32_t c = 1; c < nc; ++c)
+                if (km_cmp(xy[2 * i], xy[2 * i + 1], sx[c], sy[c], cnt[c], sx[b], sy[b], cnt[b]) < 0) b = c;
+            if (asg[i] != b) {
+                asg[i] = b;
+                changed = 1;
+            }
+        }
+        if (!changed) break;
+        int64_t nsx[16] = {0}, nsy[16] = {0}, ncnt[16] = {0};
+        for (uint32_t i = 0; i < n; ++i) {
+            nsx[asg[i]] += xy[2 * i];
+            nsy[asg[i]] += xy[2 * i + 1];
+            ncnt[asg[i]] += 1;
+        }
+        for (uint32_t c = 0; c < nc; ++c)
+            if (ncnt[c]) {
+                sx[c] = nsx[c];
+                sy[c] = nsy[c];
+                cnt[c] = ncnt[c];
+            }
+    }
+}
+
+static uint64_t route_len(const uint32_t *D, uint32_t n, const uint32_t *r, uint32_t k, int reversed)
+{
+    uint64_t s = 0;
+    for (uint32_t t = 0; t + 1 < k; ++t) {
+        const uint32_t a = reversed ? r[k - 1 - t] : r[t], b = reversed ? r[k - 2 - t] : r[t + 1];
+        s = route_add(s, D[(size_t)a * n + b]);
+    }
+    return s;
+}
+
+/* n <= 64 stops, positions xy[2n]; m clusters requested (1..8), clusters
+ * of at most max_cluster (<= 20) stops, m grown up to m_max (<= 8).  Writes
+ * the global route (indices 0..n-1) and its length; *m_used = clusters
+ * used.  Returns 0, or -1 when no m <= m_max keeps every cluster small. */
+int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32_t m, uint32_t max_cluster,
+                        uint32_t m_max, uint64_t *cost, uint32_t *route, uint32_t *m_used)
+{
+    if (n == 0) {
+        *cost = 0;
+        *m_used = 0;
+        return 0;
+    }
+    if (n > 64 || m == 0 || m_max > 8 || max_cluster > 20) return -1;
+    uint32_t asg[64];
+    uint32_t mm = m;
+    for (;; ++mm) {
+        if (mm > m_max) return -1;
+        orc_kmeans(n, xy, mm, asg);
+        uint32_t sz[16] = {0};
+        for (uint32_t i = 0; i < n; ++i) sz[asg[i]]++;
+        int ok = 1;
+        for (uint32_t c = 0; c < mm; ++c)
+            if (sz[c] > max_cluster) ok = 0;
+        if (ok) break;
+    }
+    /* per non-empty cluster: its picks in index order and their route */
+    uint32_t members[8][64], csz[8], croute[8][64], ncl = 0;
+    uint64_t flen[8], rlen[8];
+    for (uint32_t c = 0; c < mm; ++c) {
+        uint32_t k = 0;
+        for (uint32_t i = 0; i < n; ++i)
+            if (asg[i] == c) members[ncl][k++] = i;
+        if (!k) continue;
+        uint32_t *sub = (uint32_t *)malloc((size_t)k * k * sizeof(uint32_t));
+        if (!sub) return -1;
+        for (uint32_t a = 0; a < k; ++a)
+            for (uint32_t b = 0; b < k; ++b) sub[a * k + b] = D[(size_t)members[ncl][a] * n + members[ncl][b]];
+        uint64_t cl;
+        uint32_t lr[64];
+        const int rc = orc_route_held_karp(k, sub, &cl, lr);
+        free(sub);
+        if (rc) return -1;
+        for (uint32_t t = 0; t < k; ++t) croute[ncl][t] = members[ncl][lr[t]];
+        csz[ncl] = k;
+        flen[ncl] = route_len(D, n, croute[ncl], k, 0);
+        rlen[ncl] = route_len(D, n, croute[ncl], k, 1);
+        ++ncl;
+    }
+    /* chain the clusters: permutations in lexicographic order, then masks */
+    uint32_t perm[8];
+    for (uint32_t c = 0; c < ncl; ++c) perm[c] = c;
+    uint64_t best = ORC_ROUTE_INF;
+    uint32_t best_perm[8], best_mask = 0;
+    int have = 0;
+    for (;;) {
+        for (uint32_t mask = 0; mask < (1u << ncl); ++mask) {
+            uint64_t s = 0;
+            for (uint32_t q = 0; q < ncl; ++q) {
+                const uint32_t c = perm[q], rev = (mask >> c) & 1u;
+                s = (s == ORC_ROUTE_INF) ? s : (rev ? (rlen[c] == ORC_ROUTE_INF ? ORC_ROUTE_INF : s + rlen[c])
+                                                    : (flen[c] == ORC_ROUTE_INF ? ORC_ROUTE_INF : s + flen[c]));
+                if (q + 1 < ncl) {
+                    const uint32_t c2 = perm[q + 1], rev2 = (mask >> c2) & 1u;
+                    const uint32_t end = rev ? croute[c][0] : croute[c][csz[c] - 1];
+                    const uint32_t beg = rev2 ? croute[c2][csz[c2] - 1] : croute[c2][0];
+                    s = route_add(s, D[(size_t)end * n + beg]);
+                }
+            }
+            if (!have || s < best) {
+                have = 1;
+                best = s;
+                best_mask = mask;
+                for (uint32_t q = 0; q < ncl; ++q) best_perm[q] = perm[q];
+            }
+        }
+        /* next permutation (lexicographic) */
+        int i = (int)ncl - 2;
+        while (i >= 0 && perm[i] >= perm[i + 1]) --i;
+        if (i < 0) break;
+        int j = (int)ncl - 1;
+        while (perm[j] <= perm[i]) --j;
+        uint32_t t = perm[i];
+        perm[i] = perm[j];
+        perm[j] = t;
+        for (int a = i + 1, b = (int)ncl - 1; a < b; ++a, --b) {
+            t = perm[a];
+            perm[a] = perm[b];
+            perm[b] = t;
+        }
+    }
+    uint32_t w = 0;
+    for (uint32_t q = 0; q < ncl; ++q) {
+        const uint32_t c = best_perm[q], rev = (best_mask >> c) & 1u;
+        for (uint32_t t = 0; t < csz[c]; ++t) route[w++] = rev ? croute[c][csz[c] - 1 - t] : croute[c][t];
+    }
+    *cost = best;
+    *m_used = mm;
+    return 0;
+}
+
+int orc_order_routes_clustered(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *D, const int32_t *xy,
+                               uint32_t m, uint32_t max_cluster, uint32_t m_max, uint64_t *cost, uint32_t *route,
+                               uint32_t *m_used, int nthreads)
+{
+    uint64_t *base = (uint64_t *)malloc(((size_t)num_orders + 1) * sizeof(uint64_t));
+    if (!base) return -1;
+    base[0] = 0;
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        const uint64_t P = pick_off[o + 1] - pick_off[o];
+        base[o + 1] = base[o] + P * P;
+    }
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+#endif
+    for (int64_t o = 0; o < (int64_t)num_orders; ++o) {
+        const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        if (orc_route_clustered(P, D + base[o], xy + 2 * (size_t)a, m, max_cluster, m_max, cost + o, route + a,
+                                m_used + o) != 0)
+            bad |= 1;
+    }
+    free(base);
+    return bad ? -1 : 0;
+}

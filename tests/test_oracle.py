@@ -381,3 +381,142 @@ def test_order_routes_batches_orders():
     for o, m in enumerate(mats):
         c, r = oracle.route(m)
         assert cost[o] == c and rt[off[o]:off[o + 1]].tolist() == r.tolist()
+
+
+# ------------------------------------------------- cluster-decomposed routes
+def test_theorem_counts_match_paper():
+    """The candidates the clustered route compares -- every order of the
+    cluster routes times every orientation -- number m!2^m directed, i.e.
+    m!2^(m-1) undirected global routes (the theorem), and with (n_j!)/2
+    undirected routes inside each cluster the totals are the printed ones."""
+    import itertools
+    import math
+    vals = {}
+    for l in open(_golden("paper_numbers.txt")):
+        l = l.split("#")[0].split()
+        if l:
+            vals[l[0]] = int(float(l[1]))
+
+    def undirected(seqs):
+        return {min(s, s[::-1]) for s in seqs}
+
+    for key, n, m in (("thm_n12_m2", 12, 2), ("thm_n12_m3", 12, 3), ("thm_n12_m4", 12, 4), ("thm_n15_m3", 15, 3)):
+        k = n // m
+        routes = [tuple(range(c * k, (c + 1) * k)) for c in range(m)]
+        glob = set()
+        for perm in itertools.permutations(range(m)):
+            for mask in range(1 << m):
+                seq = ()
+                for c in perm:
+                    seq += routes[c][::-1] if (mask >> c) & 1 else routes[c]
+                glob.add(seq)
+        assert len(glob) == math.factorial(m) * 2 ** m
+        n_glob = len(undirected(glob))
+        assert n_glob == math.factorial(m) * 2 ** (m - 1)
+        # undirected routes inside a cluster of k stops, by enumeration for
+        # small k (k! / 2 for k >= 2)
+        inner = len(undirected(itertools.permutations(range(k)))) if k <= 7 else math.factorial(k) // 2
+        assert n_glob + m * inner == vals[key], key
+
+
+def _blob_points(rng, n, m, spread=3, gap=100):
+    lab = np.arange(n) % m
+    cen = np.array([[gap * c, gap * (c % 2)] for c in range(m)])
+    return cen[lab] + rng.integers(-spread, spread + 1, (n, 2)), lab
+
+
+def test_kmeans_pins():
+    from fractions import Fraction
+    rng = np.random.default_rng(31)
+    # well-separated blobs: the partition is the blobs (up to label order)
+    for m in (2, 3, 4):
+        xy, lab = _blob_points(rng, 24, m)
+        asg = oracle.kmeans(xy, m)
+        pairs = {(int(a), int(b)) for a, b in zip(asg, lab)}
+        assert len(pairs) == m and len({a for a, _ in pairs}) == m
+    # at the end every point sits with its nearest centre (exact rationals),
+    # centres being the means of their points: a fixed point of Lloyd's step
+    for seed in range(20):
+        r = np.random.default_rng(seed)
+        n, m = int(r.integers(2, 30)), int(r.integers(1, 6))
+        xy = r.integers(0, 40, (n, 2))
+        asg = oracle.kmeans(xy, m)
+        cents = {}
+        for c in set(asg.tolist()):
+            pts = xy[asg == c]
+            cents[c] = (Fraction(int(pts[:, 0].sum()), len(pts)), Fraction(int(pts[:, 1].sum()), len(pts)))
+        for i in range(n):
+            d = {c: (xy[i, 0] - cx) ** 2 + (xy[i, 1] - cy) ** 2 for c, (cx, cy) in cents.items()}
+            assert d[int(asg[i])] == min(d.values())
+    # as many clusters as distinct points: every point is its own cluster
+    xy = rng.choice(400, 9, replace=False)
+    xy = np.stack([xy % 20, xy // 20], 1)
+    assert sorted(oracle.kmeans(xy, 9).tolist()) == list(range(9))
+
+
+def _metric(xy):
+    return np.abs(xy[:, None, :] - xy[None, :, :]).sum(-1).astype(np.uint32)
+
+
+def test_clustered_route_stitching_by_enumeration():
+    """Given the clusters and each cluster's route, the chained route is the
+    cheapest of all orderings that keep every cluster's stops together in its
+    route's order or the reverse (brute force over all orderings)."""
+    import itertools
+    rng = np.random.default_rng(32)
+    for case in range(16):
+        n = int(rng.integers(3, 8))
+        m = int(rng.integers(2, 4))
+        xy = rng.integers(0, 30, (n, 2))
+        D = _metric(xy) if case % 2 == 0 else rng.integers(1, 40, (n, n)).astype(np.uint32)
+        np.fill_diagonal(D, 0)
+        cost, route, mu = oracle.route_clustered(D, xy, m)
+        asg = oracle.kmeans(xy, mu)
+        blocks = []
+        for c in sorted(set(asg.tolist())):
+            mem = np.flatnonzero(asg == c)
+            _, r = oracle.route(D[np.ix_(mem, mem)])
+            blocks.append(tuple(mem[r].tolist()))
+        best = None
+        for perm in itertools.permutations(range(n)):
+            pos = 0
+            ok = True
+            seen = set()
+            while pos < n:
+                b = next((b for b in blocks if perm[pos] in b), None)
+                seg = perm[pos:pos + len(b)]
+                if b in seen or (seg != b and seg != b[::-1]):
+                    ok = False
+                    break
+                seen.add(b)
+                pos += len(b)
+            if not ok:
+                continue
+            length = sum(int(D[a, b]) for a, b in zip(perm, perm[1:]))
+            best = length if best is None else min(best, length)
+        assert cost == best, (case, cost, best)
+        assert sum(int(D[a, b]) for a, b in zip(route, route[1:])) == cost
+        assert sorted(route.tolist()) == list(range(n))
+
+
+def test_clustered_route_limits():
+    rng = np.random.default_rng(33)
+    for case in range(12):
+        n = int(rng.integers(2, 9))
+        xy = np.stack([rng.choice(50, n, replace=False), rng.integers(0, 50, n)], 1)
+        D = _metric(xy)
+        exact, er = oracle.route(D)
+        # one cluster: the exact route
+        c1, r1, _ = oracle.route_clustered(D, xy, 1)
+        assert c1 == exact and r1.tolist() == er.tolist()
+        # one stop per cluster: every ordering is a candidate, so exact too
+        cn, _, mu = oracle.route_clustered(D, xy, n, max_cluster=20, m_max=8) if n <= 8 else (exact, None, n)
+        assert cn == exact
+        # any m: never shorter than the exact route
+        for m in (2, 3):
+            assert oracle.route_clustered(D, xy, m)[0] >= exact
+    # a cluster above the size limit raises the cluster count
+    xy, _ = _blob_points(rng, 30, 2, spread=4)
+    D = _metric(xy)
+    _, _, mu = oracle.route_clustered(D, xy, 2, max_cluster=12)
+    assert mu > 2
