@@ -486,10 +486,11 @@ int orc_order_routes(uint32_t num_orders, const uint32_t *pick_off, const uint32
  *  - a cluster's route is the optimal directed open route of orc_route_
  *    held_karp over its picks in increasing index order; a reversed cluster
  *    route costs its reversed steps;
- *  - chaining: non-empty clusters are ordered by cluster index; every
- *    permutation of them (lexicographic order) and every orientation mask
- *    (bit c set = cluster c reversed, ascending) is tried; the first
- *    strictly cheaper candidate wins;
+ *  - chaining: non-empty clusters are numbered in cluster index order; the
+ *    cheapest chain over every order and orientation of their routes is
+ *    found by a subset programme, and among the cheapest the
+ *    lexicographically smallest sequence of (cluster, orientation) is
+ *    returned (forward before reversed);
  *  - if K-means leaves a cluster with more than max_cluster picks, m grows
  *    by one and the clustering restarts (up to m_max).
  * Lengths are exact 64-bit sums with ORC_ROUTE_INF absorbing.             */
@@ -572,8 +573,8 @@ static uint64_t route_len(const uint32_t *D, uint32_t n, const uint32_t *r, uint
     return s;
 }
 
-/* n <= 64 stops, positions xy[2n]; m clusters requested (1..8), clusters
- * of at most max_cluster (<= 20) stops, m grown up to m_max (<= 8).  Writes
+/* n <= 64 stops, positions xy[2n]; m clusters requested (1..16), clusters
+ * of at most max_cluster (<= 20) stops, m grown up to m_max (<= 16).  Writes
  * the global route (indices 0..n-1) and its length; *m_used = clusters
  * used.  Returns 0, or -1 when no m <= m_max keeps every cluster small. */
 int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32_t m, uint32_t max_cluster,
@@ -584,7 +585,7 @@ int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32
         *m_used = 0;
         return 0;
     }
-    if (n > 64 || m == 0 || m_max > 8 || max_cluster > 20) return -1;
+    if (n > 64 || m == 0 || m_max > 16 || max_cluster > 20) return -1;
     uint32_t asg[64];
     uint32_t mm = m;
     for (;; ++mm) {
@@ -598,8 +599,8 @@ int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32
         if (ok) break;
     }
     /* per non-empty cluster: its picks in index order and their route */
-    uint32_t members[8][64], csz[8], croute[8][64], ncl = 0;
-    uint64_t flen[8], rlen[8];
+    uint32_t members[16][64], csz[16], croute[16][64], ncl = 0;
+    uint64_t flen[16], rlen[16];
     for (uint32_t c = 0; c < mm; ++c) {
         uint32_t k = 0;
         for (uint32_t i = 0; i < n; ++i)
@@ -620,53 +621,88 @@ int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32
         rlen[ncl] = route_len(D, n, croute[ncl], k, 1);
         ++ncl;
     }
-    /* chain the clusters: permutations in lexicographic order, then masks */
-    uint32_t perm[8];
-    for (uint32_t c = 0; c < ncl; ++c) perm[c] = c;
-    uint64_t best = ORC_ROUTE_INF;
-    uint32_t best_perm[8], best_mask = 0;
-    int have = 0;
-    for (;;) {
-        for (uint32_t mask = 0; mask < (1u << ncl); ++mask) {
-            uint64_t s = 0;
-            for (uint32_t q = 0; q < ncl; ++q) {
-                const uint32_t c = perm[q], rev = (mask >> c) & 1u;
-                s = (s == ORC_ROUTE_INF) ? s : (rev ? (rlen[c] == ORC_ROUTE_INF ? ORC_ROUTE_INF : s + rlen[c])
-                                                    : (flen[c] == ORC_ROUTE_INF ? ORC_ROUTE_INF : s + flen[c]));
-                if (q + 1 < ncl) {
-                    const uint32_t c2 = perm[q + 1], rev2 = (mask >> c2) & 1u;
-                    const uint32_t end = rev ? croute[c][0] : croute[c][csz[c] - 1];
-                    const uint32_t beg = rev2 ? croute[c2][csz[c2] - 1] : croute[c2][0];
-                    s = route_add(s, D[(size_t)end * n + beg]);
+    /* chain the clusters.  A piece is a cluster route in one orientation
+     * (o = 0 forward, 1 reversed); g(S, c, o) is the cheapest chain that
+     * starts with piece (c, o) and uses exactly the clusters of S:
+     * g({c}, c, o) = len(c, o), g(S, c, o) = len(c, o) + min over c' in
+     * S\{c}, o' of D[end(c, o)][start(c', o')] + g(S\{c}, c', o').  This is
+     * the minimum over every order and orientation of the cluster routes;
+     * the chain read back greedily is the lexicographically smallest
+     * sequence of (cluster, orientation) among the cheapest. */
+    const uint32_t K = ncl, nsK = 1u << K;
+    uint64_t *gtab = (uint64_t *)malloc((size_t)nsK * K * 2 * sizeof(uint64_t));
+    if (!gtab) return -1;
+#define G(S_, c_, o_) gtab[((size_t)(S_) * K + (c_)) * 2 + (o_)]
+    uint32_t pstart[16][2], pend[16][2];
+    uint64_t plen[16][2];
+    for (uint32_t c = 0; c < K; ++c) {
+        pstart[c][0] = croute[c][0];
+        pend[c][0] = croute[c][csz[c] - 1];
+        pstart[c][1] = pend[c][0];
+        pend[c][1] = pstart[c][0];
+        plen[c][0] = flen[c];
+        plen[c][1] = rlen[c];
+    }
+    for (uint32_t S = 1; S < nsK; ++S)
+        for (uint32_t c = 0; c < K; ++c) {
+            if (!(S & (1u << c))) continue;
+            const uint32_t R = S & ~(1u << c);
+            for (uint32_t o = 0; o < 2; ++o) {
+                uint64_t inner = R ? ORC_ROUTE_INF : 0;
+                for (uint32_t c2 = 0; c2 < K; ++c2) {
+                    if (!(R & (1u << c2))) continue;
+                    for (uint32_t o2 = 0; o2 < 2; ++o2) {
+                        const uint64_t v = route_add(G(R, c2, o2), D[(size_t)pend[c][o] * n + pstart[c2][o2]]);
+                        if (v < inner) inner = v;
+                    }
                 }
-            }
-            if (!have || s < best) {
-                have = 1;
-                best = s;
-                best_mask = mask;
-                for (uint32_t q = 0; q < ncl; ++q) best_perm[q] = perm[q];
+                G(S, c, o) = (inner == ORC_ROUTE_INF || plen[c][o] == ORC_ROUTE_INF) ? ORC_ROUTE_INF
+                                                                                      : inner + plen[c][o];
             }
         }
-        /* next permutation (lexicographic) */
-        int i = (int)ncl - 2;
-        while (i >= 0 && perm[i] >= perm[i + 1]) --i;
-        if (i < 0) break;
-        int j = (int)ncl - 1;
-        while (perm[j] <= perm[i]) --j;
-        uint32_t t = perm[i];
-        perm[i] = perm[j];
-        perm[j] = t;
-        for (int a = i + 1, b = (int)ncl - 1; a < b; ++a, --b) {
-            t = perm[a];
-            perm[a] = perm[b];
-            perm[b] = t;
+    uint64_t best = ORC_ROUTE_INF;
+    for (uint32_t c = 0; c < K; ++c)
+        for (uint32_t o = 0; o < 2; ++o)
+            if (G(nsK - 1, c, o) < best) best = G(nsK - 1, c, o);
+    uint32_t cc = 0, oo = 0;
+    while (G(nsK - 1, cc, oo) != best) {
+        if (++oo == 2) {
+            oo = 0;
+            ++cc;
         }
     }
-    uint32_t w = 0;
-    for (uint32_t q = 0; q < ncl; ++q) {
-        const uint32_t c = best_perm[q], rev = (best_mask >> c) & 1u;
-        for (uint32_t t = 0; t < csz[c]; ++t) route[w++] = rev ? croute[c][csz[c] - 1 - t] : croute[c][t];
+    uint32_t S = nsK - 1, w = 0;
+    for (;;) {
+        for (uint32_t t = 0; t < csz[cc]; ++t) route[w++] = oo ? croute[cc][csz[cc] - 1 - t] : croute[cc][t];
+        const uint32_t R = S & ~(1u << cc);
+        if (!R) break;
+        uint64_t inner = ORC_ROUTE_INF;
+        for (uint32_t c2 = 0; c2 < K; ++c2)
+            if (R & (1u << c2))
+                for (uint32_t o2 = 0; o2 < 2; ++o2) {
+                    const uint64_t v = route_add(G(R, c2, o2), D[(size_t)pend[cc][oo] * n + pstart[c2][o2]]);
+                    if (v < inner) inner = v;
+                }
+        uint32_t nc2 = 0, no2 = 0;
+        for (uint32_t c2 = 0; c2 < K; ++c2) {
+            if (!(R & (1u << c2))) continue;
+            if (route_add(G(R, c2, 0), D[(size_t)pend[cc][oo] * n + pstart[c2][0]]) == inner) {
+                nc2 = c2;
+                no2 = 0;
+                break;
+            }
+            if (route_add(G(R, c2, 1), D[(size_t)pend[cc][oo] * n + pstart[c2][1]]) == inner) {
+                nc2 = c2;
+                no2 = 1;
+                break;
+            }
+        }
+        S = R;
+        cc = nc2;
+        oo = no2;
     }
+#undef G
+    free(gtab);
     *cost = best;
     *m_used = mm;
     return 0;

@@ -497,6 +497,18 @@ def test_clustered_route_stitching_by_enumeration():
         assert cost == best, (case, cost, best)
         assert sum(int(D[a, b]) for a, b in zip(route, route[1:])) == cost
         assert sorted(route.tolist()) == list(range(n))
+        # among the cheapest chains, the smallest (cluster, orientation) sequence
+        chains = []
+        for perm in itertools.permutations(range(len(blocks))):
+            for ori in itertools.product((0, 1), repeat=len(blocks)):
+                seq = []
+                for c, o in zip(perm, ori):
+                    seq += list(blocks[c][::-1] if o else blocks[c])
+                length = sum(int(D[a, b]) for a, b in zip(seq, seq[1:]))
+                chains.append((length, list(zip(perm, ori)), seq))
+        low = min(c[0] for c in chains)
+        first = min((c for c in chains if c[0] == low), key=lambda c: c[1])
+        assert route.tolist() == first[2], case
 
 
 def test_clustered_route_limits():
