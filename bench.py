@@ -17,7 +17,9 @@ Prints ONE JSON line:
                on a bounded sample of the same orders
   route_leg    the next step on the path: exact open routes (wr_order_routes)
                over 12-stop windows of the batch's own matrices, routes/s,
-               with its ALU roofline and the CPU oracle beside it
+               with its ALU roofline and the CPU oracle beside it; and
+               cluster-decomposed routes (wr_order_routes_clustered) over
+               the whole 32-pick orders
 """
 from __future__ import annotations
 
@@ -212,6 +214,40 @@ def route_leg(wr, ctx, D_host, n_orders, P, stops, steps, warmup, with_cpu):
     return res
 
 
+def cluster_leg(wr, ctx, D_host, off, picks, W, m, steps, warmup, with_cpu):
+    """Cluster-decomposed routes (wr_order_routes_clustered) over every
+    order of the batch at full size, positions from the grid: routes/s with
+    matrices and positions resident in HBM, and the CPU oracle beside it."""
+    import torch
+    xy = np.stack([picks % W, picks // W], 1).astype(np.int32)
+    n_orders = len(off) - 1
+    dev = torch.device("cuda:0")
+    d_dist = torch.from_numpy(D_host.view(np.int32).copy()).to(dev)
+    d_xy = torch.from_numpy(xy.copy()).to(dev)
+    d_len = torch.zeros(n_orders, dtype=torch.int64, device=dev)
+    d_rt = torch.zeros(int(off[-1]), dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        _, _, used = ctx.order_routes_clustered(off, d_dist, d_xy, m, d_len, d_rt)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        _, _, used = ctx.order_routes_clustered(off, d_dist, d_xy, m, d_len, d_rt)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    res = {"workload": f"{n_orders} orders of {int(off[1] - off[0])} picks, {m} clusters requested "
+                       f"(used: {np.bincount(used).tolist()} orders by cluster count)",
+           "value": round(n_orders / dt, 1), "unit": "routes/s", "ms_per_call": round(dt * 1e3, 4)}
+    if with_cpu:
+        import oracle
+        t = time.perf_counter()
+        oracle.order_routes_clustered(off, D_host, xy, m, m_max=10, nthreads=oracle.max_threads())
+        tc = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": round(n_orders / tc, 1), "unit": "routes/s",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"all {n_orders} orders, {tc:.2f} s wall"}
+    return res
+
+
 def cpu_baseline(wl, target_core_s: float):
     import oracle
     g = wl.graph
@@ -369,6 +405,8 @@ def main():
             D_host = out.cpu().numpy().view(np.uint32)[:n_orders * P0 * P0]
             res["route_leg"] = route_leg(wr, ctx, D_host, n_orders, P0, args.route_stops, args.steps,
                                          args.warmup, not args.no_cpu_baseline)
+            res["route_leg"]["clustered"] = cluster_leg(wr, ctx, D_host, off, picks, g.W, 3, args.steps,
+                                                        args.warmup, not args.no_cpu_baseline)
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
         res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds, args.tile or 512)

@@ -232,6 +232,45 @@ wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const uint32_t *
                           const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
                           uint32_t flags, void *stream);
 
+/* Cluster-decomposed route over each order's stops (the theorem of the
+ * Route Optimization section): the stops are split into m clusters by
+ * K-means on their positions (a cluster's centre is the mean position of
+ * its picks, routes-and-clusters subsection), the optimal open route is
+ * found inside each cluster (as in wr_order_routes), and the global route is
+ * the cheapest chaining of the cluster routes over every order of the
+ * clusters and every orientation of each, adding the steps between
+ * consecutive clusters' ends.  Not optimal in general, never shorter than
+ * wr_order_routes' result, and served for orders too large for it.
+ * Readings where the section is silent: farthest-point initial centres
+ * from the first pick (ties to the smaller index); Lloyd steps until no
+ * assignment changes, at most 100 (ties to the smaller cluster, an empty
+ * cluster keeps its centre); distances to centres compared exactly in
+ * integers; m grows by one while a cluster has more than
+ * WR_ROUTE_MAX_STOPS picks; the cheapest chain is found by a subset
+ * programme over (clusters used, first cluster, its orientation), and among
+ * the cheapest the lexicographically smallest sequence of (cluster,
+ * orientation) is returned, forward before reversed.
+ *
+ * pick_offsets, dist, length_out, route_out: as for wr_order_routes, with
+ *               P_o <= WR_CLUSTER_MAX_STOPS.
+ * pick_xy:      int32[2 * pick_offsets[num_orders]]: (x, y) of each pick,
+ *               |x|, |y| < 2^16 (host, or device with WR_DEVICE_PTRS).
+ * m:            clusters requested, 1 <= m <= WR_CLUSTER_MAX_CLUSTERS.
+ * clusters_out: uint32[num_orders] (host, whatever the flags) or NULL:
+ *               clusters each order used.
+ * Errors: WR_E_INVALID (NULL, bad offsets, m out of range, unknown flags),
+ * WR_E_UNSUPPORTED (an order above WR_CLUSTER_MAX_STOPS stops, or one that
+ * no m <= WR_CLUSTER_MAX_CLUSTERS splits into small enough clusters),
+ * WR_E_RANGE (a position out of range, or a length reaching 2^32-1 inside
+ * a cluster), WR_E_NOMEM, WR_E_DEVICE; outputs are unspecified after an
+ * error found on the device. */
+#define WR_CLUSTER_MAX_STOPS 64u
+#define WR_CLUSTER_MAX_CLUSTERS 10u
+wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
+                                    const uint32_t *dist, const int32_t *pick_xy, uint32_t m,
+                                    uint64_t *length_out, uint32_t *route_out, uint32_t *clusters_out,
+                                    uint32_t flags, void *stream);
+
 /* Statistics of the last wr_sssp / wr_order_matrices call on this graph. */
 typedef struct wr_run_info {
     uint32_t algo;             /* WR_ALGO_* value that ran                      */

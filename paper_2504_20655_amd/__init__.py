@@ -98,6 +98,29 @@ class Context:
         _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(d), _ptr(ln), _ptr(rt), 0, None))
         return ln[:max(n, 0)], rt[:total]
 
+    def order_routes_clustered(self, pick_offsets, dist, pick_xy, m: int, lengths=None, routes=None):
+        """Cluster-decomposed route over each order's stops
+        (wr_order_routes_clustered): pick_xy holds (x, y) per pick.  Returns
+        (lengths uint64, orderings uint32, clusters used uint32 per order);
+        with device tensors for dist/pick_xy/lengths/routes the call writes
+        those in place."""
+        off = _u32(pick_offsets)
+        n = len(off) - 1
+        total = int(off[-1]) if n > 0 else 0
+        used = np.zeros(max(n, 1), dtype=np.uint32)
+        if lengths is not None:
+            _check(lib().wr_order_routes_clustered(self.h, n, _ptr(off), _ptr(dist), _ptr(pick_xy), m,
+                                                   _ptr(lengths), _ptr(routes), _ptr(used), DEVICE_PTRS,
+                                                   _stream_of(lengths)))
+            return lengths, routes, used[:n]
+        d = _u32(dist)
+        xy = np.ascontiguousarray(pick_xy, dtype=np.int32).reshape(-1)
+        ln = np.zeros(max(n, 1), dtype=np.uint64)
+        rt = np.zeros(max(total, 1), dtype=np.uint32)
+        _check(lib().wr_order_routes_clustered(self.h, n, _ptr(off), _ptr(d), _ptr(xy), m, _ptr(ln), _ptr(rt),
+                                               _ptr(used), 0, None))
+        return ln[:n], rt[:total], used[:n]
+
     def close(self):
         if getattr(self, "h", None):
             lib().wr_context_destroy(self.h)

@@ -1842,6 +1842,117 @@ __device__ __forceinline__ uint32_t rt_step(uint32_t h, uint32_t d, bool &ovf) {
     return s;
 }
 
+// LDS layout of one subset programme: binomials, the matrix, subset offsets,
+// subsets by size and the states (nmax = largest n the launch serves)
+struct RtLds {
+    uint32_t *bin, *D, *base, *ord, *H;
+};
+constexpr uint32_t RT_BIN_WORDS = ((RT_NMAX + 1) * (RT_NMAX + 1) + 1) & ~1u;   // even: later arrays stay 8-aligned
+__device__ __forceinline__ RtLds rt_layout(uint32_t *lds, uint32_t nmax) {
+    RtLds L;
+    L.bin = lds;                                     // [(RT_NMAX+1)^2] C(c, t)
+    L.D = L.bin + RT_BIN_WORDS;                      // [nmax * nmax]
+    L.base = L.D + nmax * nmax;                      // [2^nmax]
+    L.ord = L.base + (1u << nmax);                   // [2^nmax] subsets by size, colex within a size
+    L.H = L.ord + (1u << nmax);                      // [nmax * 2^(nmax-1)]
+    return L;
+}
+__host__ __device__ constexpr uint32_t rt_lds_words(uint32_t nmax) {
+    return RT_BIN_WORDS + nmax * nmax + 2u * (1u << nmax) + nmax * (1u << (nmax ? nmax - 1 : 0));
+}
+
+// binomial table; the caller synchronises before its first use
+__device__ void rt_binomials(uint32_t *bin) {
+    constexpr uint32_t NB1 = RT_NMAX + 1;
+    for (uint32_t q = threadIdx.x; q < NB1 * NB1; q += blockDim.x) {
+        const uint32_t c = q / NB1, t = q % NB1;
+        uint32_t v = t <= c ? 1u : 0u;   // C(c, t) by the product formula
+        for (uint32_t x = 1; x <= t && t <= c; ++x) v = v * (c - t + x) / x;
+        bin[q] = v;
+    }
+}
+
+// Subset offsets and subsets by size for n elements (1 <= n <= RT_NMAX), by
+// the whole workgroup; ends synchronised.
+__device__ void rt_tables(const RtLds &L, uint32_t n) {
+    constexpr uint32_t NB1 = RT_NMAX + 1;
+    const uint32_t nsub = 1u << n;
+    for (uint32_t S = threadIdx.x; S < nsub; S += blockDim.x) {
+        L.base[S] = rt_sbase(S, n);
+        // subsets smaller than |S|, then S's colex rank among its size
+        const uint32_t k = __builtin_popcount(S);
+        uint32_t pos = 0;
+        for (uint32_t x = 0; x < k; ++x) pos += L.bin[n * NB1 + x];
+        uint32_t t = 1;
+        for (uint32_t U = S; U != 0; U &= U - 1u, ++t) pos += L.bin[__builtin_ctz(U) * NB1 + t];
+        L.ord[pos] = S;
+    }
+    __syncthreads();
+}
+
+// The states h(S, i) of the n x n matrix already in L.D (1 <= n <= RT_NMAX),
+// by the whole workgroup; ends synchronised.
+__device__ void rt_solve(const RtLds &L, uint32_t n, bool &ovf) {
+    constexpr uint32_t NB1 = RT_NMAX + 1;
+    const uint32_t tid = threadIdx.x;
+    rt_tables(L, n);
+    for (uint32_t i = tid; i < n; i += blockDim.x) L.H[L.base[1u << i]] = 0u;
+    __syncthreads();
+    uint32_t lstart = 1 + n;   // the empty set and the singletons come first
+    for (uint32_t k = 2; k <= n; ++k) {
+        const uint32_t items = L.bin[n * NB1 + k] * k;
+        for (uint32_t q = tid; q < items; q += blockDim.x) {
+            const uint32_t r = q / k, m = q - r * k;
+            const uint32_t S = L.ord[lstart + r];
+            uint32_t T = S;
+            for (uint32_t x = 0; x < m; ++x) T &= T - 1u;
+            const uint32_t i = __builtin_ctz(T);
+            const uint32_t R = S & ~(1u << i);
+            const uint32_t bR = L.base[R];
+            const uint32_t *Di = L.D + i * n;
+            uint32_t best = INF, rj = 0;
+            for (uint32_t U = R; U != 0; U &= U - 1u) {
+                best = min(best, rt_step(L.H[bR + rj], Di[__builtin_ctz(U)], ovf));
+                ++rj;
+            }
+            L.H[L.base[S] + m] = best;
+        }
+        lstart += L.bin[n * NB1 + k];
+        __syncthreads();
+    }
+}
+
+// One thread: the lexicographically smallest shortest ordering into route[],
+// returning its length (INF when none is finite).
+__device__ uint32_t rt_read_route(const RtLds &L, uint32_t n, uint32_t *route) {
+    const uint32_t all = (1u << n) - 1u, bA = L.base[all];
+    uint32_t opt = INF;
+    for (uint32_t i = 0; i < n; ++i) opt = min(opt, L.H[bA + i]);
+    uint32_t cur = 0;
+    while (L.H[bA + cur] != opt) ++cur;
+    uint32_t S = all;
+    route[0] = cur;
+    for (uint32_t k = 1; k < n; ++k) {
+        const uint32_t hS = L.H[L.base[S] + __builtin_popcount(S & ((1u << cur) - 1u))];
+        const uint32_t R = S & ~(1u << cur);
+        const uint32_t bR = L.base[R];
+        uint32_t nxt = 0, rj = 0;
+        bool dummy = false;
+        for (uint32_t j = 0; j < n; ++j) {
+            if (!((R >> j) & 1u)) continue;
+            if (rt_step(L.H[bR + rj], L.D[cur * n + j], dummy) == hS) {
+                nxt = j;
+                break;
+            }
+            ++rj;
+        }
+        route[k] = nxt;
+        S = R;
+        cur = nxt;
+    }
+    return opt;
+}
+
 __global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, const uint32_t *__restrict__ off,
                                                          const uint64_t *__restrict__ mbase,
                                                          const uint32_t *__restrict__ dist,
@@ -1849,19 +1960,9 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, co
                                                          uint32_t *__restrict__ route_out,
                                                          uint32_t *__restrict__ overflow, uint32_t nmax) {
     HIP_DYNAMIC_SHARED(uint32_t, lds)
-    uint32_t *sBin = lds;                          // [(RT_NMAX+1)^2] binomials C(c, t)
-    uint32_t *sD = sBin + (RT_NMAX + 1) * (RT_NMAX + 1);   // [nmax * nmax]
-    uint32_t *sBase = sD + nmax * nmax;            // [2^nmax]
-    uint32_t *sOrd = sBase + (1u << nmax);         // [2^nmax] subsets by size, colex within a size
-    uint32_t *sH = sOrd + (1u << nmax);            // [nmax * 2^(nmax-1)]
-    constexpr uint32_t NB1 = RT_NMAX + 1;
+    const RtLds L = rt_layout(lds, nmax);
     const uint32_t tid = threadIdx.x;
-    for (uint32_t q = tid; q < NB1 * NB1; q += blockDim.x) {
-        const uint32_t c = q / NB1, t = q % NB1;
-        uint32_t v = t <= c ? 1u : 0u;   // C(c, t) by the product formula
-        for (uint32_t x = 1; x <= t && t <= c; ++x) v = v * (c - t + x) / x;
-        sBin[q] = v;
-    }
+    rt_binomials(L.bin);
     __syncthreads();   // the table is read by every thread from here on
     for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
         const uint32_t a = off[o], n = off[o + 1] - a;
@@ -1870,72 +1971,317 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, co
             continue;
         }
         const uint32_t *Dg = dist + mbase[o];
-        const uint32_t nsub = 1u << n;
-        for (uint32_t q = tid; q < n * n; q += blockDim.x) sD[q] = Dg[q];
-        for (uint32_t S = tid; S < nsub; S += blockDim.x) {
-            sBase[S] = rt_sbase(S, n);
-            // subsets smaller than |S|, then S's colex rank among its size
-            const uint32_t k = __builtin_popcount(S);
-            uint32_t pos = 0;
-            for (uint32_t x = 0; x < k; ++x) pos += sBin[n * NB1 + x];
-            uint32_t t = 1;
-            for (uint32_t U = S; U != 0; U &= U - 1u, ++t) pos += sBin[__builtin_ctz(U) * NB1 + t];
-            sOrd[pos] = S;
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < n; i += blockDim.x) sH[sBase[1u << i]] = 0u;
+        for (uint32_t q = tid; q < n * n; q += blockDim.x) L.D[q] = Dg[q];
         __syncthreads();
         bool ovf = false;
-        uint32_t lstart = 1 + n;   // the empty set and the singletons come first
-        for (uint32_t k = 2; k <= n; ++k) {
-            const uint32_t items = sBin[n * NB1 + k] * k;
-            for (uint32_t q = tid; q < items; q += blockDim.x) {
-                const uint32_t r = q / k, m = q - r * k;
-                const uint32_t S = sOrd[lstart + r];
-                uint32_t T = S;
-                for (uint32_t x = 0; x < m; ++x) T &= T - 1u;
-                const uint32_t i = __builtin_ctz(T);
-                const uint32_t R = S & ~(1u << i);
-                const uint32_t bR = sBase[R];
-                const uint32_t *Di = sD + i * n;
-                uint32_t best = INF, rj = 0;
-                for (uint32_t U = R; U != 0; U &= U - 1u) {
-                    best = min(best, rt_step(sH[bR + rj], Di[__builtin_ctz(U)], ovf));
-                    ++rj;
-                }
-                sH[sBase[S] + m] = best;
-            }
-            lstart += sBin[n * NB1 + k];
-            __syncthreads();
-        }
+        rt_solve(L, n, ovf);
         if (ovf) atomicOr(overflow, 1u);
         if (tid == 0) {
-            const uint32_t all = nsub - 1u, bA = sBase[all];
-            uint32_t opt = INF;
-            for (uint32_t i = 0; i < n; ++i) opt = min(opt, sH[bA + i]);
-            uint32_t cur = 0;
-            while (sH[bA + cur] != opt) ++cur;
-            uint32_t S = all;
-            route_out[a] = cur;
-            for (uint32_t k = 1; k < n; ++k) {
-                const uint32_t hS = sH[sBase[S] + __builtin_popcount(S & ((1u << cur) - 1u))];
-                const uint32_t R = S & ~(1u << cur);
-                const uint32_t bR = sBase[R];
-                uint32_t nxt = 0, rj = 0;
-                bool dummy = false;
-                for (uint32_t j = 0; j < n; ++j) {
-                    if (!((R >> j) & 1u)) continue;
-                    if (rt_step(sH[bR + rj], sD[cur * n + j], dummy) == hS) {
-                        nxt = j;
+            const uint32_t opt = rt_read_route(L, n, route_out + a);
+            len_out[o] = opt == INF ? ~0ull : static_cast<uint64_t>(opt);
+        }
+        __syncthreads();   // the next order reuses the LDS
+    }
+}
+
+// ------------------------------------------------- cluster-decomposed route
+// The route of the Route Optimization section's theorem: the order's stops
+// are clustered by K-means on their positions (a cluster's centre is the
+// mean position of its picks), each cluster gets its optimal open route,
+// and the global route is the cheapest chaining of the cluster routes over
+// every order of the clusters and every orientation of each.  Readings
+// where the section is silent (shared with the oracle): integer positions,
+// squared distances to a centre sum/c compared exactly as
+// |c p - sum|^2 times the other cluster's c^2 (64-bit: |x|, |y| < 2^16,
+// n <= 64); farthest-point initial centres from the first pick, ties to the
+// smaller index; Lloyd steps until no assignment changes (at most 100),
+// ties to the smaller cluster, an empty cluster keeping its centre; m grows
+// by one while some cluster has more than RT_NMAX picks; among the cheapest
+// chains the lexicographically smallest sequence of (cluster, orientation)
+// wins, forward before reversed.
+//
+// One workgroup per order: wave 0 runs K-means with a lane per pick, the
+// whole workgroup runs each cluster's subset programme, then a second
+// subset programme over the K non-empty clusters chains them:
+// g(S, c, o) = the cheapest chain that starts with cluster c in
+// orientation o and uses exactly the clusters of S, g({c}, c, o) = len(c, o),
+// g(S, c, o) = len(c, o) + min over c' in S\{c}, o' of
+// D[end(c, o)][start(c', o')] + g(S\{c}, c', o') -- the minimum over every
+// order and orientation, in 2 K 2^(K-1) states that reuse the LDS of the
+// per-cluster states.
+constexpr uint32_t RC_NMAX = 64;   // stops per order
+constexpr uint32_t RC_MMAX = 10;   // clusters: 2 * 10 * 2^9 chain states fit the state area
+constexpr uint32_t RC_ERR_RANGE = 1u, RC_ERR_CLUSTER = 2u;
+
+// value of v held by lane src of the wave (two 32-bit shuffles)
+__device__ __forceinline__ int64_t rc_shfl64(int64_t v, uint32_t src) {
+    const uint32_t lo = __shfl(static_cast<uint32_t>(static_cast<uint64_t>(v)), static_cast<int>(src), 64);
+    const uint32_t hi = __shfl(static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32), static_cast<int>(src), 64);
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ int rc_cmp(int64_t px, int64_t py, int64_t sxa, int64_t sya, int64_t ca, int64_t sxb,
+                                      int64_t syb, int64_t cb) {
+    const int64_t dxa = ca * px - sxa, dya = ca * py - sya;
+    const int64_t dxb = cb * px - sxb, dyb = cb * py - syb;
+    const int64_t a = (dxa * dxa + dya * dya) * (cb * cb);
+    const int64_t b = (dxb * dxb + dyb * dyb) * (ca * ca);
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+__global__ __launch_bounds__(RT_THREADS) void k_route_clustered(
+    uint32_t num_orders, const uint32_t *__restrict__ off, const uint64_t *__restrict__ mbase,
+    const uint32_t *__restrict__ dist, const int32_t *__restrict__ xy, uint32_t m0,
+    uint64_t *__restrict__ len_out, uint32_t *__restrict__ route_out, uint32_t *__restrict__ m_out,
+    uint32_t *__restrict__ err) {
+    HIP_DYNAMIC_SHARED(uint32_t, lds)
+    const RtLds L = rt_layout(lds, RT_NMAX);
+    uint32_t *sF = L.H + RT_NMAX * (1u << (RT_NMAX - 1));   // [RC_NMAX^2] the order's matrix
+    int32_t *sXY = reinterpret_cast<int32_t *>(sF + RC_NMAX * RC_NMAX);   // [2 RC_NMAX]
+    uint32_t *sAsg = reinterpret_cast<uint32_t *>(sXY + 2 * RC_NMAX);     // [RC_NMAX] cluster of each pick
+    uint32_t *sRoute = sAsg + RC_NMAX;          // [RC_NMAX] cluster routes, concatenated (pick indices)
+    uint32_t *sCl = sRoute + RC_NMAX;           // [RC_MMAX][4]: start in sRoute, size, forward, reverse length
+    uint32_t *sMisc = sCl + 4 * RC_MMAX;        // [4]: clusters used, non-empty clusters, flags
+    int64_t *sCen = reinterpret_cast<int64_t *>(sMisc + 4);   // [3 RC_MMAX]: sum x, sum y, count (8-aligned)
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wv = threadIdx.x >> 6;
+    rt_binomials(L.bin);
+    __syncthreads();
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = off[o], n = off[o + 1] - a;
+        if (n == 0) {
+            if (tid == 0) {
+                len_out[o] = 0;
+                m_out[o] = 0;
+            }
+            continue;
+        }
+        const uint32_t *Dg = dist + mbase[o];
+        for (uint32_t q = tid; q < n * n; q += blockDim.x) sF[q] = Dg[q];
+        for (uint32_t q = tid; q < 2 * n; q += blockDim.x) sXY[q] = xy[2 * static_cast<size_t>(a) + q];
+        __syncthreads();
+        // ---- K-means (wave 0, lane = pick), growing m while a cluster is too big
+        if (wv == 0) {
+            const bool on = lane < n;
+            const int64_t px = on ? sXY[2 * lane] : 0, py = on ? sXY[2 * lane + 1] : 0;
+            bool bad = on && (px <= -65536 || px >= 65536 || py <= -65536 || py >= 65536);
+            if (__builtin_amdgcn_ballot_w64(bad) != 0) {
+                if (lane == 0) {
+                    atomicOr(err, RC_ERR_RANGE);
+                    sMisc[1] = 0xFFFFFFFFu;
+                }
+            } else {
+                uint32_t mm = m0, used = 0xFFFFFFFFu;
+                for (; mm <= RC_MMAX; ++mm) {
+                    // farthest-point initial centres
+                    int64_t dmin = INT64_MAX;
+                    uint32_t nc = 0, cen = 0;
+                    for (;;) {
+                        const int64_t cx = sXY[2 * cen], cy = sXY[2 * cen + 1];
+                        if (lane == 0) {
+                            sCen[3 * nc] = cx;
+                            sCen[3 * nc + 1] = cy;
+                            sCen[3 * nc + 2] = 1;
+                        }
+                        ++nc;
+                        if (nc >= mm || nc >= n) break;
+                        const int64_t dx = px - cx, dy = py - cy;
+                        const int64_t d = dx * dx + dy * dy;
+                        if (on && d < dmin) dmin = d;
+                        // the pick farthest from every centre, ties to the smaller index
+                        int64_t best = on ? dmin : -1;
+                        uint32_t bi = lane;
+                        for (uint32_t sh = 1; sh < 64; sh <<= 1) {
+                            const int64_t ob = rc_shfl64(best, lane ^ sh);
+                            const uint32_t oi = __shfl(bi, static_cast<int>(lane ^ sh), 64);
+                            if (ob > best || (ob == best && oi < bi)) {
+                                best = ob;
+                                bi = oi;
+                            }
+                        }
+                        cen = bi;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t asg = 0xFFFFFFFFu;
+                    for (int it = 0; it < 100; ++it) {
+                        uint32_t b = 0;
+                        for (uint32_t c = 1; c < nc; ++c)
+                            if (rc_cmp(px, py, sCen[3 * c], sCen[3 * c + 1], sCen[3 * c + 2], sCen[3 * b],
+                                       sCen[3 * b + 1], sCen[3 * b + 2]) < 0)
+                                b = c;
+                        const bool ch = on && asg != b;
+                        if (on) asg = b;
+                        if (__builtin_amdgcn_ballot_w64(ch) == 0) break;
+                        if (on) sAsg[lane] = asg;
+                        __builtin_amdgcn_wave_barrier();
+                        // lane c < nc sums its cluster's picks
+                        if (lane < nc) {
+                            int64_t sx = 0, sy = 0, cn = 0;
+                            for (uint32_t i = 0; i < n; ++i)
+                                if (sAsg[i] == lane) {
+                                    sx += sXY[2 * i];
+                                    sy += sXY[2 * i + 1];
+                                    ++cn;
+                                }
+                            if (cn) {
+                                sCen[3 * lane] = sx;
+                                sCen[3 * lane + 1] = sy;
+                                sCen[3 * lane + 2] = cn;
+                            }
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                    if (on) sAsg[lane] = asg;
+                    __builtin_amdgcn_wave_barrier();
+                    // cluster sizes
+                    uint32_t big = 0;
+                    for (uint32_t c = 0; c < nc; ++c) {
+                        const uint32_t sz = static_cast<uint32_t>(
+                            __builtin_popcountll(__builtin_amdgcn_ballot_w64(on && asg == c)));
+                        if (sz > RT_NMAX) big = 1;
+                    }
+                    if (!big) {
+                        used = mm;
                         break;
                     }
-                    ++rj;
                 }
-                route_out[a + k] = nxt;
-                S = R;
-                cur = nxt;
+                if (lane == 0) {
+                    if (used == 0xFFFFFFFFu) atomicOr(err, RC_ERR_CLUSTER);
+                    sMisc[0] = used;
+                    sMisc[1] = used == 0xFFFFFFFFu ? 0xFFFFFFFFu : 0u;
+                }
             }
-            len_out[o] = opt == INF ? ~0ull : static_cast<uint64_t>(opt);
+        }
+        __syncthreads();
+        if (sMisc[1] == 0xFFFFFFFFu) {   // this order cannot be served; the call fails
+            if (tid == 0) {
+                len_out[o] = ~0ull;
+                m_out[o] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        // ---- each non-empty cluster: its picks in index order, their route
+        const uint32_t mm = sMisc[0];
+        uint32_t ncl = 0, pos = 0;
+        bool ovf = false;
+        for (uint32_t c = 0; c < mm; ++c) {
+            uint32_t k = 0;
+            for (uint32_t i = 0; i < n; ++i) k += sAsg[i] == c;   // uniform: every thread counts
+            if (k == 0) continue;
+            if (tid == 0) {
+                uint32_t w = 0;
+                for (uint32_t i = 0; i < n; ++i)
+                    if (sAsg[i] == c) sRoute[pos + w++] = i;   // members, index order
+            }
+            __syncthreads();
+            for (uint32_t q = tid; q < k * k; q += blockDim.x)
+                L.D[q] = sF[sRoute[pos + q / k] * n + sRoute[pos + q % k]];
+            __syncthreads();
+            rt_solve(L, k, ovf);
+            if (tid == 0) {
+                uint32_t loc[RT_NMAX], mem[RT_NMAX];
+                rt_read_route(L, k, loc);
+                for (uint32_t t = 0; t < k; ++t) mem[t] = sRoute[pos + t];
+                for (uint32_t t = 0; t < k; ++t) sRoute[pos + t] = mem[loc[t]];
+                uint32_t fl = 0, rl = 0;
+                bool dummy = false;
+                for (uint32_t t = 0; t + 1 < k; ++t) {
+                    fl = rt_step(fl, sF[sRoute[pos + t] * n + sRoute[pos + t + 1]], ovf);
+                    rl = rt_step(rl, sF[sRoute[pos + t + 1] * n + sRoute[pos + t]], ovf);
+                }
+                (void)dummy;
+                sCl[4 * ncl] = pos;
+                sCl[4 * ncl + 1] = k;
+                sCl[4 * ncl + 2] = fl;
+                sCl[4 * ncl + 3] = rl;
+            }
+            __syncthreads();
+            ++ncl;
+            pos += k;
+        }
+        // ---- chaining: subset programme over the ncl clusters (pieces (c, o))
+        rt_tables(L, ncl);
+        uint32_t *G = L.H;   // state (S, c, o) at (base[S] + rank of c in S) * 2 + o
+        {
+            constexpr uint32_t NB1 = RT_NMAX + 1;
+            for (uint32_t q = tid; q < 2 * ncl; q += blockDim.x) {
+                const uint32_t c = q >> 1, o = q & 1u;
+                G[L.base[1u << c] * 2 + o] = sCl[4 * c + 2 + o];
+            }
+            __syncthreads();
+            uint32_t lstart = 1 + ncl;
+            for (uint32_t k = 2; k <= ncl; ++k) {
+                const uint32_t items = L.bin[ncl * NB1 + k] * k;
+                for (uint32_t q = tid; q < items; q += blockDim.x) {
+                    const uint32_t r = q / k, mi = q - r * k;
+                    const uint32_t S = L.ord[lstart + r];
+                    uint32_t T = S;
+                    for (uint32_t x = 0; x < mi; ++x) T &= T - 1u;
+                    const uint32_t c = __builtin_ctz(T);
+                    const uint32_t R = S & ~(1u << c);
+                    const uint32_t bR = L.base[R];
+                    for (uint32_t o = 0; o < 2; ++o) {
+                        const uint32_t p0 = sCl[4 * c], k0 = sCl[4 * c + 1];
+                        const uint32_t end = o ? sRoute[p0] : sRoute[p0 + k0 - 1];
+                        uint32_t inner = INF, rj = 0;
+                        for (uint32_t U = R; U != 0; U &= U - 1u, ++rj) {
+                            const uint32_t c2 = __builtin_ctz(U);
+                            const uint32_t p2 = sCl[4 * c2], k2 = sCl[4 * c2 + 1];
+                            inner = min(inner, rt_step(G[(bR + rj) * 2], sF[end * n + sRoute[p2]], ovf));
+                            inner = min(inner, rt_step(G[(bR + rj) * 2 + 1], sF[end * n + sRoute[p2 + k2 - 1]], ovf));
+                        }
+                        G[(L.base[S] + mi) * 2 + o] = rt_step(inner, sCl[4 * c + 2 + o], ovf);
+                    }
+                }
+                lstart += L.bin[ncl * NB1 + k];
+                __syncthreads();
+            }
+        }
+        if (ovf) atomicOr(err, RC_ERR_RANGE);
+        if (tid == 0) {
+            // the cheapest first piece, then greedily the smallest next piece
+            const uint32_t all = (1u << ncl) - 1u, bA = L.base[all];
+            uint32_t best = INF;
+            for (uint32_t x = 0; x < 2 * ncl; ++x) best = min(best, G[bA * 2 + x]);
+            uint32_t x = 0;
+            while (G[bA * 2 + x] != best) ++x;
+            uint32_t cc = x >> 1, oo = x & 1u, S = all, w = 0;
+            bool dummy = false;
+            for (;;) {
+                const uint32_t p0 = sCl[4 * cc], k0 = sCl[4 * cc + 1];
+                for (uint32_t t = 0; t < k0; ++t) route_out[a + w++] = oo ? sRoute[p0 + k0 - 1 - t] : sRoute[p0 + t];
+                const uint32_t R = S & ~(1u << cc);
+                if (!R) break;
+                const uint32_t bR = L.base[R], end = oo ? sRoute[p0] : sRoute[p0 + k0 - 1];
+                uint32_t inner = INF, rj = 0;
+                for (uint32_t U = R; U != 0; U &= U - 1u, ++rj) {
+                    const uint32_t c2 = __builtin_ctz(U);
+                    const uint32_t p2 = sCl[4 * c2], k2 = sCl[4 * c2 + 1];
+                    inner = min(inner, rt_step(G[(bR + rj) * 2], sF[end * n + sRoute[p2]], dummy));
+                    inner = min(inner, rt_step(G[(bR + rj) * 2 + 1], sF[end * n + sRoute[p2 + k2 - 1]], dummy));
+                }
+                uint32_t nc = 0, no = 0;
+                rj = 0;
+                for (uint32_t U = R; U != 0; U &= U - 1u, ++rj) {
+                    const uint32_t c2 = __builtin_ctz(U);
+                    const uint32_t p2 = sCl[4 * c2], k2 = sCl[4 * c2 + 1];
+                    if (rt_step(G[(bR + rj) * 2], sF[end * n + sRoute[p2]], dummy) == inner) {
+                        nc = c2;
+                        no = 0;
+                        break;
+                    }
+                    if (rt_step(G[(bR + rj) * 2 + 1], sF[end * n + sRoute[p2 + k2 - 1]], dummy) == inner) {
+                        nc = c2;
+                        no = 1;
+                        break;
+                    }
+                }
+                S = R;
+                cc = nc;
+                oo = no;
+            }
+            len_out[o] = best == INF ? ~0ull : static_cast<uint64_t>(best);
+            m_out[o] = mm;
         }
         __syncthreads();   // the next order reuses the LDS
     }
@@ -1943,9 +2289,22 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, co
 
 uint32_t route_max_stops() { return RT_NMAX; }
 
-uint32_t route_lds_bytes(uint32_t nmax) {
-    return ((RT_NMAX + 1) * (RT_NMAX + 1) + nmax * nmax + 2u * (1u << nmax) +
-            nmax * (1u << (nmax ? nmax - 1 : 0))) * 4u;
+uint32_t route_lds_bytes(uint32_t nmax) { return rt_lds_words(nmax) * 4u; }
+
+uint32_t route_clustered_lds_bytes() {
+    return (rt_lds_words(RT_NMAX) + RC_NMAX * RC_NMAX + 2 * RC_NMAX + 2 * RC_NMAX + 4 * RC_MMAX + 4 +
+            2 * 3 * RC_MMAX) * 4u;
+}
+uint32_t route_clustered_max_stops() { return RC_NMAX; }
+uint32_t route_clustered_max_clusters() { return RC_MMAX; }
+
+void launch_route_clustered(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
+                            const int32_t *xy, uint32_t m, uint64_t *len_out, uint32_t *route_out, uint32_t *m_out,
+                            uint32_t *err, uint32_t grid, hipStream_t st) {
+    if (!num_orders) return;
+    hipLaunchKernelGGL(k_route_clustered, std::min(grid, num_orders), RT_THREADS, route_clustered_lds_bytes(), st,
+                       num_orders, off, mbase, dist, xy, m, len_out, route_out, m_out, err);
+    check_launch("route_clustered");
 }
 
 void launch_route_hk(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,

@@ -80,3 +80,90 @@ extern "C" wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const
     if (ovf) fail(WR_E_RANGE, "a partial route length reached 2^32-1 (lengths are accumulated in 32 bits)");
     WR_API_END
 }
+
+extern "C" wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
+                                               const uint32_t *dist, const int32_t *pick_xy, uint32_t m,
+                                               uint64_t *length_out, uint32_t *route_out, uint32_t *clusters_out,
+                                               uint32_t flags, void *stream) {
+    WR_API_BEGIN
+    if (!ctx) fail(WR_E_INVALID, "context is NULL");
+    if (flags & ~static_cast<uint32_t>(WR_DEVICE_PTRS))
+        fail(WR_E_INVALID, "unknown flags for wr_order_routes_clustered");
+    if (m < 1 || m > route_clustered_max_clusters())
+        fail(WR_E_INVALID, "m must be between 1 and " + std::to_string(route_clustered_max_clusters()));
+    if (num_orders == 0) return WR_OK;
+    if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
+    if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
+    uint64_t cells = 0;
+    std::vector<uint64_t> mbase(num_orders);
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        if (pick_offsets[o + 1] < pick_offsets[o]) fail(WR_E_INVALID, "pick_offsets must be non-decreasing");
+        const uint32_t P = pick_offsets[o + 1] - pick_offsets[o];
+        if (P > route_clustered_max_stops())
+            fail(WR_E_UNSUPPORTED, "order " + std::to_string(o) + " has " + std::to_string(P) +
+                                       " stops; clustered routes are served for at most " +
+                                       std::to_string(route_clustered_max_stops()));
+        mbase[o] = cells;
+        cells += static_cast<uint64_t>(P) * P;
+    }
+    const uint32_t total = pick_offsets[num_orders];
+    if (!length_out) fail(WR_E_INVALID, "length_out is NULL");
+    if (total && (!route_out || !pick_xy)) fail(WR_E_INVALID, "route_out or pick_xy is NULL");
+    if (cells && !dist) fail(WR_E_INVALID, "dist is NULL");
+    const bool dev = flags & WR_DEVICE_PTRS;
+    if (!dev)
+        for (uint64_t q = 0; q < 2ull * total; ++q)
+            if (pick_xy[q] <= -65536 || pick_xy[q] >= 65536) fail(WR_E_RANGE, "pick positions must be below 2^16");
+    WR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (dev) {
+        hipEvent_t ev;
+        WR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        WR_HIP(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
+        WR_HIP(hipStreamWaitEvent(st, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
+    std::vector<uint32_t> hoff(pick_offsets, pick_offsets + num_orders + 1);
+    DBuf<uint32_t> d_off, d_err, d_dist, d_route, d_m;
+    DBuf<uint64_t> d_base, d_len;
+    DBuf<int32_t> d_xy;
+    upload(d_off, ctx, hoff, st);
+    upload(d_base, ctx, mbase, st);
+    d_err.alloc(ctx, 1);
+    launch_fill_u32(d_err.p, 1, 0u, st);
+    d_m.alloc(ctx, num_orders);
+    const uint32_t *ddist = dist;
+    const int32_t *dxy = pick_xy;
+    uint64_t *dlen = length_out;
+    uint32_t *droute = route_out;
+    if (!dev) {
+        d_dist.alloc(ctx, std::max<uint64_t>(cells, 1));
+        if (cells) WR_HIP(hipMemcpyAsync(d_dist.p, dist, cells * 4, hipMemcpyHostToDevice, st));
+        d_xy.alloc(ctx, std::max(2u * total, 2u));
+        if (total) WR_HIP(hipMemcpyAsync(d_xy.p, pick_xy, 8ull * total, hipMemcpyHostToDevice, st));
+        d_len.alloc(ctx, num_orders);
+        d_route.alloc(ctx, std::max(total, 1u));
+        ddist = d_dist.p;
+        dxy = d_xy.p;
+        dlen = d_len.p;
+        droute = d_route.p;
+    }
+    launch_route_clustered(num_orders, d_off.p, d_base.p, ddist, dxy, m, dlen, droute, d_m.p, d_err.p,
+                           static_cast<uint32_t>(ctx->num_cus), st);
+    uint32_t err = 0;
+    WR_HIP(hipMemcpyAsync(&err, d_err.p, 4, hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> hm(num_orders);
+    WR_HIP(hipMemcpyAsync(hm.data(), d_m.p, 4ull * num_orders, hipMemcpyDeviceToHost, st));
+    if (!dev) {
+        WR_HIP(hipMemcpyAsync(length_out, dlen, static_cast<size_t>(num_orders) * 8, hipMemcpyDeviceToHost, st));
+        if (total) WR_HIP(hipMemcpyAsync(route_out, droute, static_cast<size_t>(total) * 4, hipMemcpyDeviceToHost, st));
+    }
+    WR_HIP(hipStreamSynchronize(st));
+    if (err & 1u) fail(WR_E_RANGE, "a pick position is out of range or a cluster route length reached 2^32-1");
+    if (err & 2u)
+        fail(WR_E_UNSUPPORTED, "an order cannot be split into clusters of at most " +
+                                   std::to_string(route_max_stops()) + " stops with at most " +
+                                   std::to_string(route_clustered_max_clusters()) + " clusters");
+    if (clusters_out) std::copy(hm.begin(), hm.end(), clusters_out);
+    WR_API_END
+}

@@ -416,6 +416,16 @@ void launch_route_hk(uint32_t num_orders, const uint32_t *off, const uint64_t *m
                      uint64_t *len_out, uint32_t *route_out, uint32_t *overflow, uint32_t nmax, uint32_t grid,
                      hipStream_t st);
 
+// cluster-decomposed route per order (K-means on integer positions, each
+// cluster's subset programme, the cheapest chaining); *err gets
+// route_clustered_err_range() / _err_cluster() bits
+uint32_t route_clustered_max_stops();
+uint32_t route_clustered_max_clusters();
+uint32_t route_clustered_lds_bytes();
+void launch_route_clustered(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
+                            const int32_t *xy, uint32_t m, uint64_t *len_out, uint32_t *route_out, uint32_t *m_out,
+                            uint32_t *err, uint32_t grid, hipStream_t st);
+
 // order gathers: out[out_base[o] + i*P + j] = d(p_i, p_j)
 void launch_gather_rows(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
                         const uint64_t *out_base, const uint32_t *row_of_pick, const uint32_t *rows,

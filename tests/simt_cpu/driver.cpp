@@ -88,6 +88,9 @@ int main(int argc, char **argv) {
         const uint32_t no = rd();
         auto off = rdv(no + 1);
         auto picks = rdv(off[no]);
+        // mode 4: cluster count and pick positions follow the picks
+        const uint32_t m = mode == 4 ? rd() : 0;
+        auto xyu = mode == 4 ? rdv(2 * off[no]) : std::vector<uint32_t>();
         size_t total = 0;
         for (uint32_t o = 0; o < no; ++o) total += static_cast<size_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
         out.assign(total, 0);
@@ -95,6 +98,22 @@ int main(int argc, char **argv) {
         if (st == WR_OK)
             st = wr_order_matrices(g, no, off.data(), picks.data(), out.data(),
                                    want_pred ? pred.data() : nullptr, flags, nullptr);
+        if (mode == 4) {
+            // clustered routes over the matrices just computed: lengths (two
+            // words each), orderings, clusters used
+            std::vector<uint64_t> len(no);
+            std::vector<uint32_t> rt(off[no]), used(no);
+            std::vector<int32_t> xy(xyu.begin(), xyu.end());
+            if (st == WR_OK)
+                st = wr_order_routes_clustered(ctx, no, off.data(), out.data(), xy.data(), m, len.data(), rt.data(),
+                                               used.data(), 0, nullptr);
+            for (uint64_t l : len) {
+                out.push_back(static_cast<uint32_t>(l));
+                out.push_back(static_cast<uint32_t>(l >> 32));
+            }
+            out.insert(out.end(), rt.begin(), rt.end());
+            out.insert(out.end(), used.begin(), used.end());
+        }
         if (mode == 3) {
             // routes over the matrices just computed: lengths (two words
             // each, low first) and orderings follow the matrices

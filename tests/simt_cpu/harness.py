@@ -23,16 +23,18 @@ def driver(rebuild=False) -> str:
 
 def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="auto",
         pred=False, graph_capture=True, seg=None, schedule=(0, 0, 0), updates=None, timeout=600,
-        server_gap_ms=None, routes=False):
+        server_gap_ms=None, routes=False, clustered=None):
     """seg: None | ("grid", W, H, L, tw, th) | ("map", nseg, map).  With
     server_gap_ms the orders go through the request server, one every
     server_gap_ms milliseconds.  With routes=True the order matrices are
     followed by wr_order_routes over them: per order its length (two words,
-    low first), then the orderings.  Returns (status, out, pred_or_None,
-    stderr)."""
+    low first), then the orderings; clustered=(m, positions) does the same
+    with wr_order_routes_clustered and appends the clusters used.  Returns
+    (status, out, pred_or_None, stderr)."""
     V = len(row_ptr) - 1
     E = len(col)
-    mode = 0 if sources is not None else (2 if server_gap_ms is not None else (3 if routes else 1))
+    mode = 0 if sources is not None else (2 if server_gap_ms is not None else
+                                          (4 if clustered is not None else (3 if routes else 1)))
     flags = server_gap_ms if mode == 2 else ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
     parts = [np.asarray([0x57524F55, mode, flags, 1 if pred else 0, V, E], np.uint32),
              np.asarray(row_ptr, np.uint32), np.asarray(col, np.uint32), np.asarray(w, np.uint32)]
@@ -57,10 +59,14 @@ def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="a
         off = np.asarray(pick_offsets, np.uint32)
         pk = np.asarray(picks, np.uint32)
         parts += [np.asarray([len(off) - 1], np.uint32), off, pk]
+        if clustered is not None:   # (m, positions int32[2 * picks])
+            parts += [np.asarray([clustered[0]], np.uint32), np.asarray(clustered[1], np.int32).view(np.uint32).ravel()]
         sizes = np.diff(off.astype(np.int64))
         n_out = int((sizes ** 2).sum())
         if routes:   # matrices, then (length lo, hi) per order, then orderings
             n_out += 2 * (len(off) - 1) + len(pk)
+        if clustered is not None:   # ... and the clusters each order used
+            n_out += 2 * (len(off) - 1) + len(pk) + (len(off) - 1)
         n_pred = len(pk) * V if pred else 0
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")

@@ -143,3 +143,100 @@ def test_full_batch_twelve_stops(rt, ctx):
         r = rts[woff[k]:woff[k + 1]]
         assert sorted(r.tolist()) == list(range(12))
         assert ln[k] == sum(int(wins[k][a, b]) for a, b in zip(r, r[1:]))
+
+
+# ------------------------------------------------ cluster-decomposed routes
+MMAX = 10   # clusters the library serves (WR_CLUSTER_MAX_CLUSTERS)
+
+def _positions_and_metric(rng, n, span=60):
+    xy = rng.integers(0, span, (n, 2)).astype(np.int32)
+    D = np.abs(xy[:, None, :] - xy[None, :, :]).sum(-1).astype(np.uint32)
+    return xy, D
+
+
+def test_clustered_random_orders(rt, ctx):
+    rng = np.random.default_rng(26)
+    sizes = [0, 1, 2, 3, 7, 12, 13, 20, 31, 40, 64, 5, 17, 25, 36, 48]
+    mats, xys = [], []
+    for k, n in enumerate(sizes):
+        xy, D = _positions_and_metric(rng, n)
+        if k % 3 == 1:   # an asymmetric matrix over the same positions
+            D = (D + rng.integers(0, 7, (n, n))).astype(np.uint32)
+            np.fill_diagonal(D, 0)
+        mats.append(D)
+        xys.append(xy)
+    off, flat = _batch(mats)
+    xy = np.concatenate(xys) if xys else np.zeros((0, 2), np.int32)
+    for m in (1, 2, 3, 4, 6, 10):
+        ln, rts, used = ctx.order_routes_clustered(off, flat, xy, m)
+        el, er, eu = oracle.order_routes_clustered(off, flat, xy, m, m_max=MMAX)
+        assert np.array_equal(ln, el), m
+        assert np.array_equal(rts, er), m
+        assert np.array_equal(used, eu), m
+
+
+def test_clustered_full_batch(rt, ctx):
+    """The medium batch's 256 orders of 32 picks, positions from the grid,
+    three clusters requested: every order against the oracle, and never
+    shorter than the exact route on the orders' 12-pick heads."""
+    wl = make_config("medium")
+    g = wl.graph
+    G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
+    G.set_schedule(512, 8, 0)
+    G.segment_grid(g.W, g.H, 1, 24, 20)
+    off, picks = wl.pick_offsets, wl.picks
+    D = G.order_matrices(off, picks, algo="overlay")
+    xy = np.stack([picks % g.W, picks // g.W], 1).astype(np.int32)
+    ln, rts, used = ctx.order_routes_clustered(off, D, xy, 3)
+    log("clustered: clusters used", np.bincount(used).tolist())
+    el, er, eu = oracle.order_routes_clustered(off, D, xy, 3, m_max=MMAX)
+    assert np.array_equal(ln, el) and np.array_equal(rts, er) and np.array_equal(used, eu)
+    P = 32
+    heads = [D[o * P * P:(o + 1) * P * P].reshape(P, P)[:12, :12] for o in range(len(off) - 1)]
+    hoff, hflat = _batch(heads)
+    hxy = np.concatenate([xy[off[o]:off[o] + 12] for o in range(len(off) - 1)])
+    exact, _ = ctx.order_routes(hoff, hflat)
+    approx, _, _ = ctx.order_routes_clustered(hoff, hflat, hxy, 3)
+    assert (approx >= exact).all()
+    log("clustered/exact on 12-pick heads: mean", float((approx / exact).mean()))
+
+
+def test_clustered_device_pointers_and_errors(rt, ctx):
+    import torch
+    rng = np.random.default_rng(27)
+    mats, xys = [], []
+    for n in (30, 9, 64, 1):
+        xy, D = _positions_and_metric(rng, n)
+        mats.append(D)
+        xys.append(xy)
+    off, flat = _batch(mats)
+    xy = np.concatenate(xys)
+    ln, rts, used = ctx.order_routes_clustered(off, flat, xy, 3)
+    dev = torch.device("cuda:0")
+    d_dist = torch.from_numpy(flat.view(np.int32).copy()).to(dev)
+    d_xy = torch.from_numpy(xy.copy()).to(dev)
+    d_len = torch.zeros(len(off) - 1, dtype=torch.int64, device=dev)
+    d_rt = torch.zeros(int(off[-1]), dtype=torch.int32, device=dev)
+    _, _, u2 = ctx.order_routes_clustered(off, d_dist, d_xy, 3, d_len, d_rt)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_len.cpu().numpy().view(np.uint64), ln)
+    assert np.array_equal(d_rt.cpu().numpy().view(np.uint32), rts)
+    assert np.array_equal(u2, used)
+    for m in (0, 11):
+        with pytest.raises(rt.WrError) as e:
+            ctx.order_routes_clustered(off, flat, xy, m)
+        assert e.value.name == "WR_E_INVALID"
+    xy65, D65 = _positions_and_metric(rng, 65)
+    with pytest.raises(rt.WrError) as e:
+        ctx.order_routes_clustered(np.array([0, 65], np.uint32), D65.ravel(), xy65, 3)
+    assert e.value.name == "WR_E_UNSUPPORTED"
+    bad = xy.copy()
+    bad[0, 0] = 1 << 16
+    with pytest.raises(rt.WrError) as e:
+        ctx.order_routes_clustered(off, flat, bad, 3)
+    assert e.value.name == "WR_E_RANGE"
+    # forty picks at one position: no number of clusters splits them
+    same = np.zeros((40, 2), np.int32)
+    with pytest.raises(rt.WrError) as e:
+        ctx.order_routes_clustered(np.array([0, 40], np.uint32), np.zeros(1600, np.uint32), same, 2)
+    assert e.value.name == "WR_E_UNSUPPORTED"
