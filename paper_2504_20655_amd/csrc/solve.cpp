@@ -331,7 +331,7 @@ uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves,
 }
 
 // Captures K overlay passes starting at parity 1 (pass 0 of a chunk is the
-// segment kernel over the source tiles), so a replay ends at parity 1.
+// seed kernel over the sources' tiles), so a replay ends at parity 1.
 hipGraphExec_t capture_ovl_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t G, uint32_t grid,
                                   const uint32_t *F, hipStream_t st) {
     hipGraph_t graph;
@@ -538,8 +538,8 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     const uint32_t K = w.K;
     uint64_t passes = 0;
     const uint64_t cap = static_cast<uint64_t>(g->V) + 2ull * K + 8;
-    // overlay: pass 0 relaxes the source tiles with the segment kernel; the
-    // replayed passes then start at parity 1 and end there
+    // overlay: pass 0 stores the sources' in-tile exit distances (the seed
+    // kernel); the replayed passes then start at parity 1 and end there
     const uint32_t par0 = w.overlay ? 1u : 0u;
     if (w.overlay) {
         if (ts.custom_epoch != g->epoch) ensure_overlay_tables(g);
