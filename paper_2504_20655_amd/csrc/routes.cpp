@@ -8,6 +8,50 @@
 
 using namespace wr;
 
+namespace {
+
+// Validated shape of a batch of orders: per-order matrix offsets, the total
+// of matrix cells and of picks, and the largest order.
+struct RouteBatch {
+    std::vector<uint32_t> off;
+    std::vector<uint64_t> mbase;
+    uint64_t cells = 0;
+    uint32_t total = 0, nmax = 0;
+};
+
+RouteBatch route_batch(uint32_t num_orders, const uint32_t *pick_offsets, uint32_t max_stops, const char *what) {
+    if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
+    if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
+    RouteBatch b;
+    b.mbase.resize(num_orders);
+    for (uint32_t o = 0; o < num_orders; ++o) {
+        if (pick_offsets[o + 1] < pick_offsets[o]) fail(WR_E_INVALID, "pick_offsets must be non-decreasing");
+        const uint32_t P = pick_offsets[o + 1] - pick_offsets[o];
+        if (P > max_stops)
+            fail(WR_E_UNSUPPORTED, "order " + std::to_string(o) + " has " + std::to_string(P) + " stops; " + what +
+                                       " are served for at most " + std::to_string(max_stops));
+        b.mbase[o] = b.cells;
+        b.cells += static_cast<uint64_t>(P) * P;
+        b.nmax = std::max(b.nmax, P);
+    }
+    b.off.assign(pick_offsets, pick_offsets + num_orders + 1);
+    b.total = pick_offsets[num_orders];
+    return b;
+}
+
+// With caller (device) buffers, the library stream starts after the work the
+// caller queued on `stream`.
+void join_caller_stream(wr_context *ctx, bool dev, void *stream) {
+    if (!dev) return;
+    hipEvent_t ev;
+    WR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    WR_HIP(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
+    WR_HIP(hipStreamWaitEvent(ctx->stream, ev, 0));
+    (void)hipEventDestroy(ev);
+}
+
+}  // namespace
+
 extern "C" wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
                                      const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
                                      uint32_t flags, void *stream) {
@@ -15,42 +59,20 @@ extern "C" wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const
     if (!ctx) fail(WR_E_INVALID, "context is NULL");
     if (flags & ~static_cast<uint32_t>(WR_DEVICE_PTRS)) fail(WR_E_INVALID, "unknown flags for wr_order_routes");
     if (num_orders == 0) return WR_OK;
-    if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
-    if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
-    uint32_t nmax = 0;
-    uint64_t cells = 0;
-    std::vector<uint64_t> mbase(num_orders);
-    for (uint32_t o = 0; o < num_orders; ++o) {
-        if (pick_offsets[o + 1] < pick_offsets[o]) fail(WR_E_INVALID, "pick_offsets must be non-decreasing");
-        const uint32_t P = pick_offsets[o + 1] - pick_offsets[o];
-        if (P > route_max_stops())
-            fail(WR_E_UNSUPPORTED, "order " + std::to_string(o) + " has " + std::to_string(P) +
-                                       " stops; exact routes are served for at most " +
-                                       std::to_string(route_max_stops()));
-        mbase[o] = cells;
-        cells += static_cast<uint64_t>(P) * P;
-        nmax = std::max(nmax, P);
-    }
-    const uint32_t total = pick_offsets[num_orders];
+    const RouteBatch rb = route_batch(num_orders, pick_offsets, route_max_stops(), "exact routes");
+    const uint64_t cells = rb.cells;
+    const uint32_t total = rb.total, nmax = rb.nmax;
     if (!length_out) fail(WR_E_INVALID, "length_out is NULL");
     if (total && !route_out) fail(WR_E_INVALID, "route_out is NULL");
     if (cells && !dist) fail(WR_E_INVALID, "dist is NULL");
     const bool dev = flags & WR_DEVICE_PTRS;
     WR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    if (dev) {
-        // caller buffers: start after the work the caller queued on `stream`
-        hipEvent_t ev;
-        WR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        WR_HIP(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
-        WR_HIP(hipStreamWaitEvent(st, ev, 0));
-        (void)hipEventDestroy(ev);
-    }
-    std::vector<uint32_t> hoff(pick_offsets, pick_offsets + num_orders + 1);
+    join_caller_stream(ctx, dev, stream);
     DBuf<uint32_t> d_off, d_flag, d_dist, d_route;
     DBuf<uint64_t> d_base, d_len;
-    upload(d_off, ctx, hoff, st);
-    upload(d_base, ctx, mbase, st);
+    upload(d_off, ctx, rb.off, st);
+    upload(d_base, ctx, rb.mbase, st);
     d_flag.alloc(ctx, 1);
     launch_fill_u32(d_flag.p, 1, 0u, st);
     const uint32_t *ddist = dist;
@@ -92,21 +114,9 @@ extern "C" wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_ord
     if (m < 1 || m > route_clustered_max_clusters())
         fail(WR_E_INVALID, "m must be between 1 and " + std::to_string(route_clustered_max_clusters()));
     if (num_orders == 0) return WR_OK;
-    if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
-    if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
-    uint64_t cells = 0;
-    std::vector<uint64_t> mbase(num_orders);
-    for (uint32_t o = 0; o < num_orders; ++o) {
-        if (pick_offsets[o + 1] < pick_offsets[o]) fail(WR_E_INVALID, "pick_offsets must be non-decreasing");
-        const uint32_t P = pick_offsets[o + 1] - pick_offsets[o];
-        if (P > route_clustered_max_stops())
-            fail(WR_E_UNSUPPORTED, "order " + std::to_string(o) + " has " + std::to_string(P) +
-                                       " stops; clustered routes are served for at most " +
-                                       std::to_string(route_clustered_max_stops()));
-        mbase[o] = cells;
-        cells += static_cast<uint64_t>(P) * P;
-    }
-    const uint32_t total = pick_offsets[num_orders];
+    const RouteBatch rb = route_batch(num_orders, pick_offsets, route_clustered_max_stops(), "clustered routes");
+    const uint64_t cells = rb.cells;
+    const uint32_t total = rb.total;
     if (!length_out) fail(WR_E_INVALID, "length_out is NULL");
     if (total && (!route_out || !pick_xy)) fail(WR_E_INVALID, "route_out or pick_xy is NULL");
     if (cells && !dist) fail(WR_E_INVALID, "dist is NULL");
@@ -116,19 +126,12 @@ extern "C" wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_ord
             if (pick_xy[q] <= -65536 || pick_xy[q] >= 65536) fail(WR_E_RANGE, "pick positions must be below 2^16");
     WR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    if (dev) {
-        hipEvent_t ev;
-        WR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        WR_HIP(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
-        WR_HIP(hipStreamWaitEvent(st, ev, 0));
-        (void)hipEventDestroy(ev);
-    }
-    std::vector<uint32_t> hoff(pick_offsets, pick_offsets + num_orders + 1);
+    join_caller_stream(ctx, dev, stream);
     DBuf<uint32_t> d_off, d_err, d_dist, d_route, d_m;
     DBuf<uint64_t> d_base, d_len;
     DBuf<int32_t> d_xy;
-    upload(d_off, ctx, hoff, st);
-    upload(d_base, ctx, mbase, st);
+    upload(d_off, ctx, rb.off, st);
+    upload(d_base, ctx, rb.mbase, st);
     d_err.alloc(ctx, 1);
     launch_fill_u32(d_err.p, 1, 0u, st);
     d_m.alloc(ctx, num_orders);
