@@ -202,6 +202,27 @@ def route_leg(wr, ctx, D_host, n_orders, P, stops, steps, warmup, with_cpu):
            "roofline": {"kernel": "k_route_hk", "bound": "alu", "achieved": round(achieved, 3),
                         "peak": round(ALU_PEAK_TOPS, 1), "unit": "Tops/s",
                         "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None}}
+    # the paper's structure beside it: every ordering in its own thread, on
+    # 9-stop windows (9! orderings each), against the subset programme on the
+    # same windows
+    w9 = [m[s:s + 9, s:s + 9] for m in mats[:16] for s in range(0, P - 9 + 1, 8)]
+    o9 = np.arange(len(w9) + 1, dtype=np.uint32) * 9
+    f9 = np.concatenate([w.ravel() for w in w9]).astype(np.uint32)
+    d9 = torch.from_numpy(f9.view(np.int32).copy()).to(dev)
+    l9 = torch.zeros(len(w9), dtype=torch.int64, device=dev)
+    r9 = torch.zeros(len(w9) * 9, dtype=torch.int32, device=dev)
+    t9 = {}
+    for name, en in (("enumerate", True), ("subset_programme", False)):
+        ctx.order_routes(o9, d9, l9, r9, enumerate=en)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.order_routes(o9, d9, l9, r9, enumerate=en)
+        torch.cuda.synchronize()
+        t9[name] = round(len(w9) * steps / (time.perf_counter() - t), 1)
+    res["paper_structure_9_stops"] = {"workload": f"{len(w9)} routes of 9 stops", "unit": "routes/s",
+                                      "enumerate_per_thread": t9["enumerate"],
+                                      "subset_programme": t9["subset_programme"]}
     if with_cpu:
         import oracle
         k = len(wins)

@@ -221,12 +221,21 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
  * flags:        WR_DEVICE_PTRS: dist, length_out and route_out are device
  *               pointers, read and written by work ordered after `stream`
  *               (pick_offsets stays a host array).
+ *               WR_ROUTE_ENUMERATE: the paper's own structure instead (its
+ *               route-permutation kernel, numerical-experiments section): one
+ *               thread per ordering, n! orderings of n-1 steps each, for
+ *               orders of at most WR_ROUTE_ENUMERATE_MAX_STOPS stops; the same
+ *               results, kept as the baseline the subset programme is
+ *               measured against.
  * Errors: WR_E_INVALID (NULL, bad offsets, unknown flags), WR_E_UNSUPPORTED
- * (an order with more than WR_ROUTE_MAX_STOPS stops), WR_E_RANGE (the
+ * (an order with more than WR_ROUTE_MAX_STOPS stops, or more than
+ * WR_ROUTE_ENUMERATE_MAX_STOPS with WR_ROUTE_ENUMERATE), WR_E_RANGE (the
  * length of some partial route of an order reaches 2^32-1: lengths are
  * accumulated in 32 bits; outputs are then unspecified), WR_E_NOMEM,
  * WR_E_DEVICE. */
 #define WR_ROUTE_MAX_STOPS 12u
+#define WR_ROUTE_ENUMERATE 0x0400u
+#define WR_ROUTE_ENUMERATE_MAX_STOPS 10u
 #define WR_ROUTE_INF 0xFFFFFFFFFFFFFFFFull
 wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
                           const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,

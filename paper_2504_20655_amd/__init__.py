@@ -24,6 +24,7 @@ ALGO = {"auto": 0x00, "sweep": 0x10, "frontier": 0x20, "segmented": 0x30,
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 NO_GRAPH_CAPTURE = 0x0100
 TIME_KERNELS = 0x0200
+ROUTE_ENUMERATE = 0x0400
 
 STATUS = {0: "WR_OK", 1: "WR_E_INVALID", 2: "WR_E_RANGE", 3: "WR_E_NOMEM", 4: "WR_E_DEVICE",
           5: "WR_E_UNSUPPORTED", 6: "WR_E_BUSY", 7: "WR_E_INTERNAL"}
@@ -80,22 +81,24 @@ class Context:
         _check(lib().wr_context_memory(self.h, ctypes.byref(used), ctypes.byref(budget)))
         return used.value, budget.value
 
-    def order_routes(self, pick_offsets, dist, lengths=None, routes=None):
+    def order_routes(self, pick_offsets, dist, lengths=None, routes=None, enumerate: bool = False):
         """Shortest open route over each order's stops (wr_order_routes):
         dist holds the concatenated P x P matrices (numpy uint32, or a device
-        tensor with lengths/routes device tensors as well).  Returns
-        (lengths uint64[num_orders], orderings uint32[total picks])."""
+        tensor with lengths/routes device tensors as well).  enumerate=True
+        runs the permutation-per-thread baseline.  Returns (lengths
+        uint64[num_orders], orderings uint32[total picks])."""
         off = _u32(pick_offsets)
         n = len(off) - 1
         total = int(off[-1]) if n > 0 else 0
+        extra = ROUTE_ENUMERATE if enumerate else 0
         if lengths is not None:
             _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(dist), _ptr(lengths), _ptr(routes),
-                                         DEVICE_PTRS, _stream_of(lengths)))
+                                         DEVICE_PTRS | extra, _stream_of(lengths)))
             return lengths, routes
         d = _u32(dist)
         ln = np.zeros(max(n, 1), dtype=np.uint64)
         rt = np.zeros(max(total, 1), dtype=np.uint32)
-        _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(d), _ptr(ln), _ptr(rt), 0, None))
+        _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(d), _ptr(ln), _ptr(rt), extra, None))
         return ln[:max(n, 0)], rt[:total]
 
     def order_routes_clustered(self, pick_offsets, dist, pick_xy, m: int, lengths=None, routes=None):

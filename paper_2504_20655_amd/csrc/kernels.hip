@@ -2287,6 +2287,100 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_clustered(
     }
 }
 
+// The paper's route-permutation structure (numerical experiments, the
+// CUDA kernel that evaluates every ordering in its own thread), kept as the
+// baseline of the subset programme: thread q of order o takes the q-th
+// ordering in lexicographic order (factorial-base digits pick the q-th
+// unused stop at each position), sums its n-1 steps in 32 bits with WR_INF
+// absorbing, and the order's minimum of (length << 22 | q) is kept with a
+// 64-bit atomic minimum; the smallest rank among the shortest orderings is
+// the lexicographically smallest one, as the subset programme returns.
+constexpr uint32_t RP_NMAX = 10;   // 10! = 3,628,800 < 2^22 orderings
+__global__ __launch_bounds__(256) void k_route_perm(uint32_t num_orders, const uint32_t *__restrict__ off,
+                                                    const uint64_t *__restrict__ mbase,
+                                                    const uint32_t *__restrict__ dist,
+                                                    unsigned long long *__restrict__ best,
+                                                    uint32_t *__restrict__ overflow) {
+    __shared__ unsigned long long s_best[256];
+    for (uint32_t o = blockIdx.y; o < num_orders; o += gridDim.y) {
+        const uint32_t a = off[o], n = off[o + 1] - a;
+        uint32_t fact = 1;
+        for (uint32_t x = 2; x <= n; ++x) fact *= x;
+        const uint32_t *D = dist + mbase[o];
+        unsigned long long mine = ~0ull;
+        bool ovf = false;
+        for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; n > 0 && q < fact; q += gridDim.x * blockDim.x) {
+            uint32_t r = q, f = fact, used = 0, prev = 0, len = 0;
+            for (uint32_t x = 0; x < n; ++x) {
+                f /= (n - x);
+                uint32_t d = r / f;
+                r -= d * f;
+                uint32_t c = 0;
+                for (;; ++c)
+                    if (!((used >> c) & 1u) && d-- == 0) break;
+                used |= 1u << c;
+                if (x > 0) len = rt_step(len, D[prev * n + c], ovf);
+                prev = c;
+            }
+            const unsigned long long key = (static_cast<unsigned long long>(len) << 22) | q;
+            mine = key < mine ? key : mine;
+        }
+        if (ovf) atomicOr(overflow, 1u);
+        s_best[threadIdx.x] = mine;
+        __syncthreads();
+        for (uint32_t h = blockDim.x >> 1; h > 0; h >>= 1) {
+            if (threadIdx.x < h && s_best[threadIdx.x + h] < s_best[threadIdx.x]) s_best[threadIdx.x] = s_best[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && n > 0) atomicMin(best + o, s_best[0]);
+        __syncthreads();
+    }
+}
+
+// Orderings and lengths from the per-order keys of k_route_perm.
+__global__ void k_route_perm_out(uint32_t num_orders, const uint32_t *__restrict__ off,
+                                 const unsigned long long *__restrict__ best, uint64_t *__restrict__ len_out,
+                                 uint32_t *__restrict__ route_out) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < num_orders; o += gridDim.x * blockDim.x) {
+        const uint32_t a = off[o], n = off[o + 1] - a;
+        if (n == 0) {
+            len_out[o] = 0;
+            continue;
+        }
+        const unsigned long long key = best[o];
+        const uint32_t len = static_cast<uint32_t>(key >> 22);
+        uint32_t r = static_cast<uint32_t>(key & ((1u << 22) - 1u)), f = 1, used = 0;
+        for (uint32_t x = 2; x <= n; ++x) f *= x;
+        for (uint32_t x = 0; x < n; ++x) {
+            f /= (n - x);
+            uint32_t d = r / f;
+            r -= d * f;
+            uint32_t c = 0;
+            for (;; ++c)
+                if (!((used >> c) & 1u) && d-- == 0) break;
+            used |= 1u << c;
+            route_out[a + x] = c;
+        }
+        len_out[o] = len == INF ? ~0ull : static_cast<uint64_t>(len);
+    }
+}
+
+uint32_t route_enumerate_max_stops() { return RP_NMAX; }
+
+void launch_route_perm(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
+                       unsigned long long *best, uint64_t *len_out, uint32_t *route_out, uint32_t *overflow,
+                       uint32_t nmax, hipStream_t st) {
+    if (!num_orders) return;
+    uint32_t fact = 1;
+    for (uint32_t x = 2; x <= nmax; ++x) fact *= x;
+    dim3 grid(std::max(1u, std::min(1024u, (fact + 255) / 256)), std::min(num_orders, 65535u));
+    hipLaunchKernelGGL(k_route_perm, grid, 256, 0, st, num_orders, off, mbase, dist, best, overflow);
+    check_launch("route_perm");
+    hipLaunchKernelGGL(k_route_perm_out, blocks_for(num_orders, 256, 1024), 256, 0, st, num_orders, off, best,
+                       len_out, route_out);
+    check_launch("route_perm_out");
+}
+
 uint32_t route_max_stops() { return RT_NMAX; }
 
 uint32_t route_lds_bytes(uint32_t nmax) { return rt_lds_words(nmax) * 4u; }

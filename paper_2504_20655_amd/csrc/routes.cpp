@@ -57,9 +57,13 @@ extern "C" wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const
                                      uint32_t flags, void *stream) {
     WR_API_BEGIN
     if (!ctx) fail(WR_E_INVALID, "context is NULL");
-    if (flags & ~static_cast<uint32_t>(WR_DEVICE_PTRS)) fail(WR_E_INVALID, "unknown flags for wr_order_routes");
+    if (flags & ~static_cast<uint32_t>(WR_DEVICE_PTRS | WR_ROUTE_ENUMERATE))
+        fail(WR_E_INVALID, "unknown flags for wr_order_routes");
     if (num_orders == 0) return WR_OK;
-    const RouteBatch rb = route_batch(num_orders, pick_offsets, route_max_stops(), "exact routes");
+    const bool enumerate = flags & WR_ROUTE_ENUMERATE;
+    const RouteBatch rb = route_batch(num_orders, pick_offsets,
+                                      enumerate ? route_enumerate_max_stops() : route_max_stops(),
+                                      enumerate ? "enumerated routes" : "exact routes");
     const uint64_t cells = rb.cells;
     const uint32_t total = rb.total, nmax = rb.nmax;
     if (!length_out) fail(WR_E_INVALID, "length_out is NULL");
@@ -87,11 +91,19 @@ extern "C" wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const
         dlen = d_len.p;
         droute = d_route.p;
     }
-    // the LDS of the largest order bounds the workgroups per CU
-    const uint32_t lds = route_lds_bytes(std::max(nmax, 1u));
-    const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / lds));
-    launch_route_hk(num_orders, d_off.p, d_base.p, ddist, dlen, droute, d_flag.p, nmax,
-                    static_cast<uint32_t>(ctx->num_cus) * per_cu, st);
+    DBuf<uint64_t> d_key;
+    if (enumerate) {
+        d_key.alloc(ctx, num_orders);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(d_key.p), 2ull * num_orders, 0xFFFFFFFFu, st);
+        launch_route_perm(num_orders, d_off.p, d_base.p, ddist, reinterpret_cast<unsigned long long *>(d_key.p),
+                          dlen, droute, d_flag.p, nmax, st);
+    } else {
+        // the LDS of the largest order bounds the workgroups per CU
+        const uint32_t lds = route_lds_bytes(std::max(nmax, 1u));
+        const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / lds));
+        launch_route_hk(num_orders, d_off.p, d_base.p, ddist, dlen, droute, d_flag.p, nmax,
+                        static_cast<uint32_t>(ctx->num_cus) * per_cu, st);
+    }
     uint32_t ovf = 0;
     WR_HIP(hipMemcpyAsync(&ovf, d_flag.p, 4, hipMemcpyDeviceToHost, st));
     if (!dev) {

@@ -412,6 +412,12 @@ uint32_t ovl_waves();   // waves (= blocks per unit) of the overlay pass
 // length reaches WR_INF in 32 bits
 uint32_t route_max_stops();
 uint32_t route_lds_bytes(uint32_t nmax);
+// the permutation-per-thread baseline: best[o] must start at ~0 (one 64-bit
+// key per order); orders of at most route_enumerate_max_stops() stops
+uint32_t route_enumerate_max_stops();
+void launch_route_perm(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
+                       unsigned long long *best, uint64_t *len_out, uint32_t *route_out, uint32_t *overflow,
+                       uint32_t nmax, hipStream_t st);
 void launch_route_hk(uint32_t num_orders, const uint32_t *off, const uint64_t *mbase, const uint32_t *dist,
                      uint64_t *len_out, uint32_t *route_out, uint32_t *overflow, uint32_t nmax, uint32_t grid,
                      hipStream_t st);

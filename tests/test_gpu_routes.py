@@ -240,3 +240,21 @@ def test_clustered_device_pointers_and_errors(rt, ctx):
     with pytest.raises(rt.WrError) as e:
         ctx.order_routes_clustered(np.array([0, 40], np.uint32), np.zeros(1600, np.uint32), same, 2)
     assert e.value.name == "WR_E_UNSUPPORTED"
+
+
+def test_enumeration_baseline_matches(rt, ctx):
+    """The permutation-per-thread baseline (WR_ROUTE_ENUMERATE) returns the
+    subset programme's lengths and orderings, and the oracle's, up to 10
+    stops; larger orders are refused."""
+    rng = np.random.default_rng(28)
+    sizes = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 2, 5, 8, 9, 3]
+    off, flat = _batch(_random_mats(rng, sizes))
+    ln_e, rt_e = ctx.order_routes(off, flat, enumerate=True)
+    ln_h, rt_h = ctx.order_routes(off, flat)
+    el, er = oracle.order_routes(off, flat)
+    assert np.array_equal(ln_e, el) and np.array_equal(rt_e, er)
+    assert np.array_equal(ln_h, ln_e) and np.array_equal(rt_h, rt_e)
+    off11, flat11 = _batch(_random_mats(rng, [11]))
+    with pytest.raises(rt.WrError) as e:
+        ctx.order_routes(off11, flat11, enumerate=True)
+    assert e.value.name == "WR_E_UNSUPPORTED"
