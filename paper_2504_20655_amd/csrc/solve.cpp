@@ -68,6 +68,7 @@ struct SegWork {
     KernelEvents kev;
     SegBuffers buf;
     hipGraphExec_t exec = nullptr;   // K passes of the segment kernel, or of the overlay kernel
+    hipGraphExec_t exec2 = nullptr;  // overlay: 2 passes, to end a batch of replays near the expected count
     SegState ss;
     // overlay: every exit value of all S_cap rows is INF (state_clean), else
     // the rows a call may have left dirty; a call that ends cleanly resets
@@ -78,6 +79,7 @@ struct SegWork {
     ~SegWork() {
         if (st) (void)hipStreamSynchronize(st);   // a trailing reset may still run
         if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec2) (void)hipGraphExecDestroy(exec2);
     }
 };
 
@@ -106,8 +108,8 @@ struct Workspace {
     std::vector<uint32_t> stamp, slot, plan_cnt;
     uint32_t stamp_id = 0;
     // passes the last segmented / overlay solve needed (replays launched
-    // before the first convergence check)
-    uint64_t last_passes = 0;
+    // before the first convergence check), and how many of them had work
+    uint64_t last_passes = 0, last_work_passes = 0;
     DBuf<uint64_t> call_base;
     IntileJob intile;
     hipEvent_t ev_done = nullptr;   // end of a call's results, ahead of a trailing reset
@@ -488,6 +490,8 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
                    std::min(32u / ovl_waves(), std::max(1u, (160u * 1024u) / ovl_pass_lds_bytes(ts)));
     if (overlay) ensure_overlay_tables(g);
     if (graph_mode)
+        nw->exec2 = overlay ? capture_ovl_passes(ts, nw->ss, 2, G, nw->grid_ovl, ts.d_F.p, ctx->stream) : nullptr;
+    if (graph_mode)
         nw->exec = overlay ? capture_ovl_passes(ts, nw->ss, K, G, nw->grid_ovl, ts.d_F.p, ctx->stream)
                            : capture_seg_passes(ts, nw->ss, K, ts.tile_cap, waves, G, nw->grid, ctx->stream);
     ws.seg = std::move(nw);
@@ -550,22 +554,36 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     // previous solve needed (surplus passes find nothing to do and are cheap)
     Workspace &wsp = workspace(g);
     uint32_t batch = graph_mode ? static_cast<uint32_t>(std::max<uint64_t>(1, wsp.last_passes / K)) : 1u;
+    // overlay: cover the previous solve's passes with work by K-pass replays
+    // plus 2-pass ones, so the first check comes at most one pass late
+    uint32_t batch2 = 0;
+    if (graph_mode && w.exec2 && wsp.last_work_passes > 0) {
+        batch = static_cast<uint32_t>(wsp.last_work_passes / K);
+        batch2 = static_cast<uint32_t>((wsp.last_work_passes - static_cast<uint64_t>(batch) * K + 1) / 2);
+    }
     bool first = true;
     for (;;) {
         if (graph_mode) {
             for (uint32_t r = 0; r < batch; ++r) WR_HIP(hipGraphLaunch(w.exec, st));
-            passes += static_cast<uint64_t>(K) * (batch - 1);
+            for (uint32_t r = 0; r < batch2; ++r) WR_HIP(hipGraphLaunch(w.exec2, st));
+            if (batch + batch2 == 0) {
+                WR_HIP(hipGraphLaunch(w.exec, st));
+                batch = 1;
+            }
+            passes += static_cast<uint64_t>(K) * batch + 2ull * batch2;
             batch = 1;
+            batch2 = 0;
         } else if (w.overlay) {
             for (uint32_t i = 0; i < K; ++i)
                 launch_ovl_step(ts, ss, (i + 1) & 1u, w.G, w.grid_ovl, ts.d_F.p, i + 1 == K, st, w.kev.b(i),
                                 w.kev.e(i));
+            passes += K;
         } else {
             for (uint32_t i = 0; i < K; ++i)
                 launch_seg_step(ts, ss, i & 1u, ts.tile_cap, w.waves, w.G, w.grid, st, w.kev.b(i),
                                 w.kev.e(i));
+            passes += K;
         }
-        passes += K;
         if (first && overlap) overlap();
         first = false;
         WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + par0, 4, hipMemcpyDeviceToHost, st));
@@ -587,6 +605,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     info.relax_ms += ms;
     info.passes += static_cast<uint32_t>(stats[1]);
     info.work_items += stats[0];
+    if (w.overlay) wsp.last_work_passes = stats[1];
 }
 
 // ------------------------------------------------------ blocked-layout driver
