@@ -163,6 +163,13 @@ def test_clustered_random_orders(rt, ctx):
         if k % 3 == 1:   # an asymmetric matrix over the same positions
             D = (D + rng.integers(0, 7, (n, n))).astype(np.uint32)
             np.fill_diagonal(D, 0)
+        if k % 5 == 4:   # some steps cannot be taken (own generator: positions stay as drawn)
+            D = D.copy()
+            D[np.random.default_rng(100 + k).random((n, n)) < 0.2] = INF
+            np.fill_diagonal(D, 0)
+        if k == 11:      # no step can be taken: the length is infinite
+            D = np.full((n, n), INF, np.uint32)
+            np.fill_diagonal(D, 0)
         mats.append(D)
         xys.append(xy)
     off, flat = _batch(mats)
@@ -173,6 +180,7 @@ def test_clustered_random_orders(rt, ctx):
         assert np.array_equal(ln, el), m
         assert np.array_equal(rts, er), m
         assert np.array_equal(used, eu), m
+        assert ln[11] == 0xFFFFFFFFFFFFFFFF
 
 
 def test_clustered_full_batch(rt, ctx):
