@@ -113,9 +113,15 @@ struct Workspace {
     DBuf<uint64_t> call_base;
     IntileJob intile;
     hipEvent_t ev_done = nullptr;   // end of a call's results, ahead of a trailing reset
+    // recorded about two thirds into a solve's first batch of replays, when
+    // mid_valid: side-stream work that does not depend on the relaxation
+    // waits for it, so it overlaps the light last passes, not the heavy first
+    hipEvent_t ev_mid = nullptr;
+    bool mid_valid = false;
     ~Workspace() {
         seg.reset();
         if (ev_done) (void)hipEventDestroy(ev_done);
+        if (ev_mid) (void)hipEventDestroy(ev_mid);
         if (h_flag) (void)hipHostFree(h_flag);
     }
 };
@@ -562,9 +568,18 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
         batch2 = static_cast<uint32_t>((wsp.last_work_passes - static_cast<uint64_t>(batch) * K + 1) / 2);
     }
     bool first = true;
+    wsp.mid_valid = false;
     for (;;) {
         if (graph_mode) {
-            for (uint32_t r = 0; r < batch; ++r) WR_HIP(hipGraphLaunch(w.exec, st));
+            const uint32_t mid = first && overlap && batch >= 2 ? (2 * batch + 2) / 3 : batch;
+            for (uint32_t r = 0; r < batch; ++r) {
+                if (r == mid) {
+                    if (!wsp.ev_mid) WR_HIP(hipEventCreateWithFlags(&wsp.ev_mid, hipEventDisableTiming));
+                    WR_HIP(hipEventRecord(wsp.ev_mid, st));
+                    wsp.mid_valid = true;
+                }
+                WR_HIP(hipGraphLaunch(w.exec, st));
+            }
             for (uint32_t r = 0; r < batch2; ++r) WR_HIP(hipGraphLaunch(w.exec2, st));
             if (batch + batch2 == 0) {
                 WR_HIP(hipGraphLaunch(w.exec, st));
@@ -1309,11 +1324,14 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
                 WR_HIP(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
                 WR_HIP(hipEventRecord(ev_ready, st));
                 // runs once the first passes are queued, so the host builds the
-                // pair list while the GPU relaxes
+                // pair list while the GPU relaxes; the side stream starts once
+                // the heavy first passes are done (the mid-batch event), as the
+                // fix-up depends only on the tile tables
                 overlap = [&]() {
                     const IntileWork iw = intile_pairs(*g->tiles, num_orders, pick_offsets, picks, out_base.data(),
                                                        [&](uint32_t k) { return plan.uidx[k] >= lo && plan.uidx[k] < lo + n; });
-                    WR_HIP(hipStreamWaitEvent(ctx->side, ev_ready, 0));
+                    Workspace &ows = workspace(g);
+                    WR_HIP(hipStreamWaitEvent(ctx->side, ows.mid_valid ? ows.ev_mid : ev_ready, 0));
                     job.upload_and_launch(ctx, *g->tiles, iw, false, g->V, nullptr, ctx->side);
                     WR_HIP(hipEventCreateWithFlags(&ev_side, hipEventDisableTiming));
                     WR_HIP(hipEventRecord(ev_side, ctx->side));
