@@ -868,6 +868,9 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
     const uint32_t lane = lane_id();
     const uint32_t wv = uniform(threadIdx.x >> 6);
     const uint32_t nunits = uniform(*A.nunits);
+    // workgroups 0 .. nunits-1 take units until the cursor passes the end,
+    // so the others can leave without touching the cursor (light passes)
+    if (blockIdx.x >= nunits) return;
     uint32_t staged = NONE;
     for (;;) {
         if (threadIdx.x == 0) *s_unit = atomicAdd(A.cursor, 1u);
