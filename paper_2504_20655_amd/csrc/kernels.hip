@@ -868,15 +868,21 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
     const uint32_t lane = lane_id();
     const uint32_t wv = uniform(threadIdx.x >> 6);
     const uint32_t nunits = uniform(*A.nunits);
-    // workgroups 0 .. nunits-1 take units until the cursor passes the end,
-    // so the others can leave without touching the cursor (light passes)
+    // Workgroup w takes unit w first, then units gridDim + cursor++ until
+    // the end, so each unit is taken once; workgroups with no first unit
+    // leave at once (light passes), and none waits on the cursor to start.
     if (blockIdx.x >= nunits) return;
     uint32_t staged = NONE;
+    uint32_t first_unit = blockIdx.x;
     for (;;) {
-        if (threadIdx.x == 0) *s_unit = atomicAdd(A.cursor, 1u);
-        __syncthreads();
-        const uint32_t u = uniform(*s_unit);
-        __syncthreads();
+        uint32_t u = first_unit;
+        if (u == NONE) {
+            if (threadIdx.x == 0) *s_unit = gridDim.x + atomicAdd(A.cursor, 1u);
+            __syncthreads();
+            u = uniform(*s_unit);
+            __syncthreads();
+        }
+        first_unit = NONE;
         if (u >= nunits) break;
         const uint2 unit = A.units[u];
         const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
