@@ -72,6 +72,10 @@ def lib():
         L.orc_route_clustered.restype = i32
         L.orc_order_routes_clustered.argtypes = [u32, _u32p, _u32p, _i32p, u32, u32, u32, _u64p, _u32p, _u32p, i32]
         L.orc_order_routes_clustered.restype = i32
+        L.orc_route_enumerate.argtypes = [u32, _u32p, _u64p, _u32p, _u64p]
+        L.orc_route_enumerate.restype = i32
+        L.orc_chain_routes.argtypes = [u32, _u32p, _u32p, u32, _u32p, i32, _u64p, _u32p, _u64p]
+        L.orc_chain_routes.restype = i32
         _lib = L
     return _lib
 
@@ -205,6 +209,42 @@ def order_routes(pick_offsets, dist, nthreads: int = 0) -> tuple[np.ndarray, np.
     return cost[:n_orders], rt[:int(off[-1]) if n_orders else 0]
 
 
+def route_enumerate(D) -> tuple[int, np.ndarray, int]:
+    """The optimal open route by trying every ordering of the n <= 12 stops
+    (C, lexicographic order, first strict improvement kept): (length,
+    ordering, orderings compared = n!).  An independent second method
+    beside route()."""
+    M = np.ascontiguousarray(D, dtype=np.uint32)
+    n = M.shape[0]
+    cost = np.zeros(1, dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    r = np.zeros(max(n, 1), dtype=np.uint32)
+    if lib().orc_route_enumerate(n, M.reshape(-1) if n else np.zeros(1, np.uint32), cost, r, cnt) != 0:
+        raise ValueError("route enumeration: n out of range")
+    return int(cost[0]), r[:n], int(cnt[0])
+
+
+def chain_routes(pieces, D, by_subsets: bool = False) -> tuple[int, np.ndarray, int]:
+    """Cheapest chaining of cluster routes: pieces is a list of stop-index
+    sequences (each a cluster's route over the n x n matrix D); every order
+    of the pieces and every orientation of each is a candidate, the chain's
+    length adds the pieces' own steps and the steps between consecutive
+    pieces.  Returns (length, stops of the chain, chains compared); the
+    enumeration compares K! 2^K chains, by_subsets=True uses the subset
+    programme instead (count 0)."""
+    M = np.ascontiguousarray(D, dtype=np.uint32)
+    n = M.shape[0]
+    sizes = np.array([len(p) for p in pieces], dtype=np.uint32)
+    stops = np.ascontiguousarray(np.concatenate([np.asarray(p) for p in pieces]), dtype=np.uint32)
+    cost = np.zeros(1, dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    r = np.zeros(max(len(stops), 1), dtype=np.uint32)
+    if lib().orc_chain_routes(len(pieces), sizes, stops, n, M.reshape(-1), 1 if by_subsets else 0,
+                              cost, r, cnt) != 0:
+        raise ValueError("chain oracle: bad pieces")
+    return int(cost[0]), r[:len(stops)], int(cnt[0])
+
+
 def kmeans(xy, m: int) -> np.ndarray:
     """Cluster of every point (K-means with farthest-point initial centres,
     exact integer comparisons; see orc_route_clustered)."""
@@ -217,7 +257,8 @@ def kmeans(xy, m: int) -> np.ndarray:
 
 def route_clustered(D, xy, m: int, max_cluster: int = 12, m_max: int = 8):
     """Cluster-decomposed route over one order (the Route Optimization
-    section's theorem): (length, ordering, clusters used)."""
+    section's theorem): (length, ordering, clusters used).  The clusters'
+    routes are chained by enumerating every order and orientation."""
     M = np.ascontiguousarray(D, dtype=np.uint32)
     n = M.shape[0]
     P = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1)

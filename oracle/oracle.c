@@ -372,7 +372,8 @@ int orc_certificate(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
  * D[i][j] + h(S\{i}, j).  The optimum is min_i h(all, i), and the
  * lexicographically smallest optimal ordering is read greedily: the smallest
  * i with h(all, i) optimal, then repeatedly the smallest j whose step
- * D[i][j] + h(rest, j) equals h(current, i).                              */
+ * D[i][j] + h(rest, j) equals h(current, i).  When every ordering is
+ * infinite they all tie and the smallest, 0, 1, ..., n-1, is returned.     */
 #define ORC_ROUTE_INF UINT64_MAX
 
 static uint64_t route_add(uint64_t a, uint32_t d)
@@ -414,6 +415,13 @@ int orc_route_held_karp(uint32_t n, const uint32_t *D, uint64_t *cost, uint32_t 
     uint64_t opt = ORC_ROUTE_INF;
     for (uint32_t i = 0; i < n; ++i)
         if (h[all * n + i] < opt) opt = h[all * n + i];
+    if (opt == ORC_ROUTE_INF) {
+        /* every ordering infinite: they all tie, the smallest is 0, 1, ... */
+        for (uint32_t k = 0; k < n; ++k) route[k] = k;
+        *cost = opt;
+        free(h);
+        return 0;
+    }
     uint32_t cur = 0;
     while (h[all * n + cur] != opt) ++cur;
     size_t S = all;
@@ -460,6 +468,54 @@ int orc_order_routes(uint32_t num_orders, const uint32_t *pick_off, const uint32
     }
     free(base);
     return bad ? -1 : 0;
+}
+
+/* The optimal open route by its plain definition: every ordering of the n
+ * stops (n <= 12), generated depth first with the smallest unused stop
+ * first, i.e. in lexicographic order; a length is the sum of the ordering's
+ * n-1 steps (ORC_ROUTE_INF once a step is INF).  The first ordering of the
+ * smallest length is kept: the lexicographically smallest of the shortest.
+ * *count = orderings compared (n!).  A second, independent method beside
+ * the subset programme above.  Returns 0, or -1 for n > 12. */
+int orc_route_enumerate(uint32_t n, const uint32_t *D, uint64_t *cost, uint32_t *route, uint64_t *count)
+{
+    if (n > 12) return -1;
+    *count = 1;
+    *cost = 0;
+    if (n <= 1) {
+        if (n == 1) route[0] = 0;
+        return 0;
+    }
+    uint32_t cur[12], used = 0;
+    uint64_t part[12];
+    int d = 0, have = 0;
+    *count = 0;
+    cur[0] = 0;
+    for (;;) {
+        while (cur[d] < n && (used & (1u << cur[d]))) ++cur[d];
+        if (cur[d] >= n) {
+            if (d == 0) break;
+            --d;
+            used &= ~(1u << cur[d]);
+            ++cur[d];
+            continue;
+        }
+        part[d] = d == 0 ? 0 : route_add(part[d - 1], D[(size_t)cur[d - 1] * n + cur[d]]);
+        if ((uint32_t)d + 1 == n) {
+            ++*count;
+            if (!have || part[d] < *cost) {
+                have = 1;
+                *cost = part[d];
+                for (uint32_t k = 0; k < n; ++k) route[k] = cur[k];
+            }
+            ++cur[d];
+            continue;
+        }
+        used |= 1u << cur[d];
+        ++d;
+        cur[d] = 0;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -573,10 +629,218 @@ static uint64_t route_len(const uint32_t *D, uint32_t n, const uint32_t *r, uint
     return s;
 }
 
+/* Length of a chain of cluster routes ("pieces"): piece c in orientation o
+ * (0 forward, 1 reversed) starts at pstart[c][o], ends at pend[c][o] and
+ * costs plen[c][o]; consecutive pieces are joined by the step from the end
+ * of one to the start of the next. */
+static uint64_t add64(uint64_t a, uint64_t b)
+{
+    if (a == ORC_ROUTE_INF || b == ORC_ROUTE_INF) return ORC_ROUTE_INF;
+    return a + b;
+}
+
+struct chain_pieces {
+    uint32_t K, n;
+    const uint32_t *D;
+    uint32_t pstart[16][2], pend[16][2];
+    uint64_t plen[16][2];
+};
+
+/* The cheapest chain by its plain definition: every order of the K pieces
+ * and every orientation of each.  Chains are generated depth first with the
+ * smallest unused cluster first and forward before reversed, i.e. in
+ * lexicographic order of their (cluster, orientation) sequences; the first
+ * chain of the smallest length is kept, which is the lexicographically
+ * smallest among the cheapest.  *count = chains compared (K! 2^K). */
+static void chain_enumerate(const struct chain_pieces *P, uint64_t *best, uint32_t *bc, uint32_t *bo,
+                            uint64_t *count)
+{
+    const uint32_t K = P->K;
+    uint32_t sc[16], so[16];
+    uint64_t part[16];
+    uint32_t used = 0;
+    int d = 0;
+    *best = ORC_ROUTE_INF;
+    *count = 0;
+    int have = 0;
+    /* the next candidate at depth d continues from (sc[d], so[d]) */
+    sc[0] = 0;
+    so[0] = 0;
+    for (;;) {
+        /* find the next unused (cluster, orientation) at depth d from sc/so */
+        while (sc[d] < K && (used & (1u << sc[d]))) {
+            ++sc[d];
+            so[d] = 0;
+        }
+        if (sc[d] >= K) {
+            if (d == 0) break;
+            --d;
+            used &= ~(1u << sc[d]);
+            if (++so[d] == 2) {
+                so[d] = 0;
+                ++sc[d];
+            }
+            continue;
+        }
+        const uint32_t c = sc[d], o = so[d];
+        part[d] = d == 0 ? P->plen[c][o]
+                         : add64(add64(part[d - 1], route_add(0, P->D[(size_t)P->pend[sc[d - 1]][so[d - 1]] * P->n +
+                                                                       P->pstart[c][o]])),
+                                 P->plen[c][o]);
+        if ((uint32_t)d + 1 == K) {
+            ++*count;
+            if (!have || part[d] < *best) {
+                have = 1;
+                *best = part[d];
+                for (uint32_t k = 0; k < K; ++k) {
+                    bc[k] = sc[k];
+                    bo[k] = so[k];
+                }
+            }
+            if (++so[d] == 2) {
+                so[d] = 0;
+                ++sc[d];
+            }
+            continue;
+        }
+        used |= 1u << c;
+        ++d;
+        sc[d] = 0;
+        so[d] = 0;
+    }
+}
+
+/* The same minimum by a subset programme (kept as a second method and
+ * checked against the enumeration): g(S, c, o) is the cheapest chain that
+ * starts with piece (c, o) and uses exactly the clusters of S, g({c}, c, o)
+ * = len(c, o), g(S, c, o) = len(c, o) + min over c' in S\{c}, o' of the
+ * step end(c, o) -> start(c', o') + g(S\{c}, c', o'); read back greedily
+ * (smallest cluster, then orientation) it gives the same lexicographically
+ * smallest cheapest chain. */
+static int chain_subsets(const struct chain_pieces *P, uint64_t *best, uint32_t *bc, uint32_t *bo)
+{
+    const uint32_t K = P->K, nsK = 1u << K;
+    uint64_t *gtab = (uint64_t *)malloc((size_t)nsK * K * 2 * sizeof(uint64_t));
+    if (!gtab) return -1;
+#define G(S_, c_, o_) gtab[((size_t)(S_) * K + (c_)) * 2 + (o_)]
+#define STEP(c_, o_, c2_, o2_) route_add(0, P->D[(size_t)P->pend[c_][o_] * P->n + P->pstart[c2_][o2_]])
+    for (uint32_t S = 1; S < nsK; ++S)
+        for (uint32_t c = 0; c < K; ++c) {
+            if (!(S & (1u << c))) continue;
+            const uint32_t R = S & ~(1u << c);
+            for (uint32_t o = 0; o < 2; ++o) {
+                uint64_t inner = R ? ORC_ROUTE_INF : 0;
+                for (uint32_t c2 = 0; c2 < K; ++c2) {
+                    if (!(R & (1u << c2))) continue;
+                    for (uint32_t o2 = 0; o2 < 2; ++o2) {
+                        const uint64_t v = add64(G(R, c2, o2), STEP(c, o, c2, o2));
+                        if (v < inner) inner = v;
+                    }
+                }
+                G(S, c, o) = add64(inner, P->plen[c][o]);
+            }
+        }
+    uint64_t opt = ORC_ROUTE_INF;
+    for (uint32_t c = 0; c < K; ++c)
+        for (uint32_t o = 0; o < 2; ++o)
+            if (G(nsK - 1, c, o) < opt) opt = G(nsK - 1, c, o);
+    /* every chain infinite: they all tie, the smallest sequence is every
+     * cluster in index order, forward */
+    if (opt == ORC_ROUTE_INF) {
+        for (uint32_t k = 0; k < K; ++k) {
+            bc[k] = k;
+            bo[k] = 0;
+        }
+        free(gtab);
+        *best = opt;
+        return 0;
+    }
+    uint32_t cc = 0, oo = 0;
+    while (G(nsK - 1, cc, oo) != opt) {
+        if (++oo == 2) {
+            oo = 0;
+            ++cc;
+        }
+    }
+    uint32_t S = nsK - 1;
+    for (uint32_t k = 0;; ++k) {
+        bc[k] = cc;
+        bo[k] = oo;
+        const uint32_t R = S & ~(1u << cc);
+        if (!R) break;
+        /* finite here: the rest of the chain must cost G(S, cc, oo) - len */
+        const uint64_t want = G(S, cc, oo) - P->plen[cc][oo];
+        uint32_t nc2 = 0, no2 = 0;
+        int found = 0;
+        for (uint32_t c2 = 0; c2 < K && !found; ++c2) {
+            if (!(R & (1u << c2))) continue;
+            for (uint32_t o2 = 0; o2 < 2 && !found; ++o2)
+                if (add64(G(R, c2, o2), STEP(cc, oo, c2, o2)) == want) {
+                    nc2 = c2;
+                    no2 = o2;
+                    found = 1;
+                }
+        }
+        S = R;
+        cc = nc2;
+        oo = no2;
+    }
+#undef STEP
+#undef G
+    free(gtab);
+    *best = opt;
+    return 0;
+}
+
+/* Chains K <= 16 cluster routes (pieces) over an n x n matrix D: piece k
+ * holds sizes[k] stop indices at stops + (sizes[0] + ... + sizes[k-1]);
+ * writes the cheapest chain's stops into route (n entries), its length into
+ * *cost and, with the enumeration, the chains compared into *count
+ * (by_subsets != 0 uses the subset programme instead; *count is then 0).
+ * Returns 0, or -1 for a bad size or short memory. */
+int orc_chain_routes(uint32_t K, const uint32_t *sizes, const uint32_t *stops, uint32_t n, const uint32_t *D,
+                     int by_subsets, uint64_t *cost, uint32_t *route, uint64_t *count)
+{
+    if (K == 0 || K > 16) return -1;
+    struct chain_pieces P;
+    P.K = K;
+    P.n = n;
+    P.D = D;
+    const uint32_t *first[16];
+    uint32_t at = 0;
+    for (uint32_t c = 0; c < K; ++c) {
+        if (sizes[c] == 0) return -1;
+        first[c] = stops + at;
+        at += sizes[c];
+        const uint32_t k = sizes[c];
+        P.pstart[c][0] = first[c][0];
+        P.pend[c][0] = first[c][k - 1];
+        P.pstart[c][1] = P.pend[c][0];
+        P.pend[c][1] = P.pstart[c][0];
+        P.plen[c][0] = route_len(D, n, first[c], k, 0);
+        P.plen[c][1] = route_len(D, n, first[c], k, 1);
+    }
+    uint32_t bc[16], bo[16];
+    uint64_t cnt = 0;
+    if (by_subsets) {
+        if (chain_subsets(&P, cost, bc, bo)) return -1;
+    } else {
+        chain_enumerate(&P, cost, bc, bo, &cnt);
+    }
+    if (count) *count = cnt;
+    uint32_t w = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t c = bc[k], s = sizes[c];
+        for (uint32_t t = 0; t < s; ++t) route[w++] = bo[k] ? first[c][s - 1 - t] : first[c][t];
+    }
+    return 0;
+}
+
 /* n <= 64 stops, positions xy[2n]; m clusters requested (1..16), clusters
  * of at most max_cluster (<= 20) stops, m grown up to m_max (<= 16).  Writes
  * the global route (indices 0..n-1) and its length; *m_used = clusters
- * used.  Returns 0, or -1 when no m <= m_max keeps every cluster small. */
+ * used.  The clusters' routes are chained by enumeration.  Returns 0, or -1
+ * when no m <= m_max keeps every cluster small. */
 int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32_t m, uint32_t max_cluster,
                         uint32_t m_max, uint64_t *cost, uint32_t *route, uint32_t *m_used)
 {
@@ -598,112 +862,28 @@ int orc_route_clustered(uint32_t n, const uint32_t *D, const int32_t *xy, uint32
             if (sz[c] > max_cluster) ok = 0;
         if (ok) break;
     }
-    /* per non-empty cluster: its picks in index order and their route */
-    uint32_t members[16][64], csz[16], croute[16][64], ncl = 0;
-    uint64_t flen[16], rlen[16];
+    /* per non-empty cluster (in cluster index order): its picks in index
+     * order and their optimal route */
+    uint32_t sizes[16], stops[64], ncl = 0, at = 0;
     for (uint32_t c = 0; c < mm; ++c) {
-        uint32_t k = 0;
+        uint32_t members[64], k = 0;
         for (uint32_t i = 0; i < n; ++i)
-            if (asg[i] == c) members[ncl][k++] = i;
+            if (asg[i] == c) members[k++] = i;
         if (!k) continue;
         uint32_t *sub = (uint32_t *)malloc((size_t)k * k * sizeof(uint32_t));
         if (!sub) return -1;
         for (uint32_t a = 0; a < k; ++a)
-            for (uint32_t b = 0; b < k; ++b) sub[a * k + b] = D[(size_t)members[ncl][a] * n + members[ncl][b]];
+            for (uint32_t b = 0; b < k; ++b) sub[a * k + b] = D[(size_t)members[a] * n + members[b]];
         uint64_t cl;
         uint32_t lr[64];
         const int rc = orc_route_held_karp(k, sub, &cl, lr);
         free(sub);
         if (rc) return -1;
-        for (uint32_t t = 0; t < k; ++t) croute[ncl][t] = members[ncl][lr[t]];
-        csz[ncl] = k;
-        flen[ncl] = route_len(D, n, croute[ncl], k, 0);
-        rlen[ncl] = route_len(D, n, croute[ncl], k, 1);
-        ++ncl;
+        for (uint32_t t = 0; t < k; ++t) stops[at + t] = members[lr[t]];
+        sizes[ncl++] = k;
+        at += k;
     }
-    /* chain the clusters.  A piece is a cluster route in one orientation
-     * (o = 0 forward, 1 reversed); g(S, c, o) is the cheapest chain that
-     * starts with piece (c, o) and uses exactly the clusters of S:
-     * g({c}, c, o) = len(c, o), g(S, c, o) = len(c, o) + min over c' in
-     * S\{c}, o' of D[end(c, o)][start(c', o')] + g(S\{c}, c', o').  This is
-     * the minimum over every order and orientation of the cluster routes;
-     * the chain read back greedily is the lexicographically smallest
-     * sequence of (cluster, orientation) among the cheapest. */
-    const uint32_t K = ncl, nsK = 1u << K;
-    uint64_t *gtab = (uint64_t *)malloc((size_t)nsK * K * 2 * sizeof(uint64_t));
-    if (!gtab) return -1;
-#define G(S_, c_, o_) gtab[((size_t)(S_) * K + (c_)) * 2 + (o_)]
-    uint32_t pstart[16][2], pend[16][2];
-    uint64_t plen[16][2];
-    for (uint32_t c = 0; c < K; ++c) {
-        pstart[c][0] = croute[c][0];
-        pend[c][0] = croute[c][csz[c] - 1];
-        pstart[c][1] = pend[c][0];
-        pend[c][1] = pstart[c][0];
-        plen[c][0] = flen[c];
-        plen[c][1] = rlen[c];
-    }
-    for (uint32_t S = 1; S < nsK; ++S)
-        for (uint32_t c = 0; c < K; ++c) {
-            if (!(S & (1u << c))) continue;
-            const uint32_t R = S & ~(1u << c);
-            for (uint32_t o = 0; o < 2; ++o) {
-                uint64_t inner = R ? ORC_ROUTE_INF : 0;
-                for (uint32_t c2 = 0; c2 < K; ++c2) {
-                    if (!(R & (1u << c2))) continue;
-                    for (uint32_t o2 = 0; o2 < 2; ++o2) {
-                        const uint64_t v = route_add(G(R, c2, o2), D[(size_t)pend[c][o] * n + pstart[c2][o2]]);
-                        if (v < inner) inner = v;
-                    }
-                }
-                G(S, c, o) = (inner == ORC_ROUTE_INF || plen[c][o] == ORC_ROUTE_INF) ? ORC_ROUTE_INF
-                                                                                      : inner + plen[c][o];
-            }
-        }
-    uint64_t best = ORC_ROUTE_INF;
-    for (uint32_t c = 0; c < K; ++c)
-        for (uint32_t o = 0; o < 2; ++o)
-            if (G(nsK - 1, c, o) < best) best = G(nsK - 1, c, o);
-    uint32_t cc = 0, oo = 0;
-    while (G(nsK - 1, cc, oo) != best) {
-        if (++oo == 2) {
-            oo = 0;
-            ++cc;
-        }
-    }
-    uint32_t S = nsK - 1, w = 0;
-    for (;;) {
-        for (uint32_t t = 0; t < csz[cc]; ++t) route[w++] = oo ? croute[cc][csz[cc] - 1 - t] : croute[cc][t];
-        const uint32_t R = S & ~(1u << cc);
-        if (!R) break;
-        uint64_t inner = ORC_ROUTE_INF;
-        for (uint32_t c2 = 0; c2 < K; ++c2)
-            if (R & (1u << c2))
-                for (uint32_t o2 = 0; o2 < 2; ++o2) {
-                    const uint64_t v = route_add(G(R, c2, o2), D[(size_t)pend[cc][oo] * n + pstart[c2][o2]]);
-                    if (v < inner) inner = v;
-                }
-        uint32_t nc2 = 0, no2 = 0;
-        for (uint32_t c2 = 0; c2 < K; ++c2) {
-            if (!(R & (1u << c2))) continue;
-            if (route_add(G(R, c2, 0), D[(size_t)pend[cc][oo] * n + pstart[c2][0]]) == inner) {
-                nc2 = c2;
-                no2 = 0;
-                break;
-            }
-            if (route_add(G(R, c2, 1), D[(size_t)pend[cc][oo] * n + pstart[c2][1]]) == inner) {
-                nc2 = c2;
-                no2 = 1;
-                break;
-            }
-        }
-        S = R;
-        cc = nc2;
-        oo = no2;
-    }
-#undef G
-    free(gtab);
-    *cost = best;
+    if (orc_chain_routes(ncl, sizes, stops, n, D, 0, cost, route, NULL)) return -1;
     *m_used = mm;
     return 0;
 }

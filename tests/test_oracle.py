@@ -333,6 +333,15 @@ def _route_cases():
         cases.append(m)
         pts = rng.integers(0, 20, (n, 2))
         cases.append(np.abs(pts[:, None, :] - pts[None, :, :]).sum(-1))   # L1 metric
+    for n in range(3, 8):
+        # one stop cut off from the rest: every ordering is infinite, while
+        # paths among the other stops stay finite (the tie-break must not
+        # follow them)
+        m = rng.integers(1, 40, (n, n))
+        k = int(rng.integers(0, n))
+        m[k, :] = INF
+        m[:, k] = INF
+        cases.append(m)
     for m in cases:
         np.fill_diagonal(m, 0)
     return [m.astype(np.uint32) for m in cases]
@@ -385,38 +394,172 @@ def test_order_routes_batches_orders():
 
 # ------------------------------------------------- cluster-decomposed routes
 def test_theorem_counts_match_paper():
-    """The candidates the clustered route compares -- every order of the
-    cluster routes times every orientation -- number m!2^m directed, i.e.
-    m!2^(m-1) undirected global routes (the theorem), and with (n_j!)/2
-    undirected routes inside each cluster the totals are the printed ones."""
-    import itertools
+    """The printed costs of the theorem (m!2^(m-1) undirected chains plus
+    n_j!/2 undirected routes inside each of the m clusters) from the
+    candidates the oracle itself compares: its chaining enumeration counts
+    m!2^m directed chains and its route enumeration n_j! directed orderings,
+    each pair of travel directions making one undirected route."""
     import math
     vals = {}
     for l in open(_golden("paper_numbers.txt")):
         l = l.split("#")[0].split()
         if l:
             vals[l[0]] = int(float(l[1]))
-
-    def undirected(seqs):
-        return {min(s, s[::-1]) for s in seqs}
-
     for key, n, m in (("thm_n12_m2", 12, 2), ("thm_n12_m3", 12, 3), ("thm_n12_m4", 12, 4), ("thm_n15_m3", 15, 3)):
         k = n // m
-        routes = [tuple(range(c * k, (c + 1) * k)) for c in range(m)]
-        glob = set()
-        for perm in itertools.permutations(range(m)):
-            for mask in range(1 << m):
-                seq = ()
-                for c in perm:
-                    seq += routes[c][::-1] if (mask >> c) & 1 else routes[c]
-                glob.add(seq)
-        assert len(glob) == math.factorial(m) * 2 ** m
-        n_glob = len(undirected(glob))
-        assert n_glob == math.factorial(m) * 2 ** (m - 1)
-        # undirected routes inside a cluster of k stops, by enumeration for
-        # small k (k! / 2 for k >= 2)
-        inner = len(undirected(itertools.permutations(range(k)))) if k <= 7 else math.factorial(k) // 2
-        assert n_glob + m * inner == vals[key], key
+        D = np.zeros((n, n), np.uint32)
+        pieces = [list(range(c * k, (c + 1) * k)) for c in range(m)]
+        _, chain, n_chains = oracle.chain_routes(pieces, D)
+        assert sorted(chain.tolist()) == list(range(n))
+        assert n_chains == math.factorial(m) * 2 ** m
+        inner = 0
+        for p in pieces:
+            _, _, n_orderings = oracle.route_enumerate(D[np.ix_(p, p)])
+            assert n_orderings == math.factorial(len(p))
+            inner += n_orderings // 2
+        assert n_chains // 2 + inner == vals[key], key
+
+
+def test_route_held_karp_matches_c_enumeration():
+    """The subset programme against the second, independent method (every
+    ordering in C) at the sizes the GPU serves, up to 10 stops (and one of
+    11): lengths and the lexicographic tie-break."""
+    rng = np.random.default_rng(21)
+    for n in (8, 9, 10):
+        for kind in range(4):
+            if kind == 0:
+                D = rng.integers(0, 60, (n, n))
+            elif kind == 1:
+                D = rng.integers(0, 3, (n, n))
+            elif kind == 2:
+                D = rng.integers(1, 40, (n, n))
+                D[rng.random((n, n)) < 0.35] = INF
+            else:
+                pts = rng.integers(0, 12, (n, 2))
+                D = np.abs(pts[:, None, :] - pts[None, :, :]).sum(-1)
+            if n == 9 and kind == 2:
+                # a stop cut off from the rest: every ordering infinite
+                D[n // 2, :] = INF
+                D[:, n // 2] = INF
+            D = D.astype(np.uint32)
+            np.fill_diagonal(D, 0)
+            c1, r1 = oracle.route(D)
+            c2, r2, cnt = oracle.route_enumerate(D)
+            assert c1 == c2 and r1.tolist() == r2.tolist(), (n, kind)
+            import math
+            assert cnt == math.factorial(n)
+    D = rng.integers(0, 4, (11, 11)).astype(np.uint32)
+    np.fill_diagonal(D, 0)
+    c1, r1 = oracle.route(D)
+    c2, r2, _ = oracle.route_enumerate(D)
+    assert c1 == c2 and r1.tolist() == r2.tolist()
+
+
+def test_route_c_enumeration_matches_python():
+    """The C enumeration against the pure-Python one (itertools) on the
+    small case families, INF steps and ties included."""
+    from oracle.brute import route_by_enumeration
+    for D in _route_cases():
+        c, r, _ = oracle.route_enumerate(D)
+        best, p = route_by_enumeration(D.tolist())
+        assert c == (oracle.ROUTE_INF if best is None else best)
+        assert r.tolist() == p
+
+
+def _random_pieces(rng, K, n_extra=0):
+    """K cluster routes over n = sum of sizes stops (sizes 1..4), shuffled."""
+    sizes = rng.integers(1, 5, K)
+    n = int(sizes.sum()) + n_extra
+    perm = rng.permutation(n)[:int(sizes.sum())]
+    pieces, at = [], 0
+    for s in sizes:
+        pieces.append(perm[at:at + s].tolist())
+        at += s
+    return pieces, n
+
+
+def test_chain_subsets_match_enumeration():
+    """The chaining subset programme (second method) against the plain
+    enumeration of every order and orientation, K up to 8 clusters, on
+    asymmetric, tie-heavy and INF-bearing matrices."""
+    rng = np.random.default_rng(22)
+    for case in range(60):
+        K = 1 + case % 8
+        pieces, n = _random_pieces(rng, K, n_extra=case % 3)
+        kind = case % 4
+        if kind == 0:
+            D = rng.integers(0, 50, (n, n))
+        elif kind == 1:
+            D = rng.integers(0, 3, (n, n))
+        elif kind == 2:
+            D = rng.integers(1, 30, (n, n))
+            D[rng.random((n, n)) < 0.3] = INF
+        else:
+            # one stop cut off: every chain infinite while parts stay finite
+            D = rng.integers(1, 30, (n, n))
+            k = pieces[-1][0]
+            D[k, :] = INF
+            D[:, k] = INF
+        D = D.astype(np.uint32)
+        np.fill_diagonal(D, 0)
+        c1, r1, cnt = oracle.chain_routes(pieces, D)
+        c2, r2, _ = oracle.chain_routes(pieces, D, by_subsets=True)
+        assert c1 == c2 and r1.tolist() == r2.tolist(), case
+        import math
+        assert cnt == math.factorial(K) * 2 ** K
+
+
+def _py_chain(pieces, D):
+    """Cheapest chain by itertools: every order of the pieces times every
+    orientation; the smallest (cluster, orientation) sequence among the
+    cheapest.  Returns (length or None if infinite, stops)."""
+    import itertools
+    best = None
+    for perm in itertools.permutations(range(len(pieces))):
+        for ori in itertools.product((0, 1), repeat=len(pieces)):
+            seq = []
+            for c, o in zip(perm, ori):
+                seq += pieces[c][::-1] if o else pieces[c]
+            length = 0
+            for a, b in zip(seq, seq[1:]):
+                if D[a][b] == INF:
+                    length = None
+                    break
+                length += int(D[a][b])
+            key = list(zip(perm, ori))
+            if best is None or (length is not None and (best[0] is None or length < best[0])):
+                if best is None or length is not None:
+                    best = (length, key, seq)
+    return best[0], best[2]
+
+
+def test_clustered_route_by_python_enumeration():
+    """Whole clustered routes at 8..12 stops and 4..6 clusters against a
+    pure-Python reconstruction: the oracle's K-means partition (pinned on
+    its own), each cluster's route by trying every ordering of its stops,
+    and the chaining by trying every order and orientation."""
+    from oracle.brute import route_by_enumeration
+    rng = np.random.default_rng(23)
+    for case in range(18):
+        n = int(rng.integers(8, 13))
+        m = int(rng.integers(4, 7))
+        xy = rng.integers(0, 40, (n, 2))
+        D = _metric(xy) if case % 2 == 0 else rng.integers(1, 40, (n, n)).astype(np.uint32)
+        np.fill_diagonal(D, 0)
+        cost, route, mu = oracle.route_clustered(D, xy, m)
+        assert mu == m
+        asg = oracle.kmeans(xy, m)
+        pieces = []
+        for c in range(m):
+            mem = np.flatnonzero(asg == c)
+            if len(mem) == 0:
+                continue
+            sub = D[np.ix_(mem, mem)].tolist()
+            _, r = route_by_enumeration(sub)
+            pieces.append(mem[r].tolist())
+        length, seq = _py_chain(pieces, D.tolist())
+        assert cost == length, (case, cost, length)
+        assert route.tolist() == seq, case
 
 
 def _blob_points(rng, n, m, spread=3, gap=100):
