@@ -1,25 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the warehouse routing hot path on one MI355X.
 
-One step = one wr_order_matrices call over the whole batch of the medium
-workload (512x512 rack grid, 256 orders x 32 picks, multi-source relaxation
-in one call): planning, relaxation of every distinct pick, and the gather of
-all 256 pick-to-pick matrices into device memory.  The graph is uploaded
-(and segmented) before the timed region; picks are host index arrays, as the
-C ABI defines them.
+Headline (one JSON line): routed orders/s on the uneven-batch workload, the
+largest single-GPU order workload: a 2048x2048 rack-aisle grid
+(V=4,194,304, E=8,567,292), 10k orders whose pick lists (sizes geometric
+with mean 12, clipped to 2..64) are drawn from 100k Zipf(1.1)-popular
+slots, all orders in one wr_order_matrices call.  One step = that call with
+host pick arrays in and every order's P x P matrix host-visible out:
+planning, relaxation of every distinct pick, the gather of all matrices and
+their copy to the host.  The graph is uploaded, segmented and autotuned
+(grid tile shape, blocks per unit, passes per replay) before the timed
+region; the tuning time is reported beside the rate.
 
-Prints ONE JSON line:
-  value        routed orders/s (whole job; one GPU)
-  roofline     dominant kernel (the relaxation pass of the schedule) against HBM:
-               algorithmic bytes per launch / its average launch duration,
-               timed live with HIP events recorded around each launch
-  cpu_baseline the CPU oracle (Dijkstra per distinct pick, all host cores)
-               on a bounded sample of the same orders
-  route_leg    the next step on the path: exact open routes (wr_order_routes)
-               over 12-stop windows of the batch's own matrices, routes/s,
-               with its ALU roofline and the CPU oracle beside it; and
-               cluster-decomposed routes (wr_order_routes_clustered) over
-               the whole 32-pick orders
+Beside the headline:
+  roofline      the dominant kernel (the overlay pass) against HBM:
+                algorithmic bytes per launch (the byte model: 8 B per
+                reached vertex per distinct source + 8 B per reached arc per
+                block of 64 sources) / its average launch duration, timed
+                live with HIP events on the library's stream; `traffic` is
+                the bytes the pass really moves (rocprofv3 FETCH_SIZE and
+                WRITE_SIZE, scaled by a copy of known size) per launch over
+                the same duration, when the committed counters were taken on
+                the current kernel source
+  cpu_baseline  the CPU oracle (Dijkstra per distinct pick, all host cores)
+                on a bounded sample of the same orders
+  legs          medium (512x512, 256 orders x 32 picks), segmented (4096x4096
+                in 256x256 segments, 1024 sources: GTEPS of full distance
+                rows, segmented vs unsegmented), tiny (20x40, one order of 8
+                picks; the paper-structured baseline in the paper's
+                (V-1)E/t convention), the paper-structured baseline B1 (one
+                order at a time, thread per arc) on medium and uneven
+  route_leg     exact routes over windows of the medium batch's matrices and
+                cluster-decomposed routes over its whole orders
+  serving       the continuous-batching server on 3 x 1024^2 levels at
+                Poisson rates 500, 2000 and 8000 orders/s (p50/p99)
 """
 from __future__ import annotations
 
@@ -37,7 +51,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit integer VALU ops: CUs x SIMDs x lanes x clock
 PASS_KERNEL = {"overlay": "k_ovl_pass", "segmented": "k_segb_pass"}
+DEFAULT_SEGMENT = (24, 20)   # grid tile the tuner starts from
 
 
 def parse():
@@ -45,25 +61,52 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--algo", default="overlay")
-    ap.add_argument("--tile", type=int, default=512, help="tile vertices (0 = library default)")
-    ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--passes", type=int, default=0)
-    ap.add_argument("--segment", default="grid:24x20", help="auto | grid:TWxTH")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU work of the oracle sample (core-seconds)")
+    ap.add_argument("--legs", default="medium,segmented,tiny,routes,serving",
+                    help="legs beside the uneven headline, comma-separated ('' = none)")
+    ap.add_argument("--no-autotune", action="store_true", help="run the 24x20 grid tiles untuned")
+    ap.add_argument("--autotune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "wroute_tune"),
+                    help="directory of the autotuner's JSON caches")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="target CPU work of each oracle sample (core-seconds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--b1-orders", type=int, default=2,
-                    help="orders of the paper-structured B1 baseline to time (0 = skip)")
-    ap.add_argument("--serve-rates", default="500,2000",
-                    help="Poisson arrival rates (orders/s) of the serving leg, comma-separated ('' = skip)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
-    ap.add_argument("--route-stops", type=int, default=12,
-                    help="stops per route in the exact-route leg (0 = skip the leg)")
+    ap.add_argument("--b1-orders", type=int, default=1,
+                    help="orders of the paper-structured B1 baseline to time per workload (0 = skip)")
+    ap.add_argument("--serve-rates", default="500,2000,8000",
+                    help="Poisson arrival rates (orders/s) of the serving leg, comma-separated")
+    ap.add_argument("--serve-seconds", type=float, default=1.5, help="arrival window per rate")
+    ap.add_argument("--route-stops", type=int, default=12, help="stops per route in the exact-route leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device once (a dispatch of known "
                          "traffic that scales the HBM byte counters of a profiler run)")
     return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def graph_for(wr, ctx, wl, tune=True, cache_dir=None):
+    """The launch configuration the benchmark times (and the full-size
+    parity tests check): the workload's grid cut into grid tiles, the
+    overlay schedule with tiles of at most 512 vertices, tuned by
+    wr_autotune on as many spread sources as the workload has distinct
+    picks.  Returns (graph, tuning seconds)."""
+    g = wl.graph
+    G = wr.Graph(ctx, g.row_ptr, g.col, g.w)
+    G.set_schedule(512, 8, 0)
+    tw, th = wl.segment_tile or DEFAULT_SEGMENT
+    G.segment_grid(g.W, g.H, g.levels, tw, th)
+    t = 0.0
+    if tune and wl.segment_tile is None:
+        hint = int(min(32768, len(np.unique(wl.picks)))) if wl.picks is not None else 4096
+        cache = None
+        if cache_dir:
+            os.makedirs(cache_dir, exist_ok=True)
+            cache = os.path.join(cache_dir, f"{wl.name}_{g.W}x{g.H}x{g.levels}.json")
+        t0 = time.perf_counter()
+        G.autotune(hint, cache)
+        t = time.perf_counter() - t0
+    return G, t
 
 
 def reach_tables(g):
@@ -86,11 +129,11 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
+def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch of the pass kernel from the committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", f"{kernel}_medium_traffic.json")))
+        t = json.load(open(os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")))
     except (OSError, ValueError):
         return None
     if t.get("kernel_src_sha") != kernel_source_sha():
@@ -98,7 +141,269 @@ def load_traffic(kernel: str):
     return t.get("bytes_per_launch")
 
 
-def serving_leg(wr, ctx, rates, seconds, tile):
+def copy_bandwidth_gbs(mib=2048):
+    """Device-to-device copy rate (read + write bytes per second), the
+    practical HBM ceiling the measured traffic is also compared with."""
+    import torch
+    n = mib << 18
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = 2.0 * n * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return bw
+
+
+def order_leg(wr, wl, G, steps, warmup, tag, host_out=True, copy_gbs=None):
+    """Times one whole-batch wr_order_matrices call per step; with host_out
+    the matrices come back to host memory inside the timed region."""
+    import torch
+    g = wl.graph
+    off, picks = wl.pick_offsets, wl.picks
+    n_orders = wl.num_orders
+    total = int((np.diff(off.astype(np.int64)) ** 2).sum())
+    out = None if host_out else torch.empty(total, dtype=torch.int32, device="cuda")
+
+    def step():
+        if host_out:
+            return G.order_matrices(off, picks, algo="overlay")
+        G.order_matrices(off, picks, out=out, algo="overlay")
+        torch.cuda.synchronize()
+        return out
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, passes, items = [], 0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        step()
+        lat.append(time.perf_counter() - ts)
+        info = G.last_run()
+        passes += info["passes"]
+        items += info["work_items"]
+    elapsed = time.perf_counter() - t0
+    log(f"{tag}: {n_orders * steps / elapsed:.0f} orders/s, {elapsed / steps * 1e3:.2f} ms per step")
+
+    # kernel-timing region: the same steps with HIP events recorded on the
+    # library's stream around every launch of the pass kernel (passes are
+    # launched eagerly so each launch can be bracketed)
+    kern_ms, kern_n, kern_bytes, kern_relax = 0.0, 0, 0, 0
+    for _ in range(steps):
+        G.order_matrices(off, picks, algo="overlay", time_kernels=True)
+        ti = G.last_run()
+        kern_ms += ti["kernel_ms"]
+        kern_n += ti["kernel_launches"]
+        kern_bytes += ti["alg_bytes"]
+        kern_relax += ti["relaxations"]
+
+    # useful work of one step: every distinct pick relaxes its reachable arcs
+    vreach, ereach = reach_tables(g)
+    uniq = np.unique(picks)
+    useful_arcs = float(ereach[uniq].sum())
+    # the plain relaxation's byte model: each reached (vertex, source)
+    # distance written and read once, each reached arc streamed once per
+    # block of 64 sources; the overlay moves far less than this, so the
+    # model's rate is an equivalent bandwidth, not a bound
+    model_bytes = float((8.0 * vreach[uniq] + 8.0 * ereach[uniq] / 64.0).sum())
+    ms_per_step = elapsed / steps * 1e3
+    kern_ms_step = kern_ms / steps
+    launches_step = kern_n / steps
+    avg_launch_s = kern_ms_step / max(launches_step, 1) * 1e-3
+    # the pass's own algorithmic bytes (library counters): a 256-byte row of
+    # 64 source values per incoming cross arc and per exit of every visited
+    # tile, 4 bytes per exit value stored
+    alg_per_launch = kern_bytes / max(kern_n, 1)
+    achieved = alg_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else None
+    model_gbs = model_bytes / max(launches_step, 1) / avg_launch_s / 1e9 if avg_launch_s > 0 else None
+    traffic_b = load_traffic("k_ovl_pass", wl.name)
+    traffic = traffic_b / avg_launch_s / 1e9 if traffic_b and avg_launch_s > 0 else None
+    seg = G.segment_info()
+    res = {
+        "orders_per_s": round(n_orders * steps / elapsed, 1),
+        "ms_per_step": round(ms_per_step, 4),
+        "p50_batch_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+        "p99_batch_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+        "output": "host" if host_out else "device",
+        "orders": n_orders, "picks": int(len(picks)), "unique_sources": int(len(uniq)),
+        "matrix_entries": total,
+        "gteps": round(useful_arcs / (ms_per_step * 1e-3) / 1e9, 2),
+        "passes_per_step": passes / steps,
+        "visits_per_step": items / steps,
+        "schedule": G.schedule(), "tiles": seg["tiles"], "ports": seg["boundary"],
+        "roofline": {
+            "kernel": "k_ovl_pass", "bound": "hbm",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": round(traffic, 1) if traffic else None,
+            "traffic_frac": round(traffic / HBM_PEAK_GBS, 4) if traffic else None,
+            "traffic_vs_copy": round(traffic / copy_gbs, 4) if traffic and copy_gbs else None,
+            "traffic_bytes_per_launch": traffic_b,
+            "alg_bytes_per_launch": round(alg_per_launch),
+            "launches_per_step": launches_step,
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "kernel_ms_per_step": round(kern_ms_step, 3),
+            "plain_bf_model_gbs": round(model_gbs, 1) if model_gbs else None,
+            "plain_bf_model_bytes_per_step": model_bytes,
+        },
+        "relaxations_per_s": round(kern_relax / max(kern_ms, 1e-9) * 1e3, 1),
+    }
+    return res
+
+
+def cpu_orders_baseline(wl, core_seconds):
+    """The oracle (one Dijkstra per distinct pick, all host threads) on the
+    first orders of the batch, sized to about `core_seconds` of CPU work."""
+    import oracle
+    g = wl.graph
+    off, picks = wl.pick_offsets, wl.picks
+    t = time.perf_counter()
+    oracle.dijkstra(g.row_ptr, g.col, g.w, int(picks[0]))
+    per_src = time.perf_counter() - t
+    mean_p = len(picks) / max(wl.num_orders, 1)
+    k = int(max(1, min(wl.num_orders, round(core_seconds / max(per_src, 1e-4) / mean_p))))
+    threads = oracle.max_threads()
+    sub_off = off[:k + 1]
+    sub_picks = picks[:int(sub_off[-1])]
+    t = time.perf_counter()
+    oracle.order_matrices(g.row_ptr, g.col, g.w, sub_off, sub_picks, nthreads=threads)
+    wall = time.perf_counter() - t
+    n_src = len(np.unique(sub_picks))
+    return {"value": round(k / wall, 3), "unit": "orders/s", "cores": int(min(threads, n_src)),
+            "kind": "oracle",
+            "sample": f"first {k} of {wl.num_orders} orders ({n_src} distinct picks, one "
+                      f"Dijkstra each, {wall:.1f} s wall)"}
+
+
+def b1_leg(G, wl, k):
+    """The paper's structure on the same GPU: one order at a time, one
+    thread per arc, the order's picks looped in each thread, one launch per
+    round and a host-read changed flag."""
+    import torch
+    off, picks = wl.pick_offsets, wl.picks
+    k = min(k, wl.num_orders)
+    sub_off = off[:k + 1]
+    sub_picks = picks[:int(sub_off[-1])]
+    sizes = np.diff(sub_off.astype(np.int64))
+    o1 = torch.empty(int((sizes ** 2).sum()), dtype=torch.int32, device="cuda")
+    t = time.perf_counter()
+    G.order_matrices(sub_off, sub_picks, out=o1, algo="edge_b1")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    return {"value": round(k / tb, 3), "unit": "orders/s",
+            "sample": f"first {k} orders, one order at a time, thread per arc, "
+                      f"host-checked early exit ({G.last_run()['passes']} rounds)"}
+
+
+def segmented_leg(wr, ctx, steps):
+    """4096x4096 grid in 256x256-cell segments (cut into LDS tiles of at most
+    512 vertices), 1024 sources: full distance rows of every source into
+    device memory (GTEPS), the 1024 x 1024 matrix between the sources, and
+    the unsegmented frontier schedule on a bounded sample of sources."""
+    import torch
+    from wgen import make_config
+    wl = make_config("segmented")
+    g = wl.graph
+    src = wl.sources
+    G, _ = graph_for(wr, ctx, wl, tune=False)
+    vreach, ereach = reach_tables(g)
+    useful = float(ereach[src].sum())
+    out = torch.empty(len(src) * g.V, dtype=torch.int32, device="cuda")
+    G.sssp(src, algo="overlay", out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = max(1, min(steps, 3))
+    for _ in range(reps):
+        G.sssp(src, algo="overlay", out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    info = G.last_run()
+    del out
+    torch.cuda.empty_cache()
+    log(f"segmented: {len(src)} full rows in {dt * 1e3:.1f} ms")
+    off = np.array([0, len(src)], dtype=np.uint32)
+    mo = torch.empty(len(src) ** 2, dtype=torch.int32, device="cuda")
+    G.order_matrices(off, src, out=mo, algo="overlay")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        G.order_matrices(off, src, out=mo, algo="overlay")
+    torch.cuda.synchronize()
+    dm = (time.perf_counter() - t) / reps
+    # unsegmented: the frontier schedule over the whole graph, one source
+    # at a time (its cost per source grows with the sources sharing a block)
+    ns = 2
+    fo = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    t = time.perf_counter()
+    for i in range(ns):
+        G.sssp(src[i:i + 1], algo="frontier", out=fo)
+    torch.cuda.synchronize()
+    df = (time.perf_counter() - t) / ns
+    seg = G.segment_info()
+    G.close()
+    return {"workload": f"segmented: 4096x4096 rack-aisle grid (V={g.V}, E={g.E}), 256x256-cell segments "
+                        f"({seg['tiles']} LDS tiles, {seg['boundary']} ports), {len(src)} sources",
+            "full_rows_ms": round(dt * 1e3, 3), "gteps": round(useful / dt / 1e9, 2),
+            "passes": info["passes"], "visits": info["work_items"],
+            "matrix_1024_ms": round(dm * 1e3, 3),
+            "segmented_ms_per_source": round(dt * 1e3 / len(src), 4),
+            "unsegmented_frontier_ms_per_source": round(df * 1e3, 3),
+            "unsegmented_sample": f"{ns} sources, one per call, frontier schedule",
+            "segmented_speedup_per_source": round(df / (dt / len(src)), 1)}
+
+
+def tiny_leg(wr, ctx, steps):
+    """20x40 grid, one order of 8 picks: the overlay call (µs per order) and
+    the paper-faithful baseline B0 (exactly V-1 rounds, the 8 picks looped in
+    each arc's thread), quoted in the paper's (V-1)E/t convention."""
+    import torch
+    from wgen import make_config
+    wl = make_config("tiny")
+    g = wl.graph
+    G, _ = graph_for(wr, ctx, wl, tune=False)
+    off, picks = wl.pick_offsets, wl.picks
+    out = torch.empty(64, dtype=torch.int32, device="cuda")
+    G.order_matrices(off, picks, out=out, algo="overlay")
+    torch.cuda.synchronize()
+    n = max(steps, 20)
+    t = time.perf_counter()
+    for _ in range(n):
+        G.order_matrices(off, picks, out=out, algo="overlay")
+    torch.cuda.synchronize()
+    do = (time.perf_counter() - t) / n
+    rows = torch.empty(len(picks) * g.V, dtype=torch.int32, device="cuda")
+    G.sssp(picks, algo="edge_b0", out=rows)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    G.sssp(picks, algo="edge_b0", out=rows)
+    torch.cuda.synchronize()
+    d0 = time.perf_counter() - t
+    r0 = G.last_run()["passes"]
+    t = time.perf_counter()
+    G.sssp(picks, algo="edge_b1", out=rows)
+    torch.cuda.synchronize()
+    d1 = time.perf_counter() - t
+    r1 = G.last_run()["passes"]
+    G.close()
+    return {"workload": f"tiny: 20x40 grid (V={g.V}, E={g.E}), 1 order x 8 picks",
+            "overlay_us_per_order": round(do * 1e6, 1),
+            "b0_ms": round(d0 * 1e3, 3), "b0_rounds": r0,
+            "b0_mteps_paper_convention": round((g.V - 1) * g.E / d0 / 1e6, 1),
+            "b1_ms": round(d1 * 1e3, 3), "b1_rounds": r1,
+            "paper_context": "2627 MTEPS at V=9,716, E=26,999 on an RTX 6000 (GPU Implementation subsection)"}
+
+
+def serving_leg(wr, ctx, rates, seconds):
     """Continuous-batching server on the serving warehouse (3 levels of
     1024x1024 joined by lifts): Poisson order arrivals with sizes uniform in
     2..128, and 1% congestion updates every 100 ms applied between steps.
@@ -108,9 +413,7 @@ def serving_leg(wr, ctx, rates, seconds, tile):
     wl = make_config("serving")
     g = wl.graph
     ex = wl.extra
-    G = wr.Graph(ctx, g.row_ptr, g.col, g.w)
-    G.set_schedule(tile, 8, 0)
-    G.segment_grid(g.W, g.H, g.levels, 24, 20)
+    G, _ = graph_for(wr, ctx, wl, tune=False)
     rng = np.random.default_rng(wl.seed + 7)
     cand = g.aisle_adjacent_vertices()
 
@@ -148,6 +451,7 @@ def serving_leg(wr, ctx, rates, seconds, tile):
                     break
                 time.sleep(min(target - now, 0.0005))
             tickets.append(srv.submit(orders[i]))
+        t_sub = time.perf_counter() - t0
         srv.drain()
         wall = time.perf_counter() - t0
         st = srv.stats()
@@ -157,17 +461,16 @@ def serving_leg(wr, ctx, rates, seconds, tile):
         out.append({"rate": rate, "orders": n, "weight_ticks": ticks,
                     "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                     "mean_ms": round(st["mean_ms"], 3), "orders_per_s": round(n / wall, 1),
+                    "arrival_window_s": round(t_sub, 3), "wall_s": round(wall, 3),
+                    "saturated": bool(n / wall < 0.9 * rate),
                     "max_inflight": st["max_inflight_requests"], "steps": st["steps"],
                     "failed": st["failed"]})
-        print(f"serving rate {rate}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
-              f"({n} orders, {ticks} weight ticks)", file=sys.stderr, flush=True)
+        log(f"serving rate {rate}/s: {n / wall:.0f} orders/s completed, p50 {st['p50_ms']:.2f} ms "
+            f"p99 {st['p99_ms']:.2f} ms ({n} orders, {ticks} weight ticks)")
     G.close()
     return {"workload": "serving: 3 levels of 1024x1024 (V=3,145,728, E=6,422,650), 64 lifts (w=50), "
                         "P ~ U{2..128}, 1% congestion per 100 ms",
             "seconds_per_rate": seconds, "runs": out}
-
-
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit integer VALU ops: CUs x SIMDs x lanes x clock
 
 
 def route_leg(wr, ctx, D_host, n_orders, P, stops, steps, warmup, with_cpu):
@@ -269,28 +572,6 @@ def cluster_leg(wr, ctx, D_host, off, picks, W, m, steps, warmup, with_cpu):
     return res
 
 
-def cpu_baseline(wl, target_core_s: float):
-    import oracle
-    g = wl.graph
-    off, picks = wl.pick_offsets, wl.picks
-    t = time.perf_counter()
-    oracle.dijkstra(g.row_ptr, g.col, g.w, int(picks[0]))
-    per_src = time.perf_counter() - t
-    P = int(off[1] - off[0])
-    k = int(max(1, min(wl.num_orders, round(target_core_s / max(per_src, 1e-4) / P))))
-    threads = oracle.max_threads()
-    sub_off = off[:k + 1]
-    sub_picks = picks[:int(sub_off[-1])]
-    t = time.perf_counter()
-    oracle.order_matrices(g.row_ptr, g.col, g.w, sub_off, sub_picks, nthreads=threads)
-    wall = time.perf_counter() - t
-    n_src = len(np.unique(sub_picks))
-    return {"value": round(k / wall, 3), "unit": "orders/s", "cores": int(min(threads, n_src)),
-            "kind": "oracle",
-            "sample": f"first {k} of {wl.num_orders} orders ({n_src} distinct picks, one "
-                      f"Dijkstra each, {wall:.1f} s wall)"}
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -301,136 +582,90 @@ def main():
     import paper_2504_20655_amd as wr
     from wgen import make_config
 
-    wl = make_config("medium")
-    g = wl.graph
-    off, picks = wl.pick_offsets, wl.picks
-    n_orders = wl.num_orders
-    total = int((np.diff(off.astype(np.int64)) ** 2).sum())
-
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    with_cpu = not args.no_cpu_baseline
     ctx = wr.Context(0)
-    G = wr.Graph(ctx, g.row_ptr, g.col, g.w)
-    if args.tile or args.waves or args.passes:
-        G.set_schedule(args.tile, args.waves, args.passes)
-    if args.segment.startswith("grid:"):
-        tw, th = (int(x) for x in args.segment[5:].split("x"))
-        G.segment_grid(g.W, g.H, 1, tw, th)
-    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    copy_gbs = copy_bandwidth_gbs()
 
-    # throughput region: passes replayed from captured hipGraphs
-    for _ in range(args.warmup):
-        G.order_matrices(off, picks, out=out, algo=args.algo)
-    torch.cuda.synchronize()
-    lat, relax_ms, passes, items = [], 0.0, 0, 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        G.order_matrices(off, picks, out=out, algo=args.algo)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
-        info = G.last_run()
-        relax_ms += info["relax_ms"]
-        passes += info["passes"]
-        items += info["work_items"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    info = G.last_run()
-
-    # kernel-timing region: the same steps with HIP events recorded on the
-    # library's stream around every launch of the relaxation kernel (passes
-    # are launched eagerly so each launch can be bracketed)
-    G.order_matrices(off, picks, out=out, algo=args.algo, time_kernels=True)
-    kern_ms, kern_n = 0.0, 0
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        G.order_matrices(off, picks, out=out, algo=args.algo, time_kernels=True)
-        ti = G.last_run()
-        kern_ms += ti["kernel_ms"]
-        kern_n += ti["kernel_launches"]
-    torch.cuda.synchronize()
-    eager_ms_step = (time.perf_counter() - t1) / args.steps * 1e3
-
-    # useful work of one step: every distinct pick relaxes its reachable arcs
-    vreach, ereach = reach_tables(g)
-    uniq = np.unique(picks)
-    useful_arcs = float(ereach[uniq].sum())
-    # algorithmic HBM bytes: each reached (vertex, source) distance written
-    # once and read once (8 B), and each reached arc's (col, w) streamed once
-    # per block of 64 sources (8 B / 64)
-    alg_bytes = float((8.0 * vreach[uniq] + 8.0 * ereach[uniq] / 64.0).sum())
-
-    ms_per_step = elapsed / args.steps * 1e3
-    orders_per_s = n_orders * args.steps / elapsed
-    kern_ms_step = kern_ms / args.steps
-    launches_step = kern_n / args.steps
-    achieved = alg_bytes / (kern_ms_step * 1e-3) / 1e9 if kern_ms_step > 0 else None
-    kernel = PASS_KERNEL.get(info["algo"], "relaxation pass")
-    traffic = load_traffic(kernel)
-    seg = G.segment_info()
-
+    # headline: the uneven batch, matrices host-visible
+    wl = make_config("uneven")
+    log(f"uneven: {wl.num_orders} orders, {len(wl.picks)} picks")
+    G, tune_s = graph_for(wr, ctx, wl, tune=not args.no_autotune, cache_dir=args.autotune_cache)
+    log(f"uneven: tuned in {tune_s:.1f} s: {G.schedule()}")
+    head = order_leg(wr, wl, G, args.steps, args.warmup, "uneven", host_out=True, copy_gbs=copy_gbs)
+    head["autotune_s"] = round(tune_s, 2)
+    if args.b1_orders > 0:
+        head["baseline_b1"] = b1_leg(G, wl, args.b1_orders)
+    G.close()
+    roof = head.pop("roofline")
     res = {
         "metric": "routed orders/s",
-        "value": round(orders_per_s, 1),
+        "value": head["orders_per_s"],
         "unit": "orders/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "medium: 512x512 rack-aisle grid (V=262144, E=536188), w in 1..10, "
-                        "256 orders x 32 picks, all orders in one multi-source call",
-            "orders": n_orders, "picks": int(len(picks)), "unique_sources": int(len(uniq)),
-            "algo": info["algo"], "tiles": seg["tiles"], "ports": seg["boundary"],
+            "workload": "uneven: 2048x2048 rack-aisle grid (V=4194304, E=8567292), w in 1..10, 10k orders "
+                        "with geometric(12) sizes in 2..64 over 100k Zipf(1.1) slots, all orders in one "
+                        "autotuned multi-source call, matrices host-visible",
+            "orders": head["orders"], "picks": head["picks"], "unique_sources": head["unique_sources"],
+            "algo": "overlay", "schedule": head["schedule"], "tiles": head["tiles"], "ports": head["ports"],
         },
-        "gteps": round(useful_arcs / (ms_per_step * 1e-3) / 1e9, 2),
-        "p50_batch_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-        "p99_batch_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-        "relax_ms_per_step": round(relax_ms / args.steps, 3),
-        "ms_per_step_eager_timed": round(eager_ms_step, 3),
-        "passes_per_step": passes / args.steps,
-        "visits_per_step": items / args.steps,
-        "roofline": {
-            "kernel": kernel,
-            "bound": "hbm",
-            "achieved": round(achieved, 1) if achieved else None,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": (round(traffic * launches_step / (kern_ms_step * 1e-3) / 1e9, 1)
-                        if traffic and kern_ms_step > 0 else None),
-            "launches_per_step": launches_step,
-            "avg_launch_us": round(kern_ms_step / max(launches_step, 1) * 1e3, 2),
-            "alg_bytes_per_step": alg_bytes,
-        },
+        "gteps": head["gteps"],
+        "p50_batch_ms": head["p50_batch_ms"],
+        "p99_batch_ms": head["p99_batch_ms"],
+        "passes_per_step": head["passes_per_step"],
+        "visits_per_step": head["visits_per_step"],
+        "autotune_s": head["autotune_s"],
+        "copy_gbs": round(copy_gbs, 1),
+        "roofline": roof,
     }
-    if args.b1_orders > 0:
-        k = min(args.b1_orders, n_orders)
-        sub_off = off[:k + 1]
-        sub_picks = picks[:int(sub_off[-1])]
-        sizes = np.diff(sub_off.astype(np.int64))
-        o1 = torch.empty(int((sizes ** 2).sum()), dtype=torch.int32, device="cuda")
-        t = time.perf_counter()
-        G.order_matrices(sub_off, sub_picks, out=o1, algo="edge_b1")
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t
-        res["baseline_b1"] = {"value": round(k / tb, 3), "unit": "orders/s",
-                              "sample": f"first {k} orders, one order at a time, thread per arc, "
-                                        f"host-checked early exit ({G.last_run()['passes']} rounds)"}
-    if args.route_stops > 0:
-        P0 = int(off[1] - off[0])
-        if all(int(off[o + 1] - off[o]) == P0 for o in range(n_orders)) and args.route_stops <= P0:
-            D_host = out.cpu().numpy().view(np.uint32)[:n_orders * P0 * P0]
-            res["route_leg"] = route_leg(wr, ctx, D_host, n_orders, P0, args.route_stops, args.steps,
-                                         args.warmup, not args.no_cpu_baseline)
-            res["route_leg"]["clustered"] = cluster_leg(wr, ctx, D_host, off, picks, g.W, 3, args.steps,
-                                                        args.warmup, not args.no_cpu_baseline)
+    if "baseline_b1" in head:
+        res["baseline_b1"] = head["baseline_b1"]
+    if with_cpu:
+        res["cpu_baseline"] = cpu_orders_baseline(wl, args.cpu_seconds)
+    res["legs"] = {}
+    del wl
+
+    if "medium" in legs or "routes" in legs:
+        wm = make_config("medium")
+        Gm, tm = graph_for(wr, ctx, wm, tune=not args.no_autotune, cache_dir=args.autotune_cache)
+        med = order_leg(wr, wm, Gm, args.steps * 2, args.warmup, "medium", host_out=True, copy_gbs=copy_gbs)
+        dev_leg = order_leg(wr, wm, Gm, args.steps * 2, args.warmup, "medium (device)", host_out=False,
+                            copy_gbs=copy_gbs)
+        med["device_output"] = {k: dev_leg[k] for k in ("orders_per_s", "ms_per_step", "p50_batch_ms",
+                                                          "p99_batch_ms", "gteps")}
+        med["autotune_s"] = round(tm, 2)
+        if args.b1_orders > 0:
+            med["baseline_b1"] = b1_leg(Gm, wm, 2 * args.b1_orders)
+        if with_cpu:
+            med["cpu_baseline"] = cpu_orders_baseline(wm, args.cpu_seconds)
+        res["legs"]["medium"] = med
+        if "routes" in legs and args.route_stops > 0:
+            off, picks = wm.pick_offsets, wm.picks
+            P0 = int(off[1] - off[0])
+            D_host = Gm.order_matrices(off, picks, algo="overlay")
+            res["route_leg"] = route_leg(wr, ctx, D_host, wm.num_orders, P0, args.route_stops, args.steps,
+                                         args.warmup, with_cpu)
+            res["route_leg"]["clustered"] = cluster_leg(wr, ctx, D_host, off, picks, wm.graph.W, 3, args.steps,
+                                                        args.warmup, with_cpu)
+        Gm.close()
+        torch.cuda.empty_cache()
+    if "tiny" in legs:
+        res["legs"]["tiny"] = tiny_leg(wr, ctx, args.steps)
+    if "segmented" in legs:
+        res["legs"]["segmented"] = segmented_leg(wr, ctx, args.steps)
+        torch.cuda.empty_cache()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
-    if rates:
-        res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds, args.tile or 512)
+    if "serving" in legs and rates:
+        res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds)
     if args.copy_probe > 0:
         n = args.copy_probe << 18
         a = torch.ones(n, dtype=torch.int32, device="cuda")
@@ -439,8 +674,6 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         res["copy_probe_bytes"] = int(n) * 4
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

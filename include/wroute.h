@@ -292,19 +292,44 @@ typedef struct wr_run_info {
     double kernel_ms;          /* with WR_TIME_KERNELS: summed duration of the
                                   relaxation kernel's launches (else 0)         */
     uint32_t kernel_launches;  /* launches timed into kernel_ms                 */
+    uint64_t relaxations;      /* overlay schedule: min-plus relaxations of its
+                                  passes (per source lane: each cross arc into
+                                  a visited tile and each entry of the tile's
+                                  port-to-exit table), else 0                   */
+    uint64_t alg_bytes;        /* overlay schedule: state bytes its passes must
+                                  move (a 256-byte row of 64 source values per
+                                  incoming cross arc and per exit of a visited
+                                  tile, 4 bytes per exit value stored), else 0 */
 } wr_run_info;
 wr_status wr_graph_last_run(const wr_graph *g, wr_run_info *info);
 
-/* Chooses schedule parameters (tile size, waves per tile, passes per
- * graph replay) by timing candidates on this graph with `sources_hint`
- * synthetic sources; every candidate gives identical distances, so results
- * never depend on the outcome.  cache_path (may be NULL) is a JSON file
- * read before and written after tuning.  Errors: WR_E_INVALID, WR_E_DEVICE. */
+/* Chooses schedule parameters by timing candidates on this graph with
+ * `sources_hint` synthetic sources (evenly spread vertices that have arcs)
+ * and keeps the fastest: with a grid segmentation (wr_graph_segment_grid)
+ * the grid tile shape (tile_w x tile_h cells; the segments the caller gave
+ * are replaced by the chosen shape), the source blocks per workgroup unit
+ * and the passes per graph replay of the overlay schedule; otherwise the
+ * tile size, waves per tile and passes per replay.  Every candidate gives
+ * identical distances, so results never depend on the outcome.  cache_path
+ * (may be NULL) is a JSON file read before and written after tuning, keyed
+ * by the graph's structure and the segmentation it was called with.
+ * Errors: WR_E_INVALID, WR_E_DEVICE. */
 wr_status wr_autotune(wr_graph *g, uint32_t sources_hint, const char *cache_path);
 
 /* Sets schedule parameters explicitly (0 keeps the current value). */
 wr_status wr_graph_set_schedule(wr_graph *g, uint32_t tile_vertices,
                                 uint32_t waves_per_group, uint32_t passes_per_replay);
+
+/* The schedule a graph runs with (as set, or as wr_autotune chose). */
+typedef struct wr_schedule {
+    uint32_t tile_vertices;      /* most vertices of one LDS tile               */
+    uint32_t waves_per_group;    /* waves per workgroup (segmented schedule)    */
+    uint32_t passes_per_replay;  /* passes captured in one graph replay          */
+    uint32_t blocks_per_unit;    /* 64-source blocks one workgroup unit visits   */
+    uint32_t grid_tile_w;        /* grid segment shape, 0 if the segmentation    */
+    uint32_t grid_tile_h;        /*   is not a grid                              */
+} wr_schedule;
+wr_status wr_graph_get_schedule(const wr_graph *g, wr_schedule *out);
 
 /* ---- continuous-batching server -------------------------------------- */
 

@@ -59,6 +59,9 @@ def lib():
         L.orc_gather_orders.restype = None
         L.orc_certificate.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p, ctypes.c_void_p]
         L.orc_certificate.restype = i32
+        L.orc_certificate_multi.argtypes = [u32, _u32p, _u32p, _u32p, u32, _u32p, _u32p, ctypes.c_void_p,
+                                            _i32p, i32]
+        L.orc_certificate_multi.restype = i32
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = i32
         _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
@@ -152,6 +155,24 @@ def certificate(row_ptr, col, w, src: int, dist, pred=None) -> int:
         p = np.ascontiguousarray(pred, dtype=np.int32)
     return lib().orc_certificate(V, rp, c, ww, int(src), d,
                                  None if p is None else p.ctypes.data_as(ctypes.c_void_p))
+
+
+def certificate_rows(row_ptr, col, w, sources, dist, pred=None, nthreads: int = 0) -> np.ndarray:
+    """certificate() of every row of a source-major [S, V] distance array
+    (and [S, V] predecessors when given), in parallel over sources; returns
+    the per-row codes (0 = proven optimal)."""
+    rp, c, ww = _csr(row_ptr, col, w)
+    V = len(rp) - 1
+    src = np.ascontiguousarray(sources, dtype=np.uint32)
+    d = np.ascontiguousarray(dist, dtype=np.uint32).reshape(len(src), V)
+    p = None
+    if pred is not None:
+        p = np.ascontiguousarray(pred, dtype=np.int32).reshape(len(src), V)
+    rc = np.zeros(max(len(src), 1), dtype=np.int32)
+    if len(src):
+        lib().orc_certificate_multi(V, rp, c, ww, len(src), src, d.reshape(-1),
+                                    None if p is None else p.ctypes.data_as(ctypes.c_void_p), rc, nthreads)
+    return rc[:len(src)]
 
 
 def order_matrices(row_ptr, col, w, pick_offsets, picks, nthreads: int = 0) -> np.ndarray:

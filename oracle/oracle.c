@@ -354,6 +354,28 @@ int orc_certificate(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
     return rc;
 }
 
+/* orc_certificate of S source-major rows dist[S*V] (and pred[S*V] when
+ * not NULL), in parallel over sources on `nthreads` threads (0 = all).
+ * rc[i] receives the code of row i; returns the number of rows whose code
+ * is not 0. */
+int orc_certificate_multi(uint32_t V, const uint32_t *row_ptr, const uint32_t *col,
+                          const uint32_t *w, uint32_t S, const uint32_t *sources,
+                          const uint32_t *dist, const int32_t *pred, int32_t *rc, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : bad)
+#endif
+    for (long i = 0; i < (long)S; ++i) {
+        rc[i] = orc_certificate(V, row_ptr, col, w, sources[i], dist + (size_t)i * V,
+                                pred ? pred + (size_t)i * V : NULL);
+        bad += rc[i] != 0;
+    }
+    (void)nthreads;
+    return bad;
+}
+
 /* ------------------------------------------------------------------ */
 /* Optimal open route over an order's stops (Route Optimization section:
  * the entrance/exit is not part of the route, so a route is an ordering of

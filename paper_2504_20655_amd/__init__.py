@@ -184,6 +184,12 @@ class Graph:
     def autotune(self, sources_hint: int = 256, cache_path: str | None = None):
         _check(lib().wr_autotune(self.h, sources_hint, cache_path.encode() if cache_path else None))
 
+    def schedule(self) -> dict:
+        """The schedule the graph runs with (wr_graph_get_schedule)."""
+        sc = _lib.Schedule()
+        _check(lib().wr_graph_get_schedule(self.h, ctypes.byref(sc)))
+        return {k: getattr(sc, k) for k, _ in sc._fields_}
+
     def update_weights(self, arc_index, new_w) -> int:
         a, v = _u32(arc_index), _u32(new_w)
         ep = ctypes.c_uint64()

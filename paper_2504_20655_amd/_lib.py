@@ -24,7 +24,13 @@ st = ctypes.c_int  # wr_status
 class RunInfo(ctypes.Structure):
     _fields_ = [("algo", u32), ("unique_sources", u32), ("chunks", u32), ("passes", u32),
                 ("work_items", u64), ("relax_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double), ("kernel_launches", u32)]
+                ("kernel_ms", ctypes.c_double), ("kernel_launches", u32), ("relaxations", u64),
+                ("alg_bytes", u64)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("tile_vertices", u32), ("waves_per_group", u32), ("passes_per_replay", u32),
+                ("blocks_per_unit", u32), ("grid_tile_w", u32), ("grid_tile_h", u32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -67,6 +73,7 @@ SIGNATURES = {
     "wr_graph_last_run": (st, [vp, vp]),
     "wr_autotune": (st, [vp, u32, ctypes.c_char_p]),
     "wr_graph_set_schedule": (st, [vp, u32, u32, u32]),
+    "wr_graph_get_schedule": (st, [vp, vp]),
     "wr_server_create": (st, [vp, vp, vp]),
     "wr_server_submit": (st, [vp, u32, vp, vp]),
     "wr_server_poll": (st, [vp, u64, vp, vp]),

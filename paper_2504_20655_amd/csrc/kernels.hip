@@ -222,6 +222,9 @@ struct SegPassArgs {
     const uint32_t *pin_off;
     const uint2 *pin_rec;
     const uint2 *hdr2;
+    // counters: [0] visits, [1] passes with work, [2] state rows a visit
+    // reads, [3] relaxations per lane, [4] exit values stored (overlay)
+    unsigned long long *stats;
 };
 
 __device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
@@ -874,6 +877,7 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
     if (blockIdx.x >= nunits) return;
     uint32_t staged = NONE;
     uint32_t first_unit = blockIdx.x;
+    uint32_t stored = 0;   // exit values this wave stored (uniform)
     for (;;) {
         uint32_t u = first_unit;
         if (u == NONE) {
@@ -985,7 +989,9 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
                     if (j >= X) break;
                     const bool imp = m[r] < c[r];
                     if (imp) xv[static_cast<size_t>(j) * 64 + lane] = m[r];
-                    if (__builtin_amdgcn_ballot_w64(imp) == 0) continue;
+                    const uint64_t bal = __builtin_amdgcn_ballot_w64(imp);
+                    stored += static_cast<uint32_t>(__builtin_popcountll(bal));
+                    if (bal == 0) continue;
                     const uint32_t kb = uniform(s_xbeg[j]), ke = uniform(s_xbeg[j + 1]);
                     for (uint32_t kx = kb + lane; kx < ke; kx += 64)
                         A.flags[static_cast<size_t>(s_xtile[kx]) * A.S + b] = 1;
@@ -995,6 +1001,7 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         }
 #undef OVL_ISSUE_LOADS
     }
+    if (lane == 0 && stored) atomicAdd(&A.stats[4], static_cast<unsigned long long>(stored));
 }
 
 // Builds the pass's work lists from the activation flags [tile][block]:
@@ -1006,7 +1013,8 @@ __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, 
                            uint32_t *__restrict__ bucket, uint32_t G, uint2 *__restrict__ units,
                            uint32_t *__restrict__ nunits, uint32_t *__restrict__ next_nunits,
                            uint32_t *__restrict__ next_cursor, uint32_t *__restrict__ next_pending,
-                           uint32_t *__restrict__ row_pending, unsigned long long *__restrict__ stats) {
+                           uint32_t *__restrict__ row_pending, unsigned long long *__restrict__ stats,
+                           const uint4 *__restrict__ hdr, const uint2 *__restrict__ hdr2) {
     const uint32_t lane = lane_id();
     const uint32_t wpb = blockDim.x >> 6;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1038,6 +1046,11 @@ __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, 
                 ub = atomicAdd(nunits, sl);
                 atomicAdd(&stats[0], static_cast<unsigned long long>(k));
                 if (ub == 0) atomicAdd(&stats[1], 1ull);
+                // a visit reads one state row per incoming cross arc and per
+                // exit, and relaxes the arcs and the exits' table entries
+                const uint32_t hw = hdr[t].w, E = hw & 0xFFu, X = (hw >> 8) & 0xFFu, npa = hdr2[t].y;
+                atomicAdd(&stats[2], static_cast<unsigned long long>(k) * (npa + X));
+                atomicAdd(&stats[3], static_cast<unsigned long long>(k) * (npa + E * X));
             }
             ub = __builtin_amdgcn_readlane(ub, 0);
             for (uint32_t q = lane; q < sl; q += 64) units[ub + q] = make_uint2(t, q);
@@ -1462,6 +1475,7 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
     A.li_off = ts.d_li_off.p;
     A.li_arc = ts.d_li_arc.p;
     A.nsrc = ss.nsrc;
+    A.stats = ss.stats;
     return A;
 }
 
@@ -1682,7 +1696,8 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     uint32_t *nunits_nx = ss.nunits + 3u * nx, *cursor_nx = ss.cursor + 3u * nx;
     hipLaunchKernelGGL(k_ovl_plan, blocks_for(ts.T, 4, 1024), 256, 0, st, ss.flags, ts.T, ss.S,
                        ss.cnt + static_cast<size_t>(par) * ts.T, ss.bucket + static_cast<size_t>(par) * ts.T * ss.S,
-                       G, ss.units, nunits_cur, nunits_nx, cursor_nx, ss.ntiles + nx, ss.pending, ss.stats);
+                       G, ss.units, nunits_cur, nunits_nx, cursor_nx, ss.ntiles + nx, ss.pending, ss.stats,
+                       reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), reinterpret_cast<const uint2 *>(ts.d_ovl_hdr2.p));
     check_launch("ovl_plan");
     SegPassArgs A = seg_args(ts, ss, par, G);
     A.nunits = nunits_cur;

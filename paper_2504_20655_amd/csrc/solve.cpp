@@ -304,7 +304,7 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     tiles.alloc(ctx, 2ull * ts.T);
     ctr.alloc(ctx, 8);
     units.alloc(ctx, seg_units_cap(ts, S, G));
-    stats.alloc(ctx, 2);
+    stats.alloc(ctx, 8);
     src_pos.alloc(ctx, static_cast<size_t>(S) * lanes);
     src_tile.alloc(ctx, static_cast<size_t>(S) * lanes);
     ss = SegState{};
@@ -538,7 +538,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     if (w.overlay) launch_fill_u8(w.buf.flags.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 16, 0u, st);
     g_trace.mark("chunk_reset", now_ms());
     if (!w.overlay) launch_seg_seed_n(ts, ss, n, st);
     hipEvent_t e0, e1;
@@ -610,7 +610,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     g_trace.mark("replays", now_ms());
     wsp.last_passes = passes;
     WR_HIP(hipEventRecord(e1, st));
-    unsigned long long stats[2];
+    unsigned long long stats[5];
     WR_HIP(hipMemcpyAsync(stats, w.buf.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
     WR_HIP(hipStreamSynchronize(st));
     float ms = 0;
@@ -620,7 +620,11 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     info.relax_ms += ms;
     info.passes += static_cast<uint32_t>(stats[1]);
     info.work_items += stats[0];
-    if (w.overlay) wsp.last_work_passes = stats[1];
+    if (w.overlay) {
+        wsp.last_work_passes = stats[1];
+        info.relaxations += 64ull * stats[3];
+        info.alg_bytes += 256ull * stats[2] + 4ull * stats[4];
+    }
 }
 
 // ------------------------------------------------------ blocked-layout driver
@@ -989,7 +993,7 @@ StreamSolver *stream_create(wr_graph *g, uint32_t blocks) {
     launch_fill_u32(w.buf.pending.p, w.S_cap, 0u, st);
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 16, 0u, st);
     g_trace.mark("chunk_reset", now_ms());
     launch_fill_u32(w.buf.src_tile.p, static_cast<size_t>(w.S_cap) * 64, NONE, st);
     ensure_overlay_tables(g);

@@ -290,13 +290,35 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
 namespace {
 
 // Grid segments (tile_w x tile_h cells per level) and, nested in them,
-// sub-rectangles of at most `cap` cells: halve the longer side of the
-// segment rectangle until it fits.
-void grid_maps(uint32_t W, uint32_t H, uint32_t L, uint32_t tw, uint32_t th, uint32_t cap,
+// sub-rectangles holding at most `cap` vertices incident to an arc (blocked
+// cells are isolated ids and take no tile space): halve the longer side of
+// the sub-rectangle until every one of them fits.
+void grid_maps(const wr_graph *g, uint32_t W, uint32_t H, uint32_t L, uint32_t tw, uint32_t th, uint32_t cap,
                std::vector<uint32_t> &seg, uint32_t &nseg, std::vector<uint32_t> &sub, uint32_t &nsub) {
     const uint32_t tx = (W + tw - 1) / tw, ty = (H + th - 1) / th;
+    std::vector<uint8_t> inc(static_cast<size_t>(W) * H * L, 0);
+    for (uint32_t u = 0; u < g->V; ++u)
+        for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+            inc[u] = 1;
+            inc[g->col[e]] = 1;
+        }
+    auto fits = [&](uint32_t sw, uint32_t sh) {
+        const uint32_t sx = (tw + sw - 1) / sw, sy = (th + sh - 1) / sh;
+        const uint64_t n = static_cast<uint64_t>(tx) * ty * L * sx * sy;
+        std::vector<uint32_t> cnt(n, 0u);
+        for (uint32_t l = 0; l < L; ++l)
+            for (uint32_t y = 0; y < H; ++y)
+                for (uint32_t x = 0; x < W; ++x) {
+                    const size_t v = (static_cast<size_t>(l) * H + y) * W + x;
+                    if (!inc[v]) continue;
+                    const uint64_t s = (static_cast<uint64_t>(l) * ty + y / th) * tx + x / tw;
+                    const uint64_t q = (s * sy + (y % th) / sh) * sx + (x % tw) / sw;
+                    if (++cnt[q] > cap) return false;
+                }
+        return true;
+    };
     uint32_t sw = tw, sh = th;
-    while (static_cast<uint64_t>(sw) * sh > cap) {
+    while ((sw > 1 || sh > 1) && !fits(sw, sh)) {
         if (sw >= sh) sw = (sw + 1) / 2;
         else sh = (sh + 1) / 2;
     }
@@ -371,7 +393,7 @@ void rebuild_tiles_if_needed(wr_graph *g) {
     if (g->grid_W) {
         std::vector<uint32_t> seg, sub;
         uint32_t nseg, nsub;
-        grid_maps(g->grid_W, g->grid_H, g->grid_L, g->grid_tw, g->grid_th, g->tile_vertices, seg, nseg, sub,
+        grid_maps(g, g->grid_W, g->grid_H, g->grid_L, g->grid_tw, g->grid_th, g->tile_vertices, seg, nseg, sub,
                   nsub);
         build_tiles(g, seg.data(), nseg, g->tile_vertices, false, sub.data(), nsub);
     } else if (g->tiles_user) {
@@ -415,7 +437,7 @@ wr_status wr_graph_segment_grid(wr_graph *g, uint32_t W, uint32_t H, uint32_t le
     WR_HIP(hipSetDevice(g->ctx->device));
     std::vector<uint32_t> seg, sub;
     uint32_t nseg, nsub;
-    grid_maps(W, H, levels, tile_w, tile_h, g->tile_vertices, seg, nseg, sub, nsub);
+    grid_maps(g, W, H, levels, tile_w, tile_h, g->tile_vertices, seg, nseg, sub, nsub);
     build_tiles(g, seg.data(), nseg, g->tile_vertices, false, sub.data(), nsub);
     g->user_seg.swap(seg);
     g->user_num_segments = nseg;

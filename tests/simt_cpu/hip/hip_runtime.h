@@ -27,6 +27,7 @@
 
 #define __global__
 #define __device__
+#define __align__(n) alignas(n)
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
@@ -271,6 +272,12 @@ hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t g, hipGraphNode_t *
 hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
 hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipGraphExecDestroy(hipGraphExec_t e);
+// device variables are host objects here: a symbol's address is its own
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+    *p = const_cast<void *>(sym);
+    return hipSuccess;
+}
 
 namespace simt {
 void trace(const char *name, dim3 g, dim3 b, double ms);

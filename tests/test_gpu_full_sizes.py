@@ -1,15 +1,30 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
-benchmark times (overlay schedule, 24x20-cell grid segments, tiles of at
-most 512 vertices).  The oracle cannot redo whole batches here, so every
-output is checked by properties that hold at any size (zero diagonal,
-symmetry under symmetric weights, metric closure on samples), and sampled
-orders / rows are compared element by element with the oracle."""
+benchmark times (bench.graph_for: overlay schedule over grid tiles of at
+most 512 vertices, shape, blocks per unit and passes per replay chosen by
+wr_autotune for the order workloads; 256x256-cell segments for the 4096^2
+grid).
+
+* medium: every one of the 256 orders against the oracle, element by
+  element, on the first call and again on the warm-started path the
+  benchmark's steps take (third call, device output).
+* uneven: 256 sampled orders against the oracle element by element; the
+  full rows of 256 sampled distinct picks proven optimal by the oracle's
+  O(E) certificate (feasible on every arc, tight-arc reachable, INF exactly
+  where unreachable), and every matrix entry whose row source is one of
+  them equal to its certified row; properties (zero diagonal, symmetry,
+  metric closure on samples) on all 10k orders.
+* segmented: the full rows of all 1024 sources proven optimal by the
+  certificate, chunk by chunk, and the 1024 x 1024 matrix between them
+  equal to those rows; a few rows equal to the unsegmented frontier
+  schedule and to the oracle's Dijkstra.
+"""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
+from bench import graph_for
 from wgen import make_config
 
 pytestmark = pytest.mark.gpu
@@ -23,13 +38,6 @@ def log(*a):
 @pytest.fixture(scope="module")
 def ctx(rt):
     return rt.Context(0)
-
-
-def _bench_graph(rt, ctx, g, levels=1):
-    G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
-    G.set_schedule(512, 8, 0)
-    G.segment_grid(g.W, g.H, levels, 24, 20)
-    return G
 
 
 def _check_matrix(D, closure=True):
@@ -53,48 +61,152 @@ def _orders(flat, off):
     return res
 
 
-def test_medium_full_batch(rt, ctx):
+def _oracle_orders(g, off, picks, sel):
+    """Oracle matrices of orders `sel` (one Dijkstra per distinct pick)."""
+    sub_off = [0]
+    sub_picks = []
+    for o in sel:
+        a, b = int(off[o]), int(off[o + 1])
+        sub_picks.append(picks[a:b])
+        sub_off.append(sub_off[-1] + b - a)
+    sub_picks = np.concatenate(sub_picks).astype(np.uint32)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, np.asarray(sub_off, np.uint32), sub_picks)
+    return _orders(exp, np.asarray(sub_off))
+
+
+def test_medium_every_order(rt, ctx):
+    import torch
     wl = make_config("medium")
     g = wl.graph
     off, picks = wl.pick_offsets, wl.picks
-    G = _bench_graph(rt, ctx, g)
+    G, _ = graph_for(rt, ctx, wl)
+    log("medium: schedule", G.schedule())
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, off, picks)
+    log("medium: oracle done")
     got = G.order_matrices(off, picks, algo="overlay")
-    log("medium: overlay done")
-    mats = _orders(got, off)
-    for D in mats:
-        _check_matrix(D)
-    # a second, independent schedule on the same graph: bit-identical
+    assert got.shape == exp.shape
+    bad = np.flatnonzero(got != exp)
+    assert bad.size == 0, f"{bad.size} entries differ, first at {bad[:5]}"
+    # the benchmark's steps: back-to-back calls, the first replays sized
+    # from the previous call, device output
+    out = torch.empty(len(exp), dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        G.order_matrices(off, picks, out=out, algo="overlay")
+    torch.cuda.synchronize()
+    warm = out.cpu().numpy().view(np.uint32)
+    assert (warm == exp).all()
+    # an independent schedule on the same graph
     seg = G.order_matrices(off, picks, algo="segmented")
-    assert (seg == got).all()
-    rng = np.random.default_rng(1)
-    for o in rng.choice(len(mats), 8, replace=False):
+    assert (seg == exp).all()
+    G.close()
+
+
+@pytest.fixture(scope="module")
+def uneven(rt, ctx):
+    wl = make_config("uneven")
+    G, t = graph_for(rt, ctx, wl)
+    log(f"uneven: tuned in {t:.1f} s, schedule {G.schedule()}")
+    got = G.order_matrices(wl.pick_offsets, wl.picks, algo="overlay")
+    log("uneven: overlay done")
+    yield wl, G, got
+    G.close()
+
+
+def test_uneven_sampled_orders(uneven):
+    wl, G, got = uneven
+    g = wl.graph
+    off, picks = wl.pick_offsets, wl.picks
+    mats = _orders(got, off)
+    rng = np.random.default_rng(3)
+    closure = set(rng.choice(len(mats), 300, replace=False).tolist())
+    for o, D in enumerate(mats):
+        _check_matrix(D, closure=o in closure)
+    sel = np.sort(rng.choice(len(mats), 256, replace=False))
+    exp = _oracle_orders(g, off, picks, sel)
+    log("uneven: oracle done")
+    for o, E in zip(sel, exp):
+        assert (mats[o] == E).all(), f"order {o}"
+
+
+def test_uneven_certified_rows(uneven):
+    import torch
+    wl, G, got = uneven
+    g = wl.graph
+    off, picks = wl.pick_offsets, wl.picks
+    rng = np.random.default_rng(5)
+    uniq = np.unique(picks)
+    src = np.sort(rng.choice(uniq, 256, replace=False)).astype(np.uint32)
+    rows_d = torch.empty(len(src) * g.V, dtype=torch.int32, device="cuda")
+    G.sssp(src, algo="overlay", out=rows_d)
+    torch.cuda.synchronize()
+    rows = rows_d.cpu().numpy().view(np.uint32).reshape(len(src), g.V)
+    del rows_d
+    rc = oracle.certificate_rows(g.row_ptr, g.col, g.w, src, rows)
+    assert (rc == 0).all(), f"rows failing the certificate: {np.flatnonzero(rc)[:8]} codes {rc[rc != 0][:8]}"
+    log("uneven: certificate done")
+    # every matrix entry whose row source is certified equals its row
+    row_of = {int(s): i for i, s in enumerate(src)}
+    base, checked = 0, 0
+    for o in range(len(off) - 1):
         a, b = int(off[o]), int(off[o + 1])
-        exp = oracle.order_matrices(g.row_ptr, g.col, g.w, np.array([0, b - a], np.uint32), picks[a:b])
-        assert (mats[o].ravel() == exp).all(), f"order {o}"
+        P = b - a
+        D = got[base:base + P * P].reshape(P, P)
+        for i in range(P):
+            r = row_of.get(int(picks[a + i]))
+            if r is not None:
+                assert (D[i] == rows[r][picks[a:b]]).all(), f"order {o} row {i}"
+                checked += 1
+        base += P * P
+    assert checked >= 256
+    log(f"uneven: {checked} matrix rows checked against certified rows")
 
 
-def test_segmented_4096_sources(rt, ctx):
+@pytest.fixture(scope="module")
+def segmented(rt, ctx):
     wl = make_config("segmented")
     g = wl.graph
+    log("segmented: graph", g.V, g.E, "sources", len(wl.sources))
+    G, _ = graph_for(rt, ctx, wl, tune=False)
+    off = np.array([0, len(wl.sources)], dtype=np.uint32)
+    D = G.order_matrices(off, wl.sources, algo="overlay").reshape(len(wl.sources), len(wl.sources))
+    log("segmented: 1024 x 1024 matrix done")
+    yield wl, G, D
+    G.close()
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_segmented_certified_rows(segmented, part):
+    """A quarter of the 1024 sources per test, 128 full rows at a time."""
+    import torch
+    wl, G, D = segmented
+    g = wl.graph
     src = wl.sources
-    log("segmented: graph", g.V, g.E, "sources", len(src))
-    G = rt.Graph(ctx, g.row_ptr, g.col, g.w)
-    G.set_schedule(512, 8, 0)
-    tw, th = wl.segment_tile
-    G.segment_grid(g.W, g.H, 1, tw, th)
-    # all 1024 sources against each other: one 1024 x 1024 matrix
-    off = np.array([0, len(src)], dtype=np.uint32)
-    D = G.order_matrices(off, src, algo="overlay").reshape(len(src), len(src))
-    log("segmented: overlay matrix done")
     assert (np.diag(D) == 0).all() and (D == D.T).all() and (D != INF).all()
+    CH = 128
+    lo, hi = part * 256, (part + 1) * 256
+    rows_d = torch.empty(CH * g.V, dtype=torch.int32, device="cuda")
+    for c0 in range(lo, hi, CH):
+        s = src[c0:c0 + CH]
+        G.sssp(s, algo="overlay", out=rows_d)
+        torch.cuda.synchronize()
+        rows = rows_d.cpu().numpy().view(np.uint32).reshape(CH, g.V)
+        rc = oracle.certificate_rows(g.row_ptr, g.col, g.w, s, rows)
+        assert (rc == 0).all(), f"sources {c0}+{np.flatnonzero(rc)[:8]} fail with codes {rc[rc != 0][:8]}"
+        assert (rows[:, src] == D[c0:c0 + CH]).all()
+        log(f"segmented: rows {c0}..{c0 + CH} certified")
+    del rows_d
+
+
+def test_segmented_rows_equal_unsegmented(segmented):
+    """Segmented (overlay over tiles) == unsegmented (frontier over the whole
+    graph) == the oracle's Dijkstra, on a few full rows."""
+    wl, G, D = segmented
+    g = wl.graph
+    src = wl.sources
     rng = np.random.default_rng(2)
-    sub = rng.choice(len(src), 48, replace=False)
-    _check_matrix(D[np.ix_(sub, sub)])
-    # full rows of a few sources: overlay (segmented) == frontier (unsegmented) == oracle
-    pick = rng.choice(len(src), 3, replace=False)
+    pick = np.sort(rng.choice(len(src), 3, replace=False))
     s3 = src[pick]
     rows = G.sssp(s3, algo="overlay")
-    log("segmented: overlay rows done")
     fr = G.sssp(s3, algo="frontier")
     log("segmented: frontier rows done")
     assert (rows == fr).all()
@@ -104,29 +216,10 @@ def test_segmented_4096_sources(rt, ctx):
         assert (D[k] == exp[i][src]).all()
 
 
-def test_uneven_full_batch(rt, ctx):
-    wl = make_config("uneven")
-    g = wl.graph
-    off, picks = wl.pick_offsets, wl.picks
-    log("uneven: orders", len(off) - 1, "picks", len(picks))
-    G = _bench_graph(rt, ctx, g)
-    got = G.order_matrices(off, picks, algo="overlay")
-    log("uneven: overlay done")
-    mats = _orders(got, off)
-    rng = np.random.default_rng(3)
-    closure = set(rng.choice(len(mats), 300, replace=False).tolist())
-    for o, D in enumerate(mats):
-        _check_matrix(D, closure=o in closure)
-    for o in rng.choice(len(mats), 6, replace=False):
-        a, b = int(off[o]), int(off[o + 1])
-        exp = oracle.order_matrices(g.row_ptr, g.col, g.w, np.array([0, b - a], np.uint32), picks[a:b])
-        assert (mats[o].ravel() == exp).all(), f"order {o}"
-
-
 def test_serving_graph_orders(rt, ctx):
     wl = make_config("serving")
     g = wl.graph
-    G = _bench_graph(rt, ctx, g, levels=g.levels)
+    G, _ = graph_for(rt, ctx, wl, tune=False)
     rng = np.random.default_rng(4)
     cand = g.aisle_adjacent_vertices()
     sizes = [2, 17, 64, 128]
@@ -139,3 +232,4 @@ def test_serving_graph_orders(rt, ctx):
     assert (got == exp).all()
     for D in _orders(got, off):
         _check_matrix(D)
+    G.close()

@@ -198,6 +198,30 @@ def test_certificate_catches_planted_mistakes():
     assert oracle.certificate(g.row_ptr, g.col, g.w, s, d, bp) == 20
 
 
+def test_certificate_rows_flags_each_planted_row():
+    # the parallel form checks every row on its own: planted mistakes in
+    # some rows of a batch are reported on exactly those rows, with the
+    # single-row codes
+    wl = make_config("tiny")
+    g = wl.graph
+    src = np.unique(wl.picks)
+    d = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)
+    p = np.stack([oracle.canonical_pred(g.row_ptr, g.col, g.w, int(s), d[i]) for i, s in enumerate(src)])
+    assert (oracle.certificate_rows(g.row_ptr, g.col, g.w, src, d, p) == 0).all()
+    bad = d.copy()
+    free = np.flatnonzero(d[1] != INF)
+    bad[1, free[len(free) // 2]] += 1
+    bad[4, int(src[4])] = 1
+    far = int(free[np.argmax(d[6][free])])
+    bad[6, far] -= 1
+    rc = oracle.certificate_rows(g.row_ptr, g.col, g.w, src, bad, nthreads=3)
+    exp = [oracle.certificate(g.row_ptr, g.col, g.w, int(s), bad[i]) for i, s in enumerate(src)]
+    assert rc.tolist() == exp
+    assert [i for i in range(len(src)) if rc[i]] == [1, 4, 6]
+    # rows paired with the wrong source fail
+    assert (oracle.certificate_rows(g.row_ptr, g.col, g.w, src[::-1].copy(), d) != 0).all()
+
+
 def test_certificate_catches_pred_cycle():
     # two vertices joined by zero-weight arcs, both at distance 1 from 0
     rp = np.asarray([0, 2, 4, 6], dtype=np.uint32)
