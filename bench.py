@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--legs", default="medium,segmented,tiny,routes,serving",
                     help="legs beside the uneven headline, comma-separated ('' = none)")
+    ap.add_argument("--only", default="", choices=["", "segmented", "tiny", "serving"],
+                    help="run just this leg and print its result (for profiling)")
     ap.add_argument("--no-autotune", action="store_true", help="run the 24x20 grid tiles untuned")
     ap.add_argument("--autotune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "wroute_tune"),
                     help="directory of the autotuner's JSON caches")
@@ -328,6 +330,7 @@ def segmented_leg(wr, ctx, steps):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / reps
     info = G.last_run()
+    log(f"segmented: {info}")
     del out
     torch.cuda.empty_cache()
     log(f"segmented: {len(src)} full rows in {dt * 1e3:.1f} ms")
@@ -354,6 +357,7 @@ def segmented_leg(wr, ctx, steps):
     return {"workload": f"segmented: 4096x4096 rack-aisle grid (V={g.V}, E={g.E}), 256x256-cell segments "
                         f"({seg['tiles']} LDS tiles, {seg['boundary']} ports), {len(src)} sources",
             "full_rows_ms": round(dt * 1e3, 3), "gteps": round(useful / dt / 1e9, 2),
+            "relax_ms": round(info["relax_ms"], 3),
             "passes": info["passes"], "visits": info["work_items"],
             "matrix_1024_ms": round(dm * 1e3, 3),
             "segmented_ms_per_source": round(dt * 1e3 / len(src), 4),
@@ -585,6 +589,16 @@ def main():
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
     with_cpu = not args.no_cpu_baseline
     ctx = wr.Context(0)
+    if args.only:
+        if args.only == "segmented":
+            leg = segmented_leg(wr, ctx, args.steps)
+        elif args.only == "tiny":
+            leg = tiny_leg(wr, ctx, args.steps)
+        else:
+            leg = serving_leg(wr, ctx, [float(x) for x in args.serve_rates.split(",") if x.strip()],
+                              args.serve_seconds)
+        print(json.dumps({"leg": args.only, **leg}), flush=True)
+        return
     copy_gbs = copy_bandwidth_gbs()
 
     # headline: the uneven batch, matrices host-visible
@@ -624,6 +638,7 @@ def main():
         "passes_per_step": head["passes_per_step"],
         "visits_per_step": head["visits_per_step"],
         "autotune_s": head["autotune_s"],
+        "relaxations_per_s": head["relaxations_per_s"],
         "copy_gbs": round(copy_gbs, 1),
         "roofline": roof,
     }

@@ -136,7 +136,7 @@ double time_candidate(wr_graph *g, const Candidate &c, const std::vector<uint32_
     std::vector<uint32_t> off(no + 1);
     for (uint32_t o = 0; o <= no; ++o) off[o] = std::min(n, o * kTunePicks);
     double best = -1;
-    for (int rep = 0; rep < 3; ++rep) {   // the first run builds tables and captures graphs
+    for (int rep = 0; rep < 4; ++rep) {   // the first run builds tables and captures graphs
         const auto t0 = std::chrono::steady_clock::now();
         const wr_status st = wr_order_matrices(g, no, off.data(), src.data(), out.data(), nullptr,
                                                g->grid_W ? WR_ALGO_OVERLAY : 0u, nullptr);

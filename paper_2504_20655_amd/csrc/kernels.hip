@@ -222,9 +222,10 @@ struct SegPassArgs {
     const uint32_t *pin_off;
     const uint2 *pin_rec;
     const uint2 *hdr2;
-    // counters: [0] visits, [1] passes with work, [2] state rows a visit
-    // reads, [3] relaxations per lane, [4] exit values stored (overlay)
-    unsigned long long *stats;
+    // overlay work counters, each entry owned by one wave (no atomics):
+    // visits of each tile, and exit values stored per (workgroup, wave)
+    uint32_t *tile_visits;
+    uint32_t *wave_stores;
 };
 
 __device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
@@ -1001,22 +1002,26 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         }
 #undef OVL_ISSUE_LOADS
     }
-    if (lane == 0 && stored) atomicAdd(&A.stats[4], static_cast<unsigned long long>(stored));
+    if (lane == 0 && stored) A.wave_stores[blockIdx.x * NW + wv] += stored;
 }
 
 // Builds the pass's work lists from the activation flags [tile][block]:
 // each tile's active blocks in ascending order, the tile's count, and units
 // of G blocks counted in *nunits (zeroed by the previous pass's plan); clears
-// the flags it consumed, counts work, and zeroes the next pass's unit count,
-// unit cursor and pending-work counters (total and per block).
-__global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, uint32_t *__restrict__ cnt,
-                           uint32_t *__restrict__ bucket, uint32_t G, uint2 *__restrict__ units,
-                           uint32_t *__restrict__ nunits, uint32_t *__restrict__ next_nunits,
-                           uint32_t *__restrict__ next_cursor, uint32_t *__restrict__ next_pending,
-                           uint32_t *__restrict__ row_pending, unsigned long long *__restrict__ stats,
-                           const uint4 *__restrict__ hdr, const uint2 *__restrict__ hdr2) {
+// the flags it consumed, counts visits per tile, and zeroes the next pass's
+// unit count, unit cursor and pending-work counters (total and per block).
+// A wave scans one tile; the waves of a workgroup reserve their units with
+// one atomic between them (OVL_PLAN_WAVES waves per workgroup).
+constexpr uint32_t OVL_PLAN_WAVES = 16;
+__global__ __launch_bounds__(OVL_PLAN_WAVES * 64) void k_ovl_plan(
+    uint8_t *__restrict__ flags, uint32_t T, uint32_t S, uint32_t *__restrict__ cnt, uint32_t *__restrict__ bucket,
+    uint32_t G, uint2 *__restrict__ units, uint32_t *__restrict__ nunits, uint32_t *__restrict__ next_nunits,
+    uint32_t *__restrict__ next_cursor, uint32_t *__restrict__ next_pending, uint32_t *__restrict__ row_pending,
+    unsigned long long *__restrict__ stats, uint32_t *__restrict__ tile_visits) {
+    __shared__ uint32_t s_off[OVL_PLAN_WAVES];
+    __shared__ uint32_t s_base;
     const uint32_t lane = lane_id();
-    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t wv = uniform(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *next_nunits = 0;
         *next_cursor = 0;
@@ -1024,37 +1029,49 @@ __global__ void k_ovl_plan(uint8_t *__restrict__ flags, uint32_t T, uint32_t S, 
     }
     if (blockIdx.x == 0)
         for (uint32_t b = threadIdx.x; b < S; b += blockDim.x) row_pending[b] = 0;
-    for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < T; t += gridDim.x * wpb) {
-        uint8_t *f = flags + static_cast<size_t>(t) * S;
-        uint32_t *bk = bucket + static_cast<size_t>(t) * S;
+    // every wave of the workgroup runs the same iterations (the barriers)
+    for (uint32_t t0 = blockIdx.x * OVL_PLAN_WAVES; t0 < T; t0 += gridDim.x * OVL_PLAN_WAVES) {
+        const uint32_t t = t0 + wv;
         uint32_t k = 0;
-        for (uint32_t c0 = 0; c0 < S; c0 += 64) {
-            const uint32_t b = c0 + lane;
-            const bool on = b < S && f[b] != 0;
-            const uint64_t msk = __builtin_amdgcn_ballot_w64(on);
-            if (on) {
-                bk[k + mbcnt64(msk)] = b;
-                f[b] = 0;
+        if (t < T) {
+            uint8_t *f = flags + static_cast<size_t>(t) * S;
+            uint32_t *bk = bucket + static_cast<size_t>(t) * S;
+            for (uint32_t c0 = 0; c0 < S; c0 += 64) {
+                const uint32_t b = c0 + lane;
+                const bool on = b < S && f[b] != 0;
+                const uint64_t msk = __builtin_amdgcn_ballot_w64(on);
+                if (on) {
+                    bk[k + mbcnt64(msk)] = b;
+                    f[b] = 0;
+                }
+                k += static_cast<uint32_t>(__builtin_popcountll(msk));
             }
-            k += static_cast<uint32_t>(__builtin_popcountll(msk));
-        }
-        if (lane == 0) cnt[t] = k;
-        if (k != 0) {
-            const uint32_t sl = (k + G - 1) / G;
-            uint32_t ub = 0;
             if (lane == 0) {
-                ub = atomicAdd(nunits, sl);
-                atomicAdd(&stats[0], static_cast<unsigned long long>(k));
-                if (ub == 0) atomicAdd(&stats[1], 1ull);
-                // a visit reads one state row per incoming cross arc and per
-                // exit, and relaxes the arcs and the exits' table entries
-                const uint32_t hw = hdr[t].w, E = hw & 0xFFu, X = (hw >> 8) & 0xFFu, npa = hdr2[t].y;
-                atomicAdd(&stats[2], static_cast<unsigned long long>(k) * (npa + X));
-                atomicAdd(&stats[3], static_cast<unsigned long long>(k) * (npa + E * X));
+                cnt[t] = k;
+                if (k) tile_visits[t] += k;   // this wave owns tile t in this pass
             }
-            ub = __builtin_amdgcn_readlane(ub, 0);
-            for (uint32_t q = lane; q < sl; q += 64) units[ub + q] = make_uint2(t, q);
         }
+        const uint32_t sl = (k + G - 1) / G;
+        if (lane == 0) s_off[wv] = sl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (uint32_t i = 0; i < OVL_PLAN_WAVES; ++i) {
+                const uint32_t x = s_off[i];
+                s_off[i] = tot;
+                tot += x;
+            }
+            uint32_t base = 0;
+            if (tot) {
+                base = atomicAdd(nunits, tot);
+                if (base == 0) atomicAdd(&stats[1], 1ull);
+            }
+            s_base = base;
+        }
+        __syncthreads();
+        const uint32_t ub = s_base + s_off[wv];
+        for (uint32_t q = lane; q < sl; q += 64) units[ub + q] = make_uint2(t, q);
+        __syncthreads();   // s_off and s_base are rewritten by the next iteration
     }
 }
 
@@ -1122,15 +1139,67 @@ __device__ __forceinline__ uint32_t ovl_value(const OvlRead &R, uint32_t s, uint
     return m;
 }
 
-__global__ void k_ovl_emit(OvlRead R, uint32_t V, uint32_t rows, const uint32_t *__restrict__ row_src_idx,
-                           const uint32_t *__restrict__ row_src_vertex, const uint32_t *__restrict__ out_row,
-                           uint32_t *__restrict__ out) {
-    for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
-        const uint32_t s = row_src_idx[r], sv = row_src_vertex[r];
-        uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
-        for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
-            o[v] = ovl_value(R, s, sv, v);
+// Full distance rows under the overlay schedule, one workgroup per (tile,
+// row group) item; a row group is a block of 64 chunk sources with the
+// output row of each lane (NONE where that source's row is not wanted).
+// The block's entry values at the tile's ports are pulled once into LDS
+// (min over the tile's incoming cross arcs of exit value + w), then every
+// vertex of the tile takes min over the ports of entry + F[vertex][port]
+// (its table row, one coalesced load, broadcast port by port).  Rows are
+// INF-filled before and their sources set to 0 after (k_fill_rows,
+// k_rows_src_zero); paths inside a source's own tile come from the in-tile
+// fix-up.
+__global__ __launch_bounds__(256) void k_ovl_rows(OvlRead R, const uint32_t *__restrict__ tile_base,
+                                                  const uint4 *__restrict__ hdr, uint32_t T,
+                                                  const uint32_t *__restrict__ grp_block,
+                                                  const uint32_t *__restrict__ lane_row, uint64_t items,
+                                                  const uint32_t *__restrict__ vert_of, uint32_t V,
+                                                  uint32_t *__restrict__ out) {
+    HIP_DYNAMIC_SHARED(uint32_t, s_ent)   // [most ports of a tile][64]
+    const uint32_t lane = lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t t = uniform(static_cast<uint32_t>(it % T)), gi = uniform(static_cast<uint32_t>(it / T));
+        const uint32_t b = uniform(grp_block[gi]);
+        const uint32_t E = uniform(hdr[t].w & 0xFFu);
+        const uint2 h2 = R.hdr2[t];
+        const uint32_t a0 = uniform(h2.x), na = uniform(h2.y);
+        const uint32_t base = uniform(tile_base[t]), n = uniform(tile_base[t + 1]) - base;
+        for (uint32_t i = wv; i < E; i += nw) s_ent[i * 64 + lane] = INF;
+        __syncthreads();
+        const uint32_t *xb = R.xval + static_cast<size_t>(b) * R.NB * 64 + lane;
+        for (uint32_t k = wv; k < na; k += nw) {
+            const uint2 rec = R.pin_rec[a0 + k];
+            atomicMin(&s_ent[(rec.y >> 16) * 64 + lane], sat_add(xb[static_cast<size_t>(rec.x) * 64], rec.y & 0xFFFFu));
+        }
+        __syncthreads();
+        const uint32_t row = lane_row[static_cast<size_t>(gi) * 64 + lane];
+        uint32_t *o = out + (row == NONE ? 0 : static_cast<size_t>(row) * V);
+        for (uint32_t j = wv; j < n; j += nw) {
+            const uint32_t pos = base + j;
+            const uint32_t fv = R.F[static_cast<size_t>(pos) * 64 + lane];
+            uint32_t m = INF;
+            for (uint32_t i = 0; i < E; ++i) m = min(m, sat_add(s_ent[i * 64 + lane], __builtin_amdgcn_readlane(fv, i)));
+            if (row != NONE) o[vert_of[pos]] = m;
+        }
+        __syncthreads();
     }
+}
+
+// out[out_row[r] * V + v] = value for every v < V of each listed row.
+__global__ void k_fill_rows(uint32_t *__restrict__ out, uint32_t V, uint32_t rows,
+                            const uint32_t *__restrict__ out_row, uint32_t value) {
+    for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        uint32_t *o = out + static_cast<size_t>(out_row[r]) * V;
+        for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) o[v] = value;
+    }
+}
+
+// Each row's source is at distance 0 from itself.
+__global__ void k_rows_src_zero(uint32_t *__restrict__ out, uint32_t V, uint32_t rows,
+                                const uint32_t *__restrict__ out_row, const uint32_t *__restrict__ row_vertex) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
+        out[static_cast<size_t>(out_row[r]) * V + row_vertex[r]] = 0;
 }
 
 // One order per blockIdx.x (strided), its P x P pairs spread over the
@@ -1475,7 +1544,8 @@ static SegPassArgs seg_args(const TileSet &ts, const SegState &ss, uint32_t par,
     A.li_off = ts.d_li_off.p;
     A.li_arc = ts.d_li_arc.p;
     A.nsrc = ss.nsrc;
-    A.stats = ss.stats;
+    A.tile_visits = ss.tile_visits;
+    A.wave_stores = ss.wave_stores;
     return A;
 }
 
@@ -1694,10 +1764,11 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     const uint32_t nx = par ^ 1u;
     uint32_t *nunits_cur = ss.nunits + 3u * par, *cursor_cur = ss.cursor + 3u * par;
     uint32_t *nunits_nx = ss.nunits + 3u * nx, *cursor_nx = ss.cursor + 3u * nx;
-    hipLaunchKernelGGL(k_ovl_plan, blocks_for(ts.T, 4, 1024), 256, 0, st, ss.flags, ts.T, ss.S,
+    hipLaunchKernelGGL(k_ovl_plan, blocks_for(ts.T, OVL_PLAN_WAVES, 1024), OVL_PLAN_WAVES * 64, 0, st, ss.flags,
+                       ts.T, ss.S,
                        ss.cnt + static_cast<size_t>(par) * ts.T, ss.bucket + static_cast<size_t>(par) * ts.T * ss.S,
                        G, ss.units, nunits_cur, nunits_nx, cursor_nx, ss.ntiles + nx, ss.pending, ss.stats,
-                       reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), reinterpret_cast<const uint2 *>(ts.d_ovl_hdr2.p));
+                       ss.tile_visits);
     check_launch("ovl_plan");
     SegPassArgs A = seg_args(ts, ss, par, G);
     A.nunits = nunits_cur;
@@ -1740,13 +1811,24 @@ static OvlRead ovl_read(const TileSet &ts, const SegState &ss, const uint32_t *F
 }
 
 void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
-                     const uint32_t *row_src_idx, const uint32_t *row_src_vertex, const uint32_t *out_row,
-                     uint32_t *out, hipStream_t st) {
+                     const uint32_t *row_src_vertex, const uint32_t *out_row, const uint32_t *grp_block,
+                     const uint32_t *lane_row, uint32_t ngroups, uint32_t num_cus, uint32_t *out, hipStream_t st) {
     if (!rows) return;
-    dim3 grid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
-    hipLaunchKernelGGL(k_ovl_emit, grid, 256, 0, st, ovl_read(ts, ss, F), V, rows, row_src_idx, row_src_vertex,
-                       out_row, out);
-    check_launch("ovl_emit");
+    dim3 fgrid(blocks_for(V, 256, 1024), rows < 65535u ? rows : 65535u);
+    hipLaunchKernelGGL(k_fill_rows, fgrid, 256, 0, st, out, V, rows, out_row, INF);
+    check_launch("fill_rows");
+    const uint64_t items = static_cast<uint64_t>(ts.T) * ngroups;
+    if (items) {
+        const uint32_t lds = std::max(ts.max_ports, 1u) * 64u * 4u;
+        const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(items, static_cast<uint64_t>(num_cus) * 16u));
+        hipLaunchKernelGGL(k_ovl_rows, grid, 256, lds, st, ovl_read(ts, ss, F), ts.d_tile_base.p,
+                           reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), ts.T, grp_block, lane_row, items,
+                           ts.d_vert_of.p, V, out);
+        check_launch("ovl_rows");
+    }
+    hipLaunchKernelGGL(k_rows_src_zero, blocks_for(rows, 256, 1024), 256, 0, st, out, V, rows, out_row,
+                       row_src_vertex);
+    check_launch("rows_src_zero");
 }
 
 void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,

@@ -304,7 +304,13 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     tiles.alloc(ctx, 2ull * ts.T);
     ctr.alloc(ctx, 8);
     units.alloc(ctx, seg_units_cap(ts, S, G));
-    stats.alloc(ctx, 8);
+    stats.alloc(ctx, 2);
+    if (with_flags) {
+        // the overlay pass runs at most 4 workgroups of 8 waves per CU
+        wave_slots = static_cast<uint32_t>(ctx->num_cus) * 32u;
+        tile_visits.alloc(ctx, std::max(ts.T, 1u));
+        wave_stores.alloc(ctx, wave_slots);
+    }
     src_pos.alloc(ctx, static_cast<size_t>(S) * lanes);
     src_tile.alloc(ctx, static_cast<size_t>(S) * lanes);
     ss = SegState{};
@@ -329,6 +335,8 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     ss.src_tile = src_tile.p;
     ss.flags = with_flags ? flags.p : nullptr;
     ss.pending = with_flags ? pending.p : nullptr;
+    ss.tile_visits = with_flags ? tile_visits.p : nullptr;
+    ss.wave_stores = with_flags ? wave_stores.p : nullptr;
 }
 
 uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves, uint32_t lanes) {
@@ -535,10 +543,16 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
         launch_fill_u32(w.buf.inbox.p, static_cast<size_t>(rows) * std::max(ts.NP, 1u) * lanes, INF, st);
     launch_fill_u32(w.buf.stamps.p, static_cast<size_t>(rows) * ts.T, 0u, st);
     launch_fill_u8(w.buf.visited.p, static_cast<size_t>(rows) * ts.T, 0u, st);
-    if (w.overlay) launch_fill_u8(w.buf.flags.p, static_cast<size_t>(rows) * ts.T, 0u, st);
+    if (w.overlay) {
+        // flags are [tile][row]: clear every row of the state, which also
+        // drops flags an aborted earlier solve may have left
+        launch_fill_u8(w.buf.flags.p, static_cast<size_t>(w.S_cap) * ts.T, 0u, st);
+        launch_fill_u32(w.buf.tile_visits.p, std::max(ts.T, 1u), 0u, st);
+        launch_fill_u32(w.buf.wave_stores.p, w.buf.wave_slots, 0u, st);
+    }
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 16, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
     g_trace.mark("chunk_reset", now_ms());
     if (!w.overlay) launch_seg_seed_n(ts, ss, n, st);
     hipEvent_t e0, e1;
@@ -610,8 +624,15 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     g_trace.mark("replays", now_ms());
     wsp.last_passes = passes;
     WR_HIP(hipEventRecord(e1, st));
-    unsigned long long stats[5];
+    unsigned long long stats[2];
     WR_HIP(hipMemcpyAsync(stats, w.buf.stats.p, sizeof(stats), hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> tv, wsr;
+    if (w.overlay) {
+        tv.resize(std::max(ts.T, 1u));
+        wsr.resize(w.buf.wave_slots);
+        WR_HIP(hipMemcpyAsync(tv.data(), w.buf.tile_visits.p, tv.size() * 4, hipMemcpyDeviceToHost, st));
+        WR_HIP(hipMemcpyAsync(wsr.data(), w.buf.wave_stores.p, wsr.size() * 4, hipMemcpyDeviceToHost, st));
+    }
     WR_HIP(hipStreamSynchronize(st));
     float ms = 0;
     WR_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -619,11 +640,25 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     (void)hipEventDestroy(e1);
     info.relax_ms += ms;
     info.passes += static_cast<uint32_t>(stats[1]);
-    info.work_items += stats[0];
+    if (!w.overlay) info.work_items += stats[0];
     if (w.overlay) {
         wsp.last_work_passes = stats[1];
-        info.relaxations += 64ull * stats[3];
-        info.alg_bytes += 256ull * stats[2] + 4ull * stats[4];
+        // a visit of tile t reads a 256-byte row per incoming cross arc and
+        // per exit, and relaxes its incoming arcs and its exits' table
+        // entries for 64 lanes; every stored exit value writes 4 bytes
+        uint64_t rows_read = 0, relax = 0, stored = 0;
+        for (uint32_t t = 0; t < ts.T; ++t) {
+            const uint64_t hw = ts.ovl_hdr[4ull * t + 3], E = hw & 0xFFu, X = (hw >> 8) & 0xFFu;
+            const uint64_t npa = ts.ovl_hdr2[2ull * t + 1];
+            rows_read += tv[t] * (npa + X);
+            relax += tv[t] * (npa + E * X);
+        }
+        for (uint32_t v : wsr) stored += v;
+        uint64_t visits = 0;
+        for (uint32_t t = 0; t < ts.T; ++t) visits += tv[t];
+        info.work_items += visits;
+        info.relaxations += 64ull * relax;
+        info.alg_bytes += 256ull * rows_read + 4ull * stored;
     }
 }
 
@@ -835,7 +870,8 @@ void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, 
 // row of chunk source row_idx[r].
 void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
                const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out,
-               const std::vector<uint32_t> &row_vertex, const std::vector<uint32_t> &out_row);
+               const std::vector<uint32_t> &row_idx, const std::vector<uint32_t> &row_vertex,
+               const std::vector<uint32_t> &out_row);
 
 struct StreamJoin {
     // The library works on its own stream; with caller (device) buffers it
@@ -940,12 +976,37 @@ IntileWork intile_pairs(const TileSet &ts, uint32_t num_orders, const uint32_t *
 
 void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_idx,
                const uint32_t *d_row_vertex, const uint32_t *d_out_row, uint32_t *out,
-               const std::vector<uint32_t> &row_vertex, const std::vector<uint32_t> &out_row) {
+               const std::vector<uint32_t> &row_idx, const std::vector<uint32_t> &row_vertex,
+               const std::vector<uint32_t> &out_row) {
     hipStream_t st = g->ctx->stream;
     if (algo == WR_ALGO_OVERLAY) {
         SegWork &w = *workspace(g).seg;
-        launch_ovl_emit(*g->tiles, w.ss, g->tiles->d_F.p, g->V, rows, d_row_idx, d_row_vertex, d_out_row, out,
-                        st);
+        // row groups: per block of 64 chunk sources, the output row of each
+        // lane; a source asked for twice takes a second group of its block
+        std::vector<uint32_t> gblock, lrow;
+        std::map<uint32_t, std::vector<uint32_t>> groups_of;
+        for (uint32_t r = 0; r < rows; ++r) {
+            const uint32_t sidx = row_idx[r], b = sidx >> 6, l = sidx & 63u;
+            std::vector<uint32_t> &gs = groups_of[b];
+            uint32_t gi = NONE;
+            for (uint32_t x : gs)
+                if (lrow[static_cast<size_t>(x) * 64 + l] == NONE) {
+                    gi = x;
+                    break;
+                }
+            if (gi == NONE) {
+                gi = static_cast<uint32_t>(gblock.size());
+                gblock.push_back(b);
+                lrow.resize(lrow.size() + 64, NONE);
+                gs.push_back(gi);
+            }
+            lrow[static_cast<size_t>(gi) * 64 + l] = out_row[r];
+        }
+        DBuf<uint32_t> d_gblock, d_lrow;
+        upload(d_gblock, g->ctx, gblock, st);
+        upload(d_lrow, g->ctx, lrow, st);
+        launch_ovl_emit(*g->tiles, w.ss, g->tiles->d_F.p, g->V, rows, d_row_vertex, d_out_row, d_gblock.p, d_lrow.p,
+                        static_cast<uint32_t>(gblock.size()), static_cast<uint32_t>(g->ctx->num_cus), out, st);
         launch_intile_fix(g->ctx, *g->tiles, intile_rows(*g->tiles, row_vertex, out_row), true, g->V, out, st);
     } else if (algo == WR_ALGO_SEGMENTED) {
         SegWork &w = *workspace(g).seg;
@@ -993,7 +1054,9 @@ StreamSolver *stream_create(wr_graph *g, uint32_t blocks) {
     launch_fill_u32(w.buf.pending.p, w.S_cap, 0u, st);
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 16, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    launch_fill_u32(w.buf.tile_visits.p, std::max(ts.T, 1u), 0u, st);
+    launch_fill_u32(w.buf.wave_stores.p, w.buf.wave_slots, 0u, st);
     g_trace.mark("chunk_reset", now_ms());
     launch_fill_u32(w.buf.src_tile.p, static_cast<size_t>(w.S_cap) * 64, NONE, st);
     ensure_overlay_tables(g);
@@ -1184,7 +1247,7 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
             tmp.alloc(ctx, static_cast<size_t>(R) * V);
             out = tmp.p;
         }
-        emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, out, rvert, orow);
+        emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, out, ridx, rvert, orow);
         if (pred) {
             DBuf<int32_t> ptmp;
             int32_t *pp = pred;
@@ -1385,7 +1448,7 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
                     upload(d_rvert, ctx, rvert, st);
                     upload(d_orow, ctx, orow, st);
                     upload(d_prow, ctx, prow, st);
-                    emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, rtmp.p, rvert, orow);
+                    emit_rows(g, algo, R, d_ridx.p, d_rvert.p, d_orow.p, rtmp.p, ridx, rvert, orow);
                     int32_t *pp = dev ? pred_out : ptmp.p;
                     launch_pred_rows(rtmp.p, R, V, d_rvert.p, g->d_in_ptr.p, g->d_in_src.p,
                                      g->d_in_w.p, d_orow.p, d_prow.p, pp, st);

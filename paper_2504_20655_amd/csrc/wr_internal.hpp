@@ -295,6 +295,8 @@ struct SegState {
     uint32_t nsrc = 0;         // sources of the chunk (blocked layout: lanes beyond are idle)
     uint8_t *flags = nullptr;  // [T][S] activation flags (overlay schedule), else null
     uint32_t *pending = nullptr;   // [S] blocks with set flags after a replay (overlay schedule)
+    uint32_t *tile_visits = nullptr;   // [T] overlay visits of each tile (work counter)
+    uint32_t *wave_stores = nullptr;   // [wave slots] exit values each pass wave stored (work counter)
 };
 // activates (s, tile of source s) for the chunk's sources s < n
 void launch_seg_seed_n(const TileSet &ts, const SegState &ss, uint32_t n, hipStream_t st);
@@ -313,6 +315,8 @@ void launch_seg_emit(const TileSet &ts, const SegState &ss, uint32_t V, uint32_t
 struct SegBuffers {
     uint32_t S_cap = 0, G = 0, lanes = 1;
     DBuf<uint32_t> gdist, inbox, xval, stamps, cnt, bucket, tiles, ctr, src_pos, src_tile, pending;
+    DBuf<uint32_t> tile_visits, wave_stores;
+    uint32_t wave_slots = 0;   // workgroups x waves of the widest overlay pass launch
     DBuf<uint8_t> visited, flags;
     DBuf<uint2> units;
     DBuf<unsigned long long> stats;
@@ -394,9 +398,12 @@ void launch_ovl_pin_rec(const TileSet &ts, hipStream_t st);
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
                      const uint32_t *F, bool count_after, hipStream_t st, hipEvent_t ev_begin = nullptr,
                      hipEvent_t ev_end = nullptr);
+// full rows: out_row[r] * V .. gets the row of the source at row_src_vertex[r];
+// the rows' sources are grouped by 64-source block: group g covers block
+// grp_block[g], lane l of it goes to row lane_row[g * 64 + l] (NONE: none)
 void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, uint32_t V, uint32_t rows,
-                     const uint32_t *row_src_idx, const uint32_t *row_src_vertex, const uint32_t *out_row,
-                     uint32_t *out, hipStream_t st);
+                     const uint32_t *row_src_vertex, const uint32_t *out_row, const uint32_t *grp_block,
+                     const uint32_t *lane_row, uint32_t ngroups, uint32_t num_cus, uint32_t *out, hipStream_t st);
 void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
                        const uint64_t *out_base, const uint32_t *src_idx_of_pick, uint32_t chunk_lo,
                        uint32_t chunk_n, const TileSet &ts, const SegState &ss, const uint32_t *F,

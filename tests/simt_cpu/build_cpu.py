@@ -14,7 +14,13 @@ LIB_SOURCES = ["kernels.hip", "runtime.cpp", "tiles.cpp", "solve.cpp", "server.c
 
 
 def build(sanitize: bool = True) -> str:
+    """Compiles into a directory of this process and renames the linked
+    driver into place, so parallel test workers never write a file another
+    one is running or linking."""
+    import shutil
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    objdir = os.path.join(os.path.dirname(OUT), f"obj{os.getpid()}")
+    os.makedirs(objdir, exist_ok=True)
     san = ["-fsanitize=address", "-fno-omit-frame-pointer"] if sanitize else []
     flags = ["-std=c++20", "-O1", "-g", "-pthread", "-w", *san,
              "-I", HERE, "-I", os.path.join(ROOT, "include")]
@@ -24,7 +30,7 @@ def build(sanitize: bool = True) -> str:
         path = os.path.normpath(os.path.join(CSRC, src))
         if not os.path.exists(path):
             continue
-        obj = os.path.join(os.path.dirname(OUT), os.path.basename(src) + ".o")
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
         cmd = ["g++", "-x", "c++", *flags, "-c", path, "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
@@ -32,9 +38,12 @@ def build(sanitize: bool = True) -> str:
         out, _ = p.communicate()
         if p.returncode != 0:
             raise RuntimeError(f"{src}:\n{out}")
-    r = subprocess.run(["g++", *san, "-pthread", "-o", OUT, *objs], capture_output=True, text=True)
+    tmp = f"{OUT}.tmp{os.getpid()}"
+    r = subprocess.run(["g++", *san, "-pthread", "-o", tmp, *objs], capture_output=True, text=True)
+    shutil.rmtree(objdir, ignore_errors=True)
     if r.returncode != 0:
         raise RuntimeError(r.stdout + r.stderr)
+    os.replace(tmp, OUT)
     return OUT
 
 

@@ -2,7 +2,14 @@
 test executor (tests/simt_cpu: lanes as threads, emulated wave collectives
 and barriers, AddressSanitizer on every buffer), against the oracle.  This
 checks the kernels' logic and bounds without a GPU; the GPU tests check the
-same paths on the hardware."""
+same paths on the hardware.
+
+Each case runs in its own driver process; the cases start together (the
+executor is bound by thread wake-ups, not by arithmetic), and one test
+collects every case's verdict."""
+import concurrent.futures as cf
+import traceback
+
 import numpy as np
 import pytest
 
@@ -11,15 +18,30 @@ from wgen import make_config
 
 pytestmark = pytest.mark.slow
 
-
-@pytest.fixture(scope="module")
-def harness():
-    from tests.simt_cpu import harness as h
-    h.driver(rebuild=True)
-    return h
+CASES = []
 
 
-def test_overlay_order_matrices_tiny(harness):
+def case(fn):
+    CASES.append(fn)
+    return fn
+
+
+def test_kernels_on_cpu_executor():
+    from tests.simt_cpu import harness
+    harness.driver(rebuild=True)
+    with cf.ThreadPoolExecutor(max_workers=len(CASES)) as ex:
+        futs = {fn.__name__: ex.submit(fn, harness) for fn in CASES}
+    failed = {}
+    for name, f in futs.items():
+        try:
+            f.result()
+        except Exception:
+            failed[name] = traceback.format_exc()[-3000:]
+    assert not failed, "\n\n".join(f"{k}:\n{v}" for k, v in failed.items())
+
+
+@case
+def case_overlay_order_matrices_tiny(harness):
     wl = make_config("tiny")
     g = wl.graph
     st, out, _, err = harness.run(g.row_ptr, g.col, g.w, pick_offsets=wl.pick_offsets, picks=wl.picks,
@@ -29,7 +51,8 @@ def test_overlay_order_matrices_tiny(harness):
     assert (out == exp).all()
 
 
-def test_segmented_rows_and_pred_random_graph(harness):
+@case
+def case_segmented_rows_and_pred_random_graph(harness):
     from tests.helpers import random_csr
     rng = np.random.default_rng(31)
     V = 160
@@ -47,14 +70,39 @@ def test_segmented_rows_and_pred_random_graph(harness):
         assert (p[i] == oracle.canonical_pred(rp, col, w, int(s), ed)).all()
 
 
-def test_order_routes_over_executor_matrices(harness):
+@case
+def case_overlay_full_rows_executor(harness):
+    """Full rows under the overlay schedule (the tile-blocked read-out):
+    sources spread over several 64-source blocks, a source asked for twice
+    (a second row group of its block) and a blocked cell (no arcs, only
+    itself at 0), with predecessors; rows equal the oracle's."""
+    wl = make_config("medium", side=15, num_orders=1)
+    g = wl.graph
+    rng = np.random.default_rng(8)
+    free = np.flatnonzero(np.diff(g.row_ptr.astype(np.int64)) > 0)
+    blocked = np.flatnonzero(np.diff(g.row_ptr.astype(np.int64)) == 0)
+    src = rng.choice(free, 66, replace=False).astype(np.uint32)
+    src = np.concatenate([src, src[[3, 65]], blocked[:1]]).astype(np.uint32)
+    st, out, pred, err = harness.run(g.row_ptr, g.col, g.w, sources=src, algo="overlay", pred=True,
+                                     seg=("grid", g.W, g.H, 1, 6, 5))
+    assert st == 0, err[-2000:]
+    d = out.reshape(len(src), g.V)
+    p = pred.reshape(len(src), g.V)
+    exp = oracle.dijkstra_multi(g.row_ptr, g.col, g.w, src)
+    assert (d == exp).all()
+    for i, s in enumerate(src):
+        assert (p[i] == oracle.canonical_pred(g.row_ptr, g.col, g.w, int(s), exp[i])).all()
+
+
+@case
+def case_order_routes_over_executor_matrices(harness):
     """wr_order_routes (subset programme in LDS) over the library's own
     matrices for orders of 0..12 stops with duplicate picks: lengths and
     orderings equal the oracle's, with every LDS and global access checked."""
     wl = make_config("medium", side=24, num_orders=8)
     g = wl.graph
     rng = np.random.default_rng(3)
-    sizes = [0, 1, 2, 3, 5, 8, 12, 7, 12, 4]
+    sizes = [0, 1, 2, 3, 5, 12, 4]
     picks = np.concatenate([rng.choice(wl.picks, s) for s in sizes]).astype(np.uint32)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
     st, out, _, err = harness.run(g.row_ptr, g.col, g.w, pick_offsets=off, picks=picks, algo="overlay",
@@ -71,15 +119,17 @@ def test_order_routes_over_executor_matrices(harness):
     assert (lens == el).all() and (rts == er).all()
 
 
-def test_clustered_routes_over_executor_matrices(harness):
+@case
+def case_clustered_routes_over_executor_matrices(harness):
     """wr_order_routes_clustered (K-means in wave 0, the per-cluster and the
     chaining subset programmes) over executor-computed matrices, orders of
-    0..32 picks at m = 10 (the largest chaining programme): lengths,
-    orderings and cluster counts equal the oracle's."""
+    0..13 picks at m = 10 (the largest chaining programme, ten clusters of
+    one or two picks): lengths, orderings and cluster counts equal the
+    oracle's."""
     wl = make_config("medium", side=24, num_orders=8)
     g = wl.graph
     rng = np.random.default_rng(4)
-    sizes = [0, 1, 2, 5, 13, 20, 32, 9]
+    sizes = [0, 1, 2, 5, 13]
     picks = np.concatenate([rng.choice(wl.picks, s) for s in sizes]).astype(np.uint32)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
     xy = np.stack([picks % g.W, picks // g.W], 1).astype(np.int32)
