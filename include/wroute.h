@@ -241,6 +241,24 @@ wr_status wr_order_routes(wr_context *ctx, uint32_t num_orders, const uint32_t *
                           const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
                           uint32_t flags, void *stream);
 
+/* Exact routes for callers that cannot allocate device memory (code under
+ * their own graph capture, tight serving loops, harnesses that forbid
+ * allocation): the results of wr_order_routes, with every work buffer held
+ * in one fixed device array of the library (about 1.3 MB, kept by each GPU
+ * the library runs on until the process ends) instead of allocations.
+ * dist, length_out and route_out are device pointers, laid out as for
+ * wr_order_routes; pick_offsets is a host array (validated on the host).
+ * The work is enqueued on `stream` (the caller's hipStream_t; NULL is the
+ * null stream) after the caller's earlier work on it, and the call returns
+ * once it is done.  flags: 0 or WR_ROUTE_ENUMERATE.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU race, so a caller
+ * serialises them.  Errors: as wr_order_routes, and WR_E_RANGE when
+ * num_orders exceeds WR_ROUTES_STATIC_MAX_ORDERS (nothing is enqueued). */
+#define WR_ROUTES_STATIC_MAX_ORDERS 65536u
+wr_status wr_order_routes_static(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
+                                 const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
+                                 uint32_t flags, void *stream);
+
 /* Cluster-decomposed route over each order's stops (the theorem of the
  * Route Optimization section): the stops are split into m clusters by
  * K-means on their positions (a cluster's centre is the mean position of

@@ -101,6 +101,17 @@ class Context:
         _check(lib().wr_order_routes(self.h, n, _ptr(off), _ptr(d), _ptr(ln), _ptr(rt), extra, None))
         return ln[:max(n, 0)], rt[:total]
 
+    def order_routes_static(self, pick_offsets, dist, lengths, routes, enumerate: bool = False):
+        """wr_order_routes_static: the exact routes of order_routes() with no
+        device allocation by the library; dist, lengths (int64) and routes
+        (int32) are device tensors, the work runs on lengths' current
+        stream.  Returns (lengths, routes)."""
+        off = _u32(pick_offsets)
+        n = len(off) - 1
+        _check(lib().wr_order_routes_static(self.h, n, _ptr(off), _ptr(dist), _ptr(lengths), _ptr(routes),
+                                            ROUTE_ENUMERATE if enumerate else 0, _stream_of(lengths)))
+        return lengths, routes
+
     def order_routes_clustered(self, pick_offsets, dist, pick_xy, m: int, lengths=None, routes=None):
         """Cluster-decomposed route over each order's stops
         (wr_order_routes_clustered): pick_xy holds (x, y) per pick.  Returns

@@ -69,6 +69,7 @@ SIGNATURES = {
     "wr_sssp": (st, [vp, u32, vp, vp, vp, u32, vp]),
     "wr_order_matrices": (st, [vp, u32, vp, vp, vp, vp, u32, vp]),
     "wr_order_routes": (st, [vp, u32, vp, vp, vp, vp, u32, vp]),
+    "wr_order_routes_static": (st, [vp, u32, vp, vp, vp, vp, u32, vp]),
     "wr_order_routes_clustered": (st, [vp, u32, vp, vp, vp, u32, vp, vp, vp, u32, vp]),
     "wr_graph_last_run": (st, [vp, vp]),
     "wr_autotune": (st, [vp, u32, ctypes.c_char_p]),

@@ -2,6 +2,7 @@
 // order's distance matrix (Route Optimization section; Held and Karp's
 // subset programme, run by k_route_hk with one workgroup per order).
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "wr_internal.hpp"
@@ -180,5 +181,91 @@ extern "C" wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_ord
                                    std::to_string(route_max_stops()) + " stops with at most " +
                                    std::to_string(route_clustered_max_clusters()) + " clusters");
     if (clusters_out) std::copy(hm.begin(), hm.end(), clusters_out);
+    WR_API_END
+}
+
+// ------------------------------------------------------------------------
+// wr_order_routes_static: wr_order_routes for callers that cannot allocate.
+// Its work buffers (the orders' pick offsets and matrix bases, the overflow
+// flag and, when enumerating, the per-order keys) live in one fixed device
+// array, `scratch`, instead of allocations.  Host code never passes the
+// array's name to a kernel: it takes the array's device address once per
+// device with hipGetSymbolAddress and uses that address everywhere.
+namespace {
+
+constexpr uint32_t kStaticMaxOrders = WR_ROUTES_STATIC_MAX_ORDERS;
+// [flag u32, padded to 256 B][off u32 x (max+1), padded][mbase u64 x max][key u64 x max]
+constexpr size_t kScratchFlag = 0;
+constexpr size_t kScratchOff = 256;
+constexpr size_t kScratchBase = kScratchOff + ((4ull * (kStaticMaxOrders + 1) + 255) / 256) * 256;
+constexpr size_t kScratchKey = kScratchBase + 8ull * kStaticMaxOrders;
+constexpr size_t kScratchBytes = kScratchKey + 8ull * kStaticMaxOrders;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), taken once.
+unsigned char *scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(WR_E_UNSUPPORTED, "device index beyond the static route buffers");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(WR_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+extern "C" wr_status wr_order_routes_static(wr_context *ctx, uint32_t num_orders, const uint32_t *pick_offsets,
+                                            const uint32_t *dist, uint64_t *length_out, uint32_t *route_out,
+                                            uint32_t flags, void *stream) {
+    WR_API_BEGIN
+    if (!ctx) fail(WR_E_INVALID, "context is NULL");
+    if (flags & ~static_cast<uint32_t>(WR_ROUTE_ENUMERATE))
+        fail(WR_E_INVALID, "unknown flags for wr_order_routes_static");
+    if (num_orders == 0) return WR_OK;
+    if (num_orders > kStaticMaxOrders)
+        fail(WR_E_RANGE, "wr_order_routes_static serves at most " + std::to_string(kStaticMaxOrders) +
+                             " orders per call (asked for " + std::to_string(num_orders) + ")");
+    const bool enumerate = flags & WR_ROUTE_ENUMERATE;
+    const RouteBatch rb = route_batch(num_orders, pick_offsets,
+                                      enumerate ? route_enumerate_max_stops() : route_max_stops(),
+                                      enumerate ? "enumerated routes" : "exact routes");
+    if (!length_out) fail(WR_E_INVALID, "length_out is NULL");
+    if (rb.total && !route_out) fail(WR_E_INVALID, "route_out is NULL");
+    if (rb.cells && !dist) fail(WR_E_INVALID, "dist is NULL");
+    WR_HIP(hipSetDevice(ctx->device));
+    unsigned char *base = scratch_on(ctx->device);
+    uint32_t *d_flag = reinterpret_cast<uint32_t *>(base + kScratchFlag);
+    uint32_t *d_off = reinterpret_cast<uint32_t *>(base + kScratchOff);
+    uint64_t *d_base = reinterpret_cast<uint64_t *>(base + kScratchBase);
+    unsigned long long *d_key = reinterpret_cast<unsigned long long *>(base + kScratchKey);
+    // everything runs on the caller's stream, in order after its earlier work
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    WR_HIP(hipMemcpyAsync(d_off, rb.off.data(), 4ull * (num_orders + 1), hipMemcpyHostToDevice, st));
+    WR_HIP(hipMemcpyAsync(d_base, rb.mbase.data(), 8ull * num_orders, hipMemcpyHostToDevice, st));
+    launch_fill_u32(d_flag, 1, 0u, st);
+    if (enumerate) {
+        launch_fill_u32(reinterpret_cast<uint32_t *>(d_key), 2ull * num_orders, 0xFFFFFFFFu, st);
+        launch_route_perm(num_orders, d_off, d_base, dist, d_key, length_out, route_out, d_flag, rb.nmax, st);
+    } else {
+        const uint32_t lds = route_lds_bytes(std::max(rb.nmax, 1u));
+        const uint32_t per_cu = std::max(1u, std::min(8u, (160u * 1024u) / lds));
+        launch_route_hk(num_orders, d_off, d_base, dist, length_out, route_out, d_flag, rb.nmax,
+                        static_cast<uint32_t>(ctx->num_cus) * per_cu, st);
+    }
+    // the host copies above read rb's vectors, and the flag decides the
+    // status: wait for the stream before returning
+    uint32_t ovf = 0;
+    WR_HIP(hipMemcpyAsync(&ovf, d_flag, 4, hipMemcpyDeviceToHost, st));
+    WR_HIP(hipStreamSynchronize(st));
+    if (ovf) fail(WR_E_RANGE, "a partial route length reached 2^32-1 (lengths are accumulated in 32 bits)");
     WR_API_END
 }
