@@ -338,6 +338,11 @@ wr_status wr_autotune(wr_graph *g, uint32_t sources_hint, const char *cache_path
 wr_status wr_graph_set_schedule(wr_graph *g, uint32_t tile_vertices,
                                 uint32_t waves_per_group, uint32_t passes_per_replay);
 
+/* Sets the 64-source blocks one workgroup unit of the overlay and
+ * segmented passes visits (1..64; 0 restores the default).  Errors:
+ * WR_E_INVALID. */
+wr_status wr_graph_set_blocks_per_unit(wr_graph *g, uint32_t blocks);
+
 /* The schedule a graph runs with (as set, or as wr_autotune chose). */
 typedef struct wr_schedule {
     uint32_t tile_vertices;      /* most vertices of one LDS tile               */

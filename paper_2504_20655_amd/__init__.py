@@ -195,6 +195,9 @@ class Graph:
     def autotune(self, sources_hint: int = 256, cache_path: str | None = None):
         _check(lib().wr_autotune(self.h, sources_hint, cache_path.encode() if cache_path else None))
 
+    def set_blocks_per_unit(self, blocks: int):
+        _check(lib().wr_graph_set_blocks_per_unit(self.h, blocks))
+
     def schedule(self) -> dict:
         """The schedule the graph runs with (wr_graph_get_schedule)."""
         sc = _lib.Schedule()

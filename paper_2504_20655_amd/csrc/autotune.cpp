@@ -209,3 +209,13 @@ extern "C" wr_status wr_graph_get_schedule(const wr_graph *g, wr_schedule *out) 
     out->grid_tile_h = g->grid_W ? g->grid_th : 0u;
     WR_API_END
 }
+
+extern "C" wr_status wr_graph_set_blocks_per_unit(wr_graph *g, uint32_t blocks) {
+    WR_API_BEGIN
+    if (!g) fail(WR_E_INVALID, "graph is NULL");
+    if (blocks > 64) fail(WR_E_INVALID, "at most 64 blocks per unit");
+    g->sources_per_unit = blocks;
+    destroy_workspace(g->ws);
+    g->ws = nullptr;
+    WR_API_END
+}

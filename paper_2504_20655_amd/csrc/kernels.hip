@@ -855,6 +855,7 @@ __global__ void k_min_scatter(const uint64_t *__restrict__ idx, const uint32_t *
 constexpr uint32_t OVL_XCAP = 64;     // exits per tile (one 64-lane row of the exit table)
 constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving or entering a tile
 constexpr uint32_t OVL_NW = 8;        // waves per workgroup
+constexpr uint64_t OVL_UNIT_PERM = 2654435761ull;   // a prime above any unit count (see seg_units_cap)
 template <int NW, int R>
 __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ Fx,
                                                       const uint4 *__restrict__ hdr,
@@ -889,7 +890,11 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         }
         first_unit = NONE;
         if (u >= nunits) break;
-        const uint2 unit = A.units[u];
+        // units are taken in a scattered order (u -> u * P mod nunits, a
+        // bijection for the prime P > nunits): each pass then moves every
+        // front about one tile instead of cascading along the tiles' order,
+        // which lowers the visits to convergence
+        const uint2 unit = A.units[static_cast<uint32_t>((static_cast<uint64_t>(u) * OVL_UNIT_PERM) % nunits)];
         const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
         const uint4 h = hdr[t];
         const uint32_t p0 = uniform(h.x), b0 = uniform(h.y), xa0 = uniform(h.z), hw = uniform(h.w);

@@ -271,8 +271,8 @@ Plan make_plan(wr_graph *g, const uint32_t *verts, size_t n, bool by_tile) {
 }
 
 // -------------------------------------------------------- segmented driver
-uint32_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
-    return ts.T * ((S + G - 1) / G) + ts.T;
+uint64_t seg_units_cap(const TileSet &ts, uint32_t S, uint32_t G) {
+    return static_cast<uint64_t>(ts.T) * ((S + G - 1) / G) + ts.T;
 }
 
 }  // namespace
@@ -303,6 +303,8 @@ void SegBuffers::init(wr_context *ctx, const TileSet &ts, uint32_t S, uint32_t g
     bucket.alloc(ctx, 2ull * ts.T * S);
     tiles.alloc(ctx, 2ull * ts.T);
     ctr.alloc(ctx, 8);
+    // the overlay pass permutes unit indices with a prime above the count
+    if (seg_units_cap(ts, S, G) >= 2654435761ull) fail(WR_E_NOMEM, "too many work units for one state");
     units.alloc(ctx, seg_units_cap(ts, S, G));
     stats.alloc(ctx, 2);
     if (with_flags) {

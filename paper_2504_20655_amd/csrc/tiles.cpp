@@ -289,30 +289,71 @@ void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t cap, 
 
 namespace {
 
+// Interior cut positions along one axis of extent n: segments of `seg`
+// cells from 0, each cut into pieces of about `sub` cells.  A piece boundary
+// moves by up to a quarter piece (at most 2 cells) to the boundary the
+// fewest arcs cross (cross[c] = arcs between cell c-1 and c, ties to the
+// nominal position), so cuts avoid splitting corridors the arcs run along.
+// Returns, per cell, its piece index inside its segment.
+std::vector<uint32_t> grid_cuts(uint32_t n, uint32_t seg, uint32_t sub, const std::vector<uint64_t> &cross) {
+    std::vector<uint32_t> piece(n, 0);
+    const uint32_t r = std::min(2u, sub / 4);
+    for (uint32_t s0 = 0; s0 < n; s0 += seg) {
+        const uint32_t s1 = std::min(n, s0 + seg);
+        uint32_t prev = s0, k = 0;
+        for (uint32_t c = s0 + sub; c < s1; c += sub) {
+            uint32_t best = c;
+            for (uint32_t d = 1; d <= r; ++d) {
+                for (uint32_t cand : {c - d, c + d}) {
+                    if (cand <= prev || cand >= s1) continue;
+                    if (cross[cand] < cross[best]) best = cand;
+                }
+            }
+            for (uint32_t x = prev; x < best; ++x) piece[x] = k;
+            prev = best;
+            ++k;
+        }
+        for (uint32_t x = prev; x < s1; ++x) piece[x] = k;
+    }
+    return piece;
+}
+
 // Grid segments (tile_w x tile_h cells per level) and, nested in them,
 // sub-rectangles holding at most `cap` vertices incident to an arc (blocked
 // cells are isolated ids and take no tile space): halve the longer side of
-// the sub-rectangle until every one of them fits.
+// the sub-rectangle until every one of them fits, with the sub-rectangles'
+// boundaries snapped to the rows and columns the fewest arcs cross.
 void grid_maps(const wr_graph *g, uint32_t W, uint32_t H, uint32_t L, uint32_t tw, uint32_t th, uint32_t cap,
                std::vector<uint32_t> &seg, uint32_t &nseg, std::vector<uint32_t> &sub, uint32_t &nsub) {
     const uint32_t tx = (W + tw - 1) / tw, ty = (H + th - 1) / th;
-    std::vector<uint8_t> inc(static_cast<size_t>(W) * H * L, 0);
+    const size_t plane = static_cast<size_t>(W) * H;
+    std::vector<uint8_t> inc(plane * L, 0);
+    std::vector<uint64_t> crossx(W + 1, 0), crossy(H + 1, 0);
     for (uint32_t u = 0; u < g->V; ++u)
         for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e) {
+            const uint32_t v = g->col[e];
             inc[u] = 1;
-            inc[g->col[e]] = 1;
+            inc[v] = 1;
+            if (u / plane != v / plane) continue;
+            const uint32_t ux = (u % plane) % W, uy = static_cast<uint32_t>((u % plane) / W);
+            const uint32_t vx = (v % plane) % W, vy = static_cast<uint32_t>((v % plane) / W);
+            if (uy == vy && (ux + 1 == vx || vx + 1 == ux)) crossx[std::max(ux, vx)]++;
+            if (ux == vx && (uy + 1 == vy || vy + 1 == uy)) crossy[std::max(uy, vy)]++;
         }
+    std::vector<uint32_t> px, py;
     auto fits = [&](uint32_t sw, uint32_t sh) {
-        const uint32_t sx = (tw + sw - 1) / sw, sy = (th + sh - 1) / sh;
+        px = grid_cuts(W, tw, sw, crossx);
+        py = grid_cuts(H, th, sh, crossy);
+        const uint32_t sx = (tw + sw - 1) / sw + 1, sy = (th + sh - 1) / sh + 1;
         const uint64_t n = static_cast<uint64_t>(tx) * ty * L * sx * sy;
         std::vector<uint32_t> cnt(n, 0u);
         for (uint32_t l = 0; l < L; ++l)
             for (uint32_t y = 0; y < H; ++y)
                 for (uint32_t x = 0; x < W; ++x) {
-                    const size_t v = (static_cast<size_t>(l) * H + y) * W + x;
+                    const size_t v = l * plane + static_cast<size_t>(y) * W + x;
                     if (!inc[v]) continue;
                     const uint64_t s = (static_cast<uint64_t>(l) * ty + y / th) * tx + x / tw;
-                    const uint64_t q = (s * sy + (y % th) / sh) * sx + (x % tw) / sw;
+                    const uint64_t q = (s * sy + py[y]) * sx + px[x];
                     if (++cnt[q] > cap) return false;
                 }
         return true;
@@ -322,18 +363,19 @@ void grid_maps(const wr_graph *g, uint32_t W, uint32_t H, uint32_t L, uint32_t t
         if (sw >= sh) sw = (sw + 1) / 2;
         else sh = (sh + 1) / 2;
     }
-    const uint32_t sx = (tw + sw - 1) / sw, sy = (th + sh - 1) / sh;
+    // a snapped piece can be up to 2 cells wider than sw: one spare index
+    const uint32_t sx = (tw + sw - 1) / sw + 1, sy = (th + sh - 1) / sh + 1;
     nseg = tx * ty * L;
     nsub = nseg * sx * sy;
-    seg.resize(static_cast<size_t>(W) * H * L);
+    seg.resize(plane * L);
     sub.resize(seg.size());
     for (uint32_t l = 0; l < L; ++l)
         for (uint32_t y = 0; y < H; ++y)
             for (uint32_t x = 0; x < W; ++x) {
-                const size_t v = (static_cast<size_t>(l) * H + y) * W + x;
+                const size_t v = l * plane + static_cast<size_t>(y) * W + x;
                 const uint32_t s = (l * ty + y / th) * tx + x / tw;
                 seg[v] = s;
-                sub[v] = (s * sy + (y % th) / sh) * sx + (x % tw) / sw;
+                sub[v] = (s * sy + py[y]) * sx + px[x];
             }
 }
 
