@@ -1150,19 +1150,28 @@ __device__ __forceinline__ uint32_t ovl_value(const OvlRead &R, uint32_t s, uint
 // The block's entry values at the tile's ports are pulled once into LDS
 // (min over the tile's incoming cross arcs of exit value + w), then every
 // vertex of the tile takes min over the ports of entry + F[vertex][port]
-// (its table row, one coalesced load, broadcast port by port).  Rows are
-// INF-filled before and their sources set to 0 after (k_fill_rows,
+// (its table row, one coalesced load, broadcast port by port).  A wave
+// computes 32 vertices for its 64 sources into LDS and stores them
+// transposed, two rows per instruction over consecutive tile positions.
+// Rows are INF-filled before and their sources set to 0 after (k_fill_rows,
 // k_rows_src_zero); paths inside a source's own tile come from the in-tile
 // fix-up.
-__global__ __launch_bounds__(256) void k_ovl_rows(OvlRead R, const uint32_t *__restrict__ tile_base,
-                                                  const uint4 *__restrict__ hdr, uint32_t T,
-                                                  const uint32_t *__restrict__ grp_block,
-                                                  const uint32_t *__restrict__ lane_row, uint64_t items,
-                                                  const uint32_t *__restrict__ vert_of, uint32_t V,
-                                                  uint32_t *__restrict__ out) {
-    HIP_DYNAMIC_SHARED(uint32_t, s_ent)   // [most ports of a tile][64]
+constexpr uint32_t ROWS_NW = 4;      // waves per workgroup
+constexpr uint32_t ROWS_CHUNK = 32;  // vertices a wave stages at a time
+__global__ __launch_bounds__(ROWS_NW * 64) void k_ovl_rows(OvlRead R, const uint32_t *__restrict__ tile_base,
+                                                           const uint4 *__restrict__ hdr, uint32_t T,
+                                                           const uint32_t *__restrict__ grp_block,
+                                                           const uint32_t *__restrict__ lane_row, uint64_t items,
+                                                           const uint32_t *__restrict__ vert_of, uint32_t V,
+                                                           uint32_t *__restrict__ out) {
+    HIP_DYNAMIC_SHARED(uint32_t, lds)
+    uint32_t *s_row = lds;                        // [64] output row of each source lane
+    uint32_t *s_val = s_row + 64;                 // [ROWS_NW][ROWS_CHUNK][65] staged values
+    uint32_t *s_ent = s_val + ROWS_NW * ROWS_CHUNK * 65;   // [most ports of a tile][64]
     const uint32_t lane = lane_id();
-    const uint32_t wv = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    uint32_t *sv = s_val + wv * ROWS_CHUNK * 65;
+    const uint32_t j = lane & (ROWS_CHUNK - 1), h = lane / ROWS_CHUNK;   // store phase: vertex, row parity
     for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const uint32_t t = uniform(static_cast<uint32_t>(it % T)), gi = uniform(static_cast<uint32_t>(it / T));
         const uint32_t b = uniform(grp_block[gi]);
@@ -1170,22 +1179,32 @@ __global__ __launch_bounds__(256) void k_ovl_rows(OvlRead R, const uint32_t *__r
         const uint2 h2 = R.hdr2[t];
         const uint32_t a0 = uniform(h2.x), na = uniform(h2.y);
         const uint32_t base = uniform(tile_base[t]), n = uniform(tile_base[t + 1]) - base;
-        for (uint32_t i = wv; i < E; i += nw) s_ent[i * 64 + lane] = INF;
+        if (threadIdx.x < 64) s_row[lane] = lane_row[static_cast<size_t>(gi) * 64 + lane];
+        for (uint32_t i = wv; i < E; i += ROWS_NW) s_ent[i * 64 + lane] = INF;
         __syncthreads();
         const uint32_t *xb = R.xval + static_cast<size_t>(b) * R.NB * 64 + lane;
-        for (uint32_t k = wv; k < na; k += nw) {
+        for (uint32_t k = wv; k < na; k += ROWS_NW) {
             const uint2 rec = R.pin_rec[a0 + k];
             atomicMin(&s_ent[(rec.y >> 16) * 64 + lane], sat_add(xb[static_cast<size_t>(rec.x) * 64], rec.y & 0xFFFFu));
         }
         __syncthreads();
-        const uint32_t row = lane_row[static_cast<size_t>(gi) * 64 + lane];
-        uint32_t *o = out + (row == NONE ? 0 : static_cast<size_t>(row) * V);
-        for (uint32_t j = wv; j < n; j += nw) {
-            const uint32_t pos = base + j;
-            const uint32_t fv = R.F[static_cast<size_t>(pos) * 64 + lane];
-            uint32_t m = INF;
-            for (uint32_t i = 0; i < E; ++i) m = min(m, sat_add(s_ent[i * 64 + lane], __builtin_amdgcn_readlane(fv, i)));
-            if (row != NONE) o[vert_of[pos]] = m;
+        for (uint32_t c0 = wv * ROWS_CHUNK; c0 < n; c0 += ROWS_NW * ROWS_CHUNK) {
+            const uint32_t cn = min(ROWS_CHUNK, n - c0);
+            for (uint32_t q = 0; q < cn; ++q) {
+                const uint32_t fv = R.F[static_cast<size_t>(base + c0 + q) * 64 + lane];
+                uint32_t m = INF;
+                for (uint32_t i = 0; i < E; ++i)
+                    m = min(m, sat_add(s_ent[i * 64 + lane], __builtin_amdgcn_readlane(fv, i)));
+                sv[q * 65 + lane] = m;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t vj = j < cn ? vert_of[base + c0 + j] : 0u;
+            for (uint32_t l2 = 0; l2 < 32; ++l2) {
+                const uint32_t l = 2 * l2 + h;
+                const uint32_t r = s_row[l];
+                if (j < cn && r != NONE) out[static_cast<size_t>(r) * V + vj] = sv[j * 65 + l];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
     }
@@ -1824,9 +1843,9 @@ void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, u
     check_launch("fill_rows");
     const uint64_t items = static_cast<uint64_t>(ts.T) * ngroups;
     if (items) {
-        const uint32_t lds = std::max(ts.max_ports, 1u) * 64u * 4u;
+        const uint32_t lds = (64u + ROWS_NW * ROWS_CHUNK * 65u + std::max(ts.max_ports, 1u) * 64u) * 4u;
         const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(items, static_cast<uint64_t>(num_cus) * 16u));
-        hipLaunchKernelGGL(k_ovl_rows, grid, 256, lds, st, ovl_read(ts, ss, F), ts.d_tile_base.p,
+        hipLaunchKernelGGL(k_ovl_rows, grid, ROWS_NW * 64, lds, st, ovl_read(ts, ss, F), ts.d_tile_base.p,
                            reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), ts.T, grp_block, lane_row, items,
                            ts.d_vert_of.p, V, out);
         check_launch("ovl_rows");
