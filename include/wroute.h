@@ -354,6 +354,14 @@ typedef struct wr_schedule {
 } wr_schedule;
 wr_status wr_graph_get_schedule(const wr_graph *g, wr_schedule *out);
 
+/* Test hook for failure handling: the nth next device allocation (kind 1,
+ * the call fails with WR_E_NOMEM) or kernel launch (kind 2, WR_E_DEVICE)
+ * the library makes, from any thread, fails on the host before anything
+ * reaches the device; kind 0 disarms.  One fault at a time, process-wide.
+ * The environment variable WR_FAULT=alloc:N or launch:N arms it at load.
+ * Errors: WR_E_INVALID. */
+wr_status wr_debug_fault(uint32_t kind, uint64_t nth);
+
 /* ---- continuous-batching server -------------------------------------- */
 
 typedef struct wr_server_opts {

@@ -63,6 +63,13 @@ def version() -> str:
     return lib().wr_version().decode()
 
 
+def debug_fault(kind: str, nth: int = 1):
+    """Test hook (wr_debug_fault): the nth next device allocation
+    (kind="alloc") or kernel launch (kind="launch") of the library fails on
+    the host; kind="off" disarms."""
+    _check(lib().wr_debug_fault({"off": 0, "alloc": 1, "launch": 2}[kind], nth))
+
+
 def validate_csr(row_ptr, col, w) -> int:
     """Returns the wr_status of wr_validate_csr (0 = valid)."""
     rp, c, ww = _u32(row_ptr), _u32(col), _u32(w)

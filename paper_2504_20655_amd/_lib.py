@@ -76,6 +76,7 @@ SIGNATURES = {
     "wr_graph_set_schedule": (st, [vp, u32, u32, u32]),
     "wr_graph_get_schedule": (st, [vp, vp]),
     "wr_graph_set_blocks_per_unit": (st, [vp, u32]),
+    "wr_debug_fault": (st, [u32, u64]),
     "wr_server_create": (st, [vp, vp, vp]),
     "wr_server_submit": (st, [vp, u32, vp, vp]),
     "wr_server_poll": (st, [vp, u64, vp, vp]),

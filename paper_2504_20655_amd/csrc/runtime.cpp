@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <mutex>
 #include <numeric>
 
@@ -21,35 +22,37 @@ void clear_last_error() { g_last_error.clear(); }
 [[noreturn]] void fail(wr_status st, const std::string &msg) { throw Error{st, msg}; }
 
 // ------------------------------------------------------------ fault hooks
+// Test hooks: the n-th next device allocation (kind 1) or kernel launch
+// (kind 2) the library makes fails on the host with the status a real
+// failure of that call would give, before anything reaches the device.
+// Armed by wr_debug_fault, or at start-up by WR_FAULT=alloc:N | launch:N.
 namespace {
-struct FaultSpec {
-    long alloc_at = -1, launch_at = -1;
-    FaultSpec() {
+std::atomic<uint32_t> g_fault_kind{0};
+std::atomic<long> g_fault_left{0};
+struct FaultEnv {
+    FaultEnv() {
         const char *e = std::getenv("WR_FAULT");
         if (!e) return;
         std::string s(e);
         size_t c = s.find(':');
         if (c == std::string::npos) return;
-        long n = std::atol(s.c_str() + c + 1);
-        if (s.compare(0, c, "alloc") == 0) alloc_at = n;
-        if (s.compare(0, c, "launch") == 0) launch_at = n;
+        const long n = std::atol(s.c_str() + c + 1);
+        if (n <= 0) return;
+        if (s.compare(0, c, "alloc") == 0) g_fault_kind = 1;
+        if (s.compare(0, c, "launch") == 0) g_fault_kind = 2;
+        g_fault_left = n;
     }
-};
-FaultSpec &faults() {
-    static FaultSpec f;
-    return f;
+} g_fault_env;
+bool fault_now(uint32_t kind) {
+    if (g_fault_kind.load() != kind) return false;
+    if (--g_fault_left != 0) return false;
+    g_fault_kind = 0;
+    return true;
 }
-std::atomic<long> g_allocs{0}, g_launches{0};
 }  // namespace
 
-bool fault_alloc_now() {
-    long n = ++g_allocs;
-    return faults().alloc_at > 0 && n == faults().alloc_at;
-}
-bool fault_launch_now() {
-    long n = ++g_launches;
-    return faults().launch_at > 0 && n == faults().launch_at;
-}
+bool fault_alloc_now() { return fault_now(1); }
+bool fault_launch_now() { return fault_now(2); }
 
 void check_launch(const char *what) {
     hipError_t e = hipGetLastError();
@@ -348,3 +351,13 @@ wr_status wr_graph_update_weights(wr_graph *g, uint32_t n, const uint32_t *arc_i
 }
 
 }  // extern "C"
+
+extern "C" wr_status wr_debug_fault(uint32_t kind, uint64_t nth) {
+    WR_API_BEGIN
+    if (kind > 2) fail(WR_E_INVALID, "fault kind must be 0 (off), 1 (allocation) or 2 (launch)");
+    if (kind != 0 && nth == 0) fail(WR_E_INVALID, "nth must be positive");
+    g_fault_kind = 0;
+    g_fault_left = static_cast<long>(nth);
+    g_fault_kind = kind;
+    WR_API_END
+}

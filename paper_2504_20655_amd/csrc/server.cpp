@@ -319,6 +319,7 @@ bool run_stream_mode(wr_server *s) {
                 return true;
             }
         }
+        bool admitted = fresh.empty();   // the orders taken from the queue are in flight
         try {
             if (!rows.empty()) {
                 const double ta0 = clock_s();
@@ -330,6 +331,9 @@ bool run_stream_mode(wr_server *s) {
                     for (uint32_t b : L.rows) ++refcnt[b];
                     live.push_back(std::move(L));
                 }
+            }
+            admitted = true;
+            {
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->max_inflight = std::max<uint32_t>(s->max_inflight, static_cast<uint32_t>(live.size()));
             }
@@ -379,9 +383,15 @@ bool run_stream_mode(wr_server *s) {
             live.erase(std::remove_if(live.begin(), live.end(), [](const Live &L) { return !L.r; }), live.end());
             s->cv_done.notify_all();
         } catch (const Error &e) {
-            // a failed step fails the orders in flight and the state is built
-            // afresh; serving goes on (in step batching if that fails too)
+            // a failed step fails the orders in flight (and those it was
+            // admitting) and the state is built afresh; serving goes on (in
+            // step batching if that fails too)
             set_last_error(e.msg);
+            if (!admitted) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                const double t = clock_s();
+                for (Live &L : fresh) finish(s, L.r, e.st, t);
+            }
             fail_all(e.st);
             std::fill(refcnt.begin(), refcnt.end(), 0u);
             std::fill(busy.begin(), busy.end(), 0);
