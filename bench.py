@@ -24,7 +24,9 @@ Beside the headline:
                 the current kernel source
   cpu_baseline  the CPU oracle (Dijkstra per distinct pick, all host cores)
                 on a bounded sample of the same orders
-  legs          medium (512x512, 256 orders x 32 picks), segmented (4096x4096
+  legs          medium (512x512, 256 orders x 32 picks), prune (the
+                target-bounded variant beside the plain overlay, on uniform
+                and window-clustered orders), segmented (4096x4096
                 in 256x256 segments, 1024 sources: GTEPS of full distance
                 rows, segmented vs unsegmented), tiny (20x40, one order of 8
                 picks; the paper-structured baseline in the paper's
@@ -261,6 +263,33 @@ def order_leg(wr, wl, G, steps, warmup, tag, host_out=True, copy_gbs=None):
         "relaxations_per_s": round(kern_relax / max(kern_ms, 1e-9) * 1e3, 1),
     }
     return res
+
+
+def prune_leg(wr, G, wl, steps, warmup):
+    """The target-bounded variant (WR_PRUNE_TO_PICKS) beside the plain
+    overlay on the medium graph: the medium batch (uniform picks) and a batch
+    of 256 orders whose 32 picks lie in a 48x48-cell window each (as after
+    the paper's reorganisation has gathered an order's articles)."""
+    from wgen.orders import window_orders
+    g = wl.graph
+    rng = np.random.default_rng(wl.seed + 31)
+    coff, cpicks = window_orders(rng, g.aisle_adjacent_vertices(), g.W, g.H, 256, 32, 48)
+    out = {}
+    for name, off, picks in (("uniform", wl.pick_offsets, wl.picks), ("clustered", coff, cpicks)):
+        row = {}
+        for tag, pr in (("overlay", False), ("pruned", True)):
+            for _ in range(warmup):
+                G.order_matrices(off, picks, algo="overlay", prune=pr)
+            t = time.perf_counter()
+            for _ in range(steps):
+                G.order_matrices(off, picks, algo="overlay", prune=pr)
+            dt = (time.perf_counter() - t) / steps
+            info = G.last_run()
+            row[tag] = {"orders_per_s": round((len(off) - 1) / dt, 1), "ms_per_step": round(dt * 1e3, 3),
+                        "passes": info["passes"], "visits": info["work_items"]}
+        out[name] = row
+    return {"workload": "medium graph; uniform: the medium batch; clustered: 256 orders x 32 picks, each in a "
+                        "48x48-cell window; matrices copied to the host", **out}
 
 
 def cpu_orders_baseline(wl, core_seconds):
@@ -663,6 +692,7 @@ def main():
         if with_cpu:
             med["cpu_baseline"] = cpu_orders_baseline(wm, args.cpu_seconds)
         res["legs"]["medium"] = med
+        res["legs"]["prune"] = prune_leg(wr, Gm, wm, args.steps, args.warmup)
         if "routes" in legs and args.route_stops > 0:
             off, picks = wm.pick_offsets, wm.picks
             P0 = int(off[1] - off[0])

@@ -77,6 +77,9 @@ typedef enum wr_status {
 #define WR_TIME_KERNELS     0x0200u  /* record HIP events around every launch of the schedule's
                                         relaxation kernel (wr_run_info.kernel_ms); passes are
                                         then launched eagerly, not replayed from a hipGraph */
+#define WR_PRUNE_TO_PICKS   0x0800u  /* wr_order_matrices, overlay schedule: stop each source's
+                                        relaxation beyond the farthest pick it is paired with
+                                        (exact for the matrices; see wr_order_matrices) */
 
 /* ---- opaque handles -------------------------------------------------- */
 typedef struct wr_context wr_context;
@@ -191,7 +194,16 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
  * pred_out:     int32[sum_o P_o * V] or NULL: the canonical predecessor row
  *               (as in wr_sssp) of every pick, in pick order.
  * Distinct pick vertices are solved once per call, whatever order they
- * belong to.  Errors as for wr_sssp, plus WR_E_INVALID for bad offsets. */
+ * belong to.
+ * WR_PRUNE_TO_PICKS (overlay schedule; WR_ALGO_AUTO selects it): a source
+ * only needs its distances to the picks of the orders it belongs to, so a
+ * value above the length of a path already found from it to each of those
+ * picks is never stored (the bound is refined from the current tentative
+ * matrix entries after every graph replay of passes).  Every vertex on a
+ * shortest path to such a pick is no farther than the pick, so the matrices
+ * are exact; the saving is largest when an order's picks lie close
+ * together.  Not combinable with pred_out (WR_E_INVALID).
+ * Errors as for wr_sssp, plus WR_E_INVALID for bad offsets. */
 wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pick_offsets,
                             const uint32_t *picks, uint32_t *dist_out, int32_t *pred_out,
                             uint32_t flags, void *stream);

@@ -25,6 +25,7 @@ ALGO_NAME = {v: k for k, v in ALGO.items()}
 NO_GRAPH_CAPTURE = 0x0100
 TIME_KERNELS = 0x0200
 ROUTE_ENUMERATE = 0x0400
+PRUNE_TO_PICKS = 0x0800
 
 STATUS = {0: "WR_OK", 1: "WR_E_INVALID", 2: "WR_E_RANGE", 3: "WR_E_NOMEM", 4: "WR_E_DEVICE",
           5: "WR_E_UNSUPPORTED", 6: "WR_E_BUSY", 7: "WR_E_INTERNAL"}
@@ -250,15 +251,17 @@ class Graph:
 
     def order_matrices(self, pick_offsets, picks, pred: bool = False, algo: str = "auto",
                        out=None, pred_out=None, graph_capture: bool = True,
-                       time_kernels: bool = False):
+                       time_kernels: bool = False, prune: bool = False):
         """Concatenated per-order P x P matrices (uint32); with pred=True also
-        the predecessor row of every pick ([total picks, V])."""
+        the predecessor row of every pick ([total picks, V]).  prune=True
+        sets WR_PRUNE_TO_PICKS."""
         off, pk = _u32(pick_offsets), _u32(picks)
         n = len(off) - 1
         sizes = np.diff(off.astype(np.int64))
         total = int((sizes ** 2).sum())
         flags = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
         flags |= TIME_KERNELS if time_kernels else 0
+        flags |= PRUNE_TO_PICKS if prune else 0
         if out is not None:
             flags |= DEVICE_PTRS
             stream = _stream_of(out)

@@ -226,6 +226,9 @@ struct SegPassArgs {
     // visits of each tile, and exit values stored per (workgroup, wave)
     uint32_t *tile_visits;
     uint32_t *wave_stores;
+    // target-bounded passes: per source slot (block * 64 + lane) the largest
+    // value worth storing, or NULL (no bound)
+    const uint32_t *bound;
 };
 
 __device__ __forceinline__ void seg_activate(const SegPassArgs &A, uint32_t s, uint32_t t,
@@ -947,6 +950,9 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
         OVL_ISSUE_LOADS(nb)
         for (uint32_t k = 0; k < cnt; ++k) {
             const uint32_t b = nb;
+            // target-bounded passes: a value above the lane's bound is never
+            // on a shortest path to one of its source's targets
+            const uint32_t bnd = A.bound ? A.bound[static_cast<size_t>(b) * 64 + lane] : INF;
             const uint32_t *xb = A.xval + static_cast<size_t>(b) * A.NB * 64;   // uniform: exit e at xb + 64 e
             uint32_t *xv = A.xval + (static_cast<size_t>(b) * A.NB + b0) * 64;  // uniform: own exit j at xv + 64 j
             uint32_t c[R];
@@ -993,7 +999,7 @@ __global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint3
                 for (uint32_t r = 0; r < R; ++r) {
                     const uint32_t j = j0 + r;
                     if (j >= X) break;
-                    const bool imp = m[r] < c[r];
+                    const bool imp = m[r] < c[r] && m[r] <= bnd;
                     if (imp) xv[static_cast<size_t>(j) * 64 + lane] = m[r];
                     const uint64_t bal = __builtin_amdgcn_ballot_w64(imp);
                     stored += static_cast<uint32_t>(__builtin_popcountll(bal));
@@ -1241,6 +1247,32 @@ __global__ void k_gather_ovl(uint32_t num_orders, const uint32_t *__restrict__ p
             if (si < lo || si >= lo + n) continue;
             out[ob + k] = ovl_value(R, si - lo, picks[a + i], picks[a + j]);
         }
+    }
+}
+
+// Target bounds: tmp[s] = max over the (i, j) pairs of the orders whose
+// source pick i is chunk source s of the current overlay value d(s, p_j),
+// the length of a path already found (INF while some target is unreached);
+// tmp must be 0 before.  k_bound_min then keeps the smaller of the old
+// bound and tmp.
+__global__ void k_bound_pairs(uint32_t num_orders, const uint32_t *__restrict__ pick_off,
+                              const uint32_t *__restrict__ picks, const uint32_t *__restrict__ src_idx_of_pick,
+                              uint32_t lo, uint32_t n, OvlRead R, uint32_t *__restrict__ tmp) {
+    for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
+        const uint32_t a = pick_off[o], P = pick_off[o + 1] - a;
+        for (uint32_t k = blockIdx.y * blockDim.x + threadIdx.x; k < P * P; k += gridDim.y * blockDim.x) {
+            const uint32_t i = k / P, j = k - i * P;
+            const uint32_t si = src_idx_of_pick[a + i];
+            if (si < lo || si >= lo + n) continue;
+            atomicMax(&tmp[si - lo], ovl_value(R, si - lo, picks[a + i], picks[a + j]));
+        }
+    }
+}
+
+__global__ void k_bound_min(uint32_t *__restrict__ bound, uint32_t *__restrict__ tmp, uint32_t n) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        bound[s] = min(bound[s], tmp[s]);
+        tmp[s] = 0;
     }
 }
 
@@ -1782,7 +1814,7 @@ void launch_ovl_pack(const TileSet &ts, hipStream_t st) {
 // can zero the next step's pair while its own pass runs on the current one.
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32_t G, uint32_t grid,
                      const uint32_t *F, bool count_after, hipStream_t st, hipEvent_t ev_begin,
-                     hipEvent_t ev_end) {
+                     hipEvent_t ev_end, const uint32_t *bound) {
     (void)F;
     if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (overlay pass)");
     const uint32_t nx = par ^ 1u;
@@ -1797,6 +1829,7 @@ void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t par, uint32
     SegPassArgs A = seg_args(ts, ss, par, G);
     A.nunits = nunits_cur;
     A.cursor = cursor_cur;
+    A.bound = bound;
     uint32_t XM, EM, PM;
     ovl_dims(ts, XM, EM, PM);
     const uint32_t lds = ovl_pass_lds_bytes(ts);
@@ -1853,6 +1886,18 @@ void launch_ovl_emit(const TileSet &ts, const SegState &ss, const uint32_t *F, u
     hipLaunchKernelGGL(k_rows_src_zero, blocks_for(rows, 256, 1024), 256, 0, st, out, V, rows, out_row,
                        row_src_vertex);
     check_launch("rows_src_zero");
+}
+
+void launch_bound_refine(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                         const uint32_t *src_idx_of_pick, uint32_t chunk_lo, uint32_t chunk_n, const TileSet &ts,
+                         const SegState &ss, const uint32_t *F, uint32_t *bound, uint32_t *tmp, hipStream_t st) {
+    if (!num_orders || !chunk_n) return;
+    dim3 grid(std::min(num_orders, 65535u), 4);
+    hipLaunchKernelGGL(k_bound_pairs, grid, 256, 0, st, num_orders, pick_off, picks, src_idx_of_pick, chunk_lo,
+                       chunk_n, ovl_read(ts, ss, F), tmp);
+    check_launch("bound_pairs");
+    hipLaunchKernelGGL(k_bound_min, blocks_for(chunk_n, 256, 1024), 256, 0, st, bound, tmp, chunk_n);
+    check_launch("bound_min");
 }
 
 void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,

@@ -69,6 +69,8 @@ struct SegWork {
     SegBuffers buf;
     hipGraphExec_t exec = nullptr;   // K passes of the segment kernel, or of the overlay kernel
     hipGraphExec_t exec2 = nullptr;  // overlay: 2 passes, to end a batch of replays near the expected count
+    hipGraphExec_t exec_p = nullptr;  // overlay with target bounds (captured on first use)
+    DBuf<uint32_t> bound, bound_tmp;  // target bounds per source slot and their refinement scratch
     SegState ss;
     // overlay: every exit value of all S_cap rows is INF (state_clean), else
     // the rows a call may have left dirty; a call that ends cleanly resets
@@ -80,6 +82,7 @@ struct SegWork {
         if (st) (void)hipStreamSynchronize(st);   // a trailing reset may still run
         if (exec) (void)hipGraphExecDestroy(exec);
         if (exec2) (void)hipGraphExecDestroy(exec2);
+        if (exec_p) (void)hipGraphExecDestroy(exec_p);
     }
 };
 
@@ -351,11 +354,12 @@ uint32_t seg_pass_grid(const wr_context *ctx, uint32_t tile_cap, uint32_t waves,
 // Captures K overlay passes starting at parity 1 (pass 0 of a chunk is the
 // seed kernel over the sources' tiles), so a replay ends at parity 1.
 hipGraphExec_t capture_ovl_passes(const TileSet &ts, const SegState &ss, uint32_t K, uint32_t G, uint32_t grid,
-                                  const uint32_t *F, hipStream_t st) {
+                                  const uint32_t *F, hipStream_t st, const uint32_t *bound) {
     hipGraph_t graph;
     WR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-        for (uint32_t i = 0; i < K; ++i) launch_ovl_step(ts, ss, (i + 1) & 1u, G, grid, F, i + 1 == K, st);
+        for (uint32_t i = 0; i < K; ++i)
+            launch_ovl_step(ts, ss, (i + 1) & 1u, G, grid, F, i + 1 == K, st, nullptr, nullptr, bound);
     } catch (...) {
         hipGraph_t dummy = nullptr;
         (void)hipStreamEndCapture(st, &dummy);
@@ -505,10 +509,15 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
     nw->grid_ovl = static_cast<uint32_t>(ctx->num_cus) *
                    std::min(32u / ovl_waves(), std::max(1u, (160u * 1024u) / ovl_pass_lds_bytes(ts)));
     if (overlay) ensure_overlay_tables(g);
+    if (overlay) {
+        nw->bound.alloc(ctx, static_cast<size_t>(R_cap) * lanes);
+        nw->bound_tmp.alloc(ctx, static_cast<size_t>(R_cap) * lanes);
+    }
     if (graph_mode)
-        nw->exec2 = overlay ? capture_ovl_passes(ts, nw->ss, 2, G, nw->grid_ovl, ts.d_F.p, ctx->stream) : nullptr;
+        nw->exec2 = overlay ? capture_ovl_passes(ts, nw->ss, 2, G, nw->grid_ovl, ts.d_F.p, ctx->stream, nullptr)
+                            : nullptr;
     if (graph_mode)
-        nw->exec = overlay ? capture_ovl_passes(ts, nw->ss, K, G, nw->grid_ovl, ts.d_F.p, ctx->stream)
+        nw->exec = overlay ? capture_ovl_passes(ts, nw->ss, K, G, nw->grid_ovl, ts.d_F.p, ctx->stream, nullptr)
                            : capture_seg_passes(ts, nw->ss, K, ts.tile_cap, waves, G, nw->grid, ctx->stream);
     ws.seg = std::move(nw);
     return *ws.seg;
@@ -518,7 +527,8 @@ SegWork &seg_workspace(wr_graph *g, uint32_t S_need, bool graph_mode, bool timed
 // `overlap` (may be empty) runs on the host once the first passes are on the
 // GPU, so host work of the caller overlaps the relaxation.
 void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc, uint32_t lo,
-                     uint32_t n, bool graph_mode, wr_run_info &info, const std::function<void()> &overlap) {
+                     uint32_t n, bool graph_mode, wr_run_info &info, const std::function<void()> &overlap,
+                     const std::function<void()> &refine) {
     const TileSet &ts = *g->tiles;
     wr_context *ctx = g->ctx;
     hipStream_t st = ctx->stream;
@@ -555,13 +565,24 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     launch_fill_u32(w.buf.cnt.p, 2ull * ts.T, 0u, st);
     launch_fill_u32(w.buf.ctr.p, 8, 0u, st);
     launch_fill_u32(reinterpret_cast<uint32_t *>(w.buf.stats.p), 4, 0u, st);
+    // target-bounded passes (refine set): bounds start unlimited and shrink
+    // after every replay; the bounded passes are captured on first use
+    const bool bounded = w.overlay && static_cast<bool>(refine);
+    // bounded solves replay short graphs so the bounds tighten early
+    const uint32_t Kb = std::min<uint32_t>(w.K, 4u);
+    if (bounded) {
+        launch_fill_u32(w.bound.p, cap_src, INF, st);
+        launch_fill_u32(w.bound_tmp.p, cap_src, 0u, st);
+        if (graph_mode && !w.exec_p)
+            w.exec_p = capture_ovl_passes(ts, ss, Kb, w.G, w.grid_ovl, ts.d_F.p, st, w.bound.p);
+    }
     g_trace.mark("chunk_reset", now_ms());
     if (!w.overlay) launch_seg_seed_n(ts, ss, n, st);
     hipEvent_t e0, e1;
     WR_HIP(hipEventCreate(&e0));
     WR_HIP(hipEventCreate(&e1));
     WR_HIP(hipEventRecord(e0, st));
-    const uint32_t K = w.K;
+    const uint32_t K = bounded ? Kb : w.K;   // passes per replay
     uint64_t passes = 0;
     const uint64_t cap = static_cast<uint64_t>(g->V) + 2ull * K + 8;
     // overlay: pass 0 stores the sources' in-tile exit distances (the seed
@@ -578,8 +599,10 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
     uint32_t batch = graph_mode ? static_cast<uint32_t>(std::max<uint64_t>(1, wsp.last_passes / K)) : 1u;
     // overlay: cover the previous solve's passes with work by K-pass replays
     // plus 2-pass ones, so the first check comes at most one pass late
+    // (bounded passes refine their bounds after every replay instead)
+    if (bounded) batch = 1;
     uint32_t batch2 = 0;
-    if (graph_mode && w.exec2 && wsp.last_work_passes > 0) {
+    if (graph_mode && w.exec2 && wsp.last_work_passes > 0 && !bounded) {
         batch = static_cast<uint32_t>(wsp.last_work_passes / K);
         batch2 = static_cast<uint32_t>((wsp.last_work_passes - static_cast<uint64_t>(batch) * K + 1) / 2);
     }
@@ -594,11 +617,11 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
                     WR_HIP(hipEventRecord(wsp.ev_mid, st));
                     wsp.mid_valid = true;
                 }
-                WR_HIP(hipGraphLaunch(w.exec, st));
+                WR_HIP(hipGraphLaunch(bounded ? w.exec_p : w.exec, st));
             }
             for (uint32_t r = 0; r < batch2; ++r) WR_HIP(hipGraphLaunch(w.exec2, st));
             if (batch + batch2 == 0) {
-                WR_HIP(hipGraphLaunch(w.exec, st));
+                WR_HIP(hipGraphLaunch(bounded ? w.exec_p : w.exec, st));
                 batch = 1;
             }
             passes += static_cast<uint64_t>(K) * batch + 2ull * batch2;
@@ -607,7 +630,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
         } else if (w.overlay) {
             for (uint32_t i = 0; i < K; ++i)
                 launch_ovl_step(ts, ss, (i + 1) & 1u, w.G, w.grid_ovl, ts.d_F.p, i + 1 == K, st, w.kev.b(i),
-                                w.kev.e(i));
+                                w.kev.e(i), bounded ? w.bound.p : nullptr);
             passes += K;
         } else {
             for (uint32_t i = 0; i < K; ++i)
@@ -615,6 +638,7 @@ void seg_solve_chunk(wr_graph *g, SegWork &w, const std::vector<uint32_t> &usrc,
                                 w.kev.e(i));
             passes += K;
         }
+        if (bounded) refine();
         if (first && overlap) overlap();
         first = false;
         WR_HIP(hipMemcpyAsync(workspace(g).h_flag, ss.ntiles + par0, 4, hipMemcpyDeviceToHost, st));
@@ -859,9 +883,10 @@ uint32_t chunk_sources(wr_graph *g, uint32_t algo, uint32_t total, bool graph_mo
 
 void solve_chunk(wr_graph *g, uint32_t algo, const std::vector<uint32_t> &usrc, uint32_t lo,
                  uint32_t n, bool graph_mode, wr_run_info &info,
-                 const std::function<void()> &overlap = std::function<void()>()) {
+                 const std::function<void()> &overlap = std::function<void()>(),
+                 const std::function<void()> &refine = std::function<void()>()) {
     if (algo == WR_ALGO_SEGMENTED || algo == WR_ALGO_OVERLAY) {
-        seg_solve_chunk(g, *workspace(g).seg, usrc, lo, n, graph_mode, info, overlap);
+        seg_solve_chunk(g, *workspace(g).seg, usrc, lo, n, graph_mode, info, overlap, refine);
     } else {
         blk_solve_chunk(g, *workspace(g).blk, usrc, lo, n, graph_mode, info);
         if (overlap) overlap();
@@ -950,9 +975,21 @@ IntileWork intile_pairs(const TileSet &ts, uint32_t num_orders, const uint32_t *
             r0 = r1;
         }
     }
-    std::sort(e.begin(), e.end(), [](const Entry &x, const Entry &y) {
-        return x.t != y.t ? x.t < y.t : x.src < y.src;
-    });
+    // order by (tile, source): a counting sort by tile, then each tile's
+    // (short) run by source
+    {
+        std::vector<uint32_t> cnt(static_cast<size_t>(ts.T) + 1, 0u);
+        for (const Entry &x : e) cnt[x.t + 1]++;
+        for (uint32_t t = 0; t < ts.T; ++t) cnt[t + 1] += cnt[t];
+        std::vector<Entry> sorted(e.size());
+        std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (const Entry &x : e) sorted[fill[x.t]++] = x;
+        for (uint32_t t = 0; t < ts.T; ++t)
+            if (cnt[t + 1] - cnt[t] > 1)
+                std::sort(sorted.begin() + cnt[t], sorted.begin() + cnt[t + 1],
+                          [](const Entry &x, const Entry &y) { return x.src < y.src; });
+        e.swap(sorted);
+    }
     IntileWork w;
     size_t k = 0;
     while (k < e.size()) {
@@ -1169,6 +1206,7 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
     if (!g) fail(WR_E_INVALID, "graph is NULL");
     if (S == 0) return WR_OK;
     if (!sources || !dist) fail(WR_E_INVALID, "sources or dist is NULL");
+    if (flags & WR_PRUNE_TO_PICKS) fail(WR_E_INVALID, "WR_PRUNE_TO_PICKS applies to wr_order_matrices only");
     for (uint32_t i = 0; i < S; ++i)
         if (sources[i] >= g->V) fail(WR_E_INVALID, "source out of range");
     if (pred && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
@@ -1304,7 +1342,10 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
     for (uint32_t k = 0; k < NPK; ++k)
         if (picks[k] >= g->V) fail(WR_E_INVALID, "pick out of range");
     if (pred_out && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
+    const bool prune = (flags & WR_PRUNE_TO_PICKS) != 0;
+    if (prune && pred_out) fail(WR_E_INVALID, "WR_PRUNE_TO_PICKS leaves rows beyond the picks unfinished: no pred_out");
     const uint32_t algo = resolve_algo(g, flags);
+    if (prune && algo != WR_ALGO_OVERLAY) fail(WR_E_UNSUPPORTED, "WR_PRUNE_TO_PICKS runs on the overlay schedule only");
     const bool dev = (flags & WR_DEVICE_PTRS) != 0;
     const bool timed = (flags & WR_TIME_KERNELS) != 0;
     // events around individual kernels are recorded on the stream, so timed
@@ -1407,7 +1448,14 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
                     g_trace.mark("intile_setup", now_ms());
                 };
             }
-            solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info, overlap);
+            std::function<void()> refine;
+            if (prune)
+                refine = [&]() {
+                    SegWork &sw = *workspace(g).seg;
+                    launch_bound_refine(num_orders, d_off.p, d_picks.p, d_sidx.p, lo, n, *g->tiles, sw.ss,
+                                        g->tiles->d_F.p, sw.bound.p, sw.bound_tmp.p, st);
+                };
+            solve_chunk(g, algo, plan.usrc, lo, n, graph_mode, info, overlap, refine);
             g_trace.mark("solve", now_ms());
             info.chunks += 1;
             if (algo == WR_ALGO_OVERLAY) {

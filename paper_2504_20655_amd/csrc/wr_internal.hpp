@@ -397,7 +397,13 @@ void launch_ovl_pin_rec(const TileSet &ts, hipStream_t st);
 // adds the number of waves that still see set flags to ntiles[parity ^ 1]
 void launch_ovl_step(const TileSet &ts, const SegState &ss, uint32_t parity, uint32_t G, uint32_t grid,
                      const uint32_t *F, bool count_after, hipStream_t st, hipEvent_t ev_begin = nullptr,
-                     hipEvent_t ev_end = nullptr);
+                     hipEvent_t ev_end = nullptr, const uint32_t *bound = nullptr);
+// target bounds of the chunk's sources (bound[s] for s < chunk_n): bound =
+// min(bound, max over each source's order pairs of the current overlay
+// value); tmp (chunk_n words) must be 0 and is left 0
+void launch_bound_refine(uint32_t num_orders, const uint32_t *pick_off, const uint32_t *picks,
+                         const uint32_t *src_idx_of_pick, uint32_t chunk_lo, uint32_t chunk_n, const TileSet &ts,
+                         const SegState &ss, const uint32_t *F, uint32_t *bound, uint32_t *tmp, hipStream_t st);
 // full rows: out_row[r] * V .. gets the row of the source at row_src_vertex[r];
 // the rows' sources are grouped by 64-source block: group g covers block
 // grp_block[g], lane l of it goes to row lane_row[g * 64 + l] (NONE: none)

@@ -11,7 +11,7 @@ import numpy as np
 from tests.simt_cpu.build_cpu import OUT, build
 
 ALGO = {"auto": 0x00, "sweep": 0x10, "frontier": 0x20, "segmented": 0x30,
-        "edge_b1": 0x40, "edge_b0": 0x50, "overlay": 0x60}
+        "edge_b1": 0x40, "edge_b0": 0x50, "overlay": 0x60, "overlay_prune": 0x60 | 0x800}
 NO_GRAPH_CAPTURE = 0x100
 
 

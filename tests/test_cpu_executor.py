@@ -52,6 +52,25 @@ def case_overlay_order_matrices_tiny(harness):
 
 
 @case
+def case_overlay_pruned_orders(harness):
+    """Target-bounded passes (WR_PRUNE_TO_PICKS) on orders whose picks lie
+    close together, with an order of one pick, a duplicate pick and a pick
+    shared by two orders: matrices equal the oracle's."""
+    from wgen.orders import window_orders
+    wl = make_config("medium", side=24, num_orders=1)
+    g = wl.graph
+    rng = np.random.default_rng(12)
+    off, picks = window_orders(rng, g.aisle_adjacent_vertices(), g.W, g.H, 5, 6, 6)
+    sizes = list(np.diff(off.astype(np.int64))) + [1, 3]
+    picks = np.concatenate([picks, picks[:1], [picks[2], picks[2], picks[7]]]).astype(np.uint32)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    st, out, _, err = harness.run(g.row_ptr, g.col, g.w, pick_offsets=off, picks=picks, algo="overlay_prune",
+                                  seg=("grid", g.W, g.H, 1, 6, 8))
+    assert st == 0, err[-2000:]
+    assert (out == oracle.order_matrices(g.row_ptr, g.col, g.w, off, picks)).all()
+
+
+@case
 def case_segmented_rows_and_pred_random_graph(harness):
     from tests.helpers import random_csr
     rng = np.random.default_rng(31)

@@ -6,8 +6,10 @@ grid).
 
 * medium: every one of the 256 orders against the oracle, element by
   element, on the first call and again on the warm-started path the
-  benchmark's steps take (third call, device output).
-* uneven: 256 sampled orders against the oracle element by element; the
+  benchmark's steps take (third call, device output), and with the
+  target-bounded passes.
+* uneven: 256 sampled orders against the oracle element by element, and
+  the target-bounded passes equal to the full solve on all 10k orders; the
   full rows of 256 sampled distinct picks proven optimal by the oracle's
   O(E) certificate (feasible on every arc, tight-arc reachable, INF exactly
   where unreachable), and every matrix entry whose row source is one of
@@ -95,9 +97,10 @@ def test_medium_every_order(rt, ctx):
     torch.cuda.synchronize()
     warm = out.cpu().numpy().view(np.uint32)
     assert (warm == exp).all()
-    # an independent schedule on the same graph
+    # an independent schedule on the same graph, and the target-bounded passes
     seg = G.order_matrices(off, picks, algo="segmented")
     assert (seg == exp).all()
+    assert (G.order_matrices(off, picks, algo="overlay", prune=True) == exp).all()
     G.close()
 
 
@@ -126,6 +129,14 @@ def test_uneven_sampled_orders(uneven):
     log("uneven: oracle done")
     for o, E in zip(sel, exp):
         assert (mats[o] == E).all(), f"order {o}"
+
+
+def test_uneven_pruned_equals_full(uneven):
+    """The target-bounded passes give the whole batch's matrices bit for bit
+    (the full solve is checked against the oracle and the certificate)."""
+    wl, G, got = uneven
+    pr = G.order_matrices(wl.pick_offsets, wl.picks, algo="overlay", prune=True)
+    assert (pr == got).all()
 
 
 def test_uneven_certified_rows(uneven):

@@ -31,6 +31,32 @@ def uniform_orders(rng: np.random.Generator, candidates: np.ndarray,
     return _offsets(sizes), flat
 
 
+def window_orders(rng: np.random.Generator, candidates: np.ndarray, W: int, H: int,
+                  num_orders: int, size: int, window: int) -> tuple[np.ndarray, np.ndarray]:
+    """Orders whose picks lie close together, as after the paper's clustering
+    reorganisation has gathered an order's articles: order k takes ``size``
+    distinct picks uniformly from the candidates inside a ``window`` x
+    ``window`` cell square placed uniformly on the W x H grid (the square
+    grows until it holds enough candidates).  Returns (pick_offsets, picks).
+    """
+    cx, cy = candidates % W, candidates // W
+    picks = []
+    for _ in range(num_orders):
+        x0 = int(rng.integers(0, max(1, W - window + 1)))
+        y0 = int(rng.integers(0, max(1, H - window + 1)))
+        r = window
+        while True:
+            inside = np.flatnonzero((cx >= x0) & (cx < x0 + r) & (cy >= y0) & (cy < y0 + r))
+            if len(inside) >= size or r >= max(W, H):
+                break
+            r *= 2
+        idx = rng.choice(inside, size=min(size, len(inside)), replace=False)
+        picks.append(candidates[idx])
+    sizes = [len(p) for p in picks]
+    flat = (np.concatenate(picks) if picks else np.zeros(0)).astype(np.uint32)
+    return _offsets(sizes), flat
+
+
 def zipf_popularity(n_ranks: int, s: float) -> np.ndarray:
     """Finite Zipf law over ranks 1..n: p_k proportional to k^-s."""
     p = np.arange(1, n_ranks + 1, dtype=np.float64) ** (-s)
