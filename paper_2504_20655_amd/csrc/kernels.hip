@@ -2008,13 +2008,12 @@ __device__ __forceinline__ uint32_t rt_sbase(uint32_t S, uint32_t n) {
 }
 
 __device__ __forceinline__ uint32_t rt_step(uint32_t h, uint32_t d, bool &ovf) {
-    if (h == INF || d == INF) return INF;
+    // branch-free: INF absorbs; a finite sum reaching INF flags the overflow
     const uint32_t s = h + d;
-    if (s < h || s == INF) {
-        ovf = true;
-        return INF;
-    }
-    return s;
+    const bool inf = h == INF || d == INF;
+    const bool wrap = !inf && (s < h || s == INF);
+    ovf = ovf || wrap;
+    return (inf || wrap) ? INF : s;
 }
 
 // LDS layout of one subset programme: binomials, the matrix, subset offsets,
@@ -2066,11 +2065,11 @@ __device__ void rt_tables(const RtLds &L, uint32_t n) {
 }
 
 // The states h(S, i) of the n x n matrix already in L.D (1 <= n <= RT_NMAX),
-// by the whole workgroup; ends synchronised.
+// by the whole workgroup, with the subset tables of n already in L (see
+// rt_tables); ends synchronised.
 __device__ void rt_solve(const RtLds &L, uint32_t n, bool &ovf) {
     constexpr uint32_t NB1 = RT_NMAX + 1;
     const uint32_t tid = threadIdx.x;
-    rt_tables(L, n);
     for (uint32_t i = tid; i < n; i += blockDim.x) L.H[L.base[1u << i]] = 0u;
     __syncthreads();
     uint32_t lstart = 1 + n;   // the empty set and the singletons come first
@@ -2085,11 +2084,21 @@ __device__ void rt_solve(const RtLds &L, uint32_t n, bool &ovf) {
             const uint32_t R = S & ~(1u << i);
             const uint32_t bR = L.base[R];
             const uint32_t *Di = L.D + i * n;
+            // the members j of R in ascending order, with h(R, j) at
+            // consecutive states; two candidates per step keep two LDS
+            // reads of each kind in flight
             uint32_t best = INF, rj = 0;
-            for (uint32_t U = R; U != 0; U &= U - 1u) {
-                best = min(best, rt_step(L.H[bR + rj], Di[__builtin_ctz(U)], ovf));
-                ++rj;
+            uint32_t U = R;
+            for (; U != 0 && (U & (U - 1u)) != 0; rj += 2) {
+                const uint32_t j0 = __builtin_ctz(U);
+                U &= U - 1u;
+                const uint32_t j1 = __builtin_ctz(U);
+                U &= U - 1u;
+                const uint32_t c0 = rt_step(L.H[bR + rj], Di[j0], ovf);
+                const uint32_t c1 = rt_step(L.H[bR + rj + 1], Di[j1], ovf);
+                best = min(best, min(c0, c1));
             }
+            if (U != 0) best = min(best, rt_step(L.H[bR + rj], Di[__builtin_ctz(U)], ovf));
             L.H[L.base[S] + m] = best;
         }
         lstart += L.bin[n * NB1 + k];
@@ -2139,6 +2148,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, co
     const uint32_t tid = threadIdx.x;
     rt_binomials(L.bin);
     __syncthreads();   // the table is read by every thread from here on
+    uint32_t tab_n = 0;   // stops the subset tables in LDS were built for
     for (uint32_t o = blockIdx.x; o < num_orders; o += gridDim.x) {
         const uint32_t a = off[o], n = off[o + 1] - a;
         if (n == 0) {
@@ -2147,7 +2157,12 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_hk(uint32_t num_orders, co
         }
         const uint32_t *Dg = dist + mbase[o];
         for (uint32_t q = tid; q < n * n; q += blockDim.x) L.D[q] = Dg[q];
-        __syncthreads();
+        if (n != tab_n) {
+            rt_tables(L, n);   // synchronises (the matrix is then in LDS too)
+            tab_n = n;
+        } else {
+            __syncthreads();
+        }
         bool ovf = false;
         rt_solve(L, n, ovf);
         if (ovf) atomicOr(overflow, 1u);
@@ -2352,6 +2367,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_clustered(
             for (uint32_t q = tid; q < k * k; q += blockDim.x)
                 L.D[q] = sF[sRoute[pos + q / k] * n + sRoute[pos + q % k]];
             __syncthreads();
+            rt_tables(L, k);   // the chaining below rebuilds them for the clusters
             rt_solve(L, k, ovf);
             if (tid == 0) {
                 uint32_t loc[RT_NMAX], mem[RT_NMAX];
