@@ -8,7 +8,9 @@ The C part (``oracle.c`` -> ``liboracle.so``) holds Dijkstra, Jacobi
 Bellman-Ford, canonical predecessors, order gathers, CSR validation, the
 optimality certificate and the optimal open route over an order's matrix
 (Held and Karp's subset programme); ``brute.py`` enumerates simple paths on tiny graphs
-and ``closed_forms.py`` holds the grid distance formulas used as pins.
+and ``closed_forms.py`` holds the grid distance formulas used as pins;
+``wms.py`` runs the warehouse reorganisation loop (picking, clustering and
+restocking) one run at a time.
 """
 from __future__ import annotations
 
