@@ -63,9 +63,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="medium,segmented,tiny,routes,serving",
+    ap.add_argument("--legs", default="medium,segmented,tiny,routes,serving,wms",
                     help="legs beside the uneven headline, comma-separated ('' = none)")
-    ap.add_argument("--only", default="", choices=["", "segmented", "tiny", "serving"],
+    ap.add_argument("--only", default="", choices=["", "segmented", "tiny", "serving", "wms"],
                     help="run just this leg and print its result (for profiling)")
     ap.add_argument("--no-autotune", action="store_true", help="run the 24x20 grid tiles untuned")
     ap.add_argument("--autotune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "wroute_tune"),
@@ -79,6 +79,8 @@ def parse():
                     help="Poisson arrival rates (orders/s) of the serving leg, comma-separated")
     ap.add_argument("--serve-seconds", type=float, default=1.5, help="arrival window per rate")
     ap.add_argument("--route-stops", type=int, default=12, help="stops per route in the exact-route leg")
+    ap.add_argument("--wms-runs", default="2560,1024",
+                    help="runs per batch of the warehouse-loop leg: 10x10x10 and 100x100x10 warehouses")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device once (a dispatch of known "
                          "traffic that scales the HBM byte counters of a profiler run)")
@@ -605,6 +607,81 @@ def cluster_leg(wr, ctx, D_host, off, picks, W, m, steps, warmup, with_cpu):
     return res
 
 
+def wms_batch(nx, ny, nz, empty_racks, runs, iters, experiment, seed):
+    """Seeded states and orders of `runs` independent runs, generated in
+    groups of 64 runs (the generator's loops are per run)."""
+    from wgen.wms import make_wms
+    parts = [make_wms(seed + g, nx, ny, nz, empty_racks, min(64, runs - g), iters, experiment)
+             for g in range(0, runs, 64)]
+    s = parts[0]
+    s.A0 = np.concatenate([p.A0 for p in parts])
+    s.M0 = np.concatenate([p.M0 for p in parts])
+    s.orders = np.concatenate([p.orders for p in parts])
+    s.qty = np.concatenate([p.qty for p in parts])
+    return s
+
+
+def wms_leg(wr, ctx, runs_small, runs_large, steps, warmup, with_cpu, cpu_seconds):
+    """The warehouse reorganisation loop (wr_wms_run), experiment 2 (one
+    random article per purchase order), 100 iterations per run and step,
+    on the paper's 10x10x10 warehouse (11 empty racks) and its 100x100x10
+    one (1100 empty racks): run-iterations/s (applications of f) with the
+    states and orders resident in HBM, each step continuing the runs from
+    the previous step's states; the oracle beside it on one run."""
+    import torch
+    from oracle import wms as owms
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, (nx, ny, nz, er, runs) in (("paper_10x10x10", (10, 10, 10, 11, runs_small)),
+                                         ("large_100x100x10", (100, 100, 10, 1100, runs_large))):
+        if runs <= 0:
+            continue
+        iters = 100
+        s = wms_batch(nx, ny, nz, er, runs, iters, 2, 700)
+        R, T, S = s.orders.shape
+        tens = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+        A, M = tens(s.A0), tens(s.M0)
+        d_ord = tens(s.orders)
+        d_qty = tens(np.broadcast_to(s.qty[:, None, :], (R, T, S)))
+        res = (torch.empty((R, T), dtype=torch.float64, device=dev),
+               torch.empty((R, T), dtype=torch.float64, device=dev),
+               torch.empty((R, T), dtype=torch.int32, device=dev))
+        call = lambda: ctx.wms_run(A, M, d_ord, d_qty, nx, ny, nz, s.n_articles, s.mmax, s.po, s.k, out=res)
+        for _ in range(warmup):
+            call()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        leg = {"workload": f"{nx}x{ny}x{nz} nodes, {er} empty racks, {R} runs x {T} iterations of "
+                           f"20 purchase orders x 10 articles, K=3, experiment 2",
+               "value": round(R * T / dt, 1), "unit": "run-iterations/s", "ms_per_step": round(dt * 1e3, 3),
+               "moves_per_iteration": round(float(res[2].double().mean()), 2),
+               "silhouette_last": round(float(res[0][:, -1].mean()), 4)}
+        if with_cpu:
+            # the oracle on run 0 from the initial state, as many iterations
+            # as fit the CPU budget
+            t = time.perf_counter()
+            k = 0
+            A0 = s.A0[0].astype(np.int64).copy()
+            M0 = s.M0[0].astype(np.int64).copy()
+            pos = np.zeros(s.n_articles + 1, np.int64)
+            for v in np.flatnonzero(A0):
+                pos[A0[v]] = v
+            while k < T and time.perf_counter() - t < cpu_seconds / 2:
+                owms.iterate(A0, M0, pos, s.orders[0, k], s.qty[0], nx, ny, s.mmax, s.po, s.k)
+                k += 1
+            tc = time.perf_counter() - t
+            leg["cpu_baseline"] = {"value": round(k / tc, 2), "unit": "run-iterations/s", "cores": 1,
+                                   "kind": "oracle", "sample": f"run 0, first {k} iterations, {tc:.2f} s"}
+        out[name] = leg
+        del A, M, d_ord, d_qty, res
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -623,6 +700,10 @@ def main():
             leg = segmented_leg(wr, ctx, args.steps)
         elif args.only == "tiny":
             leg = tiny_leg(wr, ctx, args.steps)
+        elif args.only == "wms":
+            rs = [int(x) for x in args.wms_runs.split(",")]
+            leg = wms_leg(wr, ctx, rs[0], rs[1], args.steps, args.warmup, not args.no_cpu_baseline,
+                          args.cpu_seconds)
         else:
             leg = serving_leg(wr, ctx, [float(x) for x in args.serve_rates.split(",") if x.strip()],
                               args.serve_seconds)
@@ -707,6 +788,11 @@ def main():
         res["legs"]["tiny"] = tiny_leg(wr, ctx, args.steps)
     if "segmented" in legs:
         res["legs"]["segmented"] = segmented_leg(wr, ctx, args.steps)
+        torch.cuda.empty_cache()
+    if "wms" in legs:
+        rs = [int(x) for x in args.wms_runs.split(",")]
+        res["legs"]["wms"] = wms_leg(wr, ctx, rs[0], rs[1], max(1, args.steps // 5), 1, with_cpu,
+                                     args.cpu_seconds)
         torch.cuda.empty_cache()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if "serving" in legs and rates:

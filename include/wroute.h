@@ -310,6 +310,70 @@ wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_orders, const 
                                     uint64_t *length_out, uint32_t *route_out, uint32_t *clusters_out,
                                     uint32_t flags, void *stream);
 
+/* ---------------------------------------------------------------------
+ * The warehouse reorganisation loop (Mathematical model section: the state
+ * x = (A, M), orders, the map f and the random dynamical system
+ * x_n = f(o_n, x_{n-1}); the Clustering section's restocking rule; the WMS
+ * loop appendix: order processing, stock update, check-and-move).
+ *
+ * Node v = (k * ny + j) * nx + i is shelf k of rack (i, j).  A picking
+ * order is `purchase_orders` purchase orders of `articles_per_order` slots
+ * each (20 of 10 in the paper's experiments); slot s of purchase order p is
+ * entry p * articles_per_order + s.  One application of f, per run and
+ * iteration:
+ *   1. each purchase order's point is (sum of i, sum of j) over the racks of
+ *      its articles; the points are split into `clusters` clusters by the
+ *      K-means reading of wr_order_routes_clustered;
+ *   2. metrics of that clustering: the silhouette score of the points as
+ *      mean positions (point / articles_per_order; a point alone in its
+ *      cluster scores 0, so does one with a = b = 0) and the area of the
+ *      triangle of the first three non-empty clusters' centres (0 with
+ *      fewer); a centre is the mean rack position of its cluster's articles;
+ *   3. the picks in slot order: article a at node v with balance m, q
+ *      parcels: if m > q then m -= q; else the empty node u nearest a's
+ *      cluster centre (squared distance of rack positions, compared exactly;
+ *      ties to the smaller node id) takes a if it is strictly nearer than
+ *      v -- v becomes empty (A = 0, M = 0) and u gets a with
+ *      mmax - (q - m) parcels -- otherwise v is restocked in place to
+ *      mmax - (q - m).
+ *
+ * params:      the warehouse and the order shape (below).
+ * runs, iters: independent runs, and iterations (orders) per run.
+ * A, M:        uint32[runs][V], in/out: article per node (0 = empty, else
+ *              1..n_articles, each article at most one node per run) and
+ *              balance per node; left holding the state after `iters`
+ *              iterations.
+ * orders:      uint32[runs][iters][S] (S = purchase_orders *
+ *              articles_per_order): the article of each slot; every one
+ *              must be stored in the run's state.
+ * qty:         uint32[runs][iters][S]: parcels of each slot, at most mmax.
+ * silhouette, area: double[runs][iters]; moves: uint32[runs][iters]
+ *              (articles moved by each iteration).
+ * Every buffer is host memory, or device memory with WR_DEVICE_PTRS (then
+ * the work runs after the caller's earlier work on `stream`).  The call
+ * returns when the results are written.
+ * Limits: nx, ny <= 2048, nz <= 32, V < 2^24, nx * ny * (2 if nz <= 16 else
+ * 4) <= 65536 bytes of rack masks, purchase_orders <= 64, S <= 1024,
+ * clusters <= 10, S * max(nx, ny) <= 2^19.
+ * Errors: WR_E_INVALID (NULL, a parameter out of range, an article number
+ * above n_articles or stored twice, an order's article not stored),
+ * WR_E_RANGE (a slot of more than mmax parcels; host buffers only -- with
+ * device buffers it is WR_E_INVALID), WR_E_UNSUPPORTED (a limit above),
+ * WR_E_NOMEM, WR_E_DEVICE.  Host buffers are left unchanged by a failed
+ * call; device buffers are unspecified after an error found on the
+ * device. */
+typedef struct wr_wms_params {
+    uint32_t nx, ny, nz;            /* racks nx x ny, shelves nz              */
+    uint32_t n_articles;            /* article types 1..n_articles            */
+    uint32_t mmax;                  /* parcels of a full node                 */
+    uint32_t purchase_orders;       /* per picking order                      */
+    uint32_t articles_per_order;    /* slots per purchase order               */
+    uint32_t clusters;              /* K of the K-means step                  */
+} wr_wms_params;
+wr_status wr_wms_run(wr_context *ctx, const wr_wms_params *params, uint32_t runs, uint32_t iters, uint32_t *A,
+                     uint32_t *M, const uint32_t *orders, const uint32_t *qty, double *silhouette, double *area,
+                     uint32_t *moves, uint32_t flags, void *stream);
+
 /* Statistics of the last wr_sssp / wr_order_matrices call on this graph. */
 typedef struct wr_run_info {
     uint32_t algo;             /* WR_ALGO_* value that ran                      */

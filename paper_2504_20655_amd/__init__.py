@@ -143,6 +143,46 @@ class Context:
                                                _ptr(used), 0, None))
         return ln[:n], rt[:total], used[:n]
 
+    def wms_run(self, A, M, orders, qty, nx: int, ny: int, nz: int, n_articles: int, mmax: int = 10,
+                purchase_orders: int = 20, clusters: int = 3, out=None):
+        """The warehouse reorganisation loop (wr_wms_run): `runs`
+        independent states A, M [runs, nx*ny*nz] and picking orders
+        orders/qty [runs, iters, purchase_orders * articles_per_order]
+        (qty may also be [runs, S], the same parcels every iteration).
+        Returns (A, M, silhouette [runs, iters], area, moves).  With device
+        tensors (A, M, orders, qty int32; out = (silhouette float64, area
+        float64, moves int32)) the call runs on the tensors' stream and
+        updates A and M in place."""
+        if out is not None:
+            runs, iters, S = orders.shape
+            p = self._wms_params(nx, ny, nz, n_articles, mmax, purchase_orders, S, clusters)
+            sil, area, mv = out
+            _check(lib().wr_wms_run(self.h, ctypes.byref(p), runs, iters, _ptr(A), _ptr(M), _ptr(orders), _ptr(qty),
+                                    _ptr(sil), _ptr(area), _ptr(mv), DEVICE_PTRS, _stream_of(A)))
+            return A, M, sil, area, mv
+        o = _u32(orders)
+        runs, iters, S = o.shape
+        q = np.asarray(qty, dtype=np.uint32)
+        if q.ndim == 2:
+            q = np.broadcast_to(q[:, None, :], o.shape)
+        q = np.ascontiguousarray(q)
+        a = np.array(A, dtype=np.uint32, order="C", copy=True)
+        m = np.array(M, dtype=np.uint32, order="C", copy=True)
+        sil = np.zeros((runs, iters))
+        area = np.zeros((runs, iters))
+        mv = np.zeros((runs, iters), dtype=np.uint32)
+        p = self._wms_params(nx, ny, nz, n_articles, mmax, purchase_orders, S, clusters)
+        _check(lib().wr_wms_run(self.h, ctypes.byref(p), runs, iters, _ptr(a), _ptr(m), _ptr(o), _ptr(q),
+                                _ptr(sil), _ptr(area), _ptr(mv), 0, None))
+        return a, m, sil, area, mv
+
+    @staticmethod
+    def _wms_params(nx, ny, nz, n_articles, mmax, purchase_orders, S, clusters):
+        per = S // purchase_orders if purchase_orders else 0
+        if purchase_orders < 1 or per * purchase_orders != S:
+            raise ValueError("the order length must be a multiple of purchase_orders")
+        return _lib.WmsParams(nx, ny, nz, n_articles, mmax, purchase_orders, per, clusters)
+
     def close(self):
         if getattr(self, "h", None):
             lib().wr_context_destroy(self.h)

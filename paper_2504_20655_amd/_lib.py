@@ -33,6 +33,11 @@ class Schedule(ctypes.Structure):
                 ("blocks_per_unit", u32), ("grid_tile_w", u32), ("grid_tile_h", u32)]
 
 
+class WmsParams(ctypes.Structure):
+    _fields_ = [("nx", u32), ("ny", u32), ("nz", u32), ("n_articles", u32), ("mmax", u32),
+                ("purchase_orders", u32), ("articles_per_order", u32), ("clusters", u32)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_source_slots", u32), ("mem_budget_bytes", u64), ("max_queue", u32),
                 ("passes_per_step", u32)]
@@ -71,6 +76,7 @@ SIGNATURES = {
     "wr_order_routes": (st, [vp, u32, vp, vp, vp, vp, u32, vp]),
     "wr_order_routes_static": (st, [vp, u32, vp, vp, vp, vp, u32, vp]),
     "wr_order_routes_clustered": (st, [vp, u32, vp, vp, vp, u32, vp, vp, vp, u32, vp]),
+    "wr_wms_run": (st, [vp, vp, u32, u32, vp, vp, vp, vp, vp, vp, vp, u32, vp]),
     "wr_graph_last_run": (st, [vp, vp]),
     "wr_autotune": (st, [vp, u32, ctypes.c_char_p]),
     "wr_graph_set_schedule": (st, [vp, u32, u32, u32]),

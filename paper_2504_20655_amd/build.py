@@ -17,7 +17,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwroute.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "tiles.cpp", "solve.cpp", "server.cpp", "autotune.cpp", "routes.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "tiles.cpp", "solve.cpp", "server.cpp", "autotune.cpp", "routes.cpp",
+           "wms.hip"]
 ARCH = os.environ.get("WR_OFFLOAD_ARCH", "gfx950")
 
 

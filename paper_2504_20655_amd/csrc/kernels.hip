@@ -11,6 +11,7 @@
 // Wave64 is assumed throughout (CDNA).  Values a whole wave agrees on are
 // passed through readfirstlane so that the compiler keeps them in SGPRs and
 // loads CSR rows through the scalar cache.
+#include "kmeans_wave.hpp"
 #include "wr_internal.hpp"
 
 namespace wr {
@@ -2203,22 +2204,6 @@ constexpr uint32_t RC_NMAX = 64;   // stops per order
 constexpr uint32_t RC_MMAX = 10;   // clusters: 2 * 10 * 2^9 chain states fit the state area
 constexpr uint32_t RC_ERR_RANGE = 1u, RC_ERR_CLUSTER = 2u;
 
-// value of v held by lane src of the wave (two 32-bit shuffles)
-__device__ __forceinline__ int64_t rc_shfl64(int64_t v, uint32_t src) {
-    const uint32_t lo = __shfl(static_cast<uint32_t>(static_cast<uint64_t>(v)), static_cast<int>(src), 64);
-    const uint32_t hi = __shfl(static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32), static_cast<int>(src), 64);
-    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
-}
-
-__device__ __forceinline__ int rc_cmp(int64_t px, int64_t py, int64_t sxa, int64_t sya, int64_t ca, int64_t sxb,
-                                      int64_t syb, int64_t cb) {
-    const int64_t dxa = ca * px - sxa, dya = ca * py - sya;
-    const int64_t dxb = cb * px - sxb, dyb = cb * py - syb;
-    const int64_t a = (dxa * dxa + dya * dya) * (cb * cb);
-    const int64_t b = (dxb * dxb + dyb * dyb) * (ca * ca);
-    return a < b ? -1 : (a > b ? 1 : 0);
-}
-
 __global__ __launch_bounds__(RT_THREADS) void k_route_clustered(
     uint32_t num_orders, const uint32_t *__restrict__ off, const uint64_t *__restrict__ mbase,
     const uint32_t *__restrict__ dist, const int32_t *__restrict__ xy, uint32_t m0,
@@ -2262,69 +2247,10 @@ __global__ __launch_bounds__(RT_THREADS) void k_route_clustered(
             } else {
                 uint32_t mm = m0, used = 0xFFFFFFFFu;
                 for (; mm <= RC_MMAX; ++mm) {
-                    // farthest-point initial centres
-                    int64_t dmin = INT64_MAX;
-                    uint32_t nc = 0, cen = 0;
-                    for (;;) {
-                        const int64_t cx = sXY[2 * cen], cy = sXY[2 * cen + 1];
-                        if (lane == 0) {
-                            sCen[3 * nc] = cx;
-                            sCen[3 * nc + 1] = cy;
-                            sCen[3 * nc + 2] = 1;
-                        }
-                        ++nc;
-                        if (nc >= mm || nc >= n) break;
-                        const int64_t dx = px - cx, dy = py - cy;
-                        const int64_t d = dx * dx + dy * dy;
-                        if (on && d < dmin) dmin = d;
-                        // the pick farthest from every centre, ties to the smaller index
-                        int64_t best = on ? dmin : -1;
-                        uint32_t bi = lane;
-                        for (uint32_t sh = 1; sh < 64; sh <<= 1) {
-                            const int64_t ob = rc_shfl64(best, lane ^ sh);
-                            const uint32_t oi = __shfl(bi, static_cast<int>(lane ^ sh), 64);
-                            if (ob > best || (ob == best && oi < bi)) {
-                                best = ob;
-                                bi = oi;
-                            }
-                        }
-                        cen = bi;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    uint32_t asg = 0xFFFFFFFFu;
-                    for (int it = 0; it < 100; ++it) {
-                        uint32_t b = 0;
-                        for (uint32_t c = 1; c < nc; ++c)
-                            if (rc_cmp(px, py, sCen[3 * c], sCen[3 * c + 1], sCen[3 * c + 2], sCen[3 * b],
-                                       sCen[3 * b + 1], sCen[3 * b + 2]) < 0)
-                                b = c;
-                        const bool ch = on && asg != b;
-                        if (on) asg = b;
-                        if (__builtin_amdgcn_ballot_w64(ch) == 0) break;
-                        if (on) sAsg[lane] = asg;
-                        __builtin_amdgcn_wave_barrier();
-                        // lane c < nc sums its cluster's picks
-                        if (lane < nc) {
-                            int64_t sx = 0, sy = 0, cn = 0;
-                            for (uint32_t i = 0; i < n; ++i)
-                                if (sAsg[i] == lane) {
-                                    sx += sXY[2 * i];
-                                    sy += sXY[2 * i + 1];
-                                    ++cn;
-                                }
-                            if (cn) {
-                                sCen[3 * lane] = sx;
-                                sCen[3 * lane + 1] = sy;
-                                sCen[3 * lane + 2] = cn;
-                            }
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                    if (on) sAsg[lane] = asg;
-                    __builtin_amdgcn_wave_barrier();
+                    const uint32_t asg = wave_kmeans(on, px, py, n, mm, sXY, sCen, sAsg);
                     // cluster sizes
                     uint32_t big = 0;
-                    for (uint32_t c = 0; c < nc; ++c) {
+                    for (uint32_t c = 0; c < mm && c < n; ++c) {
                         const uint32_t sz = static_cast<uint32_t>(
                             __builtin_popcountll(__builtin_amdgcn_ballot_w64(on && asg == c)));
                         if (sz > RT_NMAX) big = 1;

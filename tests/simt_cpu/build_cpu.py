@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2504_20655_amd", "csrc")
 OUT = os.path.join(HERE, "_build", "wr_cpu_driver")
 LIB_SOURCES = ["kernels.hip", "runtime.cpp", "tiles.cpp", "solve.cpp", "server.cpp", "autotune.cpp",
-               "routes.cpp"]
+               "routes.cpp", "wms.hip"]
 
 
 def build(sanitize: bool = True) -> str:

@@ -2,6 +2,7 @@
 // C ABI under the CPU executor -- TEST INFRASTRUCTURE ONLY.  Mode 2 sends
 // the orders through the request server instead, one every `flags`
 // milliseconds, so later orders arrive while earlier ones are relaxing.
+// Mode 5 runs wr_wms_run (no graph).
 //   wr_cpu_driver <request.bin> <result.bin>
 #include <chrono>
 #include <cstdio>
@@ -20,6 +21,42 @@ static std::vector<uint32_t> rdv(size_t n) {
     return v;
 }
 
+// wr_wms_run: params, runs, iters, A, M, orders, qty -> status, A, M,
+// silhouette and area (two words per double), moves
+static int run_wms(const char *outpath) {
+    wr_wms_params p{};
+    p.nx = rd();
+    p.ny = rd();
+    p.nz = rd();
+    p.n_articles = rd();
+    p.mmax = rd();
+    p.purchase_orders = rd();
+    p.articles_per_order = rd();
+    p.clusters = rd();
+    const uint32_t runs = rd(), iters = rd();
+    const size_t V = static_cast<size_t>(p.nx) * p.ny * p.nz, S = static_cast<size_t>(p.purchase_orders) * p.articles_per_order;
+    auto A = rdv(runs * V), M = rdv(runs * V), ord = rdv(runs * iters * S), qty = rdv(runs * iters * S);
+    std::vector<double> sil(static_cast<size_t>(runs) * iters), area(sil.size());
+    std::vector<uint32_t> mv(sil.size());
+    wr_context *ctx = nullptr;
+    wr_status st = wr_context_create(0, 0, &ctx);
+    if (st == WR_OK)
+        st = wr_wms_run(ctx, &p, runs, iters, A.data(), M.data(), ord.data(), qty.data(), sil.data(), area.data(),
+                        mv.data(), 0, nullptr);
+    if (st != WR_OK) std::fprintf(stderr, "status %s: %s\n", wr_status_str(st), wr_last_error());
+    FILE *o = std::fopen(outpath, "wb");
+    const uint32_t s32 = st;
+    std::fwrite(&s32, 4, 1, o);
+    std::fwrite(A.data(), 4, A.size(), o);
+    std::fwrite(M.data(), 4, M.size(), o);
+    std::fwrite(sil.data(), 8, sil.size(), o);
+    std::fwrite(area.data(), 8, area.size(), o);
+    std::fwrite(mv.data(), 4, mv.size(), o);
+    std::fclose(o);
+    wr_context_destroy(ctx);
+    return 0;
+}
+
 int main(int argc, char **argv) {
     if (argc != 3) return 2;
     FILE *f = std::fopen(argv[1], "rb");
@@ -29,6 +66,7 @@ int main(int argc, char **argv) {
     std::fclose(f);
     if (rd() != 0x57524F55u) return 2;
     const uint32_t mode = rd(), flags = rd(), want_pred = rd();
+    if (mode == 5) return run_wms(argv[2]);
     const uint32_t V = rd(), E = rd();
     auto row_ptr = rdv(V + 1), col = rdv(E), w = rdv(E);
     wr_context *ctx = nullptr;

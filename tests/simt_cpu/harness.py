@@ -80,3 +80,33 @@ def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="a
     out = res[1:1 + n_out]
     p = res[1 + n_out:1 + n_out + n_pred].view(np.int32) if pred and status == 0 else None
     return status, out, p, r.stderr
+
+
+def run_wms(setup, runs=None, iters=None, timeout=600):
+    """wr_wms_run over a WmsSetup (its first `runs` runs and `iters`
+    iterations) through the driver.  Returns (status, A, M, silhouette,
+    area, moves, stderr)."""
+    R = setup.A0.shape[0] if runs is None else runs
+    T = setup.orders.shape[1] if iters is None else iters
+    S = setup.orders.shape[2]
+    qty = setup.qty[:R, :T] if setup.qty.ndim == 3 else np.broadcast_to(setup.qty[:R, None, :], (R, T, S))
+    parts = [np.asarray([0x57524F55, 5, 0, 0, setup.nx, setup.ny, setup.nz, setup.n_articles, setup.mmax,
+                         setup.po, S // setup.po, setup.k, R, T], np.uint32),
+             setup.A0[:R].ravel(), setup.M0[:R].ravel(), setup.orders[:R, :T].ravel(), np.ascontiguousarray(qty).ravel()]
+    V = setup.nx * setup.ny * setup.nz
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
+        np.concatenate([np.asarray(x, np.uint32).ravel() for x in parts]).tofile(fin)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+        r = subprocess.run([driver(), fin, fout], capture_output=True, text=True, timeout=timeout, env=env)
+        if r.returncode != 0 or not os.path.exists(fout):
+            raise RuntimeError(f"driver failed rc={r.returncode}\n{r.stderr[-6000:]}")
+        res = np.fromfile(fout, dtype=np.uint32)
+    status = int(res[0])
+    o = 1
+    A = res[o:o + R * V].reshape(R, V); o += R * V
+    M = res[o:o + R * V].reshape(R, V); o += R * V
+    sil = res[o:o + 2 * R * T].view(np.float64).reshape(R, T); o += 2 * R * T
+    area = res[o:o + 2 * R * T].view(np.float64).reshape(R, T); o += 2 * R * T
+    moves = res[o:o + R * T].reshape(R, T)
+    return status, A, M, sil, area, moves, r.stderr

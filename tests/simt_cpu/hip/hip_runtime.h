@@ -82,6 +82,7 @@ inline uint64_t ballot(bool p, int line = 0) {
     for (unsigned l = 0; l < w.n; ++l)
         if (w.alive[l] && w.vals[l]) m |= 1ull << l;
     w.bar->arrive_and_wait();
+    progress++;
     return m;
 }
 
@@ -97,6 +98,7 @@ inline uint32_t readfirstlane(uint32_t x, int line = 0) {
             break;
         }
     w.bar->arrive_and_wait();
+    progress++;
     return r;
 }
 
@@ -117,8 +119,10 @@ inline uint32_t shfl(uint32_t x, int src, int line = 0) {
     const unsigned s = static_cast<unsigned>(src) & 63u;
     const uint32_t r = s < w.n ? static_cast<uint32_t>(w.vals[s]) : x;
     w.bar->arrive_and_wait();
+    progress++;
     return r;
 }
+inline uint32_t shfl_xor(uint32_t x, unsigned m) { return shfl(x, static_cast<int>(cur->lane ^ m)); }
 inline uint32_t shfl_up(uint32_t x, unsigned d) {
     const unsigned l = cur->lane;
     const uint32_t r = shfl(x, l >= d ? static_cast<int>(l - d) : static_cast<int>(l));
@@ -166,6 +170,7 @@ void record(void *stream, std::function<void()> fn);
 #define __syncthreads() ::simt::syncthreads(__LINE__)
 #define __shfl(x, src, w) ::simt::shfl((x), (src), __LINE__)
 #define __shfl_up(x, d, w) ::simt::shfl_up((x), (d))
+#define __shfl_xor(x, m, w) ::simt::shfl_xor((x), static_cast<unsigned>(m))
 #define __builtin_amdgcn_ballot_w64(p) ::simt::ballot((p), __LINE__)
 #define __builtin_amdgcn_readfirstlane(x) ::simt::readfirstlane((x), __LINE__)
 #define __builtin_amdgcn_readlane(x, k) ::simt::shfl((x), static_cast<int>(k), __LINE__)
@@ -184,6 +189,12 @@ template <class T, class U>
 inline T atomicOr(T *p, U v) { return __atomic_fetch_or(p, static_cast<T>(v), __ATOMIC_SEQ_CST); }
 template <class T, class U>
 inline T atomicAnd(T *p, U v) { return __atomic_fetch_and(p, static_cast<T>(v), __ATOMIC_SEQ_CST); }
+template <class T, class U, class V>
+inline T atomicCAS(T *p, U cmp, V val) {
+    T old = static_cast<T>(cmp);
+    __atomic_compare_exchange_n(p, &old, static_cast<T>(val), false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+    return old;
+}
 template <class T, class U>
 inline T atomicMin(T *p, U vv) {
     const T v = static_cast<T>(vv);

@@ -164,3 +164,23 @@ def case_clustered_routes_over_executor_matrices(harness):
         used = out[ncell + 2 * no + len(picks):]
         el, er, eu = oracle.order_routes_clustered(off, out[:ncell], xy, m, m_max=10)
         assert (lens == el).all() and (rts == er).all() and (used == eu).all()
+
+
+@case
+def case_warehouse_loop(harness):
+    """wr_wms_run (K-means of the purchase orders, silhouette and area,
+    picks with nearest-empty restocking from the racks' shelf masks): the
+    final state, the moves, the silhouettes and the areas of every
+    iteration equal the oracle's.  An order whose random replacements repeat
+    articles (live state in the hash cells), and a small shape with more
+    than 16 shelves (32-bit rack masks), four purchase orders of three
+    articles in four clusters and fresh parcels per iteration."""
+    from oracle import wms
+    from wgen.wms import make_wms
+    for s in (make_wms(2, 10, 8, 3, 7, 1, 3, 2),
+              make_wms(5, 6, 5, 20, 3, 1, 3, 3, po=4, per_po=3, k=4, qty_per_iter=True)):
+        st, A, M, sil, area, moves, err = harness.run_wms(s)
+        assert st == 0, err[-2000:]
+        eA, eM, esil, earea, emv = wms.run(s, 0)
+        assert (A[0] == eA).all() and (M[0] == eM).all() and (moves[0] == emv).all()
+        assert (sil[0] == esil).all() and (area[0] == earea).all()

@@ -41,9 +41,11 @@ def test_one_iteration_by_hand():
     assert sil == 0.0 and area == 0.0   # one cluster: no silhouette, no triangle
 
 
-def test_silhouette_matches_scikit_learn():
+@pytest.mark.parametrize("per_po", [10, 3])
+def test_silhouette_matches_scikit_learn(per_po):
+    from scipy.spatial.distance import cdist
     from sklearn.metrics import silhouette_score
-    rng = np.random.default_rng(3)
+    rng = np.random.default_rng(3 + per_po)
     for case in range(40):
         pts = rng.integers(0, 200, (20, 2))
         if case % 4 == 0:
@@ -53,22 +55,30 @@ def test_silhouette_matches_scikit_learn():
             labels[:] = np.arange(20) % 2
         if len(set(labels.tolist())) < 2:
             continue
-        exp = silhouette_score(pts / 10.0, labels, metric="euclidean")
-        assert wms.silhouette(pts, labels) == pytest.approx(exp, rel=1e-12, abs=1e-13)
+        # scikit-learn's own Euclidean distances go through |x|^2 + |y|^2 - 2xy
+        # and lose ~1e-8; scipy's cdist takes the differences directly
+        D = cdist(pts / float(per_po), pts / float(per_po))
+        exp = silhouette_score(D, labels, metric="precomputed")
+        assert wms.silhouette(pts, labels, per_po) == pytest.approx(exp, rel=1e-12, abs=1e-13)
 
 
-def test_triangle_area_from_float_centres():
-    rng = np.random.default_rng(4)
+@pytest.mark.parametrize("per_po", [10, 7])
+def test_triangle_area_from_float_centres(per_po):
+    rng = np.random.default_rng(4 + per_po)
     for _ in range(200):
         cnt = rng.integers(1, 10, 3)
         S = rng.integers(0, 1000, (3, 2)) * cnt[:, None] + rng.integers(0, 50, (3, 2))
-        c = S / (10.0 * cnt[:, None])
+        c = S / (float(per_po) * cnt[:, None])
         (x1, y1), (x2, y2), (x3, y3) = c
         # Heron's formula on the side lengths: a different route to the area
         a, b, d = np.hypot(x2 - x3, y2 - y3), np.hypot(x1 - x3, y1 - y3), np.hypot(x1 - x2, y1 - y2)
         s = (a + b + d) / 2
         heron = np.sqrt(max(s * (s - a) * (s - b) * (s - d), 0.0))
-        assert wms.triangle_area(S, cnt) == pytest.approx(heron, rel=1e-6, abs=1e-6)
+        assert wms.triangle_area(S, cnt, per_po) == pytest.approx(heron, rel=1e-6, abs=1e-6)
+        # more clusters: the first three non-empty ones
+        S5 = np.vstack([S[:1], np.zeros((1, 2), np.int64), S[1:], rng.integers(0, 9, (1, 2))])
+        cnt5 = np.array([cnt[0], 0, cnt[1], cnt[2], 3])
+        assert wms.triangle_area(S5, cnt5, per_po) == wms.triangle_area(S, cnt, per_po)
     assert wms.triangle_area(np.ones((3, 2), np.int64), np.array([4, 0, 2])) == 0.0
 
 
@@ -110,6 +120,33 @@ def test_repeated_order_separates_clusters(seed):
     assert sil[-10:].mean() - sil[0] > 0.15
     assert area[-10:].mean() > 2.0 * max(area[0], 0.1)
     assert moves.sum() > 0
+
+
+def test_small_shape_by_hand():
+    """Two purchase orders of two articles, K = 2, on a 4 x 1 floor with two
+    shelves: both clusters are single points, so the silhouette is 0 (a point
+    alone in its cluster scores 0) and there is no triangle."""
+    nx, ny, nz = 4, 1, 2
+    # shelf 0: racks 0..3 hold 1, 2, -, 3; shelf 1: 4, -, -, -
+    A = np.array([1, 2, 0, 3, 4, 0, 0, 0], np.int64)
+    M = np.array([3, 3, 0, 3, 3, 0, 0, 0], np.int64)
+    pos = np.zeros(5, np.int64)
+    for v in np.flatnonzero(A):
+        pos[A[v]] = v
+    order = np.array([1, 4, 2, 3], np.uint32)   # PO 0 = {1, 4}: point (0, 0); PO 1 = {2, 3}: (4, 0)
+    qty = np.array([3, 1, 2, 3], np.uint32)
+    sil, area, moves = wms.iterate(A, M, pos, order, qty, nx, ny, 3, po=2, k=2)
+    # PO 0's centre is rack 0 (0/2): article 1 (m = 3 <= 3) looks for the
+    # empty node nearest i = 0: nodes 2 (i=2), 5 (i=1), 6 (i=2), 7 (i=3) ->
+    # node 5 at distance (2*1 - 0)^2 = 4, not nearer than its own rack 0
+    # (0): restocked in place to 3 - (3 - 3) = 3.  Article 4: 3 > 1 -> 2.
+    # PO 1's centre is i = 2 (4/2): article 2 at rack 1: 3 > 2 -> 1.
+    # Article 3 at rack 3 (3 <= 3): nodes 2 and 6 (rack 2) are both at
+    # distance 0 -- ties to node 2 -- strictly nearer than its own (6-4)^2 =
+    # 4: it moves to node 2 with 3 - 0 = 3.
+    assert A.tolist() == [1, 2, 3, 0, 4, 0, 0, 0]
+    assert M.tolist() == [3, 1, 3, 0, 2, 0, 0, 0]
+    assert moves == 1 and sil == 0.0 and area == 0.0
 
 
 def test_kmeans_reading_is_the_route_one():
