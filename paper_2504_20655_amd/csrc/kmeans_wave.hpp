@@ -14,16 +14,11 @@
 
 #include <cstdint>
 
+#include "wave_ops.hpp"
+
 namespace wr {
 
 constexpr int KM_MAX_STEPS = 100;
-
-// value of v held by lane src of the wave (two 32-bit shuffles)
-__device__ __forceinline__ int64_t km_shfl64(int64_t v, uint32_t src) {
-    const uint32_t lo = __shfl(static_cast<uint32_t>(static_cast<uint64_t>(v)), static_cast<int>(src), 64);
-    const uint32_t hi = __shfl(static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32), static_cast<int>(src), 64);
-    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
-}
 
 // sign of |p - Sa/ca|^2 - |p - Sb/cb|^2, with both sides multiplied by
 // (ca cb)^2 so that it stays in integers.  Exact while
@@ -38,14 +33,18 @@ __device__ __forceinline__ int km_cmp(int64_t px, int64_t py, int64_t sxa, int64
 }
 
 // Every lane of the wave calls this with its point (px, py); lanes with
-// on == false (lane >= n) take no part.  xy: the n points as int32 pairs in
-// LDS; cen: LDS scratch of 3 m int64; asg: LDS [n], left holding every
-// point's cluster.  Returns this lane's cluster (0xFFFFFFFF when !on).
-// Clusters are numbered below min(m, n).
+// on == false (lane >= n) take no part.  Coordinates must lie in
+// (-2^25, 2^25) and counts times coordinates in 32 bits.  xy: the n points
+// as int32 pairs in LDS; cen: LDS scratch of 3 m int64; asg: LDS [n], left
+// holding every point's cluster.  Returns this lane's cluster (0xFFFFFFFF
+// when !on).  Clusters are numbered below min(m, n).
 __device__ inline uint32_t wave_kmeans(bool on, int64_t px, int64_t py, uint32_t n, uint32_t m, const int32_t *xy,
                                        int64_t *cen, uint32_t *asg) {
     const uint32_t lane = threadIdx.x & 63u;
-    // farthest-point initial centres
+    const int32_t px32 = static_cast<int32_t>(px), py32 = static_cast<int32_t>(py);
+    // farthest-point initial centres: the key (d + 1) << 6 | (63 - lane)
+    // orders points by their distance to the nearest centre so far, ties to
+    // the smaller index, and puts every point above the lanes past n
     int64_t dmin = INT64_MAX;
     uint32_t nc = 0, c0 = 0;
     for (;;) {
@@ -60,17 +59,8 @@ __device__ inline uint32_t wave_kmeans(bool on, int64_t px, int64_t py, uint32_t
         const int64_t dx = px - cx, dy = py - cy;
         const int64_t d = dx * dx + dy * dy;
         if (on && d < dmin) dmin = d;
-        int64_t best = on ? dmin : -1;
-        uint32_t bi = lane;
-        for (uint32_t sh = 1; sh < 64; sh <<= 1) {
-            const int64_t ob = km_shfl64(best, lane ^ sh);
-            const uint32_t oi = __shfl(bi, static_cast<int>(lane ^ sh), 64);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        c0 = bi;
+        const uint64_t key = on ? ((static_cast<uint64_t>(dmin) + 1) << 6) | (63u - lane) : 0;
+        c0 = 63u - static_cast<uint32_t>(wave_max_u64(key) & 63u);
     }
     __builtin_amdgcn_wave_barrier();
     uint32_t a = 0xFFFFFFFFu;
@@ -83,22 +73,23 @@ __device__ inline uint32_t wave_kmeans(bool on, int64_t px, int64_t py, uint32_t
         const bool ch = on && a != b;
         if (on) a = b;
         if (__builtin_amdgcn_ballot_w64(ch) == 0) break;
-        if (on) asg[lane] = a;
-        __builtin_amdgcn_wave_barrier();
-        // lane c < nc sums its cluster's points; empty clusters keep their centre
-        if (lane < nc) {
-            int64_t sx = 0, sy = 0, cn = 0;
-            for (uint32_t i = 0; i < n; ++i)
-                if (asg[i] == lane) {
-                    sx += xy[2 * i];
-                    sy += xy[2 * i + 1];
-                    ++cn;
-                }
-            if (cn) {
-                cen[3 * lane] = sx;
-                cen[3 * lane + 1] = sy;
-                cen[3 * lane + 2] = cn;
+        // lane c < nc sums its cluster's points (broadcast from their lanes);
+        // empty clusters keep their centre
+        int32_t sx = 0, sy = 0, cn = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t ai = __builtin_amdgcn_readlane(a, i);
+            const int32_t xi = __builtin_amdgcn_readlane(px32, i), yi = __builtin_amdgcn_readlane(py32, i);
+            if (ai == lane) {
+                sx += xi;
+                sy += yi;
+                ++cn;
             }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nc && cn) {
+            cen[3 * lane] = sx;
+            cen[3 * lane + 1] = sy;
+            cen[3 * lane + 2] = cn;
         }
         __builtin_amdgcn_wave_barrier();
     }

@@ -53,26 +53,13 @@ __device__ __forceinline__ uint32_t ijk_i(uint32_t p) { return p & 2047u; }
 __device__ __forceinline__ uint32_t ijk_j(uint32_t p) { return (p >> 11) & 2047u; }
 __device__ __forceinline__ uint32_t ijk_k(uint32_t p) { return p >> 22; }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-    for (uint32_t sh = 1; sh < 64; sh <<= 1) {
-        const uint32_t lo = __shfl_xor(static_cast<uint32_t>(x), static_cast<int>(sh), 64);
-        const uint32_t hi = __shfl_xor(static_cast<uint32_t>(x >> 32), static_cast<int>(sh), 64);
-        const uint64_t o = (static_cast<uint64_t>(hi) << 32) | lo;
-        x = o < x ? o : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-// squared distance of rack (i, j) to the centre S / scale, times scale^2
-__device__ __forceinline__ uint64_t centre_d2(uint32_t i, uint32_t j, int64_t sx, int64_t sy, int64_t scale) {
-    const int64_t dx = scale * static_cast<int64_t>(i) - sx, dy = scale * static_cast<int64_t>(j) - sy;
-    return static_cast<uint64_t>(dx * dx + dy * dy);
+// squared distance of rack (i, j) to the centre S / scale, times scale^2.
+// The call's limits keep scale * i and S below 2^19, so the differences fit
+// 32 bits and their squares 38.
+__device__ __forceinline__ uint64_t centre_d2(uint32_t i, uint32_t j, int32_t sx, int32_t sy, int32_t scale) {
+    const int32_t dx = scale * static_cast<int32_t>(i) - sx, dy = scale * static_cast<int32_t>(j) - sy;
+    const uint32_t ax = static_cast<uint32_t>(dx < 0 ? -dx : dx), ay = static_cast<uint32_t>(dy < 0 ? -dy : dy);
+    return static_cast<uint64_t>(ax) * ax + static_cast<uint64_t>(ay) * ay;
 }
 
 // Empty shelves of rack r: MPW masks of 32 / MPW bits per 4-byte LDS word.
@@ -93,16 +80,17 @@ __device__ __forceinline__ uint32_t rack_bit(uint32_t r, uint32_t k) {
 // the window doubles until the best key found is nearer than any rack
 // outside it can be.
 template <uint32_t MPW>
-__device__ uint64_t nearest_empty(const uint32_t *mword, uint32_t nx, uint32_t ny, int64_t sx, int64_t sy,
-                                  int64_t scale) {
+__device__ uint64_t nearest_empty(const uint32_t *mword, uint32_t nx, uint32_t ny, int32_t sx, int32_t sy,
+                                  int32_t scale, uint32_t &ijk_out) {
     const uint32_t lane = threadIdx.x & 63u;
-    const int32_t ci = static_cast<int32_t>(std::min<int64_t>(sx / scale, static_cast<int64_t>(nx) - 1));
-    const int32_t cj = static_cast<int32_t>(std::min<int64_t>(sy / scale, static_cast<int64_t>(ny) - 1));
+    const int32_t ci = static_cast<int32_t>(std::min(static_cast<uint32_t>(sx) / static_cast<uint32_t>(scale), nx - 1));
+    const int32_t cj = static_cast<int32_t>(std::min(static_cast<uint32_t>(sy) / static_cast<uint32_t>(scale), ny - 1));
     int32_t R = 3;
     for (;;) {
         const int32_t i0 = std::max(ci - R, 0), i1 = std::min(ci + R, static_cast<int32_t>(nx) - 1);
         const int32_t j0 = std::max(cj - R, 0), j1 = std::min(cj + R, static_cast<int32_t>(ny) - 1);
         uint64_t best = NOKEY;
+        uint32_t bijk = 0;
         for (int32_t jb = j0; jb <= j1; jb += 8)
             for (int32_t ib = i0; ib <= i1; ib += 8) {
                 const int32_t i = ib + static_cast<int32_t>(lane & 7u), j = jb + static_cast<int32_t>(lane >> 3);
@@ -112,31 +100,39 @@ __device__ uint64_t nearest_empty(const uint32_t *mword, uint32_t nx, uint32_t n
                         const uint32_t k = __builtin_ctz(mk);
                         const uint32_t node = (k * ny + static_cast<uint32_t>(j)) * nx + static_cast<uint32_t>(i);
                         const uint64_t key = (centre_d2(i, j, sx, sy, scale) << 24) | node;
-                        best = key < best ? key : best;
+                        if (key < best) {
+                            best = key;
+                            bijk = pack_ijk(static_cast<uint32_t>(i), static_cast<uint32_t>(j), k);
+                        }
                     }
                 }
             }
-        best = uniform64(wave_min_u64(best));
+        const uint64_t mine = best;
+        best = wave_min_u64(best);
         // nearest any rack outside the window can be (the centre lies in
         // the window's column and row ranges)
         uint64_t lb = NOKEY;
         if (i0 > 0) {
-            const int64_t d = sx - scale * (i0 - 1);
-            lb = std::min(lb, static_cast<uint64_t>(d * d));
+            const uint64_t d = static_cast<uint32_t>(sx - scale * (i0 - 1));
+            lb = std::min(lb, d * d);
         }
         if (i1 < static_cast<int32_t>(nx) - 1) {
-            const int64_t d = scale * (i1 + 1) - sx;
-            lb = std::min(lb, static_cast<uint64_t>(d * d));
+            const uint64_t d = static_cast<uint32_t>(scale * (i1 + 1) - sx);
+            lb = std::min(lb, d * d);
         }
         if (j0 > 0) {
-            const int64_t d = sy - scale * (j0 - 1);
-            lb = std::min(lb, static_cast<uint64_t>(d * d));
+            const uint64_t d = static_cast<uint32_t>(sy - scale * (j0 - 1));
+            lb = std::min(lb, d * d);
         }
         if (j1 < static_cast<int32_t>(ny) - 1) {
-            const int64_t d = scale * (j1 + 1) - sy;
-            lb = std::min(lb, static_cast<uint64_t>(d * d));
+            const uint64_t d = static_cast<uint32_t>(scale * (j1 + 1) - sy);
+            lb = std::min(lb, d * d);
         }
-        if (lb == NOKEY || (best != NOKEY && (best >> 24) < lb)) return best;
+        if (lb == NOKEY || (best != NOKEY && (best >> 24) < lb)) {
+            const uint64_t won = __builtin_amdgcn_ballot_w64(mine == best && best != NOKEY);
+            ijk_out = won ? __builtin_amdgcn_readlane(bijk, static_cast<uint32_t>(__builtin_ctzll(won))) : 0u;
+            return best;
+        }
         R = 2 * R + 1;
     }
 }
@@ -151,16 +147,17 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
     const uint32_t kc = std::min(P.k, po);   // clusters K-means can fill
     // ---- LDS: 8-byte arrays first
     int64_t *cen = reinterpret_cast<int64_t *>(lds);   // [3 KMAX] K-means scratch
-    int64_t *cS = cen + 3 * WMS_KMAX;                   // [3 KMAX] sum x, sum y, count per cluster
-    uint64_t *best = reinterpret_cast<uint64_t *>(cS + 3 * WMS_KMAX);   // [KMAX] nearest empty key
+    uint64_t *best = reinterpret_cast<uint64_t *>(cen + 3 * WMS_KMAX);   // [KMAX] nearest empty key
     double *sSil = reinterpret_cast<double *>(best + WMS_KMAX);          // [POMAX]
     uint32_t *sArt = reinterpret_cast<uint32_t *>(sSil + WMS_POMAX);     // [S]
     uint32_t *sQty = sArt + S, *sIJK = sQty + S, *sM = sIJK + S, *sCell = sM + S;
-    uint32_t *hKey = sCell + S, *hCnt = hKey + H, *hIJK = hCnt + H, *hM = hIJK + H;
-    uint32_t *sMov = hM + H;                     // [3 S] moves: from node, to node, article
-    int32_t *xy = reinterpret_cast<int32_t *>(sMov + 3 * S);   // [2 POMAX]
+    // hash cells of the order's articles: key (bit 31 = picked more than
+    // once), and the live node and balance of a repeated article
+    uint32_t *hKey = sCell + S, *hIJK = hKey + H, *hM = hIJK + H;
+    int32_t *xy = reinterpret_cast<int32_t *>(hM + H);   // [2 POMAX]
     uint32_t *asg = reinterpret_cast<uint32_t *>(xy + 2 * WMS_POMAX);   // [POMAX]
-    uint32_t *mword = asg + WMS_POMAX;           // rack masks, MPW per 4-byte word
+    int32_t *cS = reinterpret_cast<int32_t *>(asg + WMS_POMAX);   // [3 KMAX] sum x, sum y, count per cluster
+    uint32_t *mword = reinterpret_cast<uint32_t *>(cS + 3 * WMS_KMAX);   // rack masks, MPW per 4-byte word
     const uint32_t mwords = (racks + MPW - 1) / MPW;
 
     uint32_t *Ar = P.A + static_cast<size_t>(run) * V;
@@ -173,6 +170,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
     __syncthreads();
     bool bad = false;
     for (uint32_t k = 0; k < nz; ++k)
+#pragma unroll 4
         for (uint32_t r = lane; r < racks; r += 64) {
             const uint32_t v = k * racks + r, a = Ar[v];
             if (a == 0)
@@ -183,6 +181,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
                 pos[a] = v;
         }
     __syncthreads();
+#pragma unroll 4
     for (uint32_t v = lane; v < V; v += 64) {
         const uint32_t a = Ar[v];
         if (a != 0 && a <= N && pos[a] != v) bad = true;   // an article at two nodes
@@ -194,10 +193,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
 
     for (uint32_t it = 0; it < P.iters; ++it) {
         const size_t ob = (static_cast<size_t>(run) * P.iters + it) * S;
-        for (uint32_t h = lane; h < H; h += 64) {
-            hKey[h] = 0;
-            hCnt[h] = 0;
-        }
+        for (uint32_t h = lane; h < H; h += 64) hKey[h] = 0;
         __syncthreads();
         // ---- gather the order's slots: article, parcels, node, balance
         for (uint32_t s = lane; s < S; s += 64) {
@@ -213,13 +209,17 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
             sQty[s] = q;
             sIJK[s] = pack_ijk(i, t % ny, t / ny);
             sM[s] = m;
+            // linear probing; H > S cells always leave one free
             uint32_t h = (a * 2654435761u) & (H - 1);
             for (;;) {
                 const uint32_t old = atomicCAS(&hKey[h], 0u, a);
-                if (old == 0u || old == a) break;
+                if (old == 0u) break;
+                if ((old & ~DUP) == a) {
+                    atomicOr(&hKey[h], DUP);
+                    break;
+                }
                 h = (h + 1) & (H - 1);
             }
-            atomicAdd(&hCnt[h], 1u);
             sCell[s] = h;
         }
         if (__builtin_amdgcn_ballot_w64(bad)) {
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
         // an article picked more than once in this order: its live state in the cell
         for (uint32_t s = lane; s < S; s += 64) {
             const uint32_t h = sCell[s];
-            if (hCnt[h] > 1) {
+            if (hKey[h] & DUP) {
                 sCell[s] = h | DUP;
                 hIJK[h] = sIJK[s];
                 hM[h] = sM[s];
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
         const uint32_t my = wave_kmeans(on, px, py, po, P.k, xy, cen, asg);
         __syncthreads();
         if (lane < WMS_KMAX) {
-            int64_t sx = 0, sy = 0, cn = 0;
+            int32_t sx = 0, sy = 0, cn = 0;
             for (uint32_t i = 0; i < po; ++i)
                 if (asg[i] == lane) {
                     sx += xy[2 * i];
@@ -265,36 +265,38 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
             cS[3 * lane + 2] = cn;
         }
         __syncthreads();
-        // ---- silhouette of the points (distances of mean positions)
-        if (on) {
-            const int64_t nown = cS[3 * my + 2];
-            double si = 0.0;
-            if (nown > 1) {
-                double a = 0.0;
-                for (uint32_t j = 0; j < po; ++j)
-                    if (j != lane && asg[j] == my) {
-                        const int64_t dx = px - xy[2 * j], dy = py - xy[2 * j + 1];
-                        a += std::sqrt(static_cast<double>(dx * dx + dy * dy)) / static_cast<double>(per);
-                    }
-                a /= static_cast<double>(nown - 1);
-                double b = __builtin_inf();
-                for (uint32_t c = 0; c < kc; ++c) {
-                    const int64_t nc = cS[3 * c + 2];
-                    if (c == my || nc == 0) continue;
-                    double sum = 0.0;
-                    for (uint32_t j = 0; j < po; ++j)
-                        if (asg[j] == c) {
-                            const int64_t dx = px - xy[2 * j], dy = py - xy[2 * j + 1];
-                            sum += std::sqrt(static_cast<double>(dx * dx + dy * dy)) / static_cast<double>(per);
-                        }
-                    b = std::fmin(b, sum / static_cast<double>(nc));
+        // ---- silhouette of the points (distances of mean positions): one
+        // distance per pair, summed per cluster in ascending point order
+        const int32_t px32 = static_cast<int32_t>(px), py32 = static_cast<int32_t>(py);
+        {
+            double acc[WMS_KMAX];
+#pragma unroll
+            for (uint32_t c = 0; c < WMS_KMAX; ++c) acc[c] = 0.0;
+            for (uint32_t j = 0; j < po; ++j) {
+                const int64_t dx = px - __builtin_amdgcn_readlane(px32, j);
+                const int64_t dy = py - __builtin_amdgcn_readlane(py32, j);
+                const double d = std::sqrt(static_cast<double>(dx * dx + dy * dy)) / static_cast<double>(per);
+                const uint32_t cj = __builtin_amdgcn_readlane(my, j);
+#pragma unroll
+                for (uint32_t c = 0; c < WMS_KMAX; ++c)
+                    if (c < kc && c == cj) acc[c] += d;   // d(i, i) = 0 adds nothing
+            }
+            if (on) {
+                const int32_t nown = cS[3 * my + 2];
+                double si = 0.0, a = 0.0, b = __builtin_inf();
+#pragma unroll
+                for (uint32_t c = 0; c < WMS_KMAX; ++c) {
+                    if (c >= kc) continue;
+                    const int32_t nc = cS[3 * c + 2];
+                    if (c == my) a = acc[c] / static_cast<double>(nown - 1);
+                    else if (nc > 0) b = std::fmin(b, acc[c] / static_cast<double>(nc));
                 }
-                if (b != __builtin_inf()) {
+                if (nown > 1 && b != __builtin_inf()) {
                     const double mx = std::fmax(a, b);
                     si = mx == 0.0 ? 0.0 : (b - a) / mx;
                 }
+                sSil[lane] = si;
             }
-            sSil[lane] = si;
         }
         __syncthreads();
         if (lane == 0) {
@@ -318,12 +320,27 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
             }
             P.area[static_cast<size_t>(run) * P.iters + it] = area;
         }
-        // ---- the picks, in order
+        // ---- the picks, in order.  A chunk of 64 slots is evaluated at once
+        // against the state as it stands; the first slot that would change
+        // shared state (a move), needs a nearest-empty search, or picks an
+        // article picked earlier in the order ends the chunk's final prefix
+        // and runs alone; then the rest of the chunk is evaluated again.
         uint32_t valid = 0, nmov = 0;   // clusters whose cached nearest empty node is current
+        // cluster c's centre and cached nearest empty node live in lane c
+        int32_t cl_sx = 0, cl_sy = 0, cl_scale = 1;
+        uint64_t cl_best = NOKEY;
+        uint32_t cl_bijk = 0;
+        if (lane < kc) {
+            cl_sx = cS[3 * lane];
+            cl_sy = cS[3 * lane + 1];
+            cl_scale = static_cast<int32_t>(per) * cS[3 * lane + 2];
+        }
         for (uint32_t c0 = 0; c0 < S; c0 += 64) {
             const uint32_t s = c0 + lane;
-            const bool in = s < S;
+            const uint32_t nl = std::min(64u, S - c0);
+            const bool in = lane < nl;
             uint32_t rq = 0, rijk = 0, rm = 0, rcell = 0, rart = 0, rc = 0;
+            uint64_t rdv = 0;   // the slot node's distance to its cluster's centre
             if (in) {
                 rq = sQty[s];
                 rijk = sIJK[s];
@@ -331,9 +348,47 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
                 rcell = sCell[s];
                 rart = sArt[s];
                 rc = asg[s / per];
+                rdv = centre_d2(ijk_i(rijk), ijk_j(rijk), cS[3 * rc], cS[3 * rc + 1],
+                                static_cast<int32_t>(per) * cS[3 * rc + 2]);
             }
-            const uint32_t nl = std::min(64u, S - c0);
-            for (uint32_t l = 0; l < nl; ++l) {
+            uint32_t start = 0;
+            for (;;) {
+                // nearest-empty searches for the clusters the remaining
+                // restocks need (each serves at least its first one)
+                const bool restock = in && lane >= start && !(rcell & DUP) && rm <= rq;
+                for (uint32_t c = 0; c < kc; ++c) {
+                    if ((valid >> c) & 1u) continue;
+                    if (!__builtin_amdgcn_ballot_w64(restock && rc == c)) continue;
+                    uint32_t bij = 0;
+                    const int32_t sx = __builtin_amdgcn_readlane(cl_sx, c), sy = __builtin_amdgcn_readlane(cl_sy, c);
+                    const uint64_t key =
+                        nearest_empty<MPW>(mword, nx, ny, sx, sy, __builtin_amdgcn_readlane(cl_scale, c), bij);
+                    if (lane == c) {
+                        cl_best = key;
+                        cl_bijk = bij;
+                        best[c] = key;
+                    }
+                    valid |= 1u << c;
+                }
+                __builtin_amdgcn_wave_barrier();   // lane c's best[c] before the other lanes read it
+                bool stop = false;
+                uint32_t nm = rm;
+                if (in && lane >= start) {
+                    if (rcell & DUP) {
+                        stop = true;
+                    } else if (rm > rq) {
+                        nm = rm - rq;
+                    } else {
+                        const uint64_t bk = best[rc];
+                        if (bk != NOKEY && (bk >> 24) < rdv) stop = true;
+                        else nm = P.mmax - (rq - rm);
+                    }
+                }
+                const uint64_t sm = __builtin_amdgcn_ballot_w64(stop);
+                const uint32_t l = sm ? static_cast<uint32_t>(__builtin_ctzll(sm)) : nl;
+                if (in && lane >= start && lane < l) rm = nm;   // the final prefix
+                if (l >= nl) break;
+                // ---- slot l alone
                 const uint32_t q = __builtin_amdgcn_readlane(rq, l);
                 const uint32_t cell = __builtin_amdgcn_readlane(rcell, l);
                 const bool dup = cell & DUP;
@@ -350,41 +405,56 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
                     m -= q;
                 } else {
                     const uint32_t c = __builtin_amdgcn_readlane(rc, l);
-                    const int64_t sx = cS[3 * c], sy = cS[3 * c + 1], scale = static_cast<int64_t>(per) * cS[3 * c + 2];
+                    const int32_t sx = __builtin_amdgcn_readlane(cl_sx, c), sy = __builtin_amdgcn_readlane(cl_sy, c);
+                    const int32_t scale = __builtin_amdgcn_readlane(cl_scale, c);
                     if (!((valid >> c) & 1u)) {
-                        const uint64_t key = nearest_empty<MPW>(mword, nx, ny, sx, sy, scale);
-                        best[c] = key;   // every lane writes the same value
+                        uint32_t bij = 0;
+                        const uint64_t key = nearest_empty<MPW>(mword, nx, ny, sx, sy, scale, bij);
+                        if (lane == c) {
+                            cl_best = key;
+                            cl_bijk = bij;
+                            best[c] = key;
+                        }
                         valid |= 1u << c;
                     }
-                    const uint64_t bk = uniform64(best[c]);
+                    const uint64_t bk = readlane64(cl_best, c);
                     const uint32_t iv = ijk_i(ijk), jv = ijk_j(ijk), kv = ijk_k(ijk);
                     if (bk != NOKEY && (bk >> 24) < centre_d2(iv, jv, sx, sy, scale)) {
                         // move the article to u; its node v becomes empty
                         const uint32_t u = static_cast<uint32_t>(bk & 0xFFFFFFu);
-                        const uint32_t iu = u % nx, tu = u / nx, ju = tu % ny, ku = tu / ny;
+                        const uint32_t uijk = __builtin_amdgcn_readlane(cl_bijk, c);
+                        const uint32_t iu = ijk_i(uijk), ju = ijk_j(uijk), ku = ijk_k(uijk);
                         const uint32_t v = (kv * ny + jv) * nx + iv;
                         const uint32_t ru = ju * nx + iu, rv = jv * nx + iv;
                         // every lane applies the same update to the same words
                         mword[ru / MPW] &= ~rack_bit<MPW>(ru, ku);
                         mword[rv / MPW] |= rack_bit<MPW>(rv, kv);
-                        sMov[3 * nmov] = v;
-                        sMov[3 * nmov + 1] = u;
-                        sMov[3 * nmov + 2] = dup ? hKey[hc] : __builtin_amdgcn_readlane(rart, l);
-                        ++nmov;
-                        valid &= ~(1u << c);
-                        for (uint32_t c2 = 0; c2 < kc; ++c2) {
-                            if (!((valid >> c2) & 1u)) continue;
-                            const uint64_t b2 = uniform64(best[c2]);
-                            if (b2 != NOKEY && static_cast<uint32_t>(b2 & 0xFFFFFFu) == u) {
-                                valid &= ~(1u << c2);
-                                continue;
-                            }
-                            const uint64_t kv2 =
-                                (centre_d2(iv, jv, cS[3 * c2], cS[3 * c2 + 1],
-                                           static_cast<int64_t>(per) * cS[3 * c2 + 2]) << 24) | v;
-                            if (kv2 < b2) best[c2] = kv2;
+                        // the state in HBM, in move order from one lane; the
+                        // final balances follow after the picks
+                        const uint32_t art = dup ? (hKey[hc] & ~DUP) : __builtin_amdgcn_readlane(rart, l);
+                        if (lane == 0) {
+                            Ar[v] = 0;
+                            Mr[v] = 0;
+                            Ar[u] = art;
                         }
-                        ijk = pack_ijk(iu, ju, ku);
+                        ++nmov;
+                        // the caches: cluster c's node is taken; every other
+                        // cluster drops u, or takes v when v is nearer
+                        bool drop = false;
+                        if (lane < kc && lane != c && ((valid >> lane) & 1u)) {
+                            if (cl_best != NOKEY && static_cast<uint32_t>(cl_best & 0xFFFFFFu) == u) {
+                                drop = true;
+                            } else {
+                                const uint64_t kv2 = (centre_d2(iv, jv, cl_sx, cl_sy, cl_scale) << 24) | v;
+                                if (kv2 < cl_best) {
+                                    cl_best = kv2;
+                                    cl_bijk = ijk;
+                                    best[lane] = kv2;
+                                }
+                            }
+                        }
+                        valid &= ~static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(drop)) & ~(1u << c);
+                        ijk = uijk;
                     }
                     m = P.mmax - (q - m);
                 }
@@ -395,6 +465,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
                     rijk = ijk;
                     rm = m;
                 }
+                start = l + 1;
             }
             if (in && !(rcell & DUP)) {
                 sIJK[s] = rijk;
@@ -402,15 +473,7 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
             }
         }
         __syncthreads();
-        // ---- write back: the moves in order, then balances and positions
-        if (lane == 0)
-            for (uint32_t t = 0; t < nmov; ++t) {
-                const uint32_t from = sMov[3 * t], to = sMov[3 * t + 1];
-                Ar[from] = 0;
-                Mr[from] = 0;
-                Ar[to] = sMov[3 * t + 2];
-            }
-        __syncthreads();
+        // ---- write back: balances and positions (after the moves' stores)
         for (uint32_t s = lane; s < S; s += 64) {
             const uint32_t cell = sCell[s];
             const uint32_t p = (cell & DUP) ? hIJK[cell & ~DUP] : sIJK[s];
@@ -425,8 +488,8 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
 }
 
 uint32_t wms_lds_bytes(uint32_t S, uint32_t H, uint32_t racks, uint32_t mask_bytes) {
-    const uint32_t fixed = (3 * WMS_KMAX + 3 * WMS_KMAX + WMS_KMAX + WMS_POMAX) * 8;
-    const uint32_t words = 5 * S + 4 * H + 3 * S + 2 * WMS_POMAX + WMS_POMAX;
+    const uint32_t fixed = (3 * WMS_KMAX + WMS_KMAX + WMS_POMAX) * 8;
+    const uint32_t words = 5 * S + 3 * H + 2 * WMS_POMAX + WMS_POMAX + 3 * WMS_KMAX;
     return fixed + words * 4 + ((racks * mask_bytes + 3) / 4) * 4;
 }
 
@@ -465,7 +528,7 @@ extern "C" wr_status wr_wms_run(wr_context *ctx, const wr_wms_params *p, uint32_
     if (runs == 0 || iters == 0) return WR_OK;
     const uint32_t S = static_cast<uint32_t>(S64);
     uint32_t H = 64;
-    while (H < 2 * S) H <<= 1;
+    while (H <= S) H <<= 1;
     if (!A || !M || !orders || !qty || !silhouette || !area || !moves) fail(WR_E_INVALID, "a buffer is NULL");
     const bool dev = flags & WR_DEVICE_PTRS;
     const uint64_t cells = static_cast<uint64_t>(runs) * V, ocells = static_cast<uint64_t>(runs) * iters * S;

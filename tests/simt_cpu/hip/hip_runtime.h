@@ -122,6 +122,17 @@ inline uint32_t shfl(uint32_t x, int src, int line = 0) {
     progress++;
     return r;
 }
+// DPP move within a row of 16 lanes: quad permutations, row and half-row
+// mirrors (the patterns the library uses; all lanes active)
+inline uint32_t update_dpp(uint32_t, uint32_t src, int ctrl) {
+    const unsigned l = cur->lane;
+    unsigned s;
+    if (ctrl < 0x100) s = (l & ~3u) | ((static_cast<unsigned>(ctrl) >> (2 * (l & 3u))) & 3u);
+    else if (ctrl == 0x140) s = (l & ~15u) | (15u - (l & 15u));
+    else if (ctrl == 0x141) s = (l & ~7u) | (7u - (l & 7u));
+    else std::abort();
+    return shfl(src, static_cast<int>(s));
+}
 inline uint32_t shfl_xor(uint32_t x, unsigned m) { return shfl(x, static_cast<int>(cur->lane ^ m)); }
 inline uint32_t shfl_up(uint32_t x, unsigned d) {
     const unsigned l = cur->lane;
@@ -171,6 +182,7 @@ void record(void *stream, std::function<void()> fn);
 #define __shfl(x, src, w) ::simt::shfl((x), (src), __LINE__)
 #define __shfl_up(x, d, w) ::simt::shfl_up((x), (d))
 #define __shfl_xor(x, m, w) ::simt::shfl_xor((x), static_cast<unsigned>(m))
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) ::simt::update_dpp((old), (src), (ctrl))
 #define __builtin_amdgcn_ballot_w64(p) ::simt::ballot((p), __LINE__)
 #define __builtin_amdgcn_readfirstlane(x) ::simt::readfirstlane((x), __LINE__)
 #define __builtin_amdgcn_readlane(x, k) ::simt::shfl((x), static_cast<int>(k), __LINE__)
