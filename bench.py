@@ -147,6 +147,28 @@ def load_traffic(kernel: str, workload: str):
     return t.get("bytes_per_launch")
 
 
+def wms_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("wms.hip", "kmeans_wave.hpp", "wave_ops.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2504_20655_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_wms_instructions():
+    """Wave-instructions per run-iteration of k_wms per workload, from the
+    committed rocprofv3 counter run, if it was taken on the current source."""
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "k_wms_instructions.json")))
+    except (OSError, ValueError):
+        return {}
+    if t.get("kernel_src_sha") != wms_source_sha():
+        return {}
+    return {k: v["wave_instr_per_run_iteration"] for k, v in t.get("workloads", {}).items()}
+
+
+ISSUE_PEAK = 256 * 4 * 2.4e9   # one wave-instruction per SIMD per cycle
+
+
 def copy_bandwidth_gbs(mib=2048):
     """Device-to-device copy rate (read + write bytes per second), the
     practical HBM ceiling the measured traffic is also compared with."""
@@ -631,6 +653,7 @@ def wms_leg(wr, ctx, runs_small, runs_large, steps, warmup, with_cpu, cpu_second
     import torch
     from oracle import wms as owms
     dev = torch.device("cuda:0")
+    instr = load_wms_instructions()
     out = {}
     for name, (nx, ny, nz, er, runs) in (("paper_10x10x10", (10, 10, 10, 11, runs_small)),
                                          ("large_100x100x10", (100, 100, 10, 1100, runs_large))):
@@ -660,6 +683,14 @@ def wms_leg(wr, ctx, runs_small, runs_large, steps, warmup, with_cpu, cpu_second
                "value": round(R * T / dt, 1), "unit": "run-iterations/s", "ms_per_step": round(dt * 1e3, 3),
                "moves_per_iteration": round(float(res[2].double().mean()), 2),
                "silhouette_last": round(float(res[0][:, -1].mean()), 4)}
+        # a dependent chain per run: the bound is instruction issue; the
+        # instructions per run-iteration come from the profiler's counters
+        per = instr.get(name)
+        leg["roofline"] = {"kernel": "k_wms", "bound": "issue", "unit": "T wave-instructions/s",
+                           "peak": round(ISSUE_PEAK / 1e12, 3), "traffic": None,
+                           "achieved": round(per * R * T / dt / 1e12, 4) if per else None,
+                           "frac": round(per * R * T / dt / ISSUE_PEAK, 4) if per else None,
+                           "wave_instr_per_run_iteration": per}
         if with_cpu:
             # the oracle on run 0 from the initial state, as many iterations
             # as fit the CPU budget
