@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--serve-rates", default="500,2000,8000",
                     help="Poisson arrival rates (orders/s) of the serving leg, comma-separated")
     ap.add_argument("--serve-seconds", type=float, default=1.5, help="arrival window per rate")
+    ap.add_argument("--serve-epochs", default="1,2",
+                    help="resident weight epochs of the server to run every rate with, comma-separated")
     ap.add_argument("--route-stops", type=int, default=12, help="stops per route in the exact-route leg")
     ap.add_argument("--wms-runs", default="4096,1024",
                     help="runs per batch of the warehouse-loop leg: 10x10x10 and 100x100x10 warehouses")
@@ -460,7 +462,7 @@ def tiny_leg(wr, ctx, steps):
             "paper_context": "2627 MTEPS at V=9,716, E=26,999 on an RTX 6000 (GPU Implementation subsection)"}
 
 
-def serving_leg(wr, ctx, rates, seconds):
+def serving_leg(wr, ctx, rates, seconds, epochs=(1,)):
     """Continuous-batching server on the serving warehouse (3 levels of
     1024x1024 joined by lifts): Poisson order arrivals with sizes uniform in
     2..128, and 1% congestion updates every 100 ms applied between steps.
@@ -486,13 +488,13 @@ def serving_leg(wr, ctx, rates, seconds):
         srv.poll(t)
     srv.close()
     out = []
-    for rate in rates:
+    for rate, ep in ((r, e) for e in epochs for r in rates):
         n = max(1, int(rate * seconds))
         orders = draw(n)
         arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
         ticker = CongestionTicker(np.random.default_rng(wl.seed + 11), g.edge_arc_a, g.edge_arc_b,
                                   g.edge_base_w, g.edge_is_lift, ex["congestion"], ex["congestion_extra"])
-        srv = wr.Server(G)
+        srv = wr.Server(G, resident_epochs=ep)
         tickets, ticks = [], 0
         t0 = time.perf_counter()
         next_tick = ex["tick_s"]
@@ -515,14 +517,14 @@ def serving_leg(wr, ctx, rates, seconds):
         for t in tickets:
             srv.poll(t)
         srv.close()
-        out.append({"rate": rate, "orders": n, "weight_ticks": ticks,
+        out.append({"rate": rate, "resident_epochs": ep, "orders": n, "weight_ticks": ticks,
                     "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                     "mean_ms": round(st["mean_ms"], 3), "orders_per_s": round(n / wall, 1),
                     "arrival_window_s": round(t_sub, 3), "wall_s": round(wall, 3),
                     "saturated": bool(n / wall < 0.9 * rate),
                     "max_inflight": st["max_inflight_requests"], "steps": st["steps"],
                     "failed": st["failed"]})
-        log(f"serving rate {rate}/s: {n / wall:.0f} orders/s completed, p50 {st['p50_ms']:.2f} ms "
+        log(f"serving rate {rate}/s, {ep} resident epoch(s): {n / wall:.0f} orders/s completed, p50 {st['p50_ms']:.2f} ms "
             f"p99 {st['p99_ms']:.2f} ms ({n} orders, {ticks} weight ticks)")
     G.close()
     return {"workload": "serving: 3 levels of 1024x1024 (V=3,145,728, E=6,422,650), 64 lifts (w=50), "
@@ -737,7 +739,7 @@ def main():
                           args.cpu_seconds)
         else:
             leg = serving_leg(wr, ctx, [float(x) for x in args.serve_rates.split(",") if x.strip()],
-                              args.serve_seconds)
+                              args.serve_seconds, [int(x) for x in args.serve_epochs.split(",") if x.strip()])
         print(json.dumps({"leg": args.only, **leg}), flush=True)
         return
     copy_gbs = copy_bandwidth_gbs()
@@ -827,7 +829,8 @@ def main():
         torch.cuda.empty_cache()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if "serving" in legs and rates:
-        res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds)
+        res["serving"] = serving_leg(wr, ctx, rates, args.serve_seconds,
+                                     [int(x) for x in args.serve_epochs.split(",") if x.strip()])
     if args.copy_probe > 0:
         n = args.copy_probe << 18
         a = torch.ones(n, dtype=torch.int32, device="cuda")

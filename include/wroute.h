@@ -445,6 +445,8 @@ typedef struct wr_server_opts {
     uint64_t mem_budget_bytes;   /* device bytes for in-flight work (0 = auto) */
     uint32_t max_queue;          /* queued requests before WR_E_BUSY (0 = 65536) */
     uint32_t passes_per_step;    /* relaxation passes per scheduler step (0 = auto) */
+    uint32_t resident_epochs;    /* weight epochs kept resident: 1 (or 0): an update waits
+                                    until no order is in flight; 2: see wr_server_create */
 } wr_server_opts;
 
 typedef struct wr_req_info {
@@ -466,7 +468,16 @@ typedef struct wr_stats {
 
 /* Creates a server over graph g (the server keeps g and its segmentation
  * resident; g must outlive the server and must not be used directly while
- * the server runs).  opts may be NULL for defaults. */
+ * the server runs; when the server ends, g holds every accepted update).
+ * On graphs that run the overlay schedule the server relaxes orders in
+ * block rows of 64 sources, admitted between relaxation steps.  With
+ * resident_epochs = 2 it keeps two weight epochs resident: it makes a
+ * second copy of g (same segmentation and schedule) with rows of its own;
+ * an update is applied to the copy whose rows have all retired, which then
+ * takes the new orders while the other copy's orders finish on their epoch
+ * (the rows of both copies come out of mem_budget_bytes; while both copies
+ * have orders in flight a step relaxes both).  The call returns once the
+ * server's state is built.  opts may be NULL for defaults. */
 wr_status wr_server_create(wr_graph *g, const wr_server_opts *opts, wr_server **out);
 
 /* Queues one order of P picks (host array, copied; P == 0 is allowed and
@@ -479,8 +490,11 @@ wr_status wr_server_submit(wr_server *srv, uint32_t P, const uint32_t *picks, ui
  * ticket.  info may be NULL.  A request that failed returns its status. */
 wr_status wr_server_poll(wr_server *srv, uint64_t ticket, uint32_t *dist_out, wr_req_info *info);
 
-/* Queues a weight update; it is applied between scheduler steps, and every
- * request admitted after that point is solved on the new epoch.  Arc
+/* Queues a weight update; it is applied between scheduler steps (with two
+ * resident epochs to the copy of the graph with nothing in flight, else
+ * once no order is in flight), and every request admitted after that point
+ * is solved on the new epoch (wr_req_info.epoch: the caller graph's epoch at creation plus
+ * the updates accepted before the request's admission).  Arc
  * indices are checked here (WR_E_INVALID); an update that the graph would
  * refuse at application time (WR_E_RANGE, see wr_graph_update_weights) is
  * dropped and the epoch does not advance. */

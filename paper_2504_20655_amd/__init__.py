@@ -320,10 +320,10 @@ class Server:
     stay alive, and must not be used directly, while the server runs."""
 
     def __init__(self, graph: Graph, max_source_slots: int = 0, mem_budget_bytes: int = 0,
-                 max_queue: int = 0, passes_per_step: int = 0):
+                 max_queue: int = 0, passes_per_step: int = 0, resident_epochs: int = 0):
         from ._lib import ServerOpts
         self.graph = graph
-        o = ServerOpts(max_source_slots, mem_budget_bytes, max_queue, passes_per_step)
+        o = ServerOpts(max_source_slots, mem_budget_bytes, max_queue, passes_per_step, resident_epochs)
         h = ctypes.c_void_p()
         _check(lib().wr_server_create(graph.h, ctypes.byref(o), ctypes.byref(h)))
         self.h = h

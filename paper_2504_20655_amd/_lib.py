@@ -40,7 +40,7 @@ class WmsParams(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_source_slots", u32), ("mem_budget_bytes", u64), ("max_queue", u32),
-                ("passes_per_step", u32)]
+                ("passes_per_step", u32), ("resident_epochs", u32)]
 
 
 class ReqInfo(ctypes.Structure):

@@ -8,10 +8,14 @@
 // rows no order uses any more.  Other graphs fall back to step batching: the
 // admitted orders are solved together in one multi-source call.
 //
-// Weight updates queue; admission pauses until the rows in flight have
-// converged, then the update is applied, so every order is solved entirely
-// on the epoch current at its admission.  An order's matrix is the same alone
-// or in any mix, because every schedule reaches the exact fixpoint.
+// Weight updates queue.  The streaming mode keeps two resident copies of the
+// graph, each with its own rows: an update is applied to the copy whose rows
+// have all retired, which then takes the new orders while the other copy's
+// orders finish on their own epoch; step batching (and streaming when the
+// copy cannot be made) applies updates once nothing is in flight.  Every
+// order is solved entirely on the epoch current at its admission.  An
+// order's matrix is the same alone or in any mix, because every schedule
+// reaches the exact fixpoint.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -56,7 +60,8 @@ struct wr_server {
     uint64_t budget = 0;              // device bytes an admitted batch may take
     std::mutex mu;
     std::condition_variable cv_work;  // scheduler: new requests, updates or stop
-    std::condition_variable cv_done;  // drain / poll waiters
+    std::condition_variable cv_done;  // drain / poll waiters, and the scheduler's set-up
+    bool ready = false;               // the scheduler has built its state
     std::deque<Request *> queue;      // submitted, not admitted
     std::unordered_map<uint64_t, Request *> reqs;   // ticket -> request (until polled)
     std::deque<WeightBatch> updates;
@@ -70,8 +75,7 @@ struct wr_server {
     std::vector<double> lat_ms;
     double t0 = 0;
     std::thread worker;
-    // streaming mode
-    StreamSolver *stream = nullptr;
+    uint64_t epoch_now = 0;           // epoch new orders are admitted on (streaming mode)
     // phase timers (seconds), printed at destroy when WR_TRACE is set
     double t_update = 0, t_admit = 0, t_step = 0, t_gather = 0, t_wait = 0;
     uint64_t rows_admitted = 0;
@@ -106,6 +110,13 @@ void finish(wr_server *s, Request *r, wr_status st, double t_done) {
     }
 }
 
+// The scheduler's state is built: wr_server_create may return.
+void set_ready(wr_server *s) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->ready = true;
+    s->cv_done.notify_all();
+}
+
 // Applies queued weight updates (caller: nothing in flight).
 void apply_updates(wr_server *s, std::vector<WeightBatch> &ups) {
     for (WeightBatch &u : ups) {
@@ -119,6 +130,7 @@ void apply_updates(wr_server *s, std::vector<WeightBatch> &ups) {
 
 // Step batching: every admitted order in one multi-source call.
 void run_step_mode(wr_server *s) {
+    set_ready(s);
     const uint32_t slots = s->opts.max_source_slots;
     std::vector<Request *> batch;
     std::vector<uint32_t> off, picks, out;
@@ -135,6 +147,10 @@ void run_step_mode(wr_server *s) {
             }
         }
         apply_updates(s, ups);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->epoch_now = s->g->epoch;
+        }
         // admission: queued orders in arrival order while slots and memory allow
         batch.clear();
         {
@@ -196,214 +212,372 @@ struct Live {
     std::vector<uint32_t> rows;   // distinct rows
 };
 
+// One resident copy of the graph at one weight epoch, with its own block
+// rows.  The streaming mode keeps two: new orders are admitted into the
+// current one, and a weight update is applied to the other as soon as its
+// rows have all retired, which then becomes current; the orders still in
+// flight on the old copy finish on their own epoch.
+struct Side {
+    wr_graph *g = nullptr;
+    bool owned = false;               // the server's own copy
+    StreamSolver *stream = nullptr;
+    uint64_t epoch = 0;               // server epoch of its weights
+    std::vector<WeightBatch> lag;     // applied to the other copy, not yet here
+    std::vector<uint32_t> refcnt;     // admitted orders using each row
+    std::vector<uint8_t> busy;        // row still relaxing
+    std::vector<uint32_t> free_rows;
+    std::vector<Live> live;
+    std::vector<uint32_t> pending;
+
+    void reset_rows(uint32_t R) {
+        refcnt.assign(R, 0u);
+        busy.assign(R, 0);
+        free_rows.clear();
+        for (uint32_t b = R; b-- > 0;) free_rows.push_back(b);
+    }
+};
+
+// A copy of g at its current weights: the same CSR, segmentation and
+// schedule (schedule first: the tiles are sized by it).
+wr_graph *clone_graph(wr_graph *g) {
+    wr_graph *c = nullptr;
+    wr_status st = wr_graph_create_csr(g->ctx, g->V, g->E, g->row_ptr.data(), g->col.data(), g->w.data(), 0, &c);
+    if (st != WR_OK) fail(st, std::string("copying the graph: ") + wr_last_error());
+    c->tile_vertices = g->tile_vertices;
+    c->waves_per_group = g->waves_per_group;
+    c->lanes = g->lanes;
+    c->sources_per_unit = g->sources_per_unit;
+    c->passes_per_replay = g->passes_per_replay;
+    if (g->grid_W)
+        st = wr_graph_segment_grid(c, g->grid_W, g->grid_H, g->grid_L, g->grid_tw, g->grid_th);
+    else if (g->tiles_user)
+        st = wr_graph_set_segments(c, g->user_seg.data(), g->user_num_segments);
+    if (st != WR_OK) {
+        const std::string msg = wr_last_error();
+        wr_graph_destroy(c);
+        fail(st, "segmenting the graph's copy: " + msg);
+    }
+    return c;
+}
+
+// Applies update batches to one copy; returns those it accepted (a batch the
+// graph refuses is dropped, and would be refused by the other copy too).
+std::vector<WeightBatch> apply_to(wr_graph *g, std::vector<WeightBatch> &ups) {
+    std::vector<WeightBatch> ok;
+    for (WeightBatch &u : ups) {
+        uint64_t ep = 0;
+        const wr_status st =
+            wr_graph_update_weights(g, static_cast<uint32_t>(u.arc.size()), u.arc.data(), u.w.data(), &ep);
+        if (st != WR_OK)
+            set_last_error(std::string("server weight update rejected: ") + wr_status_str(st));
+        else
+            ok.push_back(std::move(u));
+    }
+    ups.clear();
+    return ok;
+}
+
 // Streaming mode; returns false (nothing admitted yet) if the state cannot
 // be built, and then the caller falls back to step batching.
 bool run_stream_mode(wr_server *s) {
     wr_graph *g = s->g;
     uint32_t want = (s->opts.max_source_slots + 63) / 64;
+    Side S[2];
+    S[0].g = g;
+    S[0].epoch = g->epoch;
+    const bool two = s->opts.resident_epochs >= 2;
     try {
         const uint64_t per = stream_bytes_per_block(g);
-        const uint64_t fit = s->budget > (8ull << 20) ? (s->budget - (8ull << 20)) / per : 0;
+        // rows for each copy's state (besides the second copy's graph and tables)
+        const uint64_t fit = s->budget > (8ull << 20) ? (s->budget - (8ull << 20)) / ((two ? 2 : 1) * per) : 0;
         want = static_cast<uint32_t>(std::min<uint64_t>(want, fit));
         if (!want) return false;
-        s->stream = stream_create(g, want);
+        S[0].stream = stream_create(g, want);
     } catch (const Error &) {
-        return false;
+        return false;   // step batching signals ready
     }
-    const uint32_t R = stream_blocks(s->stream);
-    std::vector<uint32_t> refcnt(R, 0);       // admitted orders using the row
-    std::vector<uint8_t> busy(R, 0);          // row still relaxing
-    std::vector<uint32_t> free_rows;
-    for (uint32_t b = R; b-- > 0;) free_rows.push_back(b);
-    std::vector<Live> live;
-    std::vector<uint32_t> pending;
-    std::vector<WeightBatch> ups;
-    auto fail_all = [&](wr_status st) {
+    const uint32_t R = stream_blocks(S[0].stream);
+    S[0].reset_rows(R);
+    // the second copy is made before serving starts; without it updates
+    // wait for the rows in flight, as with one copy
+    if (two) try {
+        S[1].g = clone_graph(g);
+        S[1].owned = true;
+        S[1].epoch = S[0].epoch;
+        S[1].stream = stream_create(S[1].g, R);
+        S[1].reset_rows(R);
+    } catch (...) {
+        set_last_error("no second copy of the graph: weight updates wait for the orders in flight");
+        if (S[1].stream) stream_destroy(S[1].stream);
+        S[1].stream = nullptr;
+        if (S[1].g) wr_graph_destroy(S[1].g);
+        S[1].g = nullptr;
+        S[1].owned = false;
+    }
+    set_ready(s);
+    uint32_t cur = 0;
+    std::vector<WeightBatch> waiting;   // updates taken from the queue, not applied yet
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->epoch_now = S[0].epoch;
+    }
+    auto fail_side = [&](Side &d, wr_status st) {
         std::unique_lock<std::mutex> lk(s->mu);
         const double t = clock_s();
-        for (Live &L : live) finish(s, L.r, st, t);
-        live.clear();
+        for (Live &L : d.live) finish(s, L.r, st, t);
+        d.live.clear();
         s->cv_done.notify_all();
     };
+    // the caller's graph ends at the newest accepted weights
+    auto catch_up_caller = [&]() {
+        if (!S[0].lag.empty()) {
+            (void)apply_to(S[0].g, S[0].lag);
+            S[0].lag.clear();
+        }
+    };
+    // steps one copy's rows once and retires its converged orders
+    auto step_side = [&](Side &d) {
+        const double ts0 = clock_s();
+        stream_step(d.stream, d.pending);
+        s->t_step += clock_s() - ts0;
+        for (uint32_t b = 0; b < R; ++b)
+            if (d.busy[b] && !d.pending[b]) d.busy[b] = 0;
+        std::vector<uint32_t> off(1, 0u), picks, slots;
+        std::vector<size_t> done;
+        for (size_t i = 0; i < d.live.size(); ++i) {
+            bool ok = true;
+            for (uint32_t b : d.live[i].rows) ok = ok && !d.busy[b];
+            if (!ok) continue;
+            done.push_back(i);
+            picks.insert(picks.end(), d.live[i].r->picks.begin(), d.live[i].r->picks.end());
+            slots.insert(slots.end(), d.live[i].slot.begin(), d.live[i].slot.end());
+            off.push_back(static_cast<uint32_t>(picks.size()));
+        }
+        if (done.empty()) return;
+        uint64_t total = 0;
+        for (size_t o = 0; o + 1 < off.size(); ++o)
+            total += static_cast<uint64_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
+        std::vector<uint32_t> out(total);
+        const double tg0 = clock_s();
+        stream_gather(d.stream, off, picks, slots, out.data());
+        s->t_gather += clock_s() - tg0;
+        const double t_done = clock_s();
+        std::lock_guard<std::mutex> lk(s->mu);
+        uint64_t at = 0;
+        for (size_t k = 0; k < done.size(); ++k) {
+            Live &L = d.live[done[k]];
+            const uint64_t n = static_cast<uint64_t>(L.r->picks.size()) * L.r->picks.size();
+            L.r->dist.assign(out.begin() + at, out.begin() + at + n);
+            at += n;
+            finish(s, L.r, WR_OK, t_done);
+            for (uint32_t b : L.rows)
+                if (--d.refcnt[b] == 0) d.free_rows.push_back(b);
+            L.r = nullptr;
+        }
+        d.live.erase(std::remove_if(d.live.begin(), d.live.end(), [](const Live &L) { return !L.r; }),
+                     d.live.end());
+        s->cv_done.notify_all();
+    };
+    // serving moves to step batching on the caller's graph (weights beyond
+    // the overlay tables' range): the other copy's orders finish first
+    auto to_step_mode = [&](uint32_t bad) {
+        Side &o = S[1 - bad];
+        while (o.stream && !o.live.empty()) step_side(o);
+        for (Side &d : S) {
+            if (d.stream) stream_destroy(d.stream);
+            d.stream = nullptr;
+        }
+        catch_up_caller();
+        if (S[1].owned) wr_graph_destroy(S[1].g);
+        S[1].g = nullptr;
+        run_step_mode(s);
+        return true;
+    };
     for (;;) {
-        std::vector<Request *> adm;
-        std::vector<uint32_t> rows, srcv;
+        Side &C = S[cur];
         std::vector<Live> fresh;
+        std::vector<uint32_t> rows, srcv;
+        bool admitting = true;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             const double tw0 = clock_s();
-            if (live.empty())
+            if (S[0].live.empty() && S[1].live.empty() && waiting.empty())
                 s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->updates.empty(); });
             s->t_wait += clock_s() - tw0;
-            if (s->stop && s->queue.empty() && s->updates.empty() && live.empty()) return true;
-            const bool update_waiting = !s->updates.empty();
-            if (update_waiting && live.empty()) {
-                while (!s->updates.empty()) {
-                    ups.push_back(std::move(s->updates.front()));
-                    s->updates.pop_front();
+            if (s->stop && s->queue.empty() && s->updates.empty() && waiting.empty() && S[0].live.empty() &&
+                S[1].live.empty()) {
+                lk.unlock();
+                for (Side &d : S) {
+                    if (d.stream) stream_destroy(d.stream);
+                    d.stream = nullptr;
                 }
+                catch_up_caller();
+                if (S[1].owned) wr_graph_destroy(S[1].g);
+                S[1].g = nullptr;
+                return true;
             }
-            if (!update_waiting) {
-                // admission in arrival order while free rows last; the picks
-                // of the orders admitted together share source lanes
-                std::unordered_map<uint32_t, uint32_t> slot_of;
-                std::vector<uint32_t> group;   // distinct picks of the group
-                const double now = clock_s() - s->t0;
-                while (!s->queue.empty()) {
-                    Request *r = s->queue.front();
-                    // distinct picks of the order, and those new to this group
-                    std::unordered_map<uint32_t, uint32_t> seen;
-                    uint32_t add = 0;
-                    for (uint32_t v : r->picks)
-                        if (seen.emplace(v, 0u).second && !slot_of.count(v)) ++add;
-                    if ((seen.size() + 63) / 64 > R) {
-                        // larger than the whole state: can never be admitted
-                        s->queue.pop_front();
-                        r->info.t_admit = now;
-                        finish(s, r, WR_E_NOMEM, clock_s());
-                        s->cv_done.notify_all();
-                        continue;
-                    }
-                    if ((group.size() + add + 63) / 64 > free_rows.size()) break;
-                    s->queue.pop_front();
-                    for (uint32_t v : r->picks)
-                        if (slot_of.emplace(v, 0u).second) group.push_back(v);
-                    Live L;
-                    L.r = r;
-                    r->info.t_admit = now;
-                    r->info.epoch = g->epoch;
-                    fresh.push_back(std::move(L));
-                }
-                if (!group.empty()) {
-                    // lanes in tile order: a row's sources start close together,
-                    // so their wavefronts share tile visits
-                    const std::vector<uint32_t> &tile_of = g->tiles->tile_of;
-                    const std::vector<uint64_t> &tkey = tile_order_keys(g);
-                    auto k = [&](uint32_t x) { return tile_of[x] == NONE ? ~0ull : tkey[tile_of[x]]; };
-                    std::sort(group.begin(), group.end(), [&](uint32_t x, uint32_t y) {
-                        if (k(x) != k(y)) return k(x) < k(y);
-                        if (tile_of[x] != tile_of[y]) return tile_of[x] < tile_of[y];
-                        return x < y;
-                    });
-                    const size_t nrows = (group.size() + 63) / 64;
-                    for (size_t i = 0; i < nrows; ++i) {
-                        rows.push_back(free_rows.back());
-                        free_rows.pop_back();
-                    }
-                    srcv.assign(nrows * 64, NONE);
-                    for (size_t k = 0; k < group.size(); ++k) {
-                        srcv[k] = group[k];
-                        slot_of[group[k]] = rows[k / 64] * 64 + static_cast<uint32_t>(k % 64);
-                    }
-                    for (Live &L : fresh) {
-                        for (uint32_t v : L.r->picks) L.slot.push_back(slot_of[v]);
-                        for (uint32_t sl : L.slot) L.rows.push_back(sl / 64);
-                        std::sort(L.rows.begin(), L.rows.end());
-                        L.rows.erase(std::unique(L.rows.begin(), L.rows.end()), L.rows.end());
-                    }
-                }
+            while (!s->updates.empty()) {
+                waiting.push_back(std::move(s->updates.front()));
+                s->updates.pop_front();
             }
         }
-        if (!ups.empty()) {
+        // ---- weight updates: onto the copy with nothing in flight
+        if (!waiting.empty()) {
+            const uint32_t o = 1 - cur;
             const double tu0 = clock_s();
-            apply_updates(s, ups);
-            s->t_update += clock_s() - tu0;
-            // nothing is in flight; weights beyond the overlay tables' range
-            // move serving to step batching
-            try {
-                (void)stream_bytes_per_block(g);
-            } catch (const Error &) {
-                stream_destroy(s->stream);
-                s->stream = nullptr;
-                run_step_mode(s);
-                return true;
+            uint32_t target = NONE;
+            if (S[o].g && S[o].live.empty())
+                target = o;
+            else if (!S[o].g && C.live.empty())
+                target = cur;
+            if (target != NONE) {
+                Side &T = S[target];
+                std::vector<WeightBatch> todo = std::move(T.lag);
+                T.lag.clear();
+                const size_t nlag = todo.size();
+                for (WeightBatch &u : waiting) todo.push_back(std::move(u));
+                waiting.clear();
+                std::vector<WeightBatch> ok = apply_to(T.g, todo);
+                // the lag had been accepted before; the new batches count
+                const uint64_t fresh_n = ok.size() >= nlag ? ok.size() - nlag : 0;
+                if (target != cur) {
+                    for (size_t k = nlag; k < ok.size(); ++k) S[cur].lag.push_back(ok[k]);
+                    T.epoch = C.epoch + fresh_n;
+                    if (fresh_n) cur = target;
+                } else {
+                    T.epoch += fresh_n;
+                }
+                s->t_update += clock_s() - tu0;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    s->epoch_now = S[cur].epoch;
+                }
+                try {
+                    (void)stream_bytes_per_block(T.g);
+                } catch (const Error &) {
+                    return to_step_mode(target);
+                }
+            } else if (!S[o].g) {
+                admitting = false;   // one copy: admission waits for the rows in flight
+            }
+        }
+        Side &A = S[cur];
+        // ---- admission in arrival order while free rows last; the picks of
+        // the orders admitted together share source lanes
+        if (admitting) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            std::unordered_map<uint32_t, uint32_t> slot_of;
+            std::vector<uint32_t> group;   // distinct picks of the group
+            const double now = clock_s() - s->t0;
+            while (!s->queue.empty()) {
+                Request *r = s->queue.front();
+                std::unordered_map<uint32_t, uint32_t> seen;
+                uint32_t add = 0;
+                for (uint32_t v : r->picks)
+                    if (seen.emplace(v, 0u).second && !slot_of.count(v)) ++add;
+                if ((seen.size() + 63) / 64 > R) {
+                    // larger than the whole state: can never be admitted
+                    s->queue.pop_front();
+                    r->info.t_admit = now;
+                    finish(s, r, WR_E_NOMEM, clock_s());
+                    s->cv_done.notify_all();
+                    continue;
+                }
+                if ((group.size() + add + 63) / 64 > A.free_rows.size()) break;
+                s->queue.pop_front();
+                for (uint32_t v : r->picks)
+                    if (slot_of.emplace(v, 0u).second) group.push_back(v);
+                Live L;
+                L.r = r;
+                r->info.t_admit = now;
+                r->info.epoch = A.epoch;
+                fresh.push_back(std::move(L));
+            }
+            if (!group.empty()) {
+                // lanes in tile order: a row's sources start close together,
+                // so their wavefronts share tile visits
+                const std::vector<uint32_t> &tile_of = A.g->tiles->tile_of;
+                const std::vector<uint64_t> &tkey = tile_order_keys(A.g);
+                auto k = [&](uint32_t x) { return tile_of[x] == NONE ? ~0ull : tkey[tile_of[x]]; };
+                std::sort(group.begin(), group.end(), [&](uint32_t x, uint32_t y) {
+                    if (k(x) != k(y)) return k(x) < k(y);
+                    if (tile_of[x] != tile_of[y]) return tile_of[x] < tile_of[y];
+                    return x < y;
+                });
+                const size_t nrows = (group.size() + 63) / 64;
+                for (size_t i = 0; i < nrows; ++i) {
+                    rows.push_back(A.free_rows.back());
+                    A.free_rows.pop_back();
+                }
+                srcv.assign(nrows * 64, NONE);
+                for (size_t k = 0; k < group.size(); ++k) {
+                    srcv[k] = group[k];
+                    slot_of[group[k]] = rows[k / 64] * 64 + static_cast<uint32_t>(k % 64);
+                }
+                for (Live &L : fresh) {
+                    for (uint32_t v : L.r->picks) L.slot.push_back(slot_of[v]);
+                    for (uint32_t sl : L.slot) L.rows.push_back(sl / 64);
+                    std::sort(L.rows.begin(), L.rows.end());
+                    L.rows.erase(std::unique(L.rows.begin(), L.rows.end()), L.rows.end());
+                }
             }
         }
         bool admitted = fresh.empty();   // the orders taken from the queue are in flight
+        uint32_t stepping = cur;
         try {
             if (!rows.empty()) {
                 const double ta0 = clock_s();
-                stream_admit(s->stream, rows, srcv);
+                stream_admit(A.stream, rows, srcv);
                 s->t_admit += clock_s() - ta0;
                 s->rows_admitted += rows.size();
-                for (uint32_t b : rows) busy[b] = 1;
+                for (uint32_t b : rows) A.busy[b] = 1;
                 for (Live &L : fresh) {
-                    for (uint32_t b : L.rows) ++refcnt[b];
-                    live.push_back(std::move(L));
+                    for (uint32_t b : L.rows) ++A.refcnt[b];
+                    A.live.push_back(std::move(L));
                 }
             }
             admitted = true;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
-                s->max_inflight = std::max<uint32_t>(s->max_inflight, static_cast<uint32_t>(live.size()));
+                s->max_inflight = std::max<uint32_t>(
+                    s->max_inflight, static_cast<uint32_t>(S[0].live.size() + S[1].live.size()));
             }
-            if (live.empty()) continue;
-            const double ts0 = clock_s();
-            stream_step(s->stream, pending);
-            s->t_step += clock_s() - ts0;
-            for (uint32_t b = 0; b < R; ++b)
-                if (busy[b] && !pending[b]) busy[b] = 0;
-            // retire the orders whose rows have all converged
-            std::vector<uint32_t> off(1, 0u), picks, slots;
-            std::vector<size_t> done;
-            for (size_t i = 0; i < live.size(); ++i) {
-                bool ok = true;
-                for (uint32_t b : live[i].rows) ok = ok && !busy[b];
-                if (!ok) continue;
-                done.push_back(i);
-                picks.insert(picks.end(), live[i].r->picks.begin(), live[i].r->picks.end());
-                slots.insert(slots.end(), live[i].slot.begin(), live[i].slot.end());
-                off.push_back(static_cast<uint32_t>(picks.size()));
+            // one step of each copy with rows in flight, the older epoch first
+            bool stepped = false;
+            for (uint32_t k = 0; k < 2; ++k) {
+                stepping = (cur + 1 + k) % 2;
+                if (S[stepping].stream && !S[stepping].live.empty()) {
+                    step_side(S[stepping]);
+                    stepped = true;
+                }
             }
-            {
+            if (stepped) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 ++s->steps;
             }
-            if (done.empty()) continue;
-            uint64_t total = 0;
-            for (size_t o = 0; o + 1 < off.size(); ++o)
-                total += static_cast<uint64_t>(off[o + 1] - off[o]) * (off[o + 1] - off[o]);
-            std::vector<uint32_t> out(total);
-            const double tg0 = clock_s();
-            stream_gather(s->stream, off, picks, slots, out.data());
-            s->t_gather += clock_s() - tg0;
-            const double t_done = clock_s();
-            std::lock_guard<std::mutex> lk(s->mu);
-            uint64_t at = 0;
-            for (size_t k = 0; k < done.size(); ++k) {
-                Live &L = live[done[k]];
-                const uint64_t n = static_cast<uint64_t>(L.r->picks.size()) * L.r->picks.size();
-                L.r->dist.assign(out.begin() + at, out.begin() + at + n);
-                at += n;
-                finish(s, L.r, WR_OK, t_done);
-                for (uint32_t b : L.rows)
-                    if (--refcnt[b] == 0) free_rows.push_back(b);
-                L.r = nullptr;
-            }
-            live.erase(std::remove_if(live.begin(), live.end(), [](const Live &L) { return !L.r; }), live.end());
-            s->cv_done.notify_all();
         } catch (const Error &e) {
-            // a failed step fails the orders in flight (and those it was
-            // admitting) and the state is built afresh; serving goes on (in
-            // step batching if that fails too)
+            // a failed step fails the orders in flight on that copy (and those
+            // being admitted), and its state is built afresh; serving goes on
+            // (in step batching if that fails too)
             set_last_error(e.msg);
             if (!admitted) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 const double t = clock_s();
                 for (Live &L : fresh) finish(s, L.r, e.st, t);
+                stepping = cur;
             }
-            fail_all(e.st);
-            std::fill(refcnt.begin(), refcnt.end(), 0u);
-            std::fill(busy.begin(), busy.end(), 0);
-            free_rows.clear();
-            for (uint32_t b = R; b-- > 0;) free_rows.push_back(b);
-            stream_destroy(s->stream);
-            s->stream = nullptr;
+            Side &d = S[stepping];
+            fail_side(d, e.st);
+            d.reset_rows(R);
+            stream_destroy(d.stream);
+            d.stream = nullptr;
             try {
-                s->stream = stream_create(g, R);
+                d.stream = stream_create(d.g, R);
             } catch (const Error &) {
-                run_step_mode(s);
-                return true;
+                if (stepping == 0 && !S[1].g) return to_step_mode(0);
+                // serve on the other copy alone, or on the caller's graph
+                fail_side(S[1 - stepping], e.st);
+                return to_step_mode(stepping);
             }
         }
     }
@@ -433,10 +607,17 @@ wr_status wr_server_create(wr_graph *g, const wr_server_opts *opts, wr_server **
     if (!s->opts.max_source_slots) s->opts.max_source_slots = 8192;
     if (!s->opts.max_queue) s->opts.max_queue = 65536;
     if (s->opts.passes_per_step) g->passes_per_replay = std::max(2u, s->opts.passes_per_step & ~1u);
+    if (s->opts.resident_epochs > 2) fail(WR_E_INVALID, "resident_epochs must be 0, 1 or 2");
     s->budget = s->opts.mem_budget_bytes ? s->opts.mem_budget_bytes : g->ctx->available();
+    s->epoch_now = g->epoch;
     s->t0 = clock_s();
     wr_server *raw = s.get();
     s->worker = std::thread(scheduler, raw);
+    {
+        // serving starts once the scheduler has built its state
+        std::unique_lock<std::mutex> lk(raw->mu);
+        raw->cv_done.wait(lk, [&] { return raw->ready; });
+    }
     *out = s.release();
     WR_API_END
 }
@@ -466,7 +647,7 @@ wr_status wr_server_submit(wr_server *srv, uint32_t P, const uint32_t *picks, ui
         if (P == 0) {
             // nothing to relax: done at once on the current epoch
             raw->info.t_admit = now;
-            raw->info.epoch = srv->g->epoch;
+            raw->info.epoch = srv->epoch_now;
             finish(srv, raw, WR_OK, clock_s());
             srv->cv_done.notify_all();
         } else {
@@ -559,7 +740,6 @@ wr_status wr_server_destroy(wr_server *srv) {
         srv->cv_work.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
-    if (srv->stream) stream_destroy(srv->stream);
     if (std::getenv("WR_TRACE"))
         std::fprintf(stderr,
                      "[wroute server] steps %llu rows admitted %llu | seconds: update %.3f admit %.3f "

@@ -100,22 +100,45 @@ int main(int argc, char **argv) {
         const uint32_t no = rd();
         auto off = rdv(no + 1);
         auto picks = rdv(off[no]);
+        // weight updates: count, then per update its arcs, weights and the
+        // number of orders submitted before it
+        const uint32_t nupd = rd();
+        std::vector<std::vector<uint32_t>> ua_(nupd), uw_(nupd);
+        std::vector<uint32_t> after(nupd);
+        for (uint32_t k = 0; k < nupd; ++k) {
+            const uint32_t n = rd();
+            ua_[k] = rdv(n);
+            uw_[k] = rdv(n);
+            after[k] = rd();
+        }
         wr_server *srv = nullptr;
         wr_server_opts opts{};
         opts.max_source_slots = 128;
+        opts.resident_epochs = nupd ? 2 : 1;
         if (st == WR_OK) st = wr_server_create(g, &opts, &srv);
         std::vector<uint64_t> tickets(no);
         for (uint32_t o = 0; o < no && st == WR_OK; ++o) {
-            st = wr_server_submit(srv, off[o + 1] - off[o], picks.data() + off[o], &tickets[o]);
+            for (uint32_t k = 0; k < nupd && st == WR_OK; ++k)
+                if (after[k] == o)
+                    st = wr_server_update_weights(srv, static_cast<uint32_t>(ua_[k].size()), ua_[k].data(),
+                                                  uw_[k].data());
+            if (st == WR_OK) st = wr_server_submit(srv, off[o + 1] - off[o], picks.data() + off[o], &tickets[o]);
+            // the first order is done before the others arrive (the server's
+            // rows are built by then)
+            if (st == WR_OK && o == 0 && nupd) st = wr_server_drain(srv);
             std::this_thread::sleep_for(std::chrono::milliseconds(flags));
         }
         if (st == WR_OK) st = wr_server_drain(srv);
+        std::vector<uint32_t> epochs;
         for (uint32_t o = 0; o < no && st == WR_OK; ++o) {
             const uint32_t P = off[o + 1] - off[o];
             std::vector<uint32_t> m(static_cast<size_t>(P) * P);
-            st = wr_server_poll(srv, tickets[o], m.data(), nullptr);
+            wr_req_info info{};
+            st = wr_server_poll(srv, tickets[o], m.data(), &info);
             out.insert(out.end(), m.begin(), m.end());
+            epochs.push_back(static_cast<uint32_t>(info.epoch));
         }
+        out.insert(out.end(), epochs.begin(), epochs.end());
         wr_stats ss{};
         if (srv) wr_server_stats(srv, &ss);
         std::fprintf(stderr, "server: completed %llu steps %llu max_inflight %u\n",

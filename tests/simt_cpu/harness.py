@@ -23,10 +23,12 @@ def driver(rebuild=False) -> str:
 
 def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="auto",
         pred=False, graph_capture=True, seg=None, schedule=(0, 0, 0), updates=None, timeout=600,
-        server_gap_ms=None, routes=False, clustered=None):
+        server_gap_ms=None, server_updates=(), routes=False, clustered=None):
     """seg: None | ("grid", W, H, L, tw, th) | ("map", nseg, map).  With
     server_gap_ms the orders go through the request server, one every
-    server_gap_ms milliseconds.  With routes=True the order matrices are
+    server_gap_ms milliseconds, with server_updates = [(arcs, weights,
+    orders submitted before it), ...] queued on the way; the matrices are
+    then followed by each order's epoch.  With routes=True the order matrices are
     followed by wr_order_routes over them: per order its length (two words,
     low first), then the orderings; clustered=(m, positions) does the same
     with wr_order_routes_clustered and appends the clusters used.  Returns
@@ -59,10 +61,17 @@ def run(row_ptr, col, w, *, sources=None, pick_offsets=None, picks=None, algo="a
         off = np.asarray(pick_offsets, np.uint32)
         pk = np.asarray(picks, np.uint32)
         parts += [np.asarray([len(off) - 1], np.uint32), off, pk]
+        if mode == 2:
+            parts.append(np.asarray([len(server_updates)], np.uint32))
+            for ua_, uw_, after in server_updates:
+                parts += [np.asarray([len(ua_)], np.uint32), np.asarray(ua_, np.uint32),
+                          np.asarray(uw_, np.uint32), np.asarray([after], np.uint32)]
         if clustered is not None:   # (m, positions int32[2 * picks])
             parts += [np.asarray([clustered[0]], np.uint32), np.asarray(clustered[1], np.int32).view(np.uint32).ravel()]
         sizes = np.diff(off.astype(np.int64))
         n_out = int((sizes ** 2).sum())
+        if mode == 2:   # matrices, then each order's epoch
+            n_out += len(off) - 1
         if routes:   # matrices, then (length lo, hi) per order, then orderings
             n_out += 2 * (len(off) - 1) + len(pk)
         if clustered is not None:   # ... and the clusters each order used

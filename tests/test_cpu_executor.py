@@ -184,3 +184,45 @@ def case_warehouse_loop(harness):
         eA, eM, esil, earea, emv = wms.run(s, 0)
         assert (A[0] == eA).all() and (M[0] == eM).all() and (moves[0] == emv).all()
         assert (sil[0] == esil).all() and (area[0] == earea).all()
+
+
+@case
+def case_server_two_epochs(harness):
+    """The streaming server with two resident weight epochs
+    (resident_epochs = 2: the scheduler
+    thread, row admission, both copies' steps and read-outs, the copy of the
+    graph made at the server's start): after a first order, orders arrive one
+    every 20 ms with two updates between them; every order's matrix equals
+    the oracle's at the weights of the epoch it reports, and the epochs never
+    go back."""
+    wl = make_config("medium", side=16, num_orders=1)
+    g = wl.graph
+    rng = np.random.default_rng(12)
+    cand = g.aisle_adjacent_vertices()
+    picks = np.concatenate([rng.choice(cand, 6, replace=False) for _ in range(6)]).astype(np.uint32)
+    off = np.arange(7, dtype=np.uint32) * 6
+    ups, weights = [], [g.w.copy()]
+    for after in (2, 4):
+        arcs = rng.choice(g.E, g.E // 10, replace=False).astype(np.uint32)
+        nw = rng.integers(1, 20, len(arcs)).astype(np.uint32)
+        ups.append((arcs, nw, after))
+        w = weights[-1].copy()
+        w[arcs] = nw
+        weights.append(w)
+    st, out, _, err = harness.run(g.row_ptr, g.col, g.w, pick_offsets=off, picks=picks,
+                                  seg=("grid", g.W, g.H, 1, 8, 8), server_gap_ms=20, server_updates=ups)
+    assert st == 0, err[-2000:]
+    n = len(off) - 1
+    epochs = out[-n:].astype(np.int64)
+    # orders are solved on the epoch current at their admission, which may
+    # come after updates queued behind them (the executor's steps are slow)
+    assert (np.diff(epochs) >= 0).all() and epochs[-1] <= 2
+    assert epochs[0] == 0 and (epochs[2:] >= 1).all()
+    base = 0
+    for o in range(n):
+        P = int(off[o + 1] - off[o])
+        D = out[base:base + P * P].reshape(P, P)
+        base += P * P
+        pk = picks[off[o]:off[o + 1]]
+        exp = oracle.order_matrices(g.row_ptr, g.col, weights[epochs[o]], np.array([0, P], np.uint32), pk)
+        assert (D.ravel() == exp).all(), f"order {o} epoch {epochs[o]}"

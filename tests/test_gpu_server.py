@@ -98,11 +98,12 @@ def test_server_empty_order_and_duplicates(rt, ctx):
         srv.close()
 
 
-def test_server_weight_epochs(rt, ctx):
+@pytest.mark.parametrize("resident", [1, 2])
+def test_server_weight_epochs(rt, ctx, resident):
     wl, G = _small(rt, ctx, side=40, orders=6)
     g = wl.graph
     orders = _orders(wl)
-    srv = rt.Server(G)
+    srv = rt.Server(G, resident_epochs=resident)
     try:
         t_before = [srv.submit(pk) for pk in orders[:3]]
         first = _wait(srv, t_before)
@@ -205,3 +206,73 @@ def test_server_admits_while_others_relax(rt, ctx):
         assert srv.stats()["max_inflight_requests"] > 1
     finally:
         srv.close()
+
+
+def _expect_many(g, orders, w):
+    """Oracle matrices of several orders at weights w (one call)."""
+    off = np.concatenate([[0], np.cumsum([len(o) for o in orders])]).astype(np.uint32)
+    flat = oracle.order_matrices(g.row_ptr, g.col, w, off, np.concatenate(orders).astype(np.uint32))
+    res, base = [], 0
+    for o in orders:
+        P = len(o)
+        res.append(flat[base:base + P * P].reshape(P, P))
+        base += P * P
+    return res
+
+
+def test_server_ticks_mid_flight_full_graph(rt, ctx):
+    """Two weight epochs resident, on the full serving graph (3 x 1024^2 with
+    lifts): orders in flight when a congestion tick (1 % of the arcs) arrives
+    finish on their epoch while the orders after it run on the new one, and a
+    second tick right after waits for a copy with nothing in flight; every
+    order's matrix equals the oracle's at its own epoch's weights."""
+    from bench import graph_for
+    wl = make_config("serving")
+    g = wl.graph
+    G, _ = graph_for(rt, ctx, wl, tune=False)
+    rng = np.random.default_rng(91)
+    cand = g.aisle_adjacent_vertices()
+    pick = lambda P: cand[rng.choice(len(cand), P, replace=False)].astype(np.uint32)
+    batches = [[pick(96) for _ in range(3)], [pick(8) for _ in range(3)], [pick(6) for _ in range(2)]]
+    weights = [g.w.copy()]
+    srv = rt.Server(G, resident_epochs=2)
+    try:
+        # the server is up (its rows built) before the batches arrive, and
+        # its epoch before any update is that of a 0-pick order
+        e0 = _wait(srv, [srv.submit(np.zeros(0, np.uint32))])
+        e0 = next(iter(e0.values()))[1]["epoch"]
+        _wait(srv, [srv.submit(pick(2))])
+        tickets = [[srv.submit(o) for o in batches[0]]]
+        time.sleep(0.01)
+        for k in (1, 2):
+            arcs = rng.choice(g.E, g.E // 100, replace=False).astype(np.uint32)
+            new_w = rng.integers(1, 11, len(arcs)).astype(np.uint32)
+            srv.update_weights(arcs, new_w)
+            w = weights[-1].copy()
+            w[arcs] = new_w
+            weights.append(w)
+            tickets.append([srv.submit(o) for o in batches[k]])
+        res = _wait(srv, [t for ts in tickets for t in ts], timeout=300.0)
+    finally:
+        srv.close()
+    e_base = e0
+    infos = {t: res[t][1] for ts in tickets for t in ts}
+    # every order on one of the three epochs, and not older than its submission
+    for k, ts in enumerate(tickets):
+        for t in ts:
+            assert e_base <= infos[t]["epoch"] <= e_base + 2
+            assert infos[t]["epoch"] >= e_base + (k if k == 0 else 1)
+    # both epochs in flight at once: an order of the first epoch finished
+    # after an order of a later epoch had been admitted
+    first = [infos[t] for t in tickets[0] if infos[t]["epoch"] == e_base]
+    later = [i for i in infos.values() if i["epoch"] > e_base]
+    assert first and later
+    assert max(i["t_done"] for i in first) > min(i["t_admit"] for i in later)
+    for k, ts in enumerate(tickets):
+        for e in range(3):
+            sel = [i for i, t in enumerate(ts) if infos[t]["epoch"] == e_base + e]
+            if not sel:
+                continue
+            exp = _expect_many(g, [batches[k][i] for i in sel], weights[e])
+            for i, E in zip(sel, exp):
+                assert (res[ts[i]][0] == E).all(), f"batch {k} order {i} epoch {e}"
