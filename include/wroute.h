@@ -23,8 +23,10 @@
  *    free them.  Outputs go to caller-provided buffers.  Handles are opaque
  *    and freed by their *_destroy function (NULL is accepted and ignored).
  *  - Host vs device buffers: index inputs (sources, pick_offsets, picks,
- *    segment maps, weight updates) are always host pointers, because the
- *    batch plan is made on the host.  Output buffers (dist, pred, dist_out,
+ *    segment maps, weight updates) are host pointers, because the batch
+ *    plan is made on the host; with WR_DEVICE_INDEX the sources, offsets
+ *    and picks of wr_sssp / wr_order_matrices may be device pointers, which
+ *    the call reads back after the caller's earlier work on `stream`.  Output buffers (dist, pred, dist_out,
  *    pred_out) are host pointers unless WR_DEVICE_PTRS is set, in which case
  *    they are device pointers (for example torch's data_ptr()) and the
  *    results are written by work enqueued on `stream` (a hipStream_t, NULL =
@@ -80,6 +82,11 @@ typedef enum wr_status {
 #define WR_PRUNE_TO_PICKS   0x0800u  /* wr_order_matrices, overlay schedule: stop each source's
                                         relaxation beyond the farthest pick it is paired with
                                         (exact for the matrices; see wr_order_matrices) */
+#define WR_DEVICE_INDEX     0x1000u  /* wr_sssp sources / wr_order_matrices pick_offsets and
+                                        picks are device pointers: copied to the host on
+                                        `stream` after the caller's earlier work there (the
+                                        call waits for that work; it still returns after
+                                        convergence) */
 
 /* ---- opaque handles -------------------------------------------------- */
 typedef struct wr_context wr_context;

@@ -26,6 +26,7 @@ NO_GRAPH_CAPTURE = 0x0100
 TIME_KERNELS = 0x0200
 ROUTE_ENUMERATE = 0x0400
 PRUNE_TO_PICKS = 0x0800
+DEVICE_INDEX = 0x1000
 
 STATUS = {0: "WR_OK", 1: "WR_E_INVALID", 2: "WR_E_RANGE", 3: "WR_E_NOMEM", 4: "WR_E_DEVICE",
           5: "WR_E_UNSUPPORTED", 6: "WR_E_BUSY", 7: "WR_E_INTERNAL"}
@@ -50,6 +51,10 @@ def _check(rc: int):
 
 def _u32(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "data_ptr") and getattr(a, "is_cuda", False)
 
 
 def _ptr(a) -> ctypes.c_void_p | None:
@@ -276,9 +281,17 @@ class Graph:
         """Distances [S, V] (uint32, source-major); with pred=True also the
         canonical predecessors.  `out`/`pred_out` may be torch CUDA tensors
         of S*V 32-bit elements, in which case results stay on the device."""
+        flags = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
+        if _is_device(sources):
+            # device sources: read back after the work queued on their stream
+            if out is None:
+                raise ValueError("device sources need a device `out`")
+            S = int(sources.numel())
+            _check(lib().wr_sssp(self.h, S, _ptr(sources), _ptr(out), _ptr(pred_out),
+                                 flags | DEVICE_PTRS | DEVICE_INDEX, _stream_of(out)))
+            return out, pred_out
         src = _u32(sources)
         S = len(src)
-        flags = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
         if out is not None:
             flags |= DEVICE_PTRS
             stream = _stream_of(out)
@@ -294,7 +307,20 @@ class Graph:
                        time_kernels: bool = False, prune: bool = False):
         """Concatenated per-order P x P matrices (uint32); with pred=True also
         the predecessor row of every pick ([total picks, V]).  prune=True
-        sets WR_PRUNE_TO_PICKS."""
+        sets WR_PRUNE_TO_PICKS.  pick_offsets and picks may be torch CUDA
+        tensors (WR_DEVICE_INDEX) when `out` is one too: the call reads them
+        after the work queued on the current stream."""
+        flags0 = ALGO[algo] | (0 if graph_capture else NO_GRAPH_CAPTURE)
+        flags0 |= TIME_KERNELS if time_kernels else 0
+        flags0 |= PRUNE_TO_PICKS if prune else 0
+        if _is_device(pick_offsets) or _is_device(picks):
+            if out is None or not (_is_device(pick_offsets) and _is_device(picks)):
+                raise ValueError("device pick_offsets need device picks and a device `out`")
+            n = int(pick_offsets.numel()) - 1
+            _check(lib().wr_order_matrices(self.h, n, _ptr(pick_offsets), _ptr(picks), _ptr(out),
+                                           _ptr(pred_out), flags0 | DEVICE_PTRS | DEVICE_INDEX,
+                                           _stream_of(out)))
+            return out, pred_out
         off, pk = _u32(pick_offsets), _u32(picks)
         n = len(off) - 1
         sizes = np.diff(off.astype(np.int64))

@@ -900,6 +900,18 @@ void emit_rows(wr_graph *g, uint32_t algo, uint32_t rows, const uint32_t *d_row_
                const std::vector<uint32_t> &row_idx, const std::vector<uint32_t> &row_vertex,
                const std::vector<uint32_t> &out_row);
 
+// Index arrays given as device pointers (WR_DEVICE_INDEX): read back on the
+// caller's stream, so the values its earlier work wrote are the ones read.
+std::vector<uint32_t> fetch_index(const uint32_t *d, size_t n, void *stream) {
+    std::vector<uint32_t> h(n);
+    if (!n) return h;
+    if (!d) fail(WR_E_INVALID, "an index array is NULL");
+    hipStream_t us = static_cast<hipStream_t>(stream);
+    WR_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(uint32_t), hipMemcpyDeviceToHost, us));
+    WR_HIP(hipStreamSynchronize(us));
+    return h;
+}
+
 struct StreamJoin {
     // The library works on its own stream; with caller (device) buffers it
     // first waits for the caller's stream so earlier work on them is done.
@@ -1206,6 +1218,12 @@ wr_status wr_sssp(wr_graph *g, uint32_t S, const uint32_t *sources, uint32_t *di
     if (!g) fail(WR_E_INVALID, "graph is NULL");
     if (S == 0) return WR_OK;
     if (!sources || !dist) fail(WR_E_INVALID, "sources or dist is NULL");
+    std::vector<uint32_t> h_src;
+    if (flags & WR_DEVICE_INDEX) {
+        WR_HIP(hipSetDevice(g->ctx->device));
+        h_src = fetch_index(sources, S, stream);
+        sources = h_src.data();
+    }
     if (flags & WR_PRUNE_TO_PICKS) fail(WR_E_INVALID, "WR_PRUNE_TO_PICKS applies to wr_order_matrices only");
     for (uint32_t i = 0; i < S; ++i)
         if (sources[i] >= g->V) fail(WR_E_INVALID, "source out of range");
@@ -1327,6 +1345,13 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
     if (!g) fail(WR_E_INVALID, "graph is NULL");
     if (num_orders == 0) return WR_OK;
     if (!pick_offsets) fail(WR_E_INVALID, "pick_offsets is NULL");
+    const bool dev_index = (flags & WR_DEVICE_INDEX) != 0;
+    std::vector<uint32_t> h_off, h_picks;
+    if (dev_index) {
+        WR_HIP(hipSetDevice(g->ctx->device));
+        h_off = fetch_index(pick_offsets, static_cast<size_t>(num_orders) + 1, stream);
+        pick_offsets = h_off.data();
+    }
     if (pick_offsets[0] != 0) fail(WR_E_INVALID, "pick_offsets[0] must be 0");
     uint64_t total = 0;
     std::vector<uint64_t> out_base(num_orders);
@@ -1339,6 +1364,10 @@ wr_status wr_order_matrices(wr_graph *g, uint32_t num_orders, const uint32_t *pi
     const uint32_t NPK = pick_offsets[num_orders];
     if (NPK == 0) return WR_OK;
     if (!picks || !dist_out) fail(WR_E_INVALID, "picks or dist_out is NULL");
+    if (dev_index) {
+        h_picks = fetch_index(picks, NPK, stream);
+        picks = h_picks.data();
+    }
     for (uint32_t k = 0; k < NPK; ++k)
         if (picks[k] >= g->V) fail(WR_E_INVALID, "pick out of range");
     if (pred_out && g->zero_w) fail(WR_E_UNSUPPORTED, "predecessors need every weight >= 1");
