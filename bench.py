@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--serve-epochs", default="1,2",
                     help="resident weight epochs of the server to run every rate with, comma-separated")
     ap.add_argument("--route-stops", type=int, default=12, help="stops per route in the exact-route leg")
-    ap.add_argument("--wms-runs", default="4096,1024",
+    ap.add_argument("--wms-runs", default="4096,1792",
                     help="runs per batch of the warehouse-loop leg: 10x10x10 and 100x100x10 warehouses")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device once (a dispatch of known "

@@ -359,9 +359,10 @@ wr_status wr_order_routes_clustered(wr_context *ctx, uint32_t num_orders, const 
  * Every buffer is host memory, or device memory with WR_DEVICE_PTRS (then
  * the work runs after the caller's earlier work on `stream`).  The call
  * returns when the results are written.
- * Limits: nx, ny <= 2048, nz <= 32, V < 2^24, nx * ny * (2 if nz <= 16 else
- * 4) <= 65536 bytes of rack masks, purchase_orders <= 64, S <= 1024,
- * clusters <= 10, S * max(nx, ny) <= 2^19.
+ * Limits: nx, ny <= 2048, nz <= 32, V < 2^24, rack masks of
+ * 4 * ceil(nx * ny / m) <= 65536 bytes (m = 3 racks per word for nz <= 10,
+ * 2 for nz <= 16, else 1), purchase_orders <= 64, S <= 1024, clusters <= 10,
+ * S * max(nx, ny) <= 2^19.
  * Errors: WR_E_INVALID (NULL, a parameter out of range, an article number
  * above n_articles or stored twice, an order's article not stored),
  * WR_E_RANGE (a slot of more than mmax parcels; host buffers only -- with

@@ -62,11 +62,12 @@ __device__ __forceinline__ uint64_t centre_d2(uint32_t i, uint32_t j, int32_t sx
     return static_cast<uint64_t>(ax) * ax + static_cast<uint64_t>(ay) * ay;
 }
 
-// Empty shelves of rack r: MPW masks of 32 / MPW bits per 4-byte LDS word.
+// Empty shelves of rack r: MPW masks of 32 / MPW bits per 4-byte LDS word
+// (MPW = 1, 2, 3 for up to 32, 16, 10 shelves).
 template <uint32_t MPW>
 __device__ __forceinline__ uint32_t rack_mask(const uint32_t *mword, uint32_t r) {
     if constexpr (MPW == 1) return mword[r];
-    else return (mword[r >> 1] >> ((r & 1u) * 16u)) & 0xFFFFu;
+    else return (mword[r / MPW] >> ((32u / MPW) * (r % MPW))) & ((1u << (32u / MPW)) - 1u);
 }
 template <uint32_t MPW>
 __device__ __forceinline__ uint32_t rack_bit(uint32_t r, uint32_t k) {
@@ -487,10 +488,10 @@ __global__ __launch_bounds__(64) void k_wms(WmsArgs P) {
     }
 }
 
-uint32_t wms_lds_bytes(uint32_t S, uint32_t H, uint32_t racks, uint32_t mask_bytes) {
+uint32_t wms_lds_bytes(uint32_t S, uint32_t H, uint32_t mask_words) {
     const uint32_t fixed = (3 * WMS_KMAX + WMS_KMAX + WMS_POMAX) * 8;
     const uint32_t words = 5 * S + 3 * H + 2 * WMS_POMAX + WMS_POMAX + 3 * WMS_KMAX;
-    return fixed + words * 4 + ((racks * mask_bytes + 3) / 4) * 4;
+    return fixed + (words + mask_words) * 4;
 }
 
 }  // namespace
@@ -510,10 +511,12 @@ extern "C" wr_status wr_wms_run(wr_context *ctx, const wr_wms_params *p, uint32_
     if (P.nz < 1 || P.nz > 32) fail(WR_E_INVALID, "nz must be in 1..32");
     const uint64_t racks = static_cast<uint64_t>(P.nx) * P.ny, V = racks * P.nz;
     if (V >= (1u << 24)) fail(WR_E_UNSUPPORTED, "at most 2^24 - 1 nodes");
-    const uint32_t mask_bytes = P.nz <= 16 ? 2 : 4;
-    if (racks * mask_bytes > WMS_MASK_BYTES)
-        fail(WR_E_UNSUPPORTED, "the racks' empty-shelf masks must fit 64 KiB of LDS (nx * ny * " +
-                                   std::to_string(mask_bytes) + " bytes)");
+    // racks per 4-byte mask word: three of 10 bits, two of 16, or one
+    const uint32_t mpw = P.nz <= 10 ? 3 : (P.nz <= 16 ? 2 : 1);
+    const uint64_t mask_words = (racks + mpw - 1) / mpw;
+    if (mask_words * 4 > WMS_MASK_BYTES)
+        fail(WR_E_UNSUPPORTED, "the racks' empty-shelf masks must fit 64 KiB of LDS (" +
+                                   std::to_string(mpw) + " racks per 4 bytes)");
     if (P.n_articles < 1 || P.n_articles >= (1u << 24)) fail(WR_E_INVALID, "n_articles must be in 1..2^24-1");
     if (P.mmax < 1 || P.mmax > (1u << 30)) fail(WR_E_INVALID, "mmax must be in 1..2^30");
     if (P.purchase_orders < 1 || P.purchase_orders > WMS_POMAX)
@@ -608,9 +611,11 @@ extern "C" wr_status wr_wms_run(wr_context *ctx, const wr_wms_params *p, uint32_
         a.area = d_area.p;
         a.moves = d_mov.p;
     }
-    const uint32_t lds = wms_lds_bytes(S, H, static_cast<uint32_t>(racks), mask_bytes);
+    const uint32_t lds = wms_lds_bytes(S, H, static_cast<uint32_t>(mask_words));
     if (fault_launch_now()) fail(WR_E_DEVICE, "injected launch failure (wms)");
-    if (mask_bytes == 2)
+    if (mpw == 3)
+        hipLaunchKernelGGL(k_wms<3>, runs, 64, lds, st, a);
+    else if (mpw == 2)
         hipLaunchKernelGGL(k_wms<2>, runs, 64, lds, st, a);
     else
         hipLaunchKernelGGL(k_wms<1>, runs, 64, lds, st, a);

@@ -58,18 +58,16 @@ def make_wms(seed: int, nx: int, ny: int, nz: int, empty_racks: int, runs: int, 
         racks = rng.choice(nx * ny, size=empty_racks, replace=False)
         empty = np.zeros(nx * ny, bool)
         empty[racks] = True
-        node_rack = np.arange(V) % (nx * ny)
-        full = np.flatnonzero(~empty[node_rack])
-        A0[r, full] = rng.permutation(N) + 1
-        M0[r, full] = mmax
+        full = ~np.tile(empty, nz)     # node v = k * (nx * ny) + rack
+        A0[r][full] = rng.permutation(N) + 1
+        M0[r][full] = mmax
         base = rng.choice(N, size=P, replace=False) + 1
         qty[r] = rng.integers(1, mmax + 1, size=qty[r].shape)
-        for it in range(iters):
-            o = base.copy().reshape(po, per_po)
-            if experiment == 2:
-                o[:, 0] = rng.integers(1, N + 1, size=po)
-            elif experiment == 3:
-                slot = rng.integers(0, per_po, size=po)
-                o[np.arange(po), slot] = rng.integers(1, N + 1, size=po)
-            orders[r, it] = o.reshape(-1)
+        o = np.broadcast_to(base.reshape(1, po, per_po), (iters, po, per_po)).copy()
+        if experiment == 2:
+            o[:, :, 0] = rng.integers(1, N + 1, size=(iters, po))
+        elif experiment == 3:
+            slot = rng.integers(0, per_po, size=(iters, po))
+            o[np.arange(iters)[:, None], np.arange(po)[None, :], slot] = rng.integers(1, N + 1, size=(iters, po))
+        orders[r] = o.reshape(iters, P)
     return WmsSetup(nx, ny, nz, mmax, N, A0, M0, orders, qty, po, k)
