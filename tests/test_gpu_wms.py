@@ -192,3 +192,36 @@ def test_bad_inputs_on_device(rt, ctx):
     torch.cuda.synchronize()
     eA, eM, _, _, emv = wms.run(s, 0)
     assert (A.cpu().numpy().view(np.uint32)[0] == eA).all() and (o[2].cpu().numpy()[0] == emv).all()
+
+
+@pytest.mark.parametrize("floor", ["paper_10x10x10", "large_100x100x10"])
+def test_bench_batches_sampled_runs(rt, ctx, floor):
+    """The benchmark's own launches (bench.wms_batch, device buffers, 4,096
+    runs on 10x10x10 or 1,792 on 100x100x10, 100 iterations): sampled runs
+    against the oracle element by element."""
+    import torch
+    from bench import wms_batch
+    nx, ny, nz, er, runs = (10, 10, 10, 11, 4096) if floor == "paper_10x10x10" else (100, 100, 10, 1100, 1792)
+    s = wms_batch(nx, ny, nz, er, runs, 100, 2, 700)
+    log(f"{floor}: inputs ready")
+    R, T, S = s.orders.shape
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+    A, M = dev(s.A0), dev(s.M0)
+    out = (torch.empty((R, T), dtype=torch.float64, device="cuda"),
+           torch.empty((R, T), dtype=torch.float64, device="cuda"),
+           torch.empty((R, T), dtype=torch.int32, device="cuda"))
+    ctx.wms_run(A, M, dev(s.orders), dev(np.broadcast_to(s.qty[:, None, :], (R, T, S))), nx, ny, nz,
+                s.n_articles, s.mmax, s.po, s.k, out=out)
+    torch.cuda.synchronize()
+    sample = [0, R // 2, R - 1]
+    A_h = A[sample].cpu().numpy().view(np.uint32)
+    M_h = M[sample].cpu().numpy().view(np.uint32)
+    sil, area, mv = (out[0][sample].cpu().numpy(), out[1][sample].cpu().numpy(),
+                     out[2][sample].cpu().numpy().view(np.uint32))
+    del A, M, out
+    torch.cuda.empty_cache()
+    for q, r in enumerate(sample):
+        eA, eM, esil, earea, emv = wms.run(s, r)
+        assert (A_h[q] == eA).all() and (M_h[q] == eM).all() and (mv[q] == emv).all(), f"run {r}"
+        assert np.abs(sil[q] - esil).max() <= 1e-14 and np.abs(area[q] - earea).max() <= 1e-14 * max(1.0, earea.max())
+        log(f"{floor}: run {r} equal to the oracle")
