@@ -120,7 +120,9 @@ __global__ void k_frontier_seed(uint64_t *__restrict__ list, uint32_t *__restric
 // Push relaxation of the frontier items (block, v): each lane (source)
 // relaxes every out-arc of v; an arc target whose value dropped for any lane
 // is queued once for the next pass (a 32-bit pass stamp per (block, vertex)
-// dedups; the wave's ballot decides whether to queue).
+// dedups).  The wave collects its item's improved targets one per lane,
+// stamps them in parallel, and reserves the queue slots of the winners with
+// one atomic (their offsets from mbcnt).
 __global__ __launch_bounds__(256) void k_frontier_push(
     uint32_t *__restrict__ dist, uint32_t V, const uint32_t *__restrict__ row_ptr,
     const uint32_t *__restrict__ col, const uint32_t *__restrict__ w,
@@ -139,18 +141,26 @@ __global__ __launch_bounds__(256) void k_frontier_push(
         uint32_t *db = dist + static_cast<size_t>(b) * V * LANES;
         const uint32_t dv = db[static_cast<size_t>(v) * LANES + lane];
         const uint32_t beg = uniform(row_ptr[v]), end = uniform(row_ptr[v + 1]);
+        uint32_t tgt = 0, nq = 0;   // lane k < nq holds the k-th improved target
         for (uint32_t e = beg; e < end; ++e) {
             const uint32_t x = uniform(col[e]);
             const uint32_t nd = sat_add(dv, uniform(w[e]));
             uint32_t *px = db + static_cast<size_t>(x) * LANES + lane;
             bool imp = false;
             if (nd < *px) imp = nd < atomicMin(px, nd);
-            if (__builtin_amdgcn_ballot_w64(imp) != 0 && lane == 0) {
-                const uint32_t o = atomicMax(&stamps[static_cast<size_t>(b) * V + x], stamp);
-                if (o < stamp) {
-                    const uint32_t pos = atomicAdd(count_out, 1u);
-                    list_out[pos] = (static_cast<uint64_t>(b) << 32) | x;
-                }
+            if (__builtin_amdgcn_ballot_w64(imp) != 0) {
+                if (lane == nq) tgt = x;
+                ++nq;
+            }
+            if (nq == LANES || (e + 1 == end && nq)) {
+                bool win = false;
+                if (lane < nq) win = atomicMax(&stamps[static_cast<size_t>(b) * V + tgt], stamp) < stamp;
+                const uint64_t wm = __builtin_amdgcn_ballot_w64(win);
+                uint32_t base = 0;
+                if (lane == 0 && wm) base = atomicAdd(count_out, static_cast<uint32_t>(__builtin_popcountll(wm)));
+                base = uniform(base);
+                if (win) list_out[base + mbcnt64(wm)] = (static_cast<uint64_t>(b) << 32) | tgt;
+                nq = 0;
             }
         }
     }

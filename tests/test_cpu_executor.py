@@ -226,3 +226,27 @@ def case_server_two_epochs(harness):
         pk = picks[off[o]:off[o + 1]]
         exp = oracle.order_matrices(g.row_ptr, g.col, weights[epochs[o]], np.array([0, P], np.uint32), pk)
         assert (D.ravel() == exp).all(), f"order {o} epoch {epochs[o]}"
+
+
+@case
+def case_frontier_rows_random_graph(harness):
+    """The push-frontier schedule (wave-aggregated queue appends, pass
+    stamps) on a random graph with parallel arcs and self-loops, and on a
+    vertex of out-degree above 64 (the aggregation flushes every 64
+    targets): rows equal to the oracle's Dijkstra."""
+    from tests.helpers import random_csr
+    rng = np.random.default_rng(37)
+    V = 150
+    rp, col, w = random_csr(rng, V, 4 * V, wmax=20)
+    # vertex 0 gets 100 more arcs (to every vertex 1..100)
+    rows = [list(zip(col[rp[u]:rp[u + 1]], w[rp[u]:rp[u + 1]])) for u in range(V)]
+    rows[0] += [(x, int(rng.integers(1, 30))) for x in range(1, 101)]
+    rp2 = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.uint32)
+    col2 = np.array([x for r in rows for x, _ in r], np.uint32)
+    w2 = np.array([y for r in rows for _, y in r], np.uint32)
+    src = np.concatenate([[0], rng.choice(np.arange(1, V), 7, replace=False)]).astype(np.uint32)
+    st, out, _, err = harness.run(rp2, col2, w2, sources=src, algo="frontier")
+    assert st == 0, err[-2000:]
+    d = out.reshape(len(src), V)
+    for i, s in enumerate(src):
+        assert (d[i] == oracle.dijkstra(rp2, col2, w2, int(s))).all(), f"source {s}"
