@@ -73,7 +73,11 @@ typedef enum wr_status {
 #define WR_ALGO_EDGE_B1     0x0040u  /* paper-structured: thread per arc, early exit */
 #define WR_ALGO_EDGE_B0     0x0050u  /* paper-structured: exactly V-1 rounds         */
 #define WR_ALGO_OVERLAY     0x0060u  /* segments with per-epoch boundary tables: passes are
-                                        dense min-plus maps from ports to exits       */
+                                        dense min-plus maps from a tile's incoming cross
+                                        arcs to its exits (tiles of at most 512 vertices,
+                                        64 incoming cross arcs, 64 exits and 512 cross
+                                        arcs leaving; WR_E_UNSUPPORTED otherwise, and
+                                        WR_ALGO_AUTO then takes WR_ALGO_SEGMENTED)   */
 #define WR_ALGO_MASK        0x00F0u
 #define WR_NO_GRAPH_CAPTURE 0x0100u  /* launch passes eagerly instead of replaying a hipGraph */
 #define WR_TIME_KERNELS     0x0200u  /* record HIP events around every launch of the schedule's

@@ -844,185 +844,213 @@ __global__ void k_min_scatter(const uint64_t *__restrict__ idx, const uint32_t *
         out[idx[q]] = min(out[idx[q]], val[q]);
 }
 
-// Overlay pass: a visit of (tile t, block b) computes the block's entry
-// values at t's ports from the exit values of the neighbouring tiles
-// (entry_p = min over cross arcs e -> p of xval[e] + w), maps them through
-// t's table onto t's exits (exit_j = min_p entry_p + F[exit_j][p], a dense
-// min-plus product), and stores each exit value that dropped, flagging the
-// tiles that exit's cross arcs lead to for the next pass.  All traffic is
+// Overlay pass: a visit of (tile t, block b) computes the block's value at
+// the head of every cross arc a = (e -> p) into t from the exit values of
+// the neighbouring tiles (entry_a = xval[e] + w_a), maps them through t's
+// table onto t's exits (exit_j = min_a entry_a + F[exit_j][p(a)], a dense
+// min-plus product, which also takes the minimum over the arcs of a port),
+// and stores each exit value that dropped, flagging the tiles that exit's
+// cross arcs lead to for the next pass.  All traffic is
 // plain loads and stores: a pass reads the exit values the previous passes
 // wrote (kernel boundaries order them), and a flag set during a pass brings
 // its tile back in the next one.
 //
 // A workgroup takes one unit (a tile and up to G of its active blocks),
-// stages the tile's packed table rows, its ports' incoming arcs and its
-// exits' outgoing arcs in LDS, and runs the unit's visits one after another.
-// Wave w owns entry rows w, w + NW, ... (R of them) and exits w R .. w R +
-// R - 1: per visit it loads its entry rows (the first incoming arc of each
-// port; a port's further arcs follow in a short loop) and the current values
-// of its exits with all loads in flight, and computes its exits against LDS
-// while the loads of the unit's next visit are in flight.  Rows and exits
-// past the tile's last are clamped to it (loaded again, never stored), so
-// every load is unconditional.  LDS is sized at launch to the tiling's
-// largest tile (XM exits x EM entries, PM arcs in or out); R is the smallest
+// stages the tile's packed table rows (one column per incoming cross arc),
+// its incoming arcs and its exits' outgoing arcs in LDS, and runs the unit's
+// visits one after another.  Wave w owns entry rows w, w + NW, ... (R of
+// them; row i is incoming arc i, whose source exit and weight are the same
+// for the whole wave) and exits w R .. w R + R - 1: per visit it loads its
+// entry rows, the current values of its exits and its bound with all loads
+// in flight.  Visits are software-pipelined two deep: once a visit's entry
+// rows are in LDS its registers take the loads of the visit two ahead, so
+// every visit's rows have two visits' time to arrive.  Rows and exits past
+// the tile's last are clamped to it (loaded again, never stored), so every
+// load is unconditional.  LDS is sized at launch to the tiling's largest
+// tile (XM exits x EM entries, PM arcs in or out); R is the smallest
 // instance with NW R >= max(EM, XM).
 constexpr uint32_t OVL_XCAP = 64;     // exits per tile (one 64-lane row of the exit table)
-constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving or entering a tile
+constexpr uint32_t OVL_ECAP = 64;     // incoming cross arcs per tile (table columns)
+constexpr uint32_t OVL_PCAP = 512;    // cross arcs leaving a tile
 constexpr uint32_t OVL_NW = 8;        // waves per workgroup
 constexpr uint64_t OVL_UNIT_PERM = 2654435761ull;   // a prime above any unit count (see seg_units_cap)
 template <int NW, int R>
-__global__ __launch_bounds__(NW * 64) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ Fx,
-                                                      const uint4 *__restrict__ hdr,
-                                                      const uint32_t *__restrict__ bo_xbeg, uint32_t XM,
-                                                      uint32_t EM, uint32_t PM) {
+__global__ __launch_bounds__(NW * 64, R <= 4 ? 8 : 1) void k_ovl_pass(SegPassArgs A, const uint32_t *__restrict__ Fx,
+                                                                     const uint4 *__restrict__ hdr,
+                                                                     const uint32_t *__restrict__ bo_xbeg, uint32_t XM,
+                                                                     uint32_t EM, uint32_t PM) {
     HIP_DYNAMIC_SHARED(uint32_t, lds)
-    uint32_t *s_M = lds;                    // [XM][EM]  table rows of the exits
-    uint32_t *s_in = s_M + XM * EM;         // [EM][64]  entry values of the visit
-    uint32_t *s_xbeg = s_in + EM * 64;      // [XM + 1]  first outgoing arc of each exit
-    uint32_t *s_xtile = s_xbeg + XM + 1;    // [PM]      outgoing arcs: target tile
-    uint32_t *s_pbeg = s_xtile + PM;        // [EM + 1]  first incoming arc of each port
-    uint32_t *s_pexit = s_pbeg + EM + 1;    // [PM]      incoming arcs: source exit,
-    uint32_t *s_pw = s_pexit + PM;          //           weight
+    uint32_t *s_M = lds;                     // [XM][EM]     table rows of the exits
+    uint32_t *s_in0 = s_M + XM * EM;         // [2][EM][64]  entry values, by visit parity
+    uint32_t *s_xbeg = s_in0 + 2 * EM * 64;  // [XM + 1]     first outgoing arc of each exit
+    uint32_t *s_xtile = s_xbeg + XM + 1;     // [PM]         outgoing arcs: target tile
+    uint32_t *s_pexit = s_xtile + PM;        // [PM]         incoming arcs: source exit,
+    uint32_t *s_pw = s_pexit + PM;           //              weight
     uint32_t *s_unit = s_pw + PM;
     const uint32_t lane = lane_id();
     const uint32_t wv = uniform(threadIdx.x >> 6);
     const uint32_t nunits = uniform(*A.nunits);
+    static_assert(NW * 64 >= OVL_PCAP && NW * 64 >= OVL_ECAP, "one staging round covers a tile's arcs");
     // Workgroup w takes unit w first, then units gridDim + cursor++ until
     // the end, so each unit is taken once; workgroups with no first unit
     // leave at once (light passes), and none waits on the cursor to start.
-    if (blockIdx.x >= nunits) return;
+    uint32_t u = blockIdx.x;
+    if (u >= nunits) return;
     uint32_t staged = NONE;
-    uint32_t first_unit = blockIdx.x;
     uint32_t stored = 0;   // exit values this wave stored (uniform)
     for (;;) {
-        uint32_t u = first_unit;
-        if (u == NONE) {
-            if (threadIdx.x == 0) *s_unit = gridDim.x + atomicAdd(A.cursor, 1u);
-            __syncthreads();
-            u = uniform(*s_unit);
-            __syncthreads();
-        }
-        first_unit = NONE;
-        if (u >= nunits) break;
         // units are taken in a scattered order (u -> u * P mod nunits, a
         // bijection for the prime P > nunits): each pass then moves every
         // front about one tile instead of cascading along the tiles' order,
         // which lowers the visits to convergence
         const uint2 unit = A.units[static_cast<uint32_t>((static_cast<uint64_t>(u) * OVL_UNIT_PERM) % nunits)];
         const uint32_t t = uniform(unit.x), slice = uniform(unit.y);
+        // every load that depends on the tile alone is issued before any of
+        // them is used (one round trip): its header, its incoming-arc range,
+        // its active count and the unit's block ids (one per lane, clamped
+        // into the tile's row; only lanes below the unit's count are used)
         const uint4 h = hdr[t];
-        const uint32_t p0 = uniform(h.x), b0 = uniform(h.y), xa0 = uniform(h.z), hw = uniform(h.w);
-        const uint32_t E = hw & 0xFFu, X = (hw >> 8) & 0xFFu, na = hw >> 16;
-        if (t != staged) {
-            // all staging loads are independent: one round trip
+        const uint2 h2 = A.hdr2[t];
+        const uint32_t tot = A.cnt_cur[t];
+        const uint32_t first_k = slice * A.G;
+        const uint32_t blk = A.bucket_cur[static_cast<size_t>(t) * A.S + min(first_k + lane, A.S - 1)];
+        const uint32_t b0 = uniform(h.y), xa0 = uniform(h.z), hw = uniform(h.w);
+        const uint32_t X = (hw >> 8) & 0xFFu, na = hw >> 16;
+        const uint32_t total = uniform(tot), pa0 = uniform(h2.x), npa = uniform(h2.y);
+        const bool work = npa != 0 && X != 0;
+        if (work && t != staged) {
+            // staging, again in one round: thread q loads entry q of every
+            // staged array before writing any (a tile with exits has at
+            // least one arc leaving it, so the clamped indices stay in its
+            // ranges); only table rows can outnumber the threads
+            const uint32_t q = threadIdx.x;
             const uint32_t *rows = Fx + static_cast<size_t>(b0) * EM;
             const uint32_t nM = X * EM;
-#pragma unroll 4
-            for (uint32_t q = threadIdx.x; q < nM; q += blockDim.x) s_M[q] = rows[q];
-            for (uint32_t j = threadIdx.x; j <= X; j += blockDim.x) s_xbeg[j] = bo_xbeg[b0 + t + j];
-            for (uint32_t k = threadIdx.x; k < na; k += blockDim.x) s_xtile[k] = A.x_tile[xa0 + k];
-            const uint2 h2 = A.hdr2[t];
-            const uint32_t pa0 = uniform(h2.x), npa = uniform(h2.y);
-            for (uint32_t i = threadIdx.x; i <= E; i += blockDim.x) s_pbeg[i] = A.pin_off[p0 + i] - pa0;
-            for (uint32_t k = threadIdx.x; k < npa; k += blockDim.x) {
-                const uint2 rec = A.pin_rec[pa0 + k];
-                s_pexit[k] = rec.x;
-                s_pw[k] = rec.y & 0xFFFFu;
+            const uint32_t vM = rows[min(q, nM - 1)];
+            const uint32_t vX = bo_xbeg[b0 + t + min(q, X)];
+            const uint32_t vT = A.x_tile[xa0 + min(q, na - 1)];
+            const uint2 vR = A.pin_rec[pa0 + min(q, npa - 1)];
+            if (q < nM) s_M[q] = vM;
+            if (q <= X) s_xbeg[q] = vX;
+            if (q < na) s_xtile[q] = vT;
+            if (q < npa) {
+                s_pexit[q] = vR.x;
+                s_pw[q] = vR.y & 0xFFFFu;
             }
+#pragma unroll 4
+            for (uint32_t i = q + blockDim.x; i < nM; i += blockDim.x) s_M[i] = rows[i];
             staged = t;
             __syncthreads();
         }
-        const uint32_t total = uniform(A.cnt_cur[t]);
-        const uint32_t first_k = slice * A.G;
-        const uint32_t cnt = (E != 0 && X != 0) ? min(A.G, total - first_k) : 0u;
-        if (cnt == 0) continue;
-        const uint32_t elast = E - 1, xlast = X - 1;
-        // per entry row of this wave: row offset of its first arc's source
-        // exit, and that arc's weight (the same for every visit of the unit)
-        uint32_t eoff[R], ew[R];
-#pragma unroll
-        for (uint32_t r = 0; r < R; ++r) {
-            const uint32_t k0 = s_pbeg[min(wv + NW * r, elast)];
-            eoff[r] = s_pexit[k0] * 64u + lane;
-            ew[r] = s_pw[k0];
-        }
-        // the unit's block ids, one per lane (cnt <= G <= 64)
-        const uint32_t blk = A.bucket_cur[static_cast<size_t>(t) * A.S + first_k + min(lane, cnt - 1)];
-        uint32_t nb = __builtin_amdgcn_readfirstlane(blk);
-        uint32_t vn[R], cn[R];
-#define OVL_ISSUE_LOADS(BLK)                                                                 \
-        {                                                                                    \
-            const uint32_t *xb_ = A.xval + static_cast<size_t>(BLK) * A.NB * 64;             \
-            const uint32_t *xv_ = xb_ + static_cast<size_t>(b0) * 64;                        \
-            _Pragma("unroll") for (uint32_t r = 0; r < R; ++r) vn[r] = xb_[eoff[r]];         \
-            _Pragma("unroll") for (uint32_t r = 0; r < R; ++r)                               \
-                cn[r] = xv_[static_cast<size_t>(min(wv * R + r, xlast)) * 64 + lane];        \
-        }
-        OVL_ISSUE_LOADS(nb)
-        for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t b = nb;
-            // target-bounded passes: a value above the lane's bound is never
-            // on a shortest path to one of its source's targets
-            const uint32_t bnd = A.bound ? A.bound[static_cast<size_t>(b) * 64 + lane] : INF;
-            const uint32_t *xb = A.xval + static_cast<size_t>(b) * A.NB * 64;   // uniform: exit e at xb + 64 e
-            uint32_t *xv = A.xval + (static_cast<size_t>(b) * A.NB + b0) * 64;  // uniform: own exit j at xv + 64 j
-            uint32_t c[R];
-#pragma unroll
-            for (uint32_t r = 0; r < R; ++r) c[r] = cn[r];
+        const uint32_t cnt = work ? min(A.G, total - first_k) : 0u;
+        if (cnt != 0) {
+            const uint32_t elast = npa - 1, xlast = X - 1;
+            // per entry row of this wave: its arc's source exit and weight
+            // (uniform, and the same for every visit of the unit)
+            uint32_t erow[R], ew[R];
 #pragma unroll
             for (uint32_t r = 0; r < R; ++r) {
-                const uint32_t i = wv + NW * r;
-                if (i < E) {
-                    uint32_t e = sat_add(vn[r], ew[r]);
-                    // further incoming arcs of ports that have several
-                    const uint32_t k1 = s_pbeg[i + 1];
-                    for (uint32_t kx = s_pbeg[i] + 1; kx < k1; ++kx)
-                        e = min(e, sat_add(xb[static_cast<size_t>(s_pexit[kx]) * 64 + lane], s_pw[kx]));
-                    s_in[i * 64 + lane] = e;
-                }
+                const uint32_t k0 = min(wv + NW * r, elast);
+                erow[r] = uniform(s_pexit[k0]);
+                ew[r] = uniform(s_pw[k0]);
             }
-            __syncthreads();
-            if (k + 1 < cnt) {
-                nb = __builtin_amdgcn_readlane(blk, k + 1);
-                OVL_ISSUE_LOADS(nb)
-            }
-            // this wave's exits (rows past the tile's last repeat it): min-plus
-            // over the entry rows; rows past the tile's ports are not written
-            // this visit, their table entries are INF and a saturating add
-            // with INF is INF whatever the row holds
-            const uint32_t j0 = wv * R;
-            if (j0 < X) {
-                uint32_t m[R];
+            // a visit's loads into one register set: its entry rows, its
+            // exits' current values and its target bound (without bounds a
+            // row of the block is read instead, through a select rather than
+            // a branch, so every load is unconditional and the waits on them
+            // stay exact)
+            auto issue = [&](uint32_t (&vn)[R], uint32_t (&cn)[R], uint32_t &bn, uint32_t bid) {
+                const uint32_t *xb = A.xval + static_cast<size_t>(bid) * A.NB * 64;
+                const uint32_t *xv = xb + static_cast<size_t>(b0) * 64;
+                const uint32_t *bp = A.bound ? A.bound + static_cast<size_t>(bid) * 64 : xb;
 #pragma unroll
-                for (uint32_t r = 0; r < R; ++r) m[r] = INF;
-                for (uint32_t i = 0; i < E; i += 4) {
-                    const uint32_t e0 = s_in[i * 64 + lane], e1 = s_in[(i + 1) * 64 + lane];
-                    const uint32_t e2 = s_in[(i + 2) * 64 + lane], e3 = s_in[(i + 3) * 64 + lane];
+                for (uint32_t r = 0; r < R; ++r) vn[r] = xb[static_cast<size_t>(erow[r]) * 64 + lane];
 #pragma unroll
-                    for (uint32_t r = 0; r < R; ++r) {
-                        const uint4 f = *reinterpret_cast<const uint4 *>(s_M + min(j0 + r, xlast) * EM + i);
-                        m[r] = min(m[r], min(min(sat_add(e0, f.x), sat_add(e1, f.y)),
-                                             min(sat_add(e2, f.z), sat_add(e3, f.w))));
-                    }
-                }
-                // exits that dropped: store the value, flag the arcs' targets
+                for (uint32_t r = 0; r < R; ++r) cn[r] = xv[static_cast<size_t>(min(wv * R + r, xlast)) * 64 + lane];
+                bn = bp[lane];
+            };
+            auto visit = [&](uint32_t k, uint32_t (&vn)[R], uint32_t (&cn)[R], uint32_t &bn) {
+                const uint32_t b = __builtin_amdgcn_readlane(blk, k);
+                // target-bounded passes: a value above the lane's bound is
+                // never on a shortest path to one of its source's targets
+                const uint32_t bnd = A.bound ? bn : INF;
+                uint32_t *xv = A.xval + (static_cast<size_t>(b) * A.NB + b0) * 64;  // own exit j at xv + 64 j
+                // entry rows alternate between two buffers: a wave that
+                // starts the next visit writes the other one while slower
+                // waves may still read this one, and the visit after that
+                // writes here only once every wave has passed the next
+                // visit's barrier
+                uint32_t *s_in = s_in0 + (k & 1u) * EM * 64;
+                uint32_t c[R];
+#pragma unroll
+                for (uint32_t r = 0; r < R; ++r) c[r] = cn[r];
 #pragma unroll
                 for (uint32_t r = 0; r < R; ++r) {
-                    const uint32_t j = j0 + r;
-                    if (j >= X) break;
-                    const bool imp = m[r] < c[r] && m[r] <= bnd;
-                    if (imp) xv[static_cast<size_t>(j) * 64 + lane] = m[r];
-                    const uint64_t bal = __builtin_amdgcn_ballot_w64(imp);
-                    stored += static_cast<uint32_t>(__builtin_popcountll(bal));
-                    if (bal == 0) continue;
-                    const uint32_t kb = uniform(s_xbeg[j]), ke = uniform(s_xbeg[j + 1]);
-                    for (uint32_t kx = kb + lane; kx < ke; kx += 64)
-                        A.flags[static_cast<size_t>(s_xtile[kx]) * A.S + b] = 1;
+                    const uint32_t i = wv + NW * r;
+                    if (i < npa) s_in[i * 64 + lane] = sat_add(vn[r], ew[r]);
                 }
+                // this register set now takes the loads of the visit two
+                // ahead; they go out before the barrier, so that the wait
+                // there and this visit's exits overlap them.  Past the unit's
+                // last visit this block's rows are loaded again (cache hits):
+                // issuing always keeps each set in its registers across the
+                // loop, where a conditional issue would make the compiler
+                // copy registers whose loads are still in flight
+                issue(vn, cn, bn, k + 2 < cnt ? __builtin_amdgcn_readlane(blk, min(k + 2, 63u)) : b);
+                __syncthreads();
+                // this wave's exits (rows past the tile's last repeat it):
+                // min-plus over the entry rows; rows past the tile's arcs
+                // are not written this visit, their table entries are INF
+                // and a saturating add with INF is INF whatever the row holds
+                const uint32_t j0 = wv * R;
+                if (j0 < X) {
+                    uint32_t m[R];
+#pragma unroll
+                    for (uint32_t r = 0; r < R; ++r) m[r] = INF;
+                    for (uint32_t i = 0; i < npa; i += 4) {
+                        const uint32_t e0 = s_in[i * 64 + lane], e1 = s_in[(i + 1) * 64 + lane];
+                        const uint32_t e2 = s_in[(i + 2) * 64 + lane], e3 = s_in[(i + 3) * 64 + lane];
+#pragma unroll
+                        for (uint32_t r = 0; r < R; ++r) {
+                            const uint4 f = *reinterpret_cast<const uint4 *>(s_M + min(j0 + r, xlast) * EM + i);
+                            m[r] = min(m[r], min(min(sat_add(e0, f.x), sat_add(e1, f.y)),
+                                                 min(sat_add(e2, f.z), sat_add(e3, f.w))));
+                        }
+                    }
+                    // exits that dropped: store the value, flag the arcs' targets
+#pragma unroll
+                    for (uint32_t r = 0; r < R; ++r) {
+                        const uint32_t j = j0 + r;
+                        if (j >= X) break;
+                        const bool imp = m[r] < c[r] && m[r] <= bnd;
+                        if (imp) xv[static_cast<size_t>(j) * 64 + lane] = m[r];
+                        const uint64_t bal = __builtin_amdgcn_ballot_w64(imp);
+                        stored += static_cast<uint32_t>(__builtin_popcountll(bal));
+                        if (bal == 0) continue;
+                        const uint32_t kb = uniform(s_xbeg[j]), ke = uniform(s_xbeg[j + 1]);
+                        for (uint32_t kx = kb + lane; kx < ke; kx += 64)
+                            A.flags[static_cast<size_t>(s_xtile[kx]) * A.S + b] = 1;
+                    }
+                }
+            };
+            uint32_t vn0[R], cn0[R], bn0, vn1[R], cn1[R], bn1;
+            const uint32_t blk0 = __builtin_amdgcn_readfirstlane(blk);
+            issue(vn0, cn0, bn0, blk0);
+            issue(vn1, cn1, bn1, cnt > 1 ? __builtin_amdgcn_readlane(blk, 1) : blk0);
+            uint32_t k = 0;
+            for (; k + 1 < cnt; k += 2) {
+                visit(k, vn0, cn0, bn0);
+                visit(k + 1, vn1, cn1, bn1);
             }
-            __syncthreads();
+            if (k < cnt) visit(k, vn0, cn0, bn0);
         }
-#undef OVL_ISSUE_LOADS
+        // the unit's last visit ends without a barrier: every wave passes
+        // the two below before the next unit stages or writes entry rows
+        if (threadIdx.x == 0) *s_unit = gridDim.x + atomicAdd(A.cursor, 1u);
+        __syncthreads();
+        u = uniform(*s_unit);
+        __syncthreads();
+        if (u >= nunits) break;
     }
     if (lane == 0 && stored) A.wave_stores[blockIdx.x * NW + wv] += stored;
 }
@@ -1097,21 +1125,27 @@ __global__ __launch_bounds__(OVL_PLAN_WAVES * 64) void k_ovl_plan(
     }
 }
 
-// Packs the exits' rows of the boundary tables: Fx[exit][i] = F[pos][i]
-// for the tile's ports i, INF for i up to the row length EM.
+// Packs the exits' rows of the boundary tables with one column per incoming
+// cross arc of the tile (arcs in the order of their records, grouped by
+// port): Fx[exit][i] = F[pos][port of arc i], INF for i up to the row length
+// EM.  A port reached by several arcs repeats its column, so a pass takes
+// the minimum over those arcs in its min-plus step.
 __global__ void k_ovl_pack(const uint32_t *__restrict__ F, const uint32_t *__restrict__ tile_base,
-                           const uint32_t *__restrict__ bo_local, const uint4 *__restrict__ hdr, uint32_t T,
+                           const uint32_t *__restrict__ bo_local, const uint4 *__restrict__ hdr,
+                           const uint2 *__restrict__ hdr2, const uint32_t *__restrict__ pin_lport, uint32_t T,
                            uint32_t EM, uint32_t *__restrict__ Fx) {
     const uint32_t lane = lane_id();
     const uint32_t wpb = blockDim.x >> 6;
     for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < T; t += gridDim.x * wpb) {
         const uint32_t base = tile_base[t];
         const uint4 h = hdr[t];
-        const uint32_t b0 = h.y, E = h.w & 0xFFu, X = (h.w >> 8) & 0xFFu;
+        const uint2 h2 = hdr2[t];
+        const uint32_t b0 = h.y, X = (h.w >> 8) & 0xFFu, pa0 = h2.x, npa = h2.y;
         for (uint32_t j = 0; j < X; ++j) {
             const uint32_t pos = base + bo_local[b0 + j];
             for (uint32_t i = lane; i < EM; i += 64)
-                Fx[static_cast<size_t>(b0 + j) * EM + i] = i < E ? F[static_cast<size_t>(pos) * 64 + i] : INF;
+                Fx[static_cast<size_t>(b0 + j) * EM + i] =
+                    i < npa ? F[static_cast<size_t>(pos) * 64 + pin_lport[pa0 + i]] : INF;
         }
     }
 }
@@ -1780,9 +1814,11 @@ void launch_ovl_custom(const TileSet &ts, uint32_t tile_cap, uint32_t *F, uint32
     fail(WR_E_UNSUPPORTED, "overlay tables need tiles of at most 512 vertices");
 }
 
+// most exits, table columns (incoming cross arcs, rounded up to 4) and
+// cross arcs leaving or entering one tile
 static void ovl_dims(const TileSet &ts, uint32_t &XM, uint32_t &EM, uint32_t &PM) {
     XM = std::max(ts.max_exits, 1u);
-    EM = (std::max(ts.max_ports, 1u) + 3u) / 4u * 4u;
+    EM = (std::max(ts.max_cross_in, 1u) + 3u) / 4u * 4u;
     PM = std::max(std::max(ts.max_cross, ts.max_cross_in), 1u);
 }
 
@@ -1795,7 +1831,7 @@ uint32_t ovl_row_entries(const TileSet &ts) {
 uint32_t ovl_pass_lds_bytes(const TileSet &ts) {
     uint32_t XM, EM, PM;
     ovl_dims(ts, XM, EM, PM);
-    return (XM * EM + EM * 64 + XM + 1 + PM + EM + 1 + 2 * PM + 1) * 4;
+    return (XM * EM + 2 * EM * 64 + XM + 1 + 3 * PM + 1) * 4;
 }
 
 __global__ void k_ovl_pin_rec(uint2 *__restrict__ rec, const uint32_t *__restrict__ pin_xa,
@@ -1815,7 +1851,8 @@ void launch_ovl_pin_rec(const TileSet &ts, hipStream_t st) {
 
 void launch_ovl_pack(const TileSet &ts, hipStream_t st) {
     hipLaunchKernelGGL(k_ovl_pack, blocks_for(ts.T, 4, 4096), 256, 0, st, ts.d_F.p, ts.d_tile_base.p,
-                       ts.d_bo_local.p, reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p), ts.T, ts.ovl_em,
+                       ts.d_bo_local.p, reinterpret_cast<const uint4 *>(ts.d_ovl_hdr.p),
+                       reinterpret_cast<const uint2 *>(ts.d_ovl_hdr2.p), ts.d_pin_lport.p, ts.T, ts.ovl_em,
                        ts.d_Fx.p);
     check_launch("ovl_pack");
 }
@@ -1980,6 +2017,7 @@ void launch_intile_fix(wr_context *ctx, const TileSet &ts, const IntileWork &w, 
 
 uint32_t ovl_max_exits() { return OVL_XCAP; }
 uint32_t ovl_max_cross() { return OVL_PCAP; }
+uint32_t ovl_max_entries() { return OVL_ECAP; }
 uint32_t ovl_waves() { return OVL_NW; }
 
 

@@ -170,9 +170,10 @@ double now_ms() {
 
 bool overlay_supported(const wr_graph *g) {
     const TileSet *ts = g->tiles;
-    return ts && g->lanes == 64 && g->max_w < 65536u && ts->max_ports <= 64 &&
+    // every port has an incoming cross arc, so the arc bound also bounds the
+    // ports (the in-tile tables hold 64 of them)
+    return ts && g->lanes == 64 && g->max_w < 65536u && ts->max_cross_in <= ovl_max_entries() &&
            ts->max_exits <= ovl_max_exits() && ts->max_cross <= ovl_max_cross() &&
-           ts->max_cross_in <= ovl_max_cross() &&
            (ts->tile_cap == 256 || ts->tile_cap == 512);
 }
 
@@ -201,8 +202,9 @@ uint32_t resolve_algo(wr_graph *g, uint32_t flags) {
     if (a == WR_ALGO_AUTO) a = overlay_supported(g) ? WR_ALGO_OVERLAY : WR_ALGO_SEGMENTED;
     if (a == WR_ALGO_OVERLAY && !overlay_supported(g))
         fail(WR_E_UNSUPPORTED, "the tiling does not fit the overlay tables (tiles of at most 512 "
-                               "vertices with at most 64 ports, " + std::to_string(ovl_max_exits()) +
-                               " exits and " + std::to_string(ovl_max_cross()) + " cross arcs leaving and entering each)");
+                               "vertices with at most " + std::to_string(ovl_max_exits()) + " exits, " +
+                               std::to_string(ovl_max_entries()) + " cross arcs entering and " +
+                               std::to_string(ovl_max_cross()) + " leaving each)");
     return a;
 }
 

@@ -416,6 +416,7 @@ void launch_gather_ovl(uint32_t num_orders, const uint32_t *pick_off, const uint
                        uint32_t *out, hipStream_t st);
 uint32_t ovl_pass_lds_bytes(const TileSet &ts);
 uint32_t ovl_max_exits();
+uint32_t ovl_max_entries();
 uint32_t ovl_max_cross();
 uint32_t ovl_waves();   // waves (= blocks per unit) of the overlay pass
 
