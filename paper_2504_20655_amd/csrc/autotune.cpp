@@ -180,7 +180,8 @@ extern "C" wr_status wr_autotune(wr_graph *g, uint32_t sources_hint, const char 
         for (const auto &sh : shapes)
             if (sh[0] != prev.tw || sh[1] != prev.th) consider(Candidate{512, 8, 8, 4, sh[0], sh[1]});
         const Candidate shape = best;
-        for (uint32_t G : {2u, 3u, 6u}) consider(Candidate{shape.tile, shape.waves, shape.passes, G, shape.tw, shape.th});
+        for (uint32_t G : {2u, 3u, 6u, 8u, 12u, 16u, 24u})
+            consider(Candidate{shape.tile, shape.waves, shape.passes, G, shape.tw, shape.th});
         const Candidate unit = best;
         for (uint32_t K : {4u, 16u}) consider(Candidate{unit.tile, unit.waves, K, unit.G, unit.tw, unit.th});
     } else {
