@@ -88,6 +88,42 @@ def test_pred_refused_with_zero_weights(rt, ctx):
     assert (G.sssp([0]) == np.asarray([[0, 0]], np.uint32)).all()
 
 
+def test_overlay_refuses_tiles_with_many_incoming_arcs(rt, ctx):
+    """The overlay's exit tables have one column per incoming cross arc, at
+    most 64 per tile.  Tile A = {a, b} has 2 ports but 80 incoming cross arcs
+    (each of the 40 exits of tile B has an arc to both): the overlay refuses
+    the tiling, and the automatic choice falls back to the segmented schedule
+    with the oracle's distances."""
+    rng = np.random.default_rng(64)
+    n = 40
+    V = n + 2                       # 0 = a, 1 = b, 2.. = the chain of tile B
+    arcs = [(0, 1), (1, 0), (0, 2)]
+    for i in range(n):
+        v = 2 + i
+        arcs += [(v, 0), (v, 1)]
+        if i + 1 < n:
+            arcs += [(v, v + 1), (v + 1, v)]
+    arcs.sort()
+    src_v = np.asarray([a for a, _ in arcs], np.int64)
+    col = np.asarray([b for _, b in arcs], np.uint32)
+    rp = np.zeros(V + 1, np.uint32)
+    np.add.at(rp, src_v + 1, 1)
+    rp = np.cumsum(rp).astype(np.uint32)
+    w = rng.integers(1, 10, len(col)).astype(np.uint32)
+    G = _graph(rt, ctx, rp, col, w)
+    seg = np.ones(V, np.uint32)
+    seg[:2] = 0
+    G.set_segments(seg, 2)
+    src = np.asarray([0, 5, V - 1], np.uint32)
+    exp = oracle.dijkstra_multi(rp, col, w, src)
+    with pytest.raises(rt.WrError) as ei:
+        G.sssp(src, algo="overlay")
+    assert ei.value.name == "WR_E_UNSUPPORTED"
+    assert (G.sssp(src, algo="auto") == exp).all()
+    assert G.last_run()["algo"] == "segmented"
+    assert (G.sssp(src, algo="segmented") == exp).all()
+
+
 @pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("seg", ["grid32", "grid_rect", "bfs", "user_map"])
 def test_medium_slice_segmented(rt, ctx, seg, sched):
