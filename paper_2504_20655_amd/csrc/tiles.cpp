@@ -382,12 +382,29 @@ void grid_maps(const wr_graph *g, uint32_t W, uint32_t H, uint32_t L, uint32_t t
 }  // namespace
 
 namespace {
-// interleaves the low 21 bits of x and y (x in the even bits)
-uint64_t morton2(uint32_t x, uint32_t y) {
-    uint64_t k = 0;
-    for (uint32_t b = 0; b < 21; ++b)
-        k |= (static_cast<uint64_t>((x >> b) & 1u) << (2 * b)) | (static_cast<uint64_t>((y >> b) & 1u) << (2 * b + 1));
-    return k;
+// Position of cell (x, y) along Hilbert's curve over the n x n grid (n a
+// power of two above both coordinates): at every level the quadrant the
+// point falls in contributes its rank along the curve (lower left, upper
+// left, upper right, lower right), and the point is then mapped into that
+// quadrant's frame (the lower quadrants are traversed transposed, the lower
+// right one also mirrored), so consecutive positions are always adjacent
+// cells and a run of positions stays compact.
+uint64_t hilbert2(uint32_t n, uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += static_cast<uint64_t>(s) * s * ((3u * rx) ^ ry);
+        x &= s - 1;
+        y &= s - 1;
+        if (ry == 0) {
+            if (rx == 1) {
+                x = s - 1 - x;
+                y = s - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
 }
 }  // namespace
 
@@ -398,6 +415,8 @@ const std::vector<uint64_t> &tile_order_keys(wr_graph *g) {
     const uint64_t plane = static_cast<uint64_t>(g->grid_W) * g->grid_H;
     const bool grid = g->tiles_user && g->grid_W && g->grid_H &&
                       plane * std::max(g->grid_L, 1u) == static_cast<uint64_t>(g->V);
+    uint32_t side = 1;   // a power of two above both grid dimensions
+    while (side < std::max(g->grid_W, g->grid_H)) side <<= 1;
     for (uint32_t t = 0; t < ts.T; ++t) {
         if (!grid) {
             ts.order_key[t] = t;
@@ -413,7 +432,7 @@ const std::vector<uint64_t> &tile_order_keys(wr_graph *g) {
             ++n;
         }
         const uint32_t cx = n ? static_cast<uint32_t>(sx / n) : 0, cy = n ? static_cast<uint32_t>(sy / n) : 0;
-        ts.order_key[t] = (lv << 42) | morton2(cx, cy);
+        ts.order_key[t] = (lv << 42) | hilbert2(side, cx, cy);
     }
     return ts.order_key;
 }

@@ -483,9 +483,9 @@ void launch_weight_scatter(uint32_t n, const uint32_t *arc, const uint32_t *neww
 void build_tiles(wr_graph *g, const uint32_t *seg, uint32_t nseg, uint32_t tile_cap,
                  bool bfs_grow, const uint32_t *sub = nullptr, uint32_t nsub = 0);
 // Sort keys of the tiles for grouping sources into blocks: for a grid
-// segmentation, the Z-order (Morton) code of the tile's centroid cell per
-// level, so that consecutive tiles form compact patches; otherwise the
-// tile id.  Computed on first use and kept with the tiles.
+// segmentation, the position of the tile's centroid cell along Hilbert's
+// curve, per level, so that consecutive tiles form compact patches;
+// otherwise the tile id.  Computed on first use and kept with the tiles.
 const std::vector<uint64_t> &tile_order_keys(wr_graph *g);
 // Rank of each tile in (key, tile) order.
 const std::vector<uint32_t> &tile_order_rank(wr_graph *g);
