@@ -1086,15 +1086,24 @@ __global__ __launch_bounds__(OVL_PLAN_WAVES * 64) void k_ovl_plan(
         if (t < T) {
             uint8_t *f = flags + static_cast<size_t>(t) * S;
             uint32_t *bk = bucket + static_cast<size_t>(t) * S;
-            for (uint32_t c0 = 0; c0 < S; c0 += 64) {
-                const uint32_t b = c0 + lane;
-                const bool on = b < S && f[b] != 0;
-                const uint64_t msk = __builtin_amdgcn_ballot_w64(on);
-                if (on) {
-                    bk[k + mbcnt64(msk)] = b;
-                    f[b] = 0;
+            // the row's flags 512 at a time: all eight loads of a lane are
+            // issued before the first ballot (indices clamped into the row),
+            // so a row costs one round trip, not one per 64 blocks
+            for (uint32_t g0 = 0; g0 < S; g0 += 512) {
+                uint32_t v[8];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) v[q] = f[min(g0 + q * 64 + lane, S - 1)];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) {
+                    const uint32_t b = g0 + q * 64 + lane;
+                    const bool on = b < S && v[q] != 0;
+                    const uint64_t msk = __builtin_amdgcn_ballot_w64(on);
+                    if (on) {
+                        bk[k + mbcnt64(msk)] = b;
+                        f[b] = 0;
+                    }
+                    k += static_cast<uint32_t>(__builtin_popcountll(msk));
                 }
-                k += static_cast<uint32_t>(__builtin_popcountll(msk));
             }
             if (lane == 0) {
                 cnt[t] = k;
