@@ -88,6 +88,27 @@ def test_pred_refused_with_zero_weights(rt, ctx):
     assert (G.sssp([0]) == np.asarray([[0, 0]], np.uint32)).all()
 
 
+@pytest.mark.parametrize("tw", [16, 32, 48, 64])
+def test_overlay_tile_sizes(rt, ctx, tw):
+    """The overlay pass over square grid tiles of several sizes: larger tiles
+    have more incoming arcs and exits, so the pass runs with more rows and
+    exits per wave; matrices equal the oracle's (tilings beyond the table
+    limits are refused, never approximated)."""
+    wl = make_config("medium", side=192, num_orders=8)
+    g = wl.graph
+    G = _graph(rt, ctx, g.row_ptr, g.col, g.w)
+    G.segment_grid(g.W, g.H, 1, tw, tw)
+    exp = oracle.order_matrices(g.row_ptr, g.col, g.w, wl.pick_offsets, wl.picks)
+    try:
+        got = G.order_matrices(wl.pick_offsets, wl.picks, algo="overlay")
+    except rt.WrError as e:
+        assert e.name == "WR_E_UNSUPPORTED" and tw > 32
+        pytest.skip(f"{tw}x{tw} tiles exceed the overlay tables")
+    assert (got == exp).all()
+    again = G.order_matrices(wl.pick_offsets, wl.picks, algo="overlay", graph_capture=False)
+    assert (again == exp).all()
+
+
 def test_overlay_refuses_tiles_with_many_incoming_arcs(rt, ctx):
     """The overlay's exit tables have one column per incoming cross arc, at
     most 64 per tile.  Tile A = {a, b} has 2 ports but 80 incoming cross arcs
